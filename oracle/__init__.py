@@ -1,0 +1,3 @@
+"""FP64 CPU oracle (test infrastructure only): see oracle.oracle."""
+from .oracle import *  # noqa: F401,F403
+from .oracle import Op, build, FLOPS_HOP, FLOPS_WILSON, FLOPS_DWF  # noqa: F401
