@@ -219,8 +219,9 @@ def fp16_encode(psi, site_axes: int):
 
     ``psi`` is complex; the trailing ``site_axes`` axes (e.g. 2 for (4, 3)) form one site.
     The values are first rounded to float32; the site scale is s = max |Re|, |Im| over the site
-    (float32); each real is stored as float16(float32(v) / s) rounded to nearest even; s = 0
-    stores zeros. Returns (codes as float16 with a trailing re/im axis, scales float32).
+    (float32); with r = float32(1 / s) (correctly rounded), each real is stored as
+    float16(float32(v) * r) rounded to nearest even; s = 0 stores zeros. Returns (codes as
+    float16 with a trailing re/im axis, scales float32).
     """
     psi = np.asarray(psi)
     re = np.stack([psi.real, psi.imag], axis=-1).astype(np.float32)
@@ -228,7 +229,8 @@ def fp16_encode(psi, site_axes: int):
     flat = re.reshape(lead + (-1,))
     s = np.max(np.abs(flat), axis=-1).astype(np.float32)
     safe = np.where(s > 0, s, np.float32(1)).astype(np.float32)
-    q = (flat / safe[..., None]).astype(np.float32).astype(np.float16)
+    r = (np.float32(1.0) / safe).astype(np.float32)
+    q = (flat * r[..., None]).astype(np.float32).astype(np.float16)
     q = np.where(s[..., None] > 0, q, np.float16(0))
     return q.reshape(re.shape), s
 
