@@ -123,6 +123,68 @@ static void add_proj(cplx out[4][3], int mu, double sign, cplx v[4][3])
         }
 }
 
+/* (H psi)(x, s5) (dag = 0) or (H^dagger psi)(x, s5) (dag = 1) at one site, into acc. */
+static void hop_site(const cplx *U, const cplx *psi, const int *dims, int Ls, int dag, long x, int s5,
+                     cplx acc[4][3])
+{
+    const double sg = dag ? -1.0 : 1.0;
+    memset(acc, 0, sizeof(cplx) * 12);
+    for (int mu = 0; mu < 4; ++mu) {
+        const long xp = neighbour(dims, x, mu, +1);
+        const long xm = neighbour(dims, x, mu, -1);
+        const cplx *uf = U + (x * 4 + mu) * 9;    /* U_mu(x)      */
+        const cplx *ub = U + (xm * 4 + mu) * 9;   /* U_mu(x - mu) */
+        const cplx *pf = psi + (xp * Ls + s5) * 12;
+        const cplx *pb = psi + (xm * Ls + s5) * 12;
+        cplx v[4][3], w[4][3];
+        for (int t = 0; t < 4; ++t)
+            for (int a = 0; a < 3; ++a) {
+                cplx f = 0, b = 0;
+                for (int c = 0; c < 3; ++c) {
+                    f += uf[a * 3 + c] * pf[t * 3 + c];
+                    b += conj(ub[c * 3 + a]) * pb[t * 3 + c];
+                }
+                v[t][a] = f;
+                w[t][a] = b;
+            }
+        add_proj(acc, mu, -sg, v);   /* (1 - gamma) forward  (H), (1 + gamma) for H^dag */
+        add_proj(acc, mu, +sg, w);   /* (1 + gamma) backward (H), (1 - gamma) for H^dag */
+    }
+}
+
+/* Domain-wall (M psi)(x, s5) or (M^dagger psi)(x, s5) at one site, into o. */
+static void dwf_site(const cplx *U, const cplx *psi, const int *dims, int Ls, double M5, double mf, int dag,
+                     long x, int s5, cplx o[4][3])
+{
+    /* Chiral projectors from gamma_5; P_- is applied to s+1 and P_+ to s-1 (swapped for M^dag). */
+    cplx Pp[4][4], Pm[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            cplx d = (i == j) ? 1.0 : 0.0;
+            Pp[i][j] = 0.5 * (d + GAM[4][i][j]);
+            Pm[i][j] = 0.5 * (d - GAM[4][i][j]);
+        }
+    cplx (*Pup)[4] = dag ? Pp : Pm;
+    cplx (*Pdn)[4] = dag ? Pm : Pp;
+    cplx h[4][3];
+    hop_site(U, psi, dims, Ls, dag, x, s5, h);
+    const cplx *p = psi + (x * Ls + s5) * 12;
+    const int sp = (s5 + 1) % Ls, sm = (s5 - 1 + Ls) % Ls;
+    const double fp = (s5 == Ls - 1) ? -mf : 1.0;   /* psi~_{s+1} wall factor */
+    const double fm = (s5 == 0) ? -mf : 1.0;        /* psi~_{s-1} wall factor */
+    const cplx *pu = psi + (x * Ls + sp) * 12;
+    const cplx *pd = psi + (x * Ls + sm) * 12;
+    for (int s = 0; s < 4; ++s)
+        for (int a = 0; a < 3; ++a) {
+            cplx acc = (5.0 - M5) * p[s * 3 + a] - 0.5 * h[s][a];
+            for (int t = 0; t < 4; ++t) {
+                acc -= Pup[s][t] * fp * pu[t * 3 + a];
+                acc -= Pdn[s][t] * fm * pd[t * 3 + a];
+            }
+            o[s][a] = acc;
+        }
+}
+
 /*
  * out = H psi (dag = 0) or H^dagger psi (dag = 1) on every fifth-dimension slice; Ls = 1 for 4D.
  * The same link field is used on every slice.
@@ -131,36 +193,10 @@ void oracle_hop(const cplx *U, const cplx *psi, cplx *out, const int *dims, int 
 {
     build_gammas();
     const long V = volume(dims);
-    const double sg = dag ? -1.0 : 1.0;
 #pragma omp parallel for schedule(static)
-    for (long x = 0; x < V; ++x) {
-        for (int s5 = 0; s5 < Ls; ++s5) {
-            cplx acc[4][3];
-            memset(acc, 0, sizeof(acc));
-            for (int mu = 0; mu < 4; ++mu) {
-                const long xp = neighbour(dims, x, mu, +1);
-                const long xm = neighbour(dims, x, mu, -1);
-                const cplx *uf = U + (x * 4 + mu) * 9;    /* U_mu(x)      */
-                const cplx *ub = U + (xm * 4 + mu) * 9;   /* U_mu(x - mu) */
-                const cplx *pf = psi + (xp * Ls + s5) * 12;
-                const cplx *pb = psi + (xm * Ls + s5) * 12;
-                cplx v[4][3], w[4][3];
-                for (int t = 0; t < 4; ++t)
-                    for (int a = 0; a < 3; ++a) {
-                        cplx f = 0, b = 0;
-                        for (int c = 0; c < 3; ++c) {
-                            f += uf[a * 3 + c] * pf[t * 3 + c];
-                            b += conj(ub[c * 3 + a]) * pb[t * 3 + c];
-                        }
-                        v[t][a] = f;
-                        w[t][a] = b;
-                    }
-                add_proj(acc, mu, -sg, v);   /* (1 - gamma) forward  (H), (1 + gamma) for H^dag */
-                add_proj(acc, mu, +sg, w);   /* (1 + gamma) backward (H), (1 - gamma) for H^dag */
-            }
-            memcpy(out + (x * Ls + s5) * 12, acc, sizeof(acc));
-        }
-    }
+    for (long x = 0; x < V; ++x)
+        for (int s5 = 0; s5 < Ls; ++s5)
+            hop_site(U, psi, dims, Ls, dag, x, s5, (cplx(*)[3])(out + (x * Ls + s5) * 12));
 }
 
 /* out = D psi or D^dagger psi, D = (4 + m) - H / 2 (4D, Ls = 1). */
@@ -178,37 +214,33 @@ void oracle_dwf(const cplx *U, const cplx *psi, cplx *out, const int *dims, int 
 {
     build_gammas();
     const long V = volume(dims);
-    oracle_hop(U, psi, out, dims, Ls, dag);
-    /* Chiral projectors from gamma_5. */
-    cplx Pp[4][4], Pm[4][4];
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) {
-            cplx d = (i == j) ? 1.0 : 0.0;
-            Pp[i][j] = 0.5 * (d + GAM[4][i][j]);
-            Pm[i][j] = 0.5 * (d - GAM[4][i][j]);
-        }
-    /* Projector applied to the s+1 neighbour (P_- for M, P_+ for M^dagger) and to s-1. */
-    cplx (*Pup)[4] = dag ? Pp : Pm;
-    cplx (*Pdn)[4] = dag ? Pm : Pp;
 #pragma omp parallel for schedule(static)
-    for (long x = 0; x < V; ++x) {
-        for (int s5 = 0; s5 < Ls; ++s5) {
-            const cplx *p = psi + (x * Ls + s5) * 12;
-            const int sp = (s5 + 1) % Ls, sm = (s5 - 1 + Ls) % Ls;
-            const double fp = (s5 == Ls - 1) ? -mf : 1.0;   /* psi~_{s+1} wall factor */
-            const double fm = (s5 == 0) ? -mf : 1.0;        /* psi~_{s-1} wall factor */
-            const cplx *pu = psi + (x * Ls + sp) * 12;
-            const cplx *pd = psi + (x * Ls + sm) * 12;
-            cplx *o = out + (x * Ls + s5) * 12;
-            for (int s = 0; s < 4; ++s)
-                for (int a = 0; a < 3; ++a) {
-                    cplx acc = (5.0 - M5) * p[s * 3 + a] - 0.5 * o[s * 3 + a];
-                    for (int t = 0; t < 4; ++t) {
-                        acc -= Pup[s][t] * fp * pu[t * 3 + a];
-                        acc -= Pdn[s][t] * fm * pd[t * 3 + a];
-                    }
-                    o[s * 3 + a] = acc;
-                }
+    for (long x = 0; x < V; ++x)
+        for (int s5 = 0; s5 < Ls; ++s5)
+            dwf_site(U, psi, dims, Ls, M5, mf, dag, x, s5, (cplx(*)[3])(out + (x * Ls + s5) * 12));
+}
+
+/*
+ * Sampled evaluation for lattices too large to check whole: out[k] (12 complex) is the operator
+ * at site idx[k] (a 5D index x * Ls + s). kind 0: H, 1: D = (4 + mass) - H/2 (Ls = 1), 2: M.
+ */
+void oracle_sites(const cplx *U, const cplx *psi, cplx *out, const int *dims, int Ls, int kind, double mass,
+                  double M5, double mf, int dag, const long *idx, long n)
+{
+    build_gammas();
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n; ++k) {
+        const long x = idx[k] / Ls;
+        const int s5 = (int)(idx[k] % Ls);
+        cplx (*o)[3] = (cplx(*)[3])(out + k * 12);
+        if (kind == 2) {
+            dwf_site(U, psi, dims, Ls, M5, mf, dag, x, s5, o);
+        } else {
+            hop_site(U, psi, dims, Ls, dag, x, s5, o);
+            if (kind == 1) {
+                const cplx *p = psi + idx[k] * 12;
+                for (int j = 0; j < 12; ++j) o[j / 3][j % 3] = (4.0 + mass) * p[j] - 0.5 * o[j / 3][j % 3];
+            }
         }
     }
 }

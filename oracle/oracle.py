@@ -51,6 +51,8 @@ def _load():
     lib.oracle_cg.restype = ctypes.c_int
     lib.oracle_link_grad.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_double, ctypes.c_int]
     lib.oracle_force.argtypes = [P, P, P, ctypes.c_long]
+    lib.oracle_sites.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_int, P, ctypes.c_long]
     _lib = lib
     return lib
 
@@ -143,6 +145,21 @@ def apply(op: Op, U, psi, dag: bool = False) -> np.ndarray:
     if op.kind == 0:
         return wilson(U, psi, op.mass, dag)
     return dwf(U, psi, op.M5, op.mf, dag)
+
+
+def sites(U, psi, idx, kind: str = "hop", dag: bool = False, mass: float = 0.0, M5: float = 0.0,
+          mf: float = 0.0) -> np.ndarray:
+    """The operator at selected sites only: idx are flat site indices (x * Ls + s for 5D).
+
+    kind "hop" (H), "wilson" (D, 4D only) or "dwf" (M). Returns (len(idx), 4, 3) complex128.
+    """
+    U, psi = _c128(U), _c128(psi)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty((len(idx), 4, 3), dtype=np.complex128)
+    k = {"hop": 0, "wilson": 1, "dwf": 2}[kind]
+    _load().oracle_sites(_ptr(U), _ptr(psi), _ptr(out), _ptr(_dims(psi)), _ls(psi), k, float(mass), float(M5),
+                         float(mf), int(bool(dag)), _ptr(idx), len(idx))
+    return out
 
 
 def normal(op: Op, U, psi) -> np.ndarray:

@@ -433,3 +433,16 @@ def test_float32_rounding_bound():
     psi = F.spinor_field((4, 4, 4, 4), seed=2)
     r = psi.astype(np.complex64).astype(np.complex128)
     assert np.max(np.abs(r.real - psi.real) / np.abs(psi.real)) <= 2.0 ** -24
+
+
+def test_sampled_sites_match_whole_field():
+    """The sampled evaluation is the same per-site definition as the whole-field one."""
+    dims, Ls = (4, 2, 3, 2), 3
+    U = F.gauge_field(dims, seed=1, kind="haar")
+    psi4, psi5 = F.spinor_field(dims, seed=2), F.spinor_field(dims, seed=2, Ls=Ls)
+    idx4 = np.array([0, 5, 17, 47])
+    idx5 = np.array([0, 7, 50, 143])
+    np.testing.assert_array_equal(O.sites(U, psi4, idx4, "hop", dag=True), O.hop(U, psi4, dag=True).reshape(-1, 4, 3)[idx4])
+    np.testing.assert_array_equal(O.sites(U, psi4, idx4, "wilson", mass=0.1), O.wilson(U, psi4, 0.1).reshape(-1, 4, 3)[idx4])
+    np.testing.assert_array_equal(O.sites(U, psi5, idx5, "dwf", M5=1.8, mf=0.01),
+                                  O.dwf(U, psi5, 1.8, 0.01).reshape(-1, 4, 3)[idx5])
