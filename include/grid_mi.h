@@ -1,0 +1,195 @@
+/*
+ * grid_mi.h -- C ABI of the MI355X (gfx950) lattice hopping-operator library.
+ *
+ * The library applies the nearest-neighbour Wilson hopping term ("Wilson kernel", Grid paper
+ * Section 2.4 and Section 3) on a periodic 4D lattice, its Ls-replicated five-dimensional
+ * domain-wall extension (Section 3, Table 4 and the xc30 figure's note that the gauge field is
+ * reused Ls times), a conjugate-gradient solver on the normal equations (Section 4, "Conjugate
+ * gradient") and the adjoint of the hopping term with the gauge-link force that HMC needs
+ * (Section 4, "HMC"). The paper names these operators without printing their formulas; the
+ * definitions used are stated below and are those of the standard Wilson / Shamir formulation.
+ *
+ * Definitions (gamma matrices in the Euclidean chiral basis, gamma_k = [[0,-i s_k],[i s_k,0]],
+ * gamma_4 = [[0,1],[1,0]], direction mu = 0..3 = x,y,z,t uses gamma_{mu+1}, gamma_5 =
+ * diag(1,1,-1,-1), P_+- = (1 +- gamma_5)/2; boundaries periodic in all four directions):
+ *
+ *   H psi(x)  = sum_mu (1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu)
+ *   H^+       = the same with gamma_mu -> -gamma_mu
+ *   D         = (4 + mass) - H/2                       (Wilson fermion operator)
+ *   M psi_s   = (5 - M5) psi_s - H psi_s / 2 - P_- psi~_{s+1} - P_+ psi~_{s-1}   (Shamir DWF)
+ *               with psi~_{Ls} = -mf psi_0, psi~_{-1} = -mf psi_{Ls-1};
+ *   M^+ psi_s = (5 - M5) psi_s - H^+ psi_s / 2 - P_+ psi~_{s+1} - P_- psi~_{s-1}.
+ *
+ * Data layout (all fields site-major, x fastest, then y, z, t; complex = interleaved re, im):
+ *   spinor 4D  [Lt][Lz][Ly][Lx][4 spin][3 colour] complex
+ *   spinor 5D  [Lt][Lz][Ly][Lx][Ls][4][3]           (the fifth coordinate inside the 4D site)
+ *   links L18  [Lt][Lz][Ly][Lx][4 mu][3][3]          (row-major SU(3) matrix U_mu(x))
+ *   links L12  [Lt][Lz][Ly][Lx][4 mu][2][3]          (rows 0, 1; row 2 = conj(row0 x row1))
+ * Precisions (argument `prec`):
+ *   GRID_F64   spinors and links complex double; arithmetic in double.
+ *   GRID_F32   spinors and links complex float;  arithmetic in float.
+ *   GRID_F16S  spinors stored as IEEE half (re, im) with one float scale per (4D or 5D) site:
+ *              value = float(code) * scale; links stored as half (re, im) without scale;
+ *              arithmetic in float. The codec: s = max |re|,|im| over the site's 24 reals (in
+ *              float), code = half_rne(float(v) * (1.0f / s)), s = 0 codes zeros.
+ *
+ * Ownership and streams: the caller allocates every buffer (device memory, 16-byte aligned)
+ * and keeps ownership; the library never allocates or frees caller memory. Every call except
+ * grid_cg is asynchronous on the given HIP stream (`stream` is a hipStream_t; NULL is the
+ * default stream). Outputs must not alias inputs.
+ *
+ * Errors: 0 on success, a negative GRID_E* code otherwise. Argument checks run on the host
+ * before any HIP call, so a rejected call has no effect. grid_last_error() returns a message for
+ * the calling thread's last failure.
+ */
+#ifndef GRID_MI_H
+#define GRID_MI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GRID_OK           0
+#define GRID_EINVAL      -1   /* bad enum value, NULL pointer where one is required, aliasing  */
+#define GRID_ESHAPE      -2   /* a lattice extent below 2, Ls below 1, or a size overflow       */
+#define GRID_EDTYPE      -3   /* precision / link-format combination not supported             */
+#define GRID_EALIGN      -4   /* a pointer not 16-byte aligned                                  */
+#define GRID_EHIP        -5   /* a HIP runtime call failed                                      */
+#define GRID_ENOCONV     -6   /* CG reached maxiter without the requested true residual        */
+#define GRID_EBREAKDOWN  -7   /* CG breakdown: <p, A p> <= 0 or a non-finite scalar            */
+#define GRID_ESPACE      -8   /* workspace smaller than grid_cg_workspace_bytes() reports      */
+
+enum grid_prec { GRID_F64 = 0, GRID_F32 = 1, GRID_F16S = 2 };
+enum grid_link_fmt { GRID_L18 = 0, GRID_L12 = 1 };
+enum grid_op_kind { GRID_HOP = 0, GRID_WILSON = 1, GRID_DWF = 2 };
+
+/* Lattice extents (dims[0..3] = Lx, Ly, Lz, Lt, each >= 2) and fifth extent Ls (1 for 4D). */
+typedef struct {
+    int dims[4];
+    int Ls;
+} grid_geom;
+
+/* Operator: kind GRID_HOP (H, applied on each fifth slice when Ls > 1), GRID_WILSON (D, Ls = 1)
+ * or GRID_DWF (M); dag != 0 applies the adjoint. mass is D's m; M5, mf are M's parameters. */
+typedef struct {
+    int kind;
+    int dag;
+    double mass;
+    double M5;
+    double mf;
+} grid_op;
+
+/* Conjugate-gradient parameters. */
+typedef struct {
+    double tol;        /* target true relative residual |b - A x| / |b| (FP64), e.g. 1e-10      */
+    int maxiter;       /* cap on iterations (sloppy iterations in mixed mode)                     */
+    int sloppy_prec;   /* GRID_F64: plain FP64 CG; GRID_F32 / GRID_F16S: mixed precision         */
+    int link_fmt;      /* link format of the sloppy operator (GRID_L18 or GRID_L12)                */
+    double delta;      /* reliable-update threshold (mixed modes), e.g. 0.1                       */
+    int check_every;   /* iterations between host reads of the residual norm (>= 1), e.g. 10     */
+} grid_cg_params;
+
+/* CG results. */
+typedef struct {
+    int iterations;          /* operator iterations performed                                  */
+    int reliable_updates;    /* FP64 true-residual recomputations during the iteration (mixed) */
+    int converged;           /* 1 if true_residual <= tol                                      */
+    double true_residual;    /* |b - A x| / |b|, recomputed in FP64 at the end                  */
+    double seconds;          /* wall time of the call                                          */
+} grid_cg_stats;
+
+/*
+ * grid_dhop -- apply the hopping term or a fermion operator built on it (Section 2.4's Wilson
+ * kernel; Table 4's Ls-replicated dslash when kind = GRID_HOP and Ls > 1; Section 4's Wilson
+ * fermion action and five-dimensional chiral fermions for GRID_WILSON / GRID_DWF).
+ *
+ *   U         links in precision `prec` and format `link_fmt` (see layout above)
+ *   psi       input spinor (4D if geom->Ls == 1, else 5D) in precision `prec`
+ *   psi_scale GRID_F16S: per-site scales of psi ([V] or [V][Ls] floats); NULL otherwise
+ *   out       output spinor, same shape and precision as psi; must not overlap psi or U
+ *   out_scale GRID_F16S: per-site scales written for out; NULL otherwise
+ *   op        kind / dag / parameters; GRID_WILSON needs Ls == 1, GRID_DWF needs Ls >= 1
+ * Returns GRID_OK, or GRID_EINVAL / GRID_ESHAPE / GRID_EDTYPE / GRID_EALIGN / GRID_EHIP.
+ */
+int grid_dhop(const void *U, const void *psi, const float *psi_scale, void *out, float *out_scale,
+              const grid_geom *geom, const grid_op *op, int prec, int link_fmt, void *stream);
+
+/*
+ * grid_dwf_mdag_m -- out = M^+ M psi for the domain-wall operator (the normal operator the CG
+ * of Section 4 iterates on). tmp (and tmp_scale for GRID_F16S) receives M psi and must have
+ * psi's size. Same argument rules as grid_dhop.
+ */
+int grid_dwf_mdag_m(const void *U, const void *psi, const float *psi_scale, void *out, float *out_scale,
+                    void *tmp, float *tmp_scale, const grid_geom *geom, double M5, double mf, int prec,
+                    int link_fmt, void *stream);
+
+/*
+ * grid_cg_workspace_bytes -- device workspace grid_cg needs for this geometry and parameters.
+ * Returns 0 for invalid arguments.
+ */
+size_t grid_cg_workspace_bytes(const grid_geom *geom, const grid_cg_params *params);
+
+/*
+ * grid_cg -- solve Op^+ Op x = b by conjugate gradients (Section 4), Op = D (op->kind =
+ * GRID_WILSON) or M (GRID_DWF), in FP64 or in mixed precision with reliable updates: sloppy
+ * iterations in FP32 or FP16-storage with FP32 arithmetic, the solution, the source and each
+ * recomputed true residual in FP64, inner products and norms accumulated in FP64.
+ *
+ *   U          FP64 links, L18 layout ([V][4][3][3] complex double)
+ *   b          FP64 source; x FP64 initial guess on entry, solution on exit
+ *   workspace  device buffer of at least grid_cg_workspace_bytes() bytes, 256-byte aligned
+ *   stats      filled on return (also on GRID_ENOCONV / GRID_EBREAKDOWN)
+ * Synchronous: returns when x is final. Stops when the FP64 true relative residual is <= tol.
+ * Returns GRID_OK, GRID_ENOCONV, GRID_EBREAKDOWN or an argument / HIP error.
+ */
+int grid_cg(const void *U, const void *b, void *x, const grid_geom *geom, const grid_op *op,
+            const grid_cg_params *params, void *workspace, size_t ws_bytes, grid_cg_stats *stats,
+            void *stream);
+
+/*
+ * grid_dhop_backward -- adjoint of grid_dhop for L = Re <g, Op psi> (the gradient HMC's fermion
+ * force is built from, Section 4). Gradients follow the complex convention dL/dRe + i dL/dIm.
+ *
+ *   grad_psi  (nullable) = Op^+ g, same layout as psi
+ *   grad_U    (nullable) links [V][4][3][3] complex in precision prec:
+ *             force_mode 0: dL/dU_mu(x) = c sum_{s,spin} { [(1 - e gamma_mu) g(x)] psi(x+mu)^+
+ *                                              + psi(x) [(1 + e gamma_mu) g(x+mu)]^+ }
+ *                            with c = 1 for GRID_HOP and -1/2 otherwise, e = +1 (dag: -1);
+ *             force_mode 1: its projection onto su(3), TA(G U^+), TA(A) = (A - A^+)/2 -
+ *                            tr(A - A^+)/6, so that d/de L(exp(e X) U)|0 = Re tr(F^+ X).
+ * prec is GRID_F64 or GRID_F32 with GRID_L18 links. Returns as grid_dhop.
+ */
+int grid_dhop_backward(const void *U, const void *psi, const void *grad_out, void *grad_psi, void *grad_U,
+                       const grid_geom *geom, const grid_op *op, int prec, int force_mode, void *stream);
+
+/*
+ * grid_convert_spinor -- change the storage precision of n_sites spinor sites (24 reals each):
+ * F64 <-> F32, and F64/F32 -> F16S (encode, dst_scale receives per-site scales) or F16S ->
+ * F64/F32 (decode with src_scale). Narrowing rounds to nearest even. (The Compressor of
+ * Section 2.4 changes the precision of communicated fields; here it changes storage precision.)
+ */
+int grid_convert_spinor(const void *src, int src_prec, const float *src_scale, void *dst, int dst_prec,
+                        float *dst_scale, long n_sites, void *stream);
+
+/*
+ * grid_convert_links -- convert n_links FP64 L18 links to precision dst_prec (F64, F32, or
+ * F16S = half without scale) and format dst_fmt (L18 or L12). With reunitarise != 0 each link
+ * is first projected back to SU(3) in FP64: row 0 normalised, row 1 Gram-Schmidt against row 0
+ * and normalised, row 2 = conj(row0 x row1). Narrowing goes FP64 -> float (RNE) -> half (RNE).
+ */
+int grid_convert_links(const void *src, void *dst, int dst_prec, int dst_fmt, int reunitarise, long n_links,
+                       void *stream);
+
+/* grid_last_error -- message of the calling thread's last failed call ("" if none). */
+const char *grid_last_error(void);
+
+/* grid_version -- library version as major * 10000 + minor * 100 + patch. */
+int grid_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRID_MI_H */

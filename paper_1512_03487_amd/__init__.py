@@ -1,0 +1,12 @@
+"""MI355X-native Wilson / domain-wall hopping operator, mixed-precision CG and adjoint kernels.
+
+The compute path is the HIP library libgrid_mi.so (C ABI in include/grid_mi.h); this package is
+its thin torch binding. ``fields`` draws seeded synthetic inputs.
+"""
+from . import fields  # noqa: F401
+from .api import (F16Spinor, cg, cg_workspace_bytes, convert_links, convert_spinor, dhop,  # noqa: F401
+                  dhop_backward, dwf, dwf_mdag_m, version, wilson)
+from .autograd import DhopFn, PseudofermionActionFn  # noqa: F401
+
+__all__ = ["fields", "F16Spinor", "dhop", "wilson", "dwf", "dwf_mdag_m", "cg", "cg_workspace_bytes",
+           "dhop_backward", "convert_spinor", "convert_links", "version", "DhopFn", "PseudofermionActionFn"]

@@ -1,0 +1,94 @@
+"""ctypes binding of libgrid_mi.so (the C ABI declared in include/grid_mi.h).
+
+The library is built in-tree by ``paper_1512_03487_amd.build``. Loading fails loudly when it is
+missing: there is no CPU fallback for any entry point.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgrid_mi.so")
+
+GRID_OK, GRID_EINVAL, GRID_ESHAPE, GRID_EDTYPE, GRID_EALIGN = 0, -1, -2, -3, -4
+GRID_EHIP, GRID_ENOCONV, GRID_EBREAKDOWN, GRID_ESPACE = -5, -6, -7, -8
+GRID_F64, GRID_F32, GRID_F16S = 0, 1, 2
+GRID_L18, GRID_L12 = 0, 1
+GRID_HOP, GRID_WILSON, GRID_DWF = 0, 1, 2
+
+#: every symbol include/grid_mi.h declares
+EXPORTS = ("grid_dhop", "grid_dwf_mdag_m", "grid_cg_workspace_bytes", "grid_cg", "grid_dhop_backward",
+           "grid_convert_spinor", "grid_convert_links", "grid_last_error", "grid_version")
+
+
+class GridGeom(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int * 4), ("Ls", ctypes.c_int)]
+
+
+class GridOp(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("dag", ctypes.c_int), ("mass", ctypes.c_double),
+                ("M5", ctypes.c_double), ("mf", ctypes.c_double)]
+
+
+class GridCgParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("sloppy_prec", ctypes.c_int),
+                ("link_fmt", ctypes.c_int), ("delta", ctypes.c_double), ("check_every", ctypes.c_int)]
+
+
+class GridCgStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("reliable_updates", ctypes.c_int), ("converged", ctypes.c_int),
+                ("true_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+class GridError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"grid_mi error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libgrid_mi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1512_03487_amd.build` "
+                          "(there is no fallback implementation)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.grid_dhop.argtypes = [P, P, P, P, P, ctypes.POINTER(GridGeom), ctypes.POINTER(GridOp), I, I, P]
+    lib.grid_dhop.restype = I
+    lib.grid_dwf_mdag_m.argtypes = [P, P, P, P, P, P, P, ctypes.POINTER(GridGeom), D, D, I, I, P]
+    lib.grid_dwf_mdag_m.restype = I
+    lib.grid_cg_workspace_bytes.argtypes = [ctypes.POINTER(GridGeom), ctypes.POINTER(GridCgParams)]
+    lib.grid_cg_workspace_bytes.restype = ctypes.c_size_t
+    lib.grid_cg.argtypes = [P, P, P, ctypes.POINTER(GridGeom), ctypes.POINTER(GridOp), ctypes.POINTER(GridCgParams),
+                            P, ctypes.c_size_t, ctypes.POINTER(GridCgStats), P]
+    lib.grid_cg.restype = I
+    lib.grid_dhop_backward.argtypes = [P, P, P, P, P, ctypes.POINTER(GridGeom), ctypes.POINTER(GridOp), I, I, P]
+    lib.grid_dhop_backward.restype = I
+    lib.grid_convert_spinor.argtypes = [P, I, P, P, I, P, ctypes.c_long, P]
+    lib.grid_convert_spinor.restype = I
+    lib.grid_convert_links.argtypes = [P, P, I, I, I, ctypes.c_long, P]
+    lib.grid_convert_links.restype = I
+    lib.grid_last_error.argtypes = []
+    lib.grid_last_error.restype = ctypes.c_char_p
+    lib.grid_version.argtypes = []
+    lib.grid_version.restype = I
+    _lib = lib
+    return lib
+
+
+def check(rc: int) -> int:
+    """Raise GridError for a negative status (GRID_ENOCONV / GRID_EBREAKDOWN included)."""
+    if rc != GRID_OK:
+        raise GridError(rc, load().grid_last_error().decode())
+    return rc
+
+
+def last_error() -> str:
+    return load().grid_last_error().decode()

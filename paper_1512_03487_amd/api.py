@@ -1,0 +1,258 @@
+"""Torch-facing wrappers of the C ABI (argument marshalling only; every step runs in HIP kernels).
+
+Fields are torch tensors on a ROCm device in the site-major layout of include/grid_mi.h:
+
+* 4D spinor ``(Lt, Lz, Ly, Lx, 4, 3)`` and 5D spinor ``(Lt, Lz, Ly, Lx, Ls, 4, 3)``: complex128
+  (FP64) or complex64 (FP32); FP16 storage is an :class:`F16Spinor` (half codes with a trailing
+  re/im axis plus one float32 scale per site).
+* links ``(Lt, Lz, Ly, Lx, 4, 3, 3)`` (18-real) or ``(..., 4, 2, 3)`` (12-real), complex128 /
+  complex64, or float16 with a trailing re/im axis for FP16 storage.
+
+All calls are asynchronous on torch's current stream except :func:`cg`.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import (GRID_DWF, GRID_F16S, GRID_F32, GRID_F64, GRID_HOP, GRID_L12, GRID_L18, GRID_WILSON, GridCgParams,
+                   GridCgStats, GridGeom, GridOp, check, load)
+
+_KIND = {"hop": GRID_HOP, "wilson": GRID_WILSON, "dwf": GRID_DWF}
+_PREC = {"f64": GRID_F64, "f32": GRID_F32, "f16s": GRID_F16S}
+_FMT = {"L18": GRID_L18, "L12": GRID_L12}
+
+
+@dataclass
+class F16Spinor:
+    """FP16-storage spinor: ``codes`` float16 (site shape + (4, 3, 2)), ``scale`` float32 (site shape)."""
+    codes: torch.Tensor
+    scale: torch.Tensor
+
+    @property
+    def shape(self):
+        return tuple(self.codes.shape[:-1])
+
+    @property
+    def device(self):
+        return self.codes.device
+
+    @staticmethod
+    def empty(site_shape, device) -> "F16Spinor":
+        return F16Spinor(torch.empty(tuple(site_shape) + (4, 3, 2), dtype=torch.float16, device=device),
+                         torch.empty(tuple(site_shape), dtype=torch.float32, device=device))
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _need_cuda(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on a GPU device")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def spinor_prec(psi) -> int:
+    if isinstance(psi, F16Spinor):
+        _need_cuda(psi.codes, "psi.codes")
+        _need_cuda(psi.scale, "psi.scale")
+        return GRID_F16S
+    _need_cuda(psi, "psi")
+    if psi.dtype == torch.complex128:
+        return GRID_F64
+    if psi.dtype == torch.complex64:
+        return GRID_F32
+    raise TypeError(f"unsupported spinor dtype {psi.dtype}")
+
+
+def geom_of(psi) -> GridGeom:
+    shape = psi.shape
+    if len(shape) == 6 and tuple(shape[4:]) == (4, 3):
+        lt, lz, ly, lx = shape[:4]
+        ls = 1
+    elif len(shape) == 7 and tuple(shape[5:]) == (4, 3):
+        lt, lz, ly, lx, ls = shape[:5]
+    else:
+        raise ValueError(f"spinor shape {tuple(shape)} is neither (Lt,Lz,Ly,Lx,4,3) nor (Lt,Lz,Ly,Lx,Ls,4,3)")
+    g = GridGeom()
+    g.dims[:] = [int(lx), int(ly), int(lz), int(lt)]
+    g.Ls = int(ls)
+    return g
+
+
+def link_format(U, prec: int) -> int:
+    _need_cuda(U, "U")
+    want = {GRID_F64: torch.complex128, GRID_F32: torch.complex64, GRID_F16S: torch.float16}[prec]
+    if U.dtype != want:
+        raise TypeError(f"links must be {want} for this spinor precision (got {U.dtype})")
+    tail = tuple(U.shape[4:]) if prec != GRID_F16S else tuple(U.shape[4:-1])
+    if tail == (4, 3, 3):
+        return GRID_L18
+    if tail == (4, 2, 3):
+        return GRID_L12
+    raise ValueError(f"link shape {tuple(U.shape)} is not (..., 4, 3, 3) or (..., 4, 2, 3)")
+
+
+def _data_scale(psi):
+    if isinstance(psi, F16Spinor):
+        return psi.codes, psi.scale
+    return psi, None
+
+
+def _empty_like(psi):
+    if isinstance(psi, F16Spinor):
+        return F16Spinor.empty(psi.shape[:-2], psi.device)
+    return torch.empty_like(psi)
+
+
+def make_op(kind="hop", dag=False, mass=0.0, M5=1.8, mf=0.01) -> GridOp:
+    op = GridOp()
+    op.kind = _KIND[kind] if isinstance(kind, str) else int(kind)
+    op.dag = int(bool(dag))
+    op.mass, op.M5, op.mf = float(mass), float(M5), float(mf)
+    return op
+
+
+def dhop(U, psi, kind="hop", dag=False, mass=0.0, M5=1.8, mf=0.01, out=None):
+    """Apply H (kind "hop"), the Wilson D ("wilson") or the domain-wall M ("dwf"), or an adjoint."""
+    prec = spinor_prec(psi)
+    fmt = link_format(U, prec)
+    g = geom_of(psi)
+    if out is None:
+        out = _empty_like(psi)
+    pd, ps = _data_scale(psi)
+    od, os_ = _data_scale(out)
+    op = make_op(kind, dag, mass, M5, mf)
+    check(load().grid_dhop(_ptr(U), _ptr(pd), _ptr(ps), _ptr(od), _ptr(os_), ctypes.byref(g), ctypes.byref(op),
+                           prec, fmt, _stream(pd.device)))
+    return out
+
+
+def wilson(U, psi, mass, dag=False, out=None):
+    return dhop(U, psi, "wilson", dag=dag, mass=mass, out=out)
+
+
+def dwf(U, psi, M5, mf, dag=False, out=None):
+    return dhop(U, psi, "dwf", dag=dag, M5=M5, mf=mf, out=out)
+
+
+def dwf_mdag_m(U, psi, M5, mf, out=None, tmp=None):
+    """M^dagger M psi for the domain-wall operator."""
+    prec = spinor_prec(psi)
+    fmt = link_format(U, prec)
+    g = geom_of(psi)
+    out = _empty_like(psi) if out is None else out
+    tmp = _empty_like(psi) if tmp is None else tmp
+    pd, ps = _data_scale(psi)
+    od, os_ = _data_scale(out)
+    td, ts = _data_scale(tmp)
+    check(load().grid_dwf_mdag_m(_ptr(U), _ptr(pd), _ptr(ps), _ptr(od), _ptr(os_), _ptr(td), _ptr(ts),
+                                 ctypes.byref(g), float(M5), float(mf), prec, fmt, _stream(pd.device)))
+    return out
+
+
+def cg_params(tol=1e-10, maxiter=20000, sloppy="f64", link_fmt="L18", delta=0.1, check_every=10) -> GridCgParams:
+    p = GridCgParams()
+    p.tol, p.maxiter = float(tol), int(maxiter)
+    p.sloppy_prec = _PREC[sloppy] if isinstance(sloppy, str) else int(sloppy)
+    p.link_fmt = _FMT[link_fmt] if isinstance(link_fmt, str) else int(link_fmt)
+    p.delta, p.check_every = float(delta), int(check_every)
+    return p
+
+
+def cg_workspace_bytes(b, **params) -> int:
+    g = geom_of(b)
+    p = cg_params(**params)
+    return int(load().grid_cg_workspace_bytes(ctypes.byref(g), ctypes.byref(p)))
+
+
+def cg(U, b, kind="dwf", mass=0.0, M5=1.8, mf=0.01, x0=None, workspace=None, raise_on_fail=True, **params):
+    """Solve Op^dagger Op x = b (Op = D for kind "wilson", M for "dwf"); FP64 U, b, x.
+
+    ``params``: tol, maxiter, sloppy ("f64" | "f32" | "f16s"), link_fmt ("L18" | "L12"), delta,
+    check_every. Returns (x, stats dict). Synchronous.
+    """
+    if spinor_prec(b) != GRID_F64 or link_format(U, GRID_F64) != GRID_L18:
+        raise TypeError("cg takes complex128 b and complex128 18-real links")
+    g = geom_of(b)
+    p = cg_params(**params)
+    need = int(load().grid_cg_workspace_bytes(ctypes.byref(g), ctypes.byref(p)))
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=b.device)
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    op = make_op(kind, False, mass, M5, mf)
+    st = GridCgStats()
+    rc = load().grid_cg(_ptr(U), _ptr(b), _ptr(x), ctypes.byref(g), ctypes.byref(op), ctypes.byref(p),
+                        _ptr(workspace), ctypes.c_size_t(workspace.numel()), ctypes.byref(st), _stream(b.device))
+    stats = {"iterations": st.iterations, "reliable_updates": st.reliable_updates, "converged": bool(st.converged),
+             "true_residual": st.true_residual, "seconds": st.seconds, "status": rc}
+    if rc != 0 and raise_on_fail:
+        check(rc)
+    return x, stats
+
+
+def dhop_backward(U, psi, grad_out, kind="hop", dag=False, mass=0.0, M5=1.8, mf=0.01, want_psi=True, want_U=True,
+                  force=False):
+    """Gradients of L = Re <grad_out, Op psi>: (Op^dagger grad_out, dL/dU or its su(3) force)."""
+    prec = spinor_prec(psi)
+    if prec == GRID_F16S or spinor_prec(grad_out) != prec:
+        raise TypeError("dhop_backward takes FP64 or FP32 spinors of one precision")
+    if link_format(U, prec) != GRID_L18:
+        raise TypeError("dhop_backward takes 18-real links")
+    g = geom_of(psi)
+    gp = torch.empty_like(psi) if want_psi else None
+    gu = torch.empty(tuple(psi.shape[:4]) + (4, 3, 3), dtype=psi.dtype, device=psi.device) if want_U else None
+    op = make_op(kind, dag, mass, M5, mf)
+    check(load().grid_dhop_backward(_ptr(U), _ptr(psi), _ptr(grad_out), _ptr(gp), _ptr(gu), ctypes.byref(g),
+                                    ctypes.byref(op), prec, int(bool(force)), _stream(psi.device)))
+    return gp, gu
+
+
+def convert_spinor(x, to: str):
+    """Change a spinor's storage precision: to = "f64" | "f32" | "f16s"."""
+    src_prec = spinor_prec(x)
+    dst_prec = _PREC[to]
+    xd, xs = _data_scale(x)
+    site_shape = x.shape[:-2]
+    n = 1
+    for d in site_shape:
+        n *= int(d)
+    if dst_prec == GRID_F16S:
+        out = F16Spinor.empty(site_shape, xd.device)
+    else:
+        out = torch.empty(tuple(site_shape) + (4, 3), dtype=torch.complex128 if dst_prec == GRID_F64 else torch.complex64,
+                          device=xd.device)
+    od, os_ = _data_scale(out)
+    check(load().grid_convert_spinor(_ptr(xd), src_prec, _ptr(xs), _ptr(od), dst_prec, _ptr(os_), n, _stream(xd.device)))
+    return out
+
+
+def convert_links(U, prec="f32", fmt="L18", reunitarise=False):
+    """Narrow / compress / reunitarise FP64 18-real links."""
+    if link_format(U, GRID_F64) != GRID_L18:
+        raise TypeError("convert_links takes complex128 18-real links")
+    dst_prec, dst_fmt = _PREC[prec], _FMT[fmt]
+    rows = 3 if dst_fmt == GRID_L18 else 2
+    lead = tuple(U.shape[:5])
+    if dst_prec == GRID_F16S:
+        out = torch.empty(lead + (rows, 3, 2), dtype=torch.float16, device=U.device)
+    else:
+        out = torch.empty(lead + (rows, 3), dtype=torch.complex128 if dst_prec == GRID_F64 else torch.complex64,
+                          device=U.device)
+    n = U.numel() // 9
+    check(load().grid_convert_links(_ptr(U), _ptr(out), dst_prec, dst_fmt, int(bool(reunitarise)), n,
+                                    _stream(U.device)))
+    return out
+
+
+def version() -> int:
+    return int(load().grid_version())

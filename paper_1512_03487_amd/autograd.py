@@ -1,0 +1,59 @@
+"""torch.autograd.Function wrappers over the hand-written adjoint kernels.
+
+Gradients follow PyTorch's complex convention for a real loss, dL/dRe + i dL/dIm, so for
+out = Op psi the backward is grad_psi = Op^dagger grad_out and grad_U is the link gradient of
+Re <grad_out, Op psi> computed by grid_dhop_backward (HMC's fermion force, Section 4 of the
+paper, is its su(3) projection; ``force=True`` returns that instead).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import api
+
+
+class DhopFn(torch.autograd.Function):
+    """out = Op(U) psi with Op = H ("hop"), D ("wilson") or M ("dwf"); differentiable in U and psi."""
+
+    @staticmethod
+    def forward(ctx, U, psi, kind="hop", dag=False, mass=0.0, M5=1.8, mf=0.01):
+        ctx.save_for_backward(U, psi)
+        ctx.cfg = dict(kind=kind, dag=dag, mass=mass, M5=M5, mf=mf)
+        return api.dhop(U, psi, **ctx.cfg)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        U, psi = ctx.saved_tensors
+        g = grad_out.contiguous()
+        gp, gu = api.dhop_backward(U, psi, g, want_psi=ctx.needs_input_grad[1], want_U=ctx.needs_input_grad[0],
+                                   **ctx.cfg)
+        return gu, gp, None, None, None, None, None
+
+
+class PseudofermionActionFn(torch.autograd.Function):
+    """S = Re phi^dagger (Op^dagger Op)^-1 phi (Op = D or M, FP64), differentiable in U and phi.
+
+    The solve is recomputed in backward instead of being stored: with X = (Op^dagger Op)^-1 phi
+    and Y = Op X, dS/dU = -2 G(grad_out = Y, psi = X) and dS/dphi = 2 X.
+    """
+
+    @staticmethod
+    def forward(ctx, U, phi, kind="wilson", mass=0.1, M5=1.8, mf=0.01, tol=1e-12, sloppy="f64"):
+        ctx.save_for_backward(U, phi)
+        ctx.cfg = dict(kind=kind, mass=mass, M5=M5, mf=mf)
+        ctx.solve = dict(tol=tol, sloppy=sloppy)
+        X, _ = api.cg(U, phi, **ctx.cfg, **ctx.solve)
+        return torch.vdot(phi.reshape(-1), X.reshape(-1)).real
+
+    @staticmethod
+    def backward(ctx, gS):
+        U, phi = ctx.saved_tensors
+        X, _ = api.cg(U, phi, **ctx.cfg, **ctx.solve)
+        gU = gphi = None
+        if ctx.needs_input_grad[0]:
+            Y = api.dhop(U, X, **ctx.cfg)
+            _, G = api.dhop_backward(U, X, Y, want_psi=False, want_U=True, **ctx.cfg)
+            gU = (-2.0 * gS) * G
+        if ctx.needs_input_grad[1]:
+            gphi = (2.0 * gS) * X
+        return gU, gphi, None, None, None, None, None, None

@@ -1,0 +1,285 @@
+// C ABI of libgrid_mi: host-side argument validation, dispatch to the kernel launchers, status
+// codes and a thread-local error message. Every check runs before the first HIP call, so a
+// rejected call has no effect on the device.
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "launch.h"
+
+using namespace gridmi;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int ok() {
+    g_err[0] = '\0';
+    return GRID_OK;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(GRID_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Geometry: every extent >= 2, Ls >= 1, and V * Ls * 4 below 2^31 (kernel indices are 32-bit).
+int check_geom(const grid_geom *geom, GeomDev *g) {
+    if (!geom) return fail(GRID_EINVAL, "geom is NULL");
+    int64_t vol = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        if (geom->dims[mu] < 2) return fail(GRID_ESHAPE, "dims[%d] = %d is below 2", mu, geom->dims[mu]);
+        vol *= geom->dims[mu];
+        if (vol > (int64_t(1) << 30)) return fail(GRID_ESHAPE, "lattice volume too large");
+    }
+    if (geom->Ls < 1) return fail(GRID_ESHAPE, "Ls = %d is below 1", geom->Ls);
+    if (vol * geom->Ls * 4 >= (int64_t(1) << 31)) return fail(GRID_ESHAPE, "V * Ls too large for 32-bit indexing");
+    for (int mu = 0; mu < 4; ++mu) g->L[mu] = geom->dims[mu];
+    g->Ls = geom->Ls;
+    g->vol = static_cast<int>(vol);
+    g->n5 = static_cast<int>(vol * geom->Ls);
+    return GRID_OK;
+}
+
+int check_ptr(const void *p, const char *name, uintptr_t align) {
+    if (!p) return fail(GRID_EINVAL, "%s is NULL", name);
+    if (reinterpret_cast<uintptr_t>(p) % align) return fail(GRID_EALIGN, "%s is not %d-byte aligned", name, (int)align);
+    return GRID_OK;
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    if (!a || !b || !na || !nb) return false;
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+    return a0 < b0 + nb && b0 < a0 + na;
+}
+
+size_t spinor_site_bytes(int prec) { return prec == GRID_F64 ? 192 : prec == GRID_F32 ? 96 : 48; }
+size_t link_bytes(int prec, int fmt) {
+    const size_t rows = fmt == GRID_L12 ? 2 : 3;
+    const size_t cbytes = prec == GRID_F64 ? 16 : prec == GRID_F32 ? 8 : 4;
+    return rows * 3 * cbytes;
+}
+
+int check_prec(int prec) {
+    if (prec != GRID_F64 && prec != GRID_F32 && prec != GRID_F16S) return fail(GRID_EDTYPE, "unknown precision %d", prec);
+    return GRID_OK;
+}
+int check_fmt(int fmt) {
+    if (fmt != GRID_L18 && fmt != GRID_L12) return fail(GRID_EDTYPE, "unknown link format %d", fmt);
+    return GRID_OK;
+}
+
+// Spinor (+ scale for F16S) argument check.
+int check_spinor(const void *p, const float *scale, int prec, const char *name, const char *sname) {
+    int rc = check_ptr(p, name, 16);
+    if (rc) return rc;
+    if (prec == GRID_F16S) return check_ptr(scale, sname, 4);
+    if (scale) return fail(GRID_EINVAL, "%s must be NULL unless prec is GRID_F16S", sname);
+    return GRID_OK;
+}
+
+#define TRY(x)                   \
+    do {                         \
+        int rc_ = (x);           \
+        if (rc_) return rc_;     \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char *grid_last_error(void) { return g_err; }
+
+int grid_version(void) { return 100; }
+
+int grid_dhop(const void *U, const void *psi, const float *psi_scale, void *out, float *out_scale, const grid_geom *geom,
+              const grid_op *op, int prec, int link_fmt, void *stream) {
+    GeomDev g;
+    TRY(check_geom(geom, &g));
+    if (!op) return fail(GRID_EINVAL, "op is NULL");
+    TRY(check_prec(prec));
+    TRY(check_fmt(link_fmt));
+    if (op->kind != GRID_HOP && op->kind != GRID_WILSON && op->kind != GRID_DWF)
+        return fail(GRID_EINVAL, "unknown operator kind %d", op->kind);
+    if (op->kind == GRID_WILSON && g.Ls != 1) return fail(GRID_ESHAPE, "GRID_WILSON needs Ls == 1 (got %d)", g.Ls);
+    TRY(check_ptr(U, "U", 16));
+    TRY(check_spinor(psi, psi_scale, prec, "psi", "psi_scale"));
+    TRY(check_spinor(out, out_scale, prec, "out", "out_scale"));
+    const size_t sb = spinor_site_bytes(prec) * static_cast<size_t>(g.n5);
+    const size_t ub = link_bytes(prec, link_fmt) * static_cast<size_t>(g.vol) * 4;
+    const size_t cb = prec == GRID_F16S ? sizeof(float) * static_cast<size_t>(g.n5) : 0;
+    if (overlap(out, sb, psi, sb) || overlap(out, sb, U, ub)) return fail(GRID_EINVAL, "out overlaps psi or U");
+    if (cb && (overlap(out_scale, cb, psi_scale, cb) || overlap(out_scale, cb, out, sb) ||
+               overlap(out_scale, cb, psi, sb)))
+        return fail(GRID_EINVAL, "out_scale overlaps an input or out");
+
+    DhopArgs a;
+    a.U = U;
+    a.psi = psi;
+    a.psi_scale = psi_scale;
+    a.out = out;
+    a.out_scale = out_scale;
+    a.g = g;
+    a.prec = prec;
+    a.link_fmt = link_fmt;
+    a.kind = op->kind;
+    a.dag = op->dag ? 1 : 0;
+    a.diag = op->kind == GRID_WILSON ? 4.0 + op->mass : (op->kind == GRID_DWF ? 5.0 - op->M5 : 0.0);
+    a.mf = op->mf;
+    a.stream = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_dhop(a);
+    if (e != hipSuccess) return hip_fail(e, "grid_dhop launch");
+    return ok();
+}
+
+int grid_dwf_mdag_m(const void *U, const void *psi, const float *psi_scale, void *out, float *out_scale, void *tmp,
+                    float *tmp_scale, const grid_geom *geom, double M5, double mf, int prec, int link_fmt,
+                    void *stream) {
+    GeomDev g;
+    TRY(check_geom(geom, &g));
+    TRY(check_prec(prec));
+    TRY(check_fmt(link_fmt));
+    TRY(check_spinor(tmp, tmp_scale, prec, "tmp", "tmp_scale"));
+    const size_t sb = spinor_site_bytes(prec) * static_cast<size_t>(g.n5);
+    if (overlap(tmp, sb, psi, sb) || overlap(tmp, sb, out, sb)) return fail(GRID_EINVAL, "tmp overlaps psi or out");
+    grid_op m = {GRID_DWF, 0, 0.0, M5, mf};
+    TRY(grid_dhop(U, psi, psi_scale, tmp, tmp_scale, geom, &m, prec, link_fmt, stream));
+    m.dag = 1;
+    return grid_dhop(U, tmp, tmp_scale, out, out_scale, geom, &m, prec, link_fmt, stream);
+}
+
+int grid_dhop_backward(const void *U, const void *psi, const void *grad_out, void *grad_psi, void *grad_U,
+                       const grid_geom *geom, const grid_op *op, int prec, int force_mode, void *stream) {
+    GeomDev g;
+    TRY(check_geom(geom, &g));
+    if (!op) return fail(GRID_EINVAL, "op is NULL");
+    if (prec != GRID_F64 && prec != GRID_F32) return fail(GRID_EDTYPE, "grid_dhop_backward takes GRID_F64 or GRID_F32");
+    if (op->kind != GRID_HOP && op->kind != GRID_WILSON && op->kind != GRID_DWF)
+        return fail(GRID_EINVAL, "unknown operator kind %d", op->kind);
+    if (op->kind == GRID_WILSON && g.Ls != 1) return fail(GRID_ESHAPE, "GRID_WILSON needs Ls == 1 (got %d)", g.Ls);
+    if (force_mode != 0 && force_mode != 1) return fail(GRID_EINVAL, "force_mode must be 0 or 1");
+    TRY(check_ptr(U, "U", 16));
+    TRY(check_ptr(psi, "psi", 16));
+    TRY(check_ptr(grad_out, "grad_out", 16));
+    if (!grad_psi && !grad_U) return fail(GRID_EINVAL, "grad_psi and grad_U are both NULL");
+    const size_t sb = spinor_site_bytes(prec) * static_cast<size_t>(g.n5);
+    const size_t ub = link_bytes(prec, GRID_L18) * static_cast<size_t>(g.vol) * 4;
+    if (grad_psi) {
+        TRY(check_ptr(grad_psi, "grad_psi", 16));
+        if (overlap(grad_psi, sb, grad_out, sb) || overlap(grad_psi, sb, psi, sb) || overlap(grad_psi, sb, U, ub))
+            return fail(GRID_EINVAL, "grad_psi overlaps an input");
+    }
+    if (grad_U) {
+        TRY(check_ptr(grad_U, "grad_U", 16));
+        if (overlap(grad_U, ub, grad_out, sb) || overlap(grad_U, ub, psi, sb) || overlap(grad_U, ub, U, ub) ||
+            overlap(grad_U, ub, grad_psi, sb))
+            return fail(GRID_EINVAL, "grad_U overlaps an input or grad_psi");
+    }
+    if (grad_psi) {
+        grid_op adj = *op;
+        adj.dag = op->dag ? 0 : 1;
+        TRY(grid_dhop(U, grad_out, nullptr, grad_psi, nullptr, geom, &adj, prec, GRID_L18, stream));
+    }
+    if (grad_U) {
+        LinkGradArgs a;
+        a.U = U;
+        a.chi = grad_out;
+        a.psi = psi;
+        a.G = grad_U;
+        a.g = g;
+        a.prec = prec;
+        a.dag = op->dag ? 1 : 0;
+        a.force_mode = force_mode;
+        a.coef = op->kind == GRID_HOP ? 1.0 : -0.5;
+        a.stream = static_cast<hipStream_t>(stream);
+        hipError_t e = launch_link_grad(a);
+        if (e != hipSuccess) return hip_fail(e, "grid_dhop_backward launch");
+    }
+    return ok();
+}
+
+size_t grid_cg_workspace_bytes(const grid_geom *geom, const grid_cg_params *params) {
+    GeomDev g;
+    if (check_geom(geom, &g) || !params) return 0;
+    if (check_prec(params->sloppy_prec) || check_fmt(params->link_fmt)) return 0;
+    return cg_workspace_bytes(g, params->sloppy_prec, params->link_fmt);
+}
+
+int grid_cg(const void *U, const void *b, void *x, const grid_geom *geom, const grid_op *op, const grid_cg_params *params,
+            void *workspace, size_t ws_bytes, grid_cg_stats *stats, void *stream) {
+    GeomDev g;
+    TRY(check_geom(geom, &g));
+    if (!op || !params || !stats) return fail(GRID_EINVAL, "op, params and stats must not be NULL");
+    if (op->kind != GRID_WILSON && op->kind != GRID_DWF)
+        return fail(GRID_EINVAL, "grid_cg solves with GRID_WILSON or GRID_DWF (got kind %d)", op->kind);
+    if (op->kind == GRID_WILSON && g.Ls != 1) return fail(GRID_ESHAPE, "GRID_WILSON needs Ls == 1 (got %d)", g.Ls);
+    TRY(check_prec(params->sloppy_prec));
+    TRY(check_fmt(params->link_fmt));
+    if (!(params->tol > 0.0) || params->maxiter < 0 || params->check_every < 1)
+        return fail(GRID_EINVAL, "need tol > 0, maxiter >= 0 and check_every >= 1");
+    if (params->sloppy_prec != GRID_F64 && !(params->delta > 0.0 && params->delta < 1.0))
+        return fail(GRID_EINVAL, "reliable-update delta must lie in (0, 1)");
+    TRY(check_ptr(U, "U", 16));
+    TRY(check_ptr(b, "b", 16));
+    TRY(check_ptr(x, "x", 16));
+    TRY(check_ptr(workspace, "workspace", 256));
+    const size_t need = cg_workspace_bytes(g, params->sloppy_prec, params->link_fmt);
+    if (ws_bytes < need) return fail(GRID_ESPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    const size_t sb = static_cast<size_t>(g.n5) * 192, ub = static_cast<size_t>(g.vol) * 4 * 144;
+    if (overlap(x, sb, b, sb) || overlap(x, sb, U, ub) || overlap(workspace, need, x, sb) ||
+        overlap(workspace, need, b, sb) || overlap(workspace, need, U, ub))
+        return fail(GRID_EINVAL, "x, b, U and workspace must not overlap");
+    int status = GRID_OK;
+    memset(stats, 0, sizeof(*stats));
+    const double diag = op->kind == GRID_WILSON ? 4.0 + op->mass : 5.0 - op->M5;
+    hipError_t e = run_cg(U, b, x, g, op->kind, diag, op->mf, *params, workspace, static_cast<hipStream_t>(stream),
+                          stats, &status);
+    if (e != hipSuccess) return hip_fail(e, "grid_cg");
+    if (status == GRID_ENOCONV)
+        return fail(GRID_ENOCONV, "CG stopped after %d iterations at true residual %.3e", stats->iterations,
+                    stats->true_residual);
+    if (status == GRID_EBREAKDOWN) return fail(GRID_EBREAKDOWN, "CG breakdown after %d iterations", stats->iterations);
+    return ok();
+}
+
+int grid_convert_spinor(const void *src, int src_prec, const float *src_scale, void *dst, int dst_prec, float *dst_scale,
+                        long n_sites, void *stream) {
+    TRY(check_prec(src_prec));
+    TRY(check_prec(dst_prec));
+    if (n_sites < 0 || n_sites >= (long(1) << 31)) return fail(GRID_ESHAPE, "n_sites out of range");
+    TRY(check_spinor(src, src_scale, src_prec, "src", "src_scale"));
+    TRY(check_spinor(dst, dst_scale, dst_prec, "dst", "dst_scale"));
+    const size_t sa = spinor_site_bytes(src_prec) * n_sites, sd = spinor_site_bytes(dst_prec) * n_sites;
+    if (overlap(src, sa, dst, sd)) return fail(GRID_EINVAL, "dst overlaps src");
+    if (dst_scale && (overlap(dst_scale, 4 * n_sites, src, sa) || overlap(dst_scale, 4 * n_sites, dst, sd) ||
+                      overlap(dst_scale, 4 * n_sites, src_scale, src_scale ? 4 * n_sites : 0)))
+        return fail(GRID_EINVAL, "dst_scale overlaps another buffer");
+    hipError_t e = launch_convert_spinor(src, src_prec, src_scale, dst, dst_prec, dst_scale, n_sites,
+                                         static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "grid_convert_spinor launch");
+    return ok();
+}
+
+int grid_convert_links(const void *src, void *dst, int dst_prec, int dst_fmt, int reunitarise, long n_links,
+                       void *stream) {
+    TRY(check_prec(dst_prec));
+    TRY(check_fmt(dst_fmt));
+    if (n_links < 0 || n_links >= (long(1) << 31)) return fail(GRID_ESHAPE, "n_links out of range");
+    TRY(check_ptr(src, "src", 16));
+    TRY(check_ptr(dst, "dst", 16));
+    if (overlap(src, 144 * n_links, dst, link_bytes(dst_prec, dst_fmt) * n_links))
+        return fail(GRID_EINVAL, "dst overlaps src");
+    hipError_t e = launch_convert_links(src, dst, dst_prec, dst_fmt, reunitarise, n_links, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "grid_convert_links launch");
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,386 @@
+// Device building blocks for the hopping-term kernels (gfx950, wave64).
+//
+// * Cx<C>: a complex number in the compute precision C (double or float).
+// * Spinor storage policies SpF64 / SpF32 / SpF16S: load a site's 4x3 complex spinor (or one
+//   chiral half of it) into registers in precision C and store it back, with the per-site scale
+//   of the FP16 format applied on load and computed on store.
+// * Link storage policies: 18-real or 12-real (row 2 rebuilt as conj(row0 x row1)) in double,
+//   float or half.
+// * Spin projection to a two-spin half-spinor and its reconstruction, specialised per direction
+//   (the Compressor's spin projection of Section 2.4 done on load).
+// * Geometry: coordinates of a linear site and its periodic neighbours (Cshift semantics of
+//   Section 2.3), plus the XCD-aware block order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace gridmi {
+
+// Non-temporal (streaming) stores through clang vector types.
+typedef double v2d_t __attribute__((ext_vector_type(2)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void nt_store(void *p, double x, double y) {
+    v2d_t v = {x, y};
+    __builtin_nontemporal_store(v, reinterpret_cast<v2d_t *>(p));
+}
+__device__ __forceinline__ void nt_store(void *p, float x, float y, float z, float w) {
+    v4f_t v = {x, y, z, w};
+    __builtin_nontemporal_store(v, reinterpret_cast<v4f_t *>(p));
+}
+__device__ __forceinline__ void nt_store(void *p, unsigned x, unsigned y, unsigned z, unsigned w) {
+    v4u_t v = {x, y, z, w};
+    __builtin_nontemporal_store(v, reinterpret_cast<v4u_t *>(p));
+}
+
+template <typename C>
+struct Cx {
+    C r, i;
+};
+
+template <typename C>
+__device__ __forceinline__ Cx<C> cadd(Cx<C> a, Cx<C> b) { return {a.r + b.r, a.i + b.i}; }
+template <typename C>
+__device__ __forceinline__ Cx<C> csub(Cx<C> a, Cx<C> b) { return {a.r - b.r, a.i - b.i}; }
+// a * b
+template <typename C>
+__device__ __forceinline__ Cx<C> cmul(Cx<C> a, Cx<C> b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+// conj(a) * b
+template <typename C>
+__device__ __forceinline__ Cx<C> cmulc(Cx<C> a, Cx<C> b) { return {a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r}; }
+// acc + a * b
+template <typename C>
+__device__ __forceinline__ Cx<C> cmac(Cx<C> acc, Cx<C> a, Cx<C> b) {
+    return {acc.r + a.r * b.r - a.i * b.i, acc.i + a.r * b.i + a.i * b.r};
+}
+// acc + conj(a) * b
+template <typename C>
+__device__ __forceinline__ Cx<C> cmacc(Cx<C> acc, Cx<C> a, Cx<C> b) {
+    return {acc.r + a.r * b.r + a.i * b.i, acc.i + a.r * b.i - a.i * b.r};
+}
+// i * a
+template <typename C>
+__device__ __forceinline__ Cx<C> ctimesi(Cx<C> a) { return {-a.i, a.r}; }
+template <typename C>
+__device__ __forceinline__ Cx<C> cscale(C s, Cx<C> a) { return {s * a.r, s * a.i}; }
+template <typename C>
+__device__ __forceinline__ Cx<C> cconj(Cx<C> a) { return {a.r, -a.i}; }
+
+// ------------------------------------------------------------------------------------------
+// Spinor storage. A site is 12 complex numbers [spin][colour]; `site` counts sites (4D or 5D).
+// ------------------------------------------------------------------------------------------
+
+struct SpF64 {
+    using C = double;
+    static constexpr int kBytes = 192;
+    __device__ __forceinline__ static void load(const void *base, const float *, size_t site, Cx<C> p[4][3]) {
+        const double2 *q = reinterpret_cast<const double2 *>(base) + site * 12;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            double2 v = q[k];
+            p[k / 3][k % 3] = {v.x, v.y};
+        }
+    }
+    // spins (2h, 2h+1): h = 0 upper (P_+), h = 1 lower (P_-)
+    __device__ __forceinline__ static void load_half(const void *base, const float *, size_t site, int h,
+                                                     Cx<C> p[2][3]) {
+        const double2 *q = reinterpret_cast<const double2 *>(base) + site * 12 + h * 6;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            double2 v = q[k];
+            p[k / 3][k % 3] = {v.x, v.y};
+        }
+    }
+    __device__ __forceinline__ static void store(void *base, float *, size_t site, const Cx<C> p[4][3]) {
+        double2 *q = reinterpret_cast<double2 *>(base) + site * 12;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            nt_store(q + k, p[k / 3][k % 3].r, p[k / 3][k % 3].i);
+        }
+    }
+};
+
+struct SpF32 {
+    using C = float;
+    static constexpr int kBytes = 96;
+    __device__ __forceinline__ static void load(const void *base, const float *, size_t site, Cx<C> p[4][3]) {
+        const float4 *q = reinterpret_cast<const float4 *>(base) + site * 6;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            float4 v = q[k];
+            p[(2 * k) / 3][(2 * k) % 3] = {v.x, v.y};
+            p[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v.z, v.w};
+        }
+    }
+    __device__ __forceinline__ static void load_half(const void *base, const float *, size_t site, int h,
+                                                     Cx<C> p[2][3]) {
+        const float4 *q = reinterpret_cast<const float4 *>(base) + site * 6 + h * 3;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float4 v = q[k];
+            p[(2 * k) / 3][(2 * k) % 3] = {v.x, v.y};
+            p[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v.z, v.w};
+        }
+    }
+    __device__ __forceinline__ static void store(void *base, float *, size_t site, const Cx<C> p[4][3]) {
+        float4 *q = reinterpret_cast<float4 *>(base) + site * 6;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const Cx<C> a = p[(2 * k) / 3][(2 * k) % 3], b = p[(2 * k + 1) / 3][(2 * k + 1) % 3];
+            nt_store(q + k, a.r, a.i, b.r, b.i);
+        }
+    }
+};
+
+__device__ __forceinline__ float half_bits_to_float(uint32_t bits16) {
+    return __half2float(__ushort_as_half(static_cast<unsigned short>(bits16)));
+}
+__device__ __forceinline__ uint32_t float_to_half_bits(float v) {
+    return static_cast<uint32_t>(__half_as_ushort(__float2half_rn(v)));
+}
+
+// FP16 storage: 24 halves (48 bytes) per site and one float scale per site.
+struct SpF16S {
+    using C = float;
+    static constexpr int kBytes = 52;
+    __device__ __forceinline__ static void unpack6(uint4 w0, uint4 w1, uint4 w2, float s, Cx<C> p[4][3]) {
+        const uint32_t w[12] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w, w2.x, w2.y, w2.z, w2.w};
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            p[k / 3][k % 3] = {half_bits_to_float(w[k] & 0xffffu) * s, half_bits_to_float(w[k] >> 16) * s};
+    }
+    __device__ __forceinline__ static void load(const void *base, const float *scale, size_t site, Cx<C> p[4][3]) {
+        const uint4 *q = reinterpret_cast<const uint4 *>(base) + site * 3;
+        const float s = scale[site];
+        unpack6(q[0], q[1], q[2], s, p);
+    }
+    __device__ __forceinline__ static void load_half(const void *base, const float *scale, size_t site, int h,
+                                                     Cx<C> p[2][3]) {
+        // a half site is 6 complex = 24 bytes: 3 x 8-byte words
+        const uint2 *q = reinterpret_cast<const uint2 *>(base) + site * 6 + h * 3;
+        const float s = scale[site];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uint2 v = q[k];
+            p[(2 * k) / 3][(2 * k) % 3] = {half_bits_to_float(v.x & 0xffffu) * s, half_bits_to_float(v.x >> 16) * s};
+            p[(2 * k + 1) / 3][(2 * k + 1) % 3] = {half_bits_to_float(v.y & 0xffffu) * s,
+                                                  half_bits_to_float(v.y >> 16) * s};
+        }
+    }
+    __device__ __forceinline__ static void store(void *base, float *scale, size_t site, const Cx<C> p[4][3]) {
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(p[k / 3][k % 3].r), fabsf(p[k / 3][k % 3].i)));
+        const float inv = m > 0.f ? 1.0f / m : 0.f;
+        uint32_t w[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const float re = p[k / 3][k % 3].r * inv, im = p[k / 3][k % 3].i * inv;
+            w[k] = float_to_half_bits(re) | (float_to_half_bits(im) << 16);
+        }
+        uint4 *q = reinterpret_cast<uint4 *>(base) + site * 3;
+        nt_store(q + 0, w[0], w[1], w[2], w[3]);
+        nt_store(q + 1, w[4], w[5], w[6], w[7]);
+        nt_store(q + 2, w[8], w[9], w[10], w[11]);
+        __builtin_nontemporal_store(m, scale + site);
+    }
+};
+
+// ------------------------------------------------------------------------------------------
+// Link storage. `link` = site * 4 + mu. Loads fill u[3][3] (row 2 rebuilt for 12-real links).
+// ------------------------------------------------------------------------------------------
+
+template <typename C>
+__device__ __forceinline__ void rebuild_row2(Cx<C> u[3][3]) {
+    // row2 = conj(row0 x row1)
+    u[2][0] = cconj(csub(cmul(u[0][1], u[1][2]), cmul(u[0][2], u[1][1])));
+    u[2][1] = cconj(csub(cmul(u[0][2], u[1][0]), cmul(u[0][0], u[1][2])));
+    u[2][2] = cconj(csub(cmul(u[0][0], u[1][1]), cmul(u[0][1], u[1][0])));
+}
+
+template <int ROWS>
+struct LkF64 {
+    using C = double;
+    static constexpr int kRows = ROWS;
+    static constexpr int kBytes = ROWS * 3 * 16;
+    __device__ __forceinline__ static void load(const void *base, size_t link, Cx<C> u[3][3]) {
+        const double2 *q = reinterpret_cast<const double2 *>(base) + link * (ROWS * 3);
+#pragma unroll
+        for (int k = 0; k < ROWS * 3; ++k) {
+            double2 v = q[k];
+            u[k / 3][k % 3] = {v.x, v.y};
+        }
+        if (ROWS == 2) rebuild_row2(u);
+    }
+};
+
+template <int ROWS>
+struct LkF32 {
+    using C = float;
+    static constexpr int kRows = ROWS;
+    static constexpr int kBytes = ROWS * 3 * 8;
+    __device__ __forceinline__ static void load(const void *base, size_t link, Cx<C> u[3][3]) {
+        if (ROWS == 2) {
+            const float4 *q = reinterpret_cast<const float4 *>(base) + link * 3;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                float4 v = q[k];
+                u[(2 * k) / 3][(2 * k) % 3] = {v.x, v.y};
+                u[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v.z, v.w};
+            }
+            rebuild_row2(u);
+        } else {
+            const float2 *q = reinterpret_cast<const float2 *>(base) + link * 9;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                float2 v = q[k];
+                u[k / 3][k % 3] = {v.x, v.y};
+            }
+        }
+    }
+};
+
+template <int ROWS>
+struct LkF16 {
+    using C = float;
+    static constexpr int kRows = ROWS;
+    static constexpr int kBytes = ROWS * 3 * 4;
+    __device__ __forceinline__ static void load(const void *base, size_t link, Cx<C> u[3][3]) {
+        if (ROWS == 2) {
+            const uint2 *q = reinterpret_cast<const uint2 *>(base) + link * 3;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                uint2 v = q[k];
+                u[(2 * k) / 3][(2 * k) % 3] = {half_bits_to_float(v.x & 0xffffu), half_bits_to_float(v.x >> 16)};
+                u[(2 * k + 1) / 3][(2 * k + 1) % 3] = {half_bits_to_float(v.y & 0xffffu),
+                                                      half_bits_to_float(v.y >> 16)};
+            }
+            rebuild_row2(u);
+        } else {
+            const uint32_t *q = reinterpret_cast<const uint32_t *>(base) + link * 9;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                uint32_t v = q[k];
+                u[k / 3][k % 3] = {half_bits_to_float(v & 0xffffu), half_bits_to_float(v >> 16)};
+            }
+        }
+    }
+};
+
+// ------------------------------------------------------------------------------------------
+// Spin projection (1 + EPS gamma_MU) psi = [h; EPS A_MU^dagger h], h = psi_up + EPS A_MU psi_dn,
+// with gamma_MU = [[0, A], [A^dagger, 0]], A = -i sigma_1, -i sigma_2, -i sigma_3, 1.
+// ------------------------------------------------------------------------------------------
+
+template <int MU, int EPS, typename C>
+__device__ __forceinline__ void project(const Cx<C> p[4][3], Cx<C> h[2][3]) {
+    const C e = static_cast<C>(EPS);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (MU == 0) {          // h0 = p0 - i e p3, h1 = p1 - i e p2
+            h[0][a] = {p[0][a].r + e * p[3][a].i, p[0][a].i - e * p[3][a].r};
+            h[1][a] = {p[1][a].r + e * p[2][a].i, p[1][a].i - e * p[2][a].r};
+        } else if (MU == 1) {   // h0 = p0 - e p3, h1 = p1 + e p2
+            h[0][a] = {p[0][a].r - e * p[3][a].r, p[0][a].i - e * p[3][a].i};
+            h[1][a] = {p[1][a].r + e * p[2][a].r, p[1][a].i + e * p[2][a].i};
+        } else if (MU == 2) {   // h0 = p0 - i e p2, h1 = p1 + i e p3
+            h[0][a] = {p[0][a].r + e * p[2][a].i, p[0][a].i - e * p[2][a].r};
+            h[1][a] = {p[1][a].r - e * p[3][a].i, p[1][a].i + e * p[3][a].r};
+        } else {                // h0 = p0 + e p2, h1 = p1 + e p3
+            h[0][a] = {p[0][a].r + e * p[2][a].r, p[0][a].i + e * p[2][a].i};
+            h[1][a] = {p[1][a].r + e * p[3][a].r, p[1][a].i + e * p[3][a].i};
+        }
+    }
+}
+
+// acc += [chi; EPS A_MU^dagger chi]
+template <int MU, int EPS, typename C>
+__device__ __forceinline__ void reconstruct_add(Cx<C> acc[4][3], const Cx<C> chi[2][3]) {
+    const C e = static_cast<C>(EPS);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        acc[0][a] = cadd(acc[0][a], chi[0][a]);
+        acc[1][a] = cadd(acc[1][a], chi[1][a]);
+        if (MU == 0) {          // lower = (i e chi1, i e chi0)
+            acc[2][a] = {acc[2][a].r - e * chi[1][a].i, acc[2][a].i + e * chi[1][a].r};
+            acc[3][a] = {acc[3][a].r - e * chi[0][a].i, acc[3][a].i + e * chi[0][a].r};
+        } else if (MU == 1) {   // lower = (e chi1, -e chi0)
+            acc[2][a] = {acc[2][a].r + e * chi[1][a].r, acc[2][a].i + e * chi[1][a].i};
+            acc[3][a] = {acc[3][a].r - e * chi[0][a].r, acc[3][a].i - e * chi[0][a].i};
+        } else if (MU == 2) {   // lower = (i e chi0, -i e chi1)
+            acc[2][a] = {acc[2][a].r - e * chi[0][a].i, acc[2][a].i + e * chi[0][a].r};
+            acc[3][a] = {acc[3][a].r + e * chi[1][a].i, acc[3][a].i - e * chi[1][a].r};
+        } else {                // lower = (e chi0, e chi1)
+            acc[2][a] = {acc[2][a].r + e * chi[0][a].r, acc[2][a].i + e * chi[0][a].i};
+            acc[3][a] = {acc[3][a].r + e * chi[1][a].r, acc[3][a].i + e * chi[1][a].i};
+        }
+    }
+}
+
+// chi_k = U h_k
+template <typename C>
+__device__ __forceinline__ void su3_mul(const Cx<C> u[3][3], const Cx<C> h[2][3], Cx<C> chi[2][3]) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            Cx<C> s = cmul(u[a][0], h[k][0]);
+            s = cmac(s, u[a][1], h[k][1]);
+            s = cmac(s, u[a][2], h[k][2]);
+            chi[k][a] = s;
+        }
+}
+
+// chi_k = U^dagger h_k
+template <typename C>
+__device__ __forceinline__ void su3_adj_mul(const Cx<C> u[3][3], const Cx<C> h[2][3], Cx<C> chi[2][3]) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            Cx<C> s = cmulc(u[0][a], h[k][0]);
+            s = cmacc(s, u[1][a], h[k][1]);
+            s = cmacc(s, u[2][a], h[k][2]);
+            chi[k][a] = s;
+        }
+}
+
+// ------------------------------------------------------------------------------------------
+// Geometry
+// ------------------------------------------------------------------------------------------
+
+struct GeomDev {
+    int L[4];        // Lx, Ly, Lz, Lt
+    int Ls;          // fifth extent (1 for 4D)
+    int vol;         // 4D volume
+    int n5;          // vol * Ls
+};
+
+// Coordinates of 4D site x4 and the linear indices of its 8 periodic neighbours:
+// nb[2 mu] = x + mu-hat, nb[2 mu + 1] = x - mu-hat.
+__device__ __forceinline__ void neighbours(const GeomDev &g, int x4, int nb[8]) {
+    int r = x4;
+    int stride = 1;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const int L = g.L[mu];
+        const int c = (mu < 3) ? r % L : r;
+        r = (mu < 3) ? r / L : 0;
+        nb[2 * mu] = x4 + ((c == L - 1) ? (1 - L) * stride : stride);
+        nb[2 * mu + 1] = x4 + ((c == 0) ? (L - 1) * stride : -stride);
+        stride *= L;
+    }
+}
+
+// Hardware dispatches workgroup b to XCD b % 8. Renumber so that each XCD receives one
+// contiguous range of logical blocks: neighbouring lattice sites then share an L2.
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+    constexpr int kXcd = 8;
+    const int q = nblocks / kXcd, rem = nblocks % kXcd;
+    const int xcd = b % kXcd, k = b / kXcd;
+    return xcd * q + (xcd < rem ? xcd : rem) + k;
+}
+
+}  // namespace gridmi

@@ -1,0 +1,111 @@
+"""The C ABI library loads, exports every declared symbol, and validates arguments on the host.
+
+These run without a GPU: every call below is rejected by host-side validation before any HIP
+call, so the (fake, never dereferenced) device addresses are never touched.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1512_03487_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+A = 0x7f0000000000          # a 256-byte aligned fake address
+P = ctypes.c_void_p
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "grid_mi.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(grid_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def geom(dims=(4, 4, 4, 4), Ls=1):
+    g = _lib.GridGeom()
+    g.dims[:] = list(dims)
+    g.Ls = Ls
+    return g
+
+
+def op(kind=_lib.GRID_HOP, dag=0, mass=0.1, M5=1.8, mf=0.01):
+    return _lib.GridOp(kind, dag, mass, M5, mf)
+
+
+def dhop(lib, U=A, psi=A + 0x10000000, ps=None, out=A + 0x20000000, os_=None, g=None, o=None, prec=0, fmt=0):
+    g = g or geom()
+    o = o or op()
+    return lib.grid_dhop(P(U), P(psi), P(ps), P(out), P(os_), ctypes.byref(g), ctypes.byref(o), prec, fmt, None)
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert set(names) == set(_lib.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.grid_version() == 100
+
+
+def test_geometry_validation(lib):
+    assert lib.grid_dhop(P(A), P(A), None, P(A), None, None, ctypes.byref(op()), 0, 0, None) == _lib.GRID_EINVAL
+    assert dhop(lib, g=geom((4, 4, 1, 4))) == _lib.GRID_ESHAPE
+    assert "dims[2]" in _lib.last_error()
+    assert dhop(lib, g=geom((4, 4, 4, 4), Ls=0)) == _lib.GRID_ESHAPE
+    assert dhop(lib, g=geom((1024, 1024, 1024, 2))) == _lib.GRID_ESHAPE
+    assert dhop(lib, g=geom((64, 64, 64, 64), Ls=32)) == _lib.GRID_ESHAPE
+
+
+def test_enum_and_pointer_validation(lib):
+    assert dhop(lib, prec=7) == _lib.GRID_EDTYPE
+    assert dhop(lib, fmt=5) == _lib.GRID_EDTYPE
+    assert dhop(lib, o=op(kind=9)) == _lib.GRID_EINVAL
+    assert dhop(lib, o=op(kind=_lib.GRID_WILSON), g=geom(Ls=4)) == _lib.GRID_ESHAPE
+    assert dhop(lib, U=0) == _lib.GRID_EINVAL
+    assert dhop(lib, psi=A + 8) == _lib.GRID_EALIGN
+    assert dhop(lib, prec=_lib.GRID_F16S) == _lib.GRID_EINVAL            # missing scales
+    assert dhop(lib, ps=A + 0x30000000) == _lib.GRID_EINVAL               # scale with FP64
+    assert dhop(lib, out=A + 0x10000000 + 16) == _lib.GRID_EINVAL         # out overlaps psi
+    assert "overlap" in _lib.last_error()
+
+
+def test_backward_and_convert_validation(lib):
+    g, o = geom(), op()
+    assert lib.grid_dhop_backward(P(A), P(A + 0x1000000), P(A + 0x2000000), None, None, ctypes.byref(g),
+                                  ctypes.byref(o), 0, 0, None) == _lib.GRID_EINVAL
+    assert lib.grid_dhop_backward(P(A), P(A + 0x1000000), P(A + 0x2000000), P(A + 0x3000000), None, ctypes.byref(g),
+                                  ctypes.byref(o), _lib.GRID_F16S, 0, None) == _lib.GRID_EDTYPE
+    assert lib.grid_dhop_backward(P(A), P(A + 0x1000000), P(A + 0x2000000), P(A + 0x3000000), None, ctypes.byref(g),
+                                  ctypes.byref(o), 0, 2, None) == _lib.GRID_EINVAL
+    assert lib.grid_convert_spinor(P(A), 0, None, P(A + 0x1000000), 1, None, -1, None) == _lib.GRID_ESHAPE
+    assert lib.grid_convert_spinor(P(A), 0, None, P(A + 0x1000000), 2, None, 16, None) == _lib.GRID_EINVAL
+    assert lib.grid_convert_links(P(A), P(A + 16), 1, 0, 0, 16, None) == _lib.GRID_EINVAL   # overlap
+    assert lib.grid_convert_links(P(A), P(A + 0x1000000), 3, 0, 0, 16, None) == _lib.GRID_EDTYPE
+
+
+def test_cg_workspace_and_validation(lib):
+    g = geom((4, 4, 4, 4), Ls=8)
+    n = 4 ** 4 * 8
+    p64 = _lib.GridCgParams(1e-10, 100, _lib.GRID_F64, _lib.GRID_L18, 0.1, 10)
+    p16 = _lib.GridCgParams(1e-10, 100, _lib.GRID_F16S, _lib.GRID_L12, 0.1, 10)
+    w64 = lib.grid_cg_workspace_bytes(ctypes.byref(g), ctypes.byref(p64))
+    w16 = lib.grid_cg_workspace_bytes(ctypes.byref(g), ctypes.byref(p16))
+    assert w64 >= 4 * n * 192 and w16 >= 3 * n * 192 + n * 96 + 4 * n * 52
+    bad = _lib.GridCgParams(1e-10, 100, 9, 0, 0.1, 10)
+    assert lib.grid_cg_workspace_bytes(ctypes.byref(g), ctypes.byref(bad)) == 0
+    st = _lib.GridCgStats()
+    o = op(kind=_lib.GRID_DWF)
+    args = lambda ws, nbytes, p=p64, oo=o: (P(A), P(A + 0x1000000), P(A + 0x2000000), ctypes.byref(g), ctypes.byref(oo),
+                                            ctypes.byref(p), P(ws), ctypes.c_size_t(nbytes), ctypes.byref(st), None)
+    assert lib.grid_cg(*args(A + 0x4000000, w64 - 1)) == _lib.GRID_ESPACE
+    assert lib.grid_cg(*args(A + 0x4000000 + 128, w64)) == _lib.GRID_EALIGN
+    assert lib.grid_cg(*args(A + 0x1000000, w64)) == _lib.GRID_EINVAL                 # overlaps b
+    assert lib.grid_cg(*args(A + 0x4000000, w64, oo=op(kind=_lib.GRID_HOP))) == _lib.GRID_EINVAL
+    nodelta = _lib.GridCgParams(1e-10, 100, _lib.GRID_F32, _lib.GRID_L18, 1.5, 10)
+    assert lib.grid_cg(*args(A + 0x4000000, w64 * 4, p=nodelta)) == _lib.GRID_EINVAL
+    assert _lib.last_error()
