@@ -73,7 +73,7 @@ k_convert_spinor(const void *__restrict__ src, int src_prec, const float *__rest
     const float inv = m > 0.f ? 1.0f / m : 0.f;
     uint32_t w[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) w[k] = float_to_half_bits(v[2 * k] * inv) | (float_to_half_bits(v[2 * k + 1] * inv) << 16);
+    for (int k = 0; k < 12; ++k) w[k] = scaled_half_bits(v[2 * k], inv) | (scaled_half_bits(v[2 * k + 1], inv) << 16);
     uint4 *q = reinterpret_cast<uint4 *>(dst) + site * 3;
     q[0] = make_uint4(w[0], w[1], w[2], w[3]);
     q[1] = make_uint4(w[4], w[5], w[6], w[7]);

@@ -3,7 +3,9 @@
 // * Cx<C>: a complex number in the compute precision C (double or float).
 // * Spinor storage policies SpF64 / SpF32 / SpF16S: load a site's 4x3 complex spinor (or one
 //   chiral half of it) into registers in precision C and store it back, with the per-site scale
-//   of the FP16 format applied on load and computed on store.
+//   of the FP16 format applied on load and computed on store. Stores are plain: the L2 merges
+//   a wave's partial-line writes, whereas streaming stores of 16-byte pieces at the 96/192-byte
+//   site pitch were measured to double the HBM write traffic.
 // * Link storage policies: 18-real or 12-real (row 2 rebuilt as conj(row0 x row1)) in double,
 //   float or half.
 // * Spin projection to a two-spin half-spinor and its reconstruction, specialised per direction
@@ -17,23 +19,6 @@
 #include <stdint.h>
 
 namespace gridmi {
-
-// Non-temporal (streaming) stores through clang vector types.
-typedef double v2d_t __attribute__((ext_vector_type(2)));
-typedef float v4f_t __attribute__((ext_vector_type(4)));
-typedef unsigned int v4u_t __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void nt_store(void *p, double x, double y) {
-    v2d_t v = {x, y};
-    __builtin_nontemporal_store(v, reinterpret_cast<v2d_t *>(p));
-}
-__device__ __forceinline__ void nt_store(void *p, float x, float y, float z, float w) {
-    v4f_t v = {x, y, z, w};
-    __builtin_nontemporal_store(v, reinterpret_cast<v4f_t *>(p));
-}
-__device__ __forceinline__ void nt_store(void *p, unsigned x, unsigned y, unsigned z, unsigned w) {
-    v4u_t v = {x, y, z, w};
-    __builtin_nontemporal_store(v, reinterpret_cast<v4u_t *>(p));
-}
 
 template <typename C>
 struct Cx {
@@ -75,6 +60,16 @@ __device__ __forceinline__ Cx<C> cconj(Cx<C> a) { return {a.r, -a.i}; }
 struct SpF64 {
     using C = double;
     static constexpr int kBytes = 192;
+    static constexpr int kChunks = 12;          // 16-byte chunks per site
+    static constexpr bool kScaled = false;
+    __device__ __forceinline__ static void unpack(const uint4 *w, float, Cx<C> p[4][3]) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            double2 v;
+            __builtin_memcpy(&v, &w[k], 16);
+            p[k / 3][k % 3] = {v.x, v.y};
+        }
+    }
     __device__ __forceinline__ static void load(const void *base, const float *, size_t site, Cx<C> p[4][3]) {
         const double2 *q = reinterpret_cast<const double2 *>(base) + site * 12;
 #pragma unroll
@@ -96,15 +91,24 @@ struct SpF64 {
     __device__ __forceinline__ static void store(void *base, float *, size_t site, const Cx<C> p[4][3]) {
         double2 *q = reinterpret_cast<double2 *>(base) + site * 12;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            nt_store(q + k, p[k / 3][k % 3].r, p[k / 3][k % 3].i);
-        }
+        for (int k = 0; k < 12; ++k) q[k] = make_double2(p[k / 3][k % 3].r, p[k / 3][k % 3].i);
     }
 };
 
 struct SpF32 {
     using C = float;
     static constexpr int kBytes = 96;
+    static constexpr int kChunks = 6;
+    static constexpr bool kScaled = false;
+    __device__ __forceinline__ static void unpack(const uint4 *w, float, Cx<C> p[4][3]) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            float4 v;
+            __builtin_memcpy(&v, &w[k], 16);
+            p[(2 * k) / 3][(2 * k) % 3] = {v.x, v.y};
+            p[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v.z, v.w};
+        }
+    }
     __device__ __forceinline__ static void load(const void *base, const float *, size_t site, Cx<C> p[4][3]) {
         const float4 *q = reinterpret_cast<const float4 *>(base) + site * 6;
 #pragma unroll
@@ -129,7 +133,7 @@ struct SpF32 {
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const Cx<C> a = p[(2 * k) / 3][(2 * k) % 3], b = p[(2 * k + 1) / 3][(2 * k + 1) % 3];
-            nt_store(q + k, a.r, a.i, b.r, b.i);
+            q[k] = make_float4(a.r, a.i, b.r, b.i);
         }
     }
 };
@@ -140,11 +144,25 @@ __device__ __forceinline__ float half_bits_to_float(uint32_t bits16) {
 __device__ __forceinline__ uint32_t float_to_half_bits(float v) {
     return static_cast<uint32_t>(__half_as_ushort(__float2half_rn(v)));
 }
+// half(v * r) with the product first rounded to float: the FP16 code is defined by two roundings,
+// so the multiply must not be fused into a mixed-precision FMA that rounds once.
+// The empty asm only pins the float product in a register (an optimisation barrier; no memory
+// access), which stops instruction selection from fusing the multiply into the conversion.
+__device__ __forceinline__ uint32_t scaled_half_bits(float v, float r) {
+    float p = v * r;
+    __asm__ volatile("" : "+v"(p));
+    return float_to_half_bits(p);
+}
 
 // FP16 storage: 24 halves (48 bytes) per site and one float scale per site.
 struct SpF16S {
     using C = float;
     static constexpr int kBytes = 52;
+    static constexpr int kChunks = 3;
+    static constexpr bool kScaled = true;
+    __device__ __forceinline__ static void unpack(const uint4 *w, float s, Cx<C> p[4][3]) {
+        unpack6(w[0], w[1], w[2], s, p);
+    }
     __device__ __forceinline__ static void unpack6(uint4 w0, uint4 w1, uint4 w2, float s, Cx<C> p[4][3]) {
         const uint32_t w[12] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w, w2.x, w2.y, w2.z, w2.w};
 #pragma unroll
@@ -177,14 +195,13 @@ struct SpF16S {
         uint32_t w[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            const float re = p[k / 3][k % 3].r * inv, im = p[k / 3][k % 3].i * inv;
-            w[k] = float_to_half_bits(re) | (float_to_half_bits(im) << 16);
+            w[k] = scaled_half_bits(p[k / 3][k % 3].r, inv) | (scaled_half_bits(p[k / 3][k % 3].i, inv) << 16);
         }
         uint4 *q = reinterpret_cast<uint4 *>(base) + site * 3;
-        nt_store(q + 0, w[0], w[1], w[2], w[3]);
-        nt_store(q + 1, w[4], w[5], w[6], w[7]);
-        nt_store(q + 2, w[8], w[9], w[10], w[11]);
-        __builtin_nontemporal_store(m, scale + site);
+        q[0] = make_uint4(w[0], w[1], w[2], w[3]);
+        q[1] = make_uint4(w[4], w[5], w[6], w[7]);
+        q[2] = make_uint4(w[8], w[9], w[10], w[11]);
+        scale[site] = m;
     }
 };
 

@@ -1,0 +1,104 @@
+"""GPU CG (FP64 and mixed precision) checked by the oracle: the true residual of every returned x
+is recomputed on the CPU in FP64, and small systems are compared with the oracle's own solve.
+
+A CG solution is unique only up to the tolerance, so x is compared with the oracle solution for
+information (relative difference bounded by the condition number times tol), and the gate is
+the oracle-recomputed true residual.
+"""
+import numpy as np
+import pytest
+
+import oracle.oracle as O
+from paper_1512_03487_amd import fields as F
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+# the oracle's recomputation differs from the kernel's own FP64 residual by rounding only
+RES_SLACK = 1.05
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _announce():
+    print("\n[gpu] test_gpu_cg", flush=True)
+
+
+def test_wilson_fp64_cg_4444(gpu):
+    import paper_1512_03487_amd as gm
+    from tests.gpu_util import dev
+    dims = (4, 4, 4, 4)
+    U, b = F.gauge_field(dims, seed=1, kind="haar"), F.spinor_field(dims, seed=3)
+    x, st = gm.cg(dev(U), dev(b), kind="wilson", mass=0.1, tol=TOL, sloppy="f64", check_every=1)
+    x = x.cpu().numpy()
+    op = O.Op.wilson(0.1)
+    assert st["converged"] and st["true_residual"] <= TOL
+    assert O.true_residual(op, U, b, x) <= RES_SLACK * TOL
+    xo, sto, ito, reso = O.cg(op, U, b, tol=TOL)
+    assert sto == 0
+    print(f"wilson 4^4: gpu {st['iterations']} it, oracle {ito} it, |x-xo|/|xo| = "
+          f"{np.linalg.norm(x - xo) / np.linalg.norm(xo):.2e}")
+    assert abs(st["iterations"] - ito) <= max(3, ito // 20)
+
+
+@pytest.mark.parametrize("sloppy,fmt", [("f64", "L18"), ("f32", "L18"), ("f32", "L12"), ("f16s", "L18"),
+                                        ("f16s", "L12")])
+def test_dwf_cg_modes(gpu, sloppy, fmt):
+    import paper_1512_03487_amd as gm
+    from tests.gpu_util import dev
+    dims, Ls = (4, 4, 4, 8), 8
+    U, b = F.gauge_field(dims, seed=1, kind="haar"), F.spinor_field(dims, seed=3, Ls=Ls)
+    x, st = gm.cg(dev(U), dev(b), kind="dwf", M5=1.8, mf=0.01, tol=TOL, sloppy=sloppy, link_fmt=fmt,
+                  delta=0.1, check_every=5)
+    op = O.Op.dwf(Ls, 1.8, 0.01)
+    res = O.true_residual(op, U, b, x.cpu().numpy())
+    print(f"dwf {sloppy}/{fmt}: {st['iterations']} it, {st['reliable_updates']} reliable updates, "
+          f"kernel residual {st['true_residual']:.2e}, oracle residual {res:.2e}")
+    assert st["converged"] and res <= RES_SLACK * TOL
+
+
+def test_warm_start_and_zero_source(gpu):
+    import torch
+    import paper_1512_03487_amd as gm
+    from tests.gpu_util import dev
+    dims, Ls = (4, 4, 4, 4), 4
+    U, b = F.gauge_field(dims, seed=1, kind="haar"), F.spinor_field(dims, seed=3, Ls=Ls)
+    Ud, bd = dev(U), dev(b)
+    x1, st1 = gm.cg(Ud, bd, kind="dwf", tol=1e-4)
+    x2, st2 = gm.cg(Ud, bd, kind="dwf", tol=TOL, x0=x1)
+    x3, st3 = gm.cg(Ud, bd, kind="dwf", tol=TOL)
+    assert st2["converged"] and st2["iterations"] < st3["iterations"]
+    assert O.true_residual(O.Op.dwf(Ls, 1.8, 0.01), U, b, x2.cpu().numpy()) <= RES_SLACK * TOL
+    z, stz = gm.cg(Ud, torch.zeros_like(bd), kind="dwf", tol=TOL)
+    assert stz["converged"] and stz["iterations"] == 0 and torch.count_nonzero(z) == 0
+
+
+def test_maxiter_and_breakdown_status(gpu):
+    import paper_1512_03487_amd as gm
+    from paper_1512_03487_amd import _lib
+    from tests.gpu_util import dev
+    dims, Ls = (4, 4, 4, 4), 4
+    U, b = F.gauge_field(dims, seed=1, kind="haar"), F.spinor_field(dims, seed=3, Ls=Ls)
+    x, st = gm.cg(dev(U), dev(b), kind="dwf", tol=TOL, maxiter=7, check_every=3, raise_on_fail=False)
+    assert st["status"] == _lib.GRID_ENOCONV and st["iterations"] == 7 and not st["converged"]
+    bad = b.copy()
+    bad[0, 0, 0, 0, 0, 0, 0] = np.nan      # the host-detected breakdown path (NaN residual)
+    x, st = gm.cg(dev(U), dev(bad), kind="dwf", tol=TOL, check_every=2, raise_on_fail=False)
+    assert st["status"] == _lib.GRID_EBREAKDOWN
+    with pytest.raises(_lib.GridError):
+        gm.cg(dev(U), dev(b), kind="dwf", tol=TOL, maxiter=2)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("sloppy", ["f64", "f32", "f16s"])
+def test_config2_dwf_16_4_ls16(gpu, sloppy):
+    """16^4 x 16, M5 = 1.8, mf = 0.01, Haar links: true residual 1e-10, recomputed by the oracle."""
+    import paper_1512_03487_amd as gm
+    from tests.gpu_util import cached, dev
+    dims, Ls = (16, 16, 16, 16), 16
+    U, b = cached("gauge", dims, 1, kind="haar"), cached("spinor", dims, 3, Ls=Ls)
+    x, st = gm.cg(dev(U), dev(b), kind="dwf", M5=1.8, mf=0.01, tol=TOL, sloppy=sloppy,
+                  link_fmt="L12" if sloppy == "f16s" else "L18")
+    res = O.true_residual(O.Op.dwf(Ls, 1.8, 0.01), U, b, x.cpu().numpy())
+    print(f"config2 {sloppy}: {st['iterations']} it, {st['reliable_updates']} RU, {st['seconds']:.3f} s, "
+          f"oracle residual {res:.3e}", flush=True)
+    assert st["converged"] and res <= RES_SLACK * TOL
