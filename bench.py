@@ -1,0 +1,262 @@
+"""Benchmark: Wilson hopping operator GFLOP/s and HBM GB/s on one MI355X, plus the domain-wall CG
+time to a true residual of 1e-10 in FP64 and in mixed precision.
+
+One "step" is one application of the hopping operator H on a 16^4 lattice in FP64 with weak-field
+links exp(0.3 i H) and a Gaussian spinor (1320 flop per site). The timed loop rotates over
+several independent (U, psi, out) buffer sets whose total size exceeds the 256 MB last-level
+cache, so every application streams its inputs from HBM. Further legs (FP32, 32^4, domain wall
+24^4 x 12 in FP32 and FP16 storage, and the CG on 16^4 x 16) are reported alongside.
+
+Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--no-cg] [--no-cpu]
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Dhop GFLOP/s & HBM GB/s (1320 flop/site); DWF CG time-to-1e-10 mixed vs FP64"
+HBM_PEAK_GBS = 8000.0
+FLOPS_HOP = 1320
+# algorithmic bytes per site: read psi once, the 4 links of the site once, write out once
+SPINOR_BYTES = {"f64": 192, "f32": 96, "f16s": 52}
+LINK_BYTES = {("f64", "L18"): 144, ("f64", "L12"): 96, ("f32", "L18"): 72, ("f32", "L12"): 48,
+              ("f16s", "L18"): 36, ("f16s", "L12"): 24}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dhop_f64_16x16x16x16.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1512_03487_amd", "csrc", f) for f in ("dhop.hip", "device.h")]
+
+
+def alg_bytes_per_site(prec: str, fmt: str, Ls: int) -> float:
+    return 2 * SPINOR_BYTES[prec] + 4 * LINK_BYTES[(prec, fmt)] / Ls
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it matches the source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_sets(dims, prec, nsets, seed_u=1, seed_psi=2, kind="weak", Ls=None, fmt="L18"):
+    """nsets device copies of one seeded (U, psi) pair (traffic does not depend on the values)."""
+    import numpy as np
+    import torch
+    import paper_1512_03487_amd as gm
+    from paper_1512_03487_amd import fields
+    dev = torch.device("cuda:0")
+    U = fields.gauge_field(dims, seed=seed_u, kind=kind)
+    psi = fields.spinor_field(dims, seed=seed_psi, Ls=Ls)
+    Ud = torch.from_numpy(U).to(dev)
+    pd = torch.from_numpy(psi).to(dev)
+    if prec == "f64":
+        Uk = Ud if fmt == "L18" else Ud[..., :2, :].contiguous()
+        pk = pd
+    else:
+        Uk = gm.convert_links(Ud, prec, fmt)
+        pk = gm.convert_spinor(pd, prec)
+    del Ud, pd
+    sets = []
+    for _ in range(nsets):
+        if prec == "f16s":
+            p = gm.F16Spinor(pk.codes.clone(), pk.scale.clone())
+            o = gm.F16Spinor(torch.empty_like(pk.codes), torch.empty_like(pk.scale))
+        else:
+            p = pk.clone()
+            o = torch.empty_like(pk)
+        sets.append((Uk.clone(), p, o))
+    torch.cuda.synchronize()
+    return sets, (U, psi)
+
+
+def time_dhop(sets, steps, warmup, kind="hop", **kw):
+    """Average seconds per application over `steps` launches rotating over `sets` (HIP events)."""
+    import torch
+    import paper_1512_03487_amd as gm
+    for i in range(warmup):
+        U, p, o = sets[i % len(sets)]
+        gm.dhop(U, p, kind, out=o, **kw)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for i in range(steps):
+        U, p, o = sets[i % len(sets)]
+        gm.dhop(U, p, kind, out=o, **kw)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) * 1e-3 / steps, wall
+
+
+def leg(dims, prec, fmt, kind, Ls, steps, warmup, min_bytes=600e6):
+    sb = SPINOR_BYTES[prec] * (Ls or 1) * 2 + 4 * LINK_BYTES[(prec, fmt)]
+    vol = dims[0] * dims[1] * dims[2] * dims[3]
+    nsets = max(1, int(min_bytes // (sb * vol)) + 1)
+    sets, _ = make_sets(dims, prec, nsets, kind="haar", Ls=Ls, fmt=fmt)
+    t, _ = time_dhop(sets, steps, warmup, kind=kind, M5=1.8, mf=0.01)
+    n5 = vol * (Ls or 1)
+    gbs = alg_bytes_per_site(prec, fmt, Ls or 1) * n5 / t / 1e9
+    del sets
+    return {"lattice": list(dims), "Ls": Ls or 1, "prec": prec, "links": fmt, "op": kind,
+            "us_per_launch": round(t * 1e6, 2), "gflops": round(FLOPS_HOP * n5 / t / 1e9, 1),
+            "alg_gbs": round(gbs, 1), "roofline_frac": round(gbs / HBM_PEAK_GBS, 4), "buffer_sets": nsets}
+
+
+def cg_legs():
+    import torch
+    import paper_1512_03487_amd as gm
+    from paper_1512_03487_amd import fields
+    dev = torch.device("cuda:0")
+    dims, Ls = (16, 16, 16, 16), 16
+    U = torch.from_numpy(fields.gauge_field(dims, seed=1, kind="haar")).to(dev)
+    b = torch.from_numpy(fields.spinor_field(dims, seed=3, Ls=Ls)).to(dev)
+    out = {"lattice": list(dims), "Ls": Ls, "M5": 1.8, "mf": 0.01, "tol": 1e-10}
+    for name, sloppy, fmt in (("fp64", "f64", "L18"), ("mixed_f32", "f32", "L18"), ("mixed_f16s", "f16s", "L12")):
+        ws = torch.empty(gm.cg_workspace_bytes(b, sloppy=sloppy, link_fmt=fmt), dtype=torch.uint8, device=dev)
+        gm.cg(U, b, kind="dwf", M5=1.8, mf=0.01, tol=1e-10, sloppy=sloppy, link_fmt=fmt, workspace=ws,
+              maxiter=20, raise_on_fail=False)   # warm-up: touches the workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st = gm.cg(U, b, kind="dwf", M5=1.8, mf=0.01, tol=1e-10, sloppy=sloppy, link_fmt=fmt, workspace=ws)
+        torch.cuda.synchronize()
+        out[name] = {"seconds": round(time.perf_counter() - t0, 4), "iterations": st["iterations"],
+                     "reliable_updates": st["reliable_updates"], "true_residual": st["true_residual"],
+                     "converged": st["converged"]}
+        del ws, x
+    out["speedup_mixed_f32"] = round(out["fp64"]["seconds"] / out["mixed_f32"]["seconds"], 2)
+    out["speedup_mixed_f16s"] = round(out["fp64"]["seconds"] / out["mixed_f16s"]["seconds"], 2)
+    return out
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The FP64 oracle's H on the same 16^4 workload, timed on the host cores."""
+    from oracle import oracle as orc
+    from paper_1512_03487_amd import fields
+    dims = (16, 16, 16, 16)
+    U = fields.gauge_field(dims, seed=1, kind="weak")
+    psi = fields.spinor_field(dims, seed=2)
+    orc.hop(U, psi)    # load / warm
+    n, t0 = 0, time.perf_counter()
+    while True:
+        orc.hop(U, psi)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds_target or n >= 200:
+            break
+    vol = 16 ** 4
+    return {"value": round(FLOPS_HOP * vol * n / el / 1e9, 3), "unit": "GFLOP/s", "cores": orc.threads(),
+            "kind": "oracle", "sample": f"{n} applications of H on the 16^4 FP64 workload ({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-legs", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy three times (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (multi-GPU sharding is not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    dims = (16, 16, 16, 16)
+    vol = 16 ** 4
+    nsets = 5                                   # 5 x 63 MB > 256 MB MALL
+    sets, _ = make_sets(dims, "f64", nsets)
+    t, wall = time_dhop(sets, args.steps, args.warmup)
+    del sets
+    if args.calibrate_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    torch.cuda.empty_cache()
+    bytes_launch = alg_bytes_per_site("f64", "L18", 1) * vol
+    achieved = bytes_launch / t / 1e9
+    gflops = FLOPS_HOP * vol / t / 1e9
+
+    legs = {}
+    if not args.no_legs:
+        legs["hop_16^4_f32"] = leg((16, 16, 16, 16), "f32", "L18", "hop", None, 100, 10)
+        legs["hop_16^4_f64_cache_resident"] = None
+        s1, _ = make_sets(dims, "f64", 1)
+        t1, _ = time_dhop(s1, 100, 10)
+        legs["hop_16^4_f64_cache_resident"] = {"us_per_launch": round(t1 * 1e6, 2),
+                                               "gflops": round(FLOPS_HOP * vol / t1 / 1e9, 1),
+                                               "alg_gbs": round(bytes_launch / t1 / 1e9, 1)}
+        del s1
+        legs["hop_32^4_f32"] = leg((32, 32, 32, 32), "f32", "L18", "hop", None, 50, 5)
+        legs["hop_32^4_f32_L12"] = leg((32, 32, 32, 32), "f32", "L12", "hop", None, 50, 5)
+        legs["hop_32^4_f16s_L12"] = leg((32, 32, 32, 32), "f16s", "L12", "hop", None, 50, 5)
+        legs["dwf_24^4x12_f32"] = leg((24, 24, 24, 24), "f32", "L18", "dwf", 12, 20, 3)
+        legs["dwf_24^4x12_f16s_L12"] = leg((24, 24, 24, 24), "f16s", "L12", "dwf", 12, 20, 3)
+        torch.cuda.empty_cache()
+    cg = None if args.no_cg else cg_legs()
+    cpu = None if args.no_cpu else cpu_baseline()
+
+    traffic = measured_traffic()
+    rec = {
+        "metric": METRIC,
+        "value": round(gflops, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Wilson hopping operator H, 16^4 periodic lattice, FP64, weak-field links "
+                               "exp(0.3 i H), Gaussian spinor, repeated applications",
+                   "lattice": list(dims), "links": "L18", "buffer_sets": nsets, "flop_per_site": FLOPS_HOP},
+        "hbm_gbs_algorithmic": round(achieved, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "alg_bytes_per_launch": int(bytes_launch),
+                     "hbm_bytes_per_launch": traffic, "kernel": "k_dhop<SpF64, LkF64<3>, hop>"},
+        "cpu_baseline": cpu,
+        "legs": legs,
+        "cg_dwf_16^4x16": cg,
+        "wall_s_timed": round(wall, 4),
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

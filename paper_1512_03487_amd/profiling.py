@@ -1,0 +1,109 @@
+"""Summaries of rocprofv3 output for the hopping kernels (HBM traffic per launch, kernel times).
+
+rocprofv3's FETCH_SIZE and WRITE_SIZE counters are in KiB per dispatch; on gfx950 they are
+calibrated here against a plain device copy of known size run in the same command (a 256 MiB copy:
+the bytes it must read and write divided by what the counters report).
+
+Usage:
+  python -m paper_1512_03487_amd.profiling traffic FETCH_DIR WRITE_DIR KERNEL_SUBSTR OUT.txt [--cmd "..."]
+  python -m paper_1512_03487_amd.profiling stats KT_DIR OUT.txt [--cmd "..."]
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import os
+import sys
+
+COPY_BYTES = 256 << 20
+COPY_KERNEL = "copyBuffer"
+
+
+def _rows(d):
+    out = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        out += list(csv.DictReader(open(f)))
+    return out
+
+
+def _per_kernel(rows, counter, substr):
+    return [float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == counter and substr in r["Kernel_Name"]]
+
+
+def _calibration_copies(rows, counter):
+    """Counter values of the largest copy dispatches (the 256 MiB calibration copy)."""
+    vals = [float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == counter and COPY_KERNEL in r["Kernel_Name"]]
+    if not vals:
+        return []
+    vmax = max(vals)
+    return [v for v in vals if v >= 0.95 * vmax]
+
+
+def kernel_source_hash(root):
+    h = hashlib.sha256()
+    for f in ("dhop.hip", "device.h"):
+        with open(os.path.join(root, "paper_1512_03487_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic(fetch_dir, write_dir, kernel, out, cmd=""):
+    fr, wr = _rows(fetch_dir), _rows(write_dir)
+    fk, wk = _per_kernel(fr, "FETCH_SIZE", kernel), _per_kernel(wr, "WRITE_SIZE", kernel)
+    fc, wc = _calibration_copies(fr, "FETCH_SIZE"), _calibration_copies(wr, "WRITE_SIZE")
+    if not fk or not wk or not fc or not wc:
+        raise SystemExit("missing kernel or copy dispatches in the counter output")
+    f_factor = COPY_BYTES / (sum(fc) / len(fc) * 1024)
+    w_factor = COPY_BYTES / (sum(wc) / len(wc) * 1024)
+    f_b = sum(fk) / len(fk) * 1024 * f_factor
+    w_b = sum(wk) / len(wk) * 1024 * w_factor
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with open(out, "w") as fh:
+        fh.write(f"# HBM traffic per dispatch of kernels matching '{kernel}' (rocprofv3 --pmc)\n")
+        if cmd:
+            fh.write(f"# command: {cmd}\n")
+        fh.write(f"dispatches_fetch: {len(fk)}\ndispatches_write: {len(wk)}\n")
+        fh.write(f"fetch_kib_per_dispatch_raw: {sum(fk) / len(fk):.1f}\n")
+        fh.write(f"write_kib_per_dispatch_raw: {sum(wk) / len(wk):.1f}\n")
+        fh.write(f"copy_calibration_fetch_factor: {f_factor:.4f}\n")
+        fh.write(f"copy_calibration_write_factor: {w_factor:.4f}\n")
+        fh.write(f"hbm_read_bytes_per_launch: {f_b:.0f}\n")
+        fh.write(f"hbm_write_bytes_per_launch: {w_b:.0f}\n")
+        fh.write(f"hbm_bytes_per_launch: {f_b + w_b:.0f}\n")
+        fh.write(f"source_sha256: {kernel_source_hash(root)}\n")
+    print(open(out).read())
+
+
+def stats(kt_dir, out, cmd=""):
+    files = glob.glob(os.path.join(kt_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no kernel_stats.csv under " + kt_dir)
+    rows = list(csv.DictReader(open(files[0])))
+    with open(out, "w") as fh:
+        fh.write("# rocprofv3 --kernel-trace --stats summary\n")
+        if cmd:
+            fh.write(f"# command: {cmd}\n")
+        fh.write("| kernel | calls | avg us | min us | max us | total % |\n|---|---|---|---|---|---|\n")
+        for r in rows:
+            name = r["Name"]
+            if len(name) > 110:
+                name = name[:110] + "..."
+            fh.write(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                     f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} |\n")
+    print(open(out).read())
+
+
+if __name__ == "__main__":
+    args = sys.argv[1:]
+    cmd = ""
+    if "--cmd" in args:
+        i = args.index("--cmd")
+        cmd = args[i + 1]
+        args = args[:i] + args[i + 2:]
+    if args and args[0] == "traffic":
+        traffic(*args[1:5], cmd=cmd)
+    elif args and args[0] == "stats":
+        stats(*args[1:3], cmd=cmd)
+    else:
+        print(__doc__)
