@@ -46,29 +46,67 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Gather the spinor record `rec` of every lane of the wave through LDS with coalesced 16-byte
-// loads, and decode it into p. All 64 lanes must call this with a valid record index.
+// Coalesced wavefront gather of spinor records through LDS, in two phases so that the global
+// loads of the next gather can be in flight while the current direction computes:
+//   fetch: lane l loads 16-byte chunk c = k*64 + l of the 64 records the wave needs (record
+//          c / chunks, the record index of that lane obtained by a cross-lane shuffle), so
+//          consecutive lanes read consecutive addresses;
+//   stage: the chunks go to padded LDS slots and each lane reads its own record back.
+// All 64 lanes must take part with a valid record index.
+// 16-byte chunk as a native vector type (HIP's uint4 wraps a union, which keeps the in-flight
+// chunks from being promoted to registers).
+typedef unsigned int chunk_t __attribute__((ext_vector_type(4)));
+
 template <class SP>
-__device__ __forceinline__ void gather(const void *__restrict__ base, const float *__restrict__ scale, int rec, uint4 *lds,
-                                       Cx<typename SP::C> p[4][3]) {
+struct Fetch {
+    chunk_t w[SP::kChunks];
+    float s;
+};
+
+template <class SP>
+__device__ __forceinline__ void fetch(const void *__restrict__ base, const float *__restrict__ scale, int rec,
+                                      Fetch<SP> &f) {
     constexpr int CH = SP::kChunks;
-    constexpr int PITCH = CH + 1;   // padded record pitch (16-byte units) against bank conflicts
     const int lane = threadIdx.x & 63;
-    const uint4 *src = reinterpret_cast<const uint4 *>(base);
+    const chunk_t *src = reinterpret_cast<const chunk_t *>(base);
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
         const int c = k * 64 + lane;
         const int r = c / CH, j = c - (c / CH) * CH;
         const int n = __shfl(rec, r, 64);
-        lds[r * PITCH + j] = src[static_cast<size_t>(n) * CH + j];
+        f.w[k] = src[static_cast<size_t>(n) * CH + j];
     }
-    const float s = SP::kScaled ? scale[rec] : 1.0f;
+    f.s = SP::kScaled ? scale[rec] : 1.0f;
+}
+
+template <class SP>
+__device__ __forceinline__ void stage(const Fetch<SP> &f, chunk_t *lds, Cx<typename SP::C> p[4][3]) {
+    constexpr int CH = SP::kChunks;
+    constexpr int PITCH = CH + 1;   // padded record pitch (16-byte units) against bank conflicts
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const int c = k * 64 + lane;
+        const int r = c / CH, j = c - (c / CH) * CH;
+        lds[r * PITCH + j] = f.w[k];
+    }
     wave_sync();
     uint4 w[CH];
 #pragma unroll
-    for (int k = 0; k < CH; ++k) w[k] = lds[lane * PITCH + k];
+    for (int k = 0; k < CH; ++k) {
+        const chunk_t v = lds[lane * PITCH + k];
+        w[k] = make_uint4(v.x, v.y, v.z, v.w);
+    }
     wave_sync();
-    SP::unpack(w, s, p);
+    SP::unpack(w, f.s, p);
+}
+
+template <class SP>
+__device__ __forceinline__ void gather(const void *__restrict__ base, const float *__restrict__ scale, int rec, chunk_t *lds,
+                                       Cx<typename SP::C> p[4][3]) {
+    Fetch<SP> f;
+    fetch<SP>(base, scale, rec, f);
+    stage<SP>(f, lds, p);
 }
 
 // Pin the accumulator in registers at this point of the program. The only use of the result is
@@ -101,8 +139,8 @@ __global__ void __launch_bounds__(256)
 k_dhop(const void *__restrict__ U, const void *__restrict__ psi, const float *__restrict__ psi_scale,
        void *__restrict__ out, float *__restrict__ out_scale, GeomDev g, int T, double diag, double mf) {
     using C = typename SP::C;
-    __shared__ uint4 sm[kWaves][64 * (SP::kChunks + 1)];
-    uint4 *lds = sm[threadIdx.x >> 6];
+    __shared__ chunk_t sm[kWaves][64 * (SP::kChunks + 1)];
+    chunk_t *lds = sm[threadIdx.x >> 6];
 
     const int Ls = g.Ls;
     const int V3 = g.L[0] * g.L[1] * g.L[2];
@@ -132,43 +170,60 @@ k_dhop(const void *__restrict__ U, const void *__restrict__ psi, const float *__
         gather<SP>(psi, psi_scale, t0 * nq + qq, lds, p);
         project<3, -EF>(p, hb);
     }
+    // Records gathered per step, in order: psi(x, t+1), the six spatial neighbours at t, and the
+    // centre psi(x, t) for the Wilson / domain-wall epilogue. The next record's loads are issued
+    // before the current direction computes.
+    constexpr int NREC = (KIND == GRID_HOP) ? 7 : 8;
 #pragma unroll 1
     for (int k = 0; k < T; ++k) {
         const int t = t0 + k;
-        const int tn = (t == Lt - 1) ? 0 : t + 1;
         const int off = t * nq;
         const size_t loff = static_cast<size_t>(t) * V3;
+        const int tn = (t == Lt - 1) ? 0 : t + 1;
+        int rec[NREC];
+        rec[0] = tn * nq + qq;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) rec[1 + d] = off + nb[d] * Ls + s;
+        if (KIND != GRID_HOP) rec[7] = off + qq;
+        Fetch<SP> f;
+        fetch<SP>(psi, psi_scale, rec[0], f);
         Cx<C> acc[4][3];
 #pragma unroll
         for (int j = 0; j < 12; ++j) acc[j / 3][j % 3] = {C(0), C(0)};
         reconstruct_add<3, -EF>(acc, chi_b);
-        // forward t-hop, and the backward t-hop of the next slice from the same link
-        gather<SP>(psi, psi_scale, tn * nq + qq, lds, p);
-        LK::load(U, (loff + col) * 4 + 3, u);
-        hop_term<3, EF, false>(acc, p, u);
-        su3_adj_mul(u, hb, chi_b);
-        project<3, -EF>(p, hb);
-        // x, y, z
-#define GRIDMI_DIR(MU)                                                                       \
-        gather<SP>(psi, psi_scale, off + nb[2 * MU] * Ls + s, lds, p);                        \
-        LK::load(U, (loff + col) * 4 + MU, u);                                                \
-        hop_term<MU, EF, false>(acc, p, u);                                                   \
-        gather<SP>(psi, psi_scale, off + nb[2 * MU + 1] * Ls + s, lds, p);                    \
-        LK::load(U, (loff + nb[2 * MU + 1]) * 4 + MU, u);                                     \
-        hop_term<MU, -EF, true>(acc, p, u);
-        GRIDMI_DIR(0)
-        GRIDMI_DIR(1)
-        GRIDMI_DIR(2)
-#undef GRIDMI_DIR
-        if (KIND != GRID_HOP) {
-            // D = (4 + m) - H/2;  M = (5 - M5) - H/2 - (fifth-dimension hopping)
-            gather<SP>(psi, psi_scale, off + qq, lds, p);
-            const C d = static_cast<C>(diag);
-            const C half = static_cast<C>(0.5);
 #pragma unroll
-            for (int j = 0; j < 12; ++j) {
-                const Cx<C> a = acc[j / 3][j % 3], v = p[j / 3][j % 3];
-                acc[j / 3][j % 3] = {d * v.r - half * a.r, d * v.i - half * a.i};
+        for (int i = 0; i < NREC; ++i) {
+            stage<SP>(f, lds, p);
+            // link of this direction first, then the next record: loads complete in issue order
+            const int mu = (i == 0) ? 3 : (i - 1) / 2;
+            const bool bwd = (i >= 1 && i <= 6 && ((i - 1) & 1));
+            if (i <= 6) LK::load(U, (loff + (bwd ? nb[i - 1] : col)) * 4 + mu, u);
+            if (i + 1 < NREC) fetch<SP>(psi, psi_scale, rec[i + 1], f);
+            if (i == 0) {
+                hop_term<3, EF, false>(acc, p, u);
+                su3_adj_mul(u, hb, chi_b);       // backward t-hop of the next slice, same link
+                project<3, -EF>(p, hb);
+            } else if (i == 1) {
+                hop_term<0, EF, false>(acc, p, u);
+            } else if (i == 2) {
+                hop_term<0, -EF, true>(acc, p, u);
+            } else if (i == 3) {
+                hop_term<1, EF, false>(acc, p, u);
+            } else if (i == 4) {
+                hop_term<1, -EF, true>(acc, p, u);
+            } else if (i == 5) {
+                hop_term<2, EF, false>(acc, p, u);
+            } else if (i == 6) {
+                hop_term<2, -EF, true>(acc, p, u);
+            } else {
+                // D = (4 + m) - H/2;  M = (5 - M5) - H/2 - (fifth-dimension hopping)
+                const C dg = static_cast<C>(diag);
+                const C half = static_cast<C>(0.5);
+#pragma unroll
+                for (int j = 0; j < 12; ++j) {
+                    const Cx<C> a = acc[j / 3][j % 3], v = p[j / 3][j % 3];
+                    acc[j / 3][j % 3] = {dg * v.r - half * a.r, dg * v.i - half * a.i};
+                }
             }
         }
         if (KIND == GRID_DWF) {
