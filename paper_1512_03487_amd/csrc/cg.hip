@@ -2,7 +2,7 @@
 // in mixed precision with reliable updates (sloppy FP32 / FP16-storage iterations, FP64 solution,
 // source and true residuals).
 //
-// Device side: per-site vector kernels (24 reals per site) fused as
+// Device side: streaming vector kernels fused as
 //   dot:       <p, q>                                  -> per-block FP64 partial sums
 //   update_xr: alpha = rho / <p,q>; x += alpha p; r -= alpha q; |r|^2 partials
 //   update_p:  beta = |r_new|^2 / |r_old|^2; p = r + beta p
@@ -16,6 +16,7 @@
 // residual fell below delta times its maximum since the last update, or below the target.
 // The solve stops only on an FP64 true residual <= tol |b|.
 #include <chrono>
+#include <type_traits>
 #include <math.h>
 #include <string.h>
 
@@ -43,34 +44,41 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ part, 
     return block_sum(v, sm);
 }
 
-template <class SA, class SB>
+// ---------------------------------------------------------------------------------------------
+// Streaming vector kernels. FP64 and FP32 vectors have no per-site structure the update needs, so
+// they are processed as flat arrays of 16-byte chunks (one complex double or two complex floats):
+// consecutive lanes touch consecutive 16 bytes. FP16-storage vectors are processed in units of
+// one 16-byte code chunk (4 complex numbers, a third of a site) with 21 sites (63 lanes) per
+// wavefront, so the three lanes of a site can agree on the site's new scale when re-encoding.
+// ---------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ double dot2(double2 a, double2 b) { return a.x * b.x + a.y * b.y; }
+__device__ __forceinline__ double dot2(float4 a, float4 b) {
+    return double(a.x) * double(b.x) + double(a.y) * double(b.y) + double(a.z) * double(b.z) + double(a.w) * double(b.w);
+}
+__device__ __forceinline__ double2 axpy2(double al, double2 x, double2 y) { return make_double2(y.x + al * x.x, y.y + al * x.y); }
+__device__ __forceinline__ float4 axpy2(double al, float4 x, float4 y) {
+    const float a = static_cast<float>(al);
+    return make_float4(y.x + a * x.x, y.y + a * x.y, y.z + a * x.z, y.w + a * x.w);
+}
+
+template <typename V>
 __global__ void __launch_bounds__(kThreads)
-k_dot(const void *__restrict__ a, const float *__restrict__ as, const void *__restrict__ b, const float *__restrict__ bs,
-      int n, double *__restrict__ part) {
+k_dot_flat(const V *__restrict__ a, const V *__restrict__ b, long n, double *__restrict__ part) {
     __shared__ double sm[4];
     double acc = 0.0;
-    for (int site = blockIdx.x * kThreads + threadIdx.x; site < n; site += gridDim.x * kThreads) {
-        Cx<typename SA::C> x[4][3];
-        Cx<typename SB::C> y[4][3];
-        SA::load(a, as, site, x);
-        SB::load(b, bs, site, y);
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < 12; ++k)
-            s += double(x[k / 3][k % 3].r) * double(y[k / 3][k % 3].r) + double(x[k / 3][k % 3].i) * double(y[k / 3][k % 3].i);
-        acc += s;
-    }
+    for (long i = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * kThreads)
+        acc += dot2(a[i], b[i]);
     const double t = block_sum(acc, sm);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // alpha = sum(rr_prev) / sum(pq); x += alpha p; r -= alpha q; rr_new = |r|^2 partials.
-template <class SX, class SP, class SR, class SQ>
+template <typename V>
 __global__ void __launch_bounds__(kThreads)
-k_update_xr(void *__restrict__ x, const void *__restrict__ p, const float *__restrict__ ps, void *__restrict__ r,
-            float *__restrict__ rs, const void *__restrict__ q, const float *__restrict__ qs, int n,
-            const double *__restrict__ rr_prev, const double *__restrict__ pq_part, int np, double *__restrict__ rr_new,
-            double *__restrict__ scal) {
+k_update_xr_flat(V *__restrict__ x, const V *__restrict__ p, V *__restrict__ r, const V *__restrict__ q, long n,
+                 const double *__restrict__ rr_prev, const double *__restrict__ pq_part, int np, double *__restrict__ rr_new,
+                 double *__restrict__ scal) {
     __shared__ double sm[4];
     const double rho = sum_partials(rr_prev, np, sm);
     const double pq = sum_partials(pq_part, np, sm);
@@ -81,47 +89,21 @@ k_update_xr(void *__restrict__ x, const void *__restrict__ p, const float *__res
         scal[2] = rho;
     }
     double acc = 0.0;
-    for (int site = blockIdx.x * kThreads + threadIdx.x; site < n; site += gridDim.x * kThreads) {
-        using CX = typename SX::C;
-        using CR = typename SR::C;
-        Cx<CX> xv[4][3];
-        Cx<typename SP::C> pv[4][3];
-        Cx<CR> rv[4][3];
-        Cx<typename SQ::C> qv[4][3];
-        SX::load(x, nullptr, site, xv);
-        SP::load(p, ps, site, pv);
-        SR::load(r, rs, site, rv);
-        SQ::load(q, qs, site, qv);
-        const CX ax = static_cast<CX>(alpha);
-        const CR ar = static_cast<CR>(alpha);
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            Cx<CX> &xx = xv[k / 3][k % 3];
-            Cx<CR> &rr = rv[k / 3][k % 3];
-            xx.r += ax * static_cast<CX>(pv[k / 3][k % 3].r);
-            xx.i += ax * static_cast<CX>(pv[k / 3][k % 3].i);
-            rr.r -= ar * static_cast<CR>(qv[k / 3][k % 3].r);
-            rr.i -= ar * static_cast<CR>(qv[k / 3][k % 3].i);
-        }
-        SX::store(x, nullptr, site, xv);
-        SR::store(r, rs, site, rv);
-        // the norm is taken of the stored (possibly FP16-coded) residual
-        if (SR::kBytes == 52) SR::load(r, rs, site, rv);
-#pragma unroll
-        for (int k = 0; k < 12; ++k)
-            s += double(rv[k / 3][k % 3].r) * double(rv[k / 3][k % 3].r) + double(rv[k / 3][k % 3].i) * double(rv[k / 3][k % 3].i);
-        acc += s;
+    for (long i = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * kThreads) {
+        x[i] = axpy2(alpha, p[i], x[i]);
+        const V rn = axpy2(-alpha, q[i], r[i]);
+        r[i] = rn;
+        acc += dot2(rn, rn);
     }
     const double t = block_sum(acc, sm);
     if (threadIdx.x == 0) rr_new[blockIdx.x] = t;
 }
 
 // beta = sum(rr_new) / sum(rr_prev); p = r + beta p.
-template <class SR, class SP>
+template <typename V>
 __global__ void __launch_bounds__(kThreads)
-k_update_p(const void *__restrict__ r, const float *__restrict__ rs, void *__restrict__ p, float *__restrict__ ps, int n,
-           const double *__restrict__ rr_prev, const double *__restrict__ rr_new, int np, double *__restrict__ scal) {
+k_update_p_flat(const V *__restrict__ r, V *__restrict__ p, long n, const double *__restrict__ rr_prev,
+                const double *__restrict__ rr_new, int np, double *__restrict__ scal) {
     __shared__ double sm[4];
     const double rho = sum_partials(rr_prev, np, sm);
     const double rn = sum_partials(rr_new, np, sm);
@@ -130,81 +112,250 @@ k_update_p(const void *__restrict__ r, const float *__restrict__ rs, void *__res
         scal[3] = beta;
         scal[4] = rn;
     }
-    using CP = typename SP::C;
-    const CP b = static_cast<CP>(beta);
-    for (int site = blockIdx.x * kThreads + threadIdx.x; site < n; site += gridDim.x * kThreads) {
-        Cx<typename SR::C> rv[4][3];
-        Cx<CP> pv[4][3];
-        SR::load(r, rs, site, rv);
-        SP::load(p, ps, site, pv);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            pv[k / 3][k % 3].r = static_cast<CP>(rv[k / 3][k % 3].r) + b * pv[k / 3][k % 3].r;
-            pv[k / 3][k % 3].i = static_cast<CP>(rv[k / 3][k % 3].i) + b * pv[k / 3][k % 3].i;
-        }
-        SP::store(p, ps, site, pv);
+    for (long i = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * kThreads)
+        p[i] = axpy2(beta, p[i], r[i]);
+}
+
+// r = b - q in FP64 (flat, one complex per chunk), |r|^2 partials.
+__global__ void __launch_bounds__(kThreads)
+k_residual_f64(const double2 *__restrict__ b, const double2 *__restrict__ q, double2 *__restrict__ r, long n,
+               double *__restrict__ part) {
+    __shared__ double sm[4];
+    double acc = 0.0;
+    for (long i = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * kThreads) {
+        const double2 bv = b[i], qv = q[i];
+        const double2 rv = make_double2(bv.x - qv.x, bv.y - qv.y);
+        r[i] = rv;
+        acc += dot2(rv, rv);
+    }
+    const double t = block_sum(acc, sm);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// r = b - q in FP64 plus FP32 copies lo (and lo2) of r; chunk i covers two complex numbers.
+__global__ void __launch_bounds__(kThreads)
+k_residual_f32lo(const double2 *__restrict__ b, const double2 *__restrict__ q, double2 *__restrict__ r, float4 *__restrict__ lo,
+                 float4 *__restrict__ lo2, long n, double *__restrict__ part, double *__restrict__ part_lo) {
+    __shared__ double sm[4];
+    double acc = 0.0, acc_lo = 0.0;
+    for (long i = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * kThreads) {
+        const double2 b0 = b[2 * i], b1 = b[2 * i + 1], q0 = q[2 * i], q1 = q[2 * i + 1];
+        const double2 r0 = make_double2(b0.x - q0.x, b0.y - q0.y), r1 = make_double2(b1.x - q1.x, b1.y - q1.y);
+        r[2 * i] = r0;
+        r[2 * i + 1] = r1;
+        acc += dot2(r0, r0) + dot2(r1, r1);
+        const float4 l = make_float4(static_cast<float>(r0.x), static_cast<float>(r0.y), static_cast<float>(r1.x),
+                                     static_cast<float>(r1.y));
+        lo[i] = l;
+        if (lo2) lo2[i] = l;
+        acc_lo += dot2(l, l);
+    }
+    double t = block_sum(acc, sm);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+    t = block_sum(acc_lo, sm);
+    if (threadIdx.x == 0) part_lo[blockIdx.x] = t;
+}
+
+// x += x_hat (FP32), x_hat = 0; chunk i of x_hat covers two complex numbers of x.
+__global__ void __launch_bounds__(kThreads) k_accum_x(double2 *__restrict__ x, float4 *__restrict__ xh, long n) {
+    for (long i = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * kThreads) {
+        const float4 h = xh[i];
+        const double2 x0 = x[2 * i], x1 = x[2 * i + 1];
+        x[2 * i] = make_double2(x0.x + double(h.x), x0.y + double(h.y));
+        x[2 * i + 1] = make_double2(x1.x + double(h.z), x1.y + double(h.w));
+        xh[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
 }
 
-// r = b - q (FP64) with |r|^2 partials; optionally also copy r into `lo` (and its norm partials).
-template <class SL>
+// ---- FP16 storage: units of 8 halves (4 complex) + the site scale ----
+
+__device__ __forceinline__ void unit_decode(uint4 w, float s, float v[8]) {
+    const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        v[2 * j] = half_bits_to_float(ww[j] & 0xffffu) * s;
+        v[2 * j + 1] = half_bits_to_float(ww[j] >> 16) * s;
+    }
+}
+
+// Encode a unit with the site maximum taken over the three lanes 3r..3r+2 of the site (all 64
+// lanes execute the shuffles); returns the code chunk and the site scale.
+__device__ __forceinline__ uint4 unit_encode(const float v[8], float &site_max) {
+    float m = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) m = fmaxf(m, fabsf(v[j]));
+    const int lane = threadIdx.x & 63, r3 = 3 * (lane / 3);
+    m = fmaxf(__shfl(m, r3, 64), fmaxf(__shfl(m, r3 + 1, 64), __shfl(m, r3 + 2, 64)));
+    site_max = m;
+    const float inv = m > 0.f ? 1.0f / m : 0.f;
+    uint32_t w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[j] = scaled_half_bits(v[2 * j], inv) | (scaled_half_bits(v[2 * j + 1], inv) << 16);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Unit position in the FP16 kernels' loop: 21 sites per wavefront, unit = site * 3 + lane % 3;
+// lane 63 (and lanes past the last site) shadow a valid unit but store nothing.
+struct UnitPos {
+    long su, unit;
+    int sub;
+    bool ok;
+};
+
+__device__ __forceinline__ UnitPos unit_pos(long sb, long nsites) {
+    const int lane = threadIdx.x & 63;
+    const long site = sb + lane / 3;
+    UnitPos u;
+    u.ok = lane < 63 && site < nsites;
+    u.su = u.ok ? site : sb;
+    u.sub = lane < 63 ? lane % 3 : 0;
+    u.unit = u.su * 3 + u.sub;
+    return u;
+}
+
+__device__ __forceinline__ long unit_first() {
+    return (static_cast<long>(blockIdx.x) * (kThreads / 64) + (threadIdx.x >> 6)) * 21;
+}
+__device__ __forceinline__ long unit_stride() { return static_cast<long>(gridDim.x) * (kThreads / 64) * 21; }
+
 __global__ void __launch_bounds__(kThreads)
-k_residual(const void *__restrict__ b, const void *__restrict__ q, void *__restrict__ r, int n, double *__restrict__ part,
-           void *__restrict__ lo, float *__restrict__ los, void *__restrict__ lo2, float *__restrict__ lo2s,
-           double *__restrict__ part_lo) {
+k_dot_f16(const uint4 *__restrict__ a, const float *__restrict__ as, const uint4 *__restrict__ b, const float *__restrict__ bs,
+          long nsites, double *__restrict__ part) {
+    __shared__ double sm[4];
+    double acc = 0.0;
+    for (long u = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; u < nsites * 3; u += static_cast<long>(gridDim.x) * kThreads) {
+        float va[8], vb[8];
+        unit_decode(a[u], as[u / 3], va);
+        unit_decode(b[u], bs[u / 3], vb);
+        double d = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) d += double(va[j]) * double(vb[j]);
+        acc += d;
+    }
+    const double t = block_sum(acc, sm);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// alpha = sum(rr_prev) / sum(pq); x_hat (FP32) += alpha p; r -= alpha q (FP16 re-encoded).
+__global__ void __launch_bounds__(kThreads)
+k_update_xr_f16(float4 *__restrict__ xh, const uint4 *__restrict__ p, const float *__restrict__ ps, uint4 *__restrict__ r,
+                float *__restrict__ rs, const uint4 *__restrict__ q, const float *__restrict__ qs, long nsites,
+                const double *__restrict__ rr_prev, const double *__restrict__ pq_part, int np, double *__restrict__ rr_new,
+                double *__restrict__ scal) {
+    __shared__ double sm[4];
+    const double rho = sum_partials(rr_prev, np, sm);
+    const double pq = sum_partials(pq_part, np, sm);
+    const double alpha = rho / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        scal[0] = alpha;
+        scal[1] = pq;
+        scal[2] = rho;
+    }
+    const float al = static_cast<float>(alpha);
+    double acc = 0.0;
+    for (long sb = unit_first(); sb < nsites; sb += unit_stride()) {
+        const UnitPos u = unit_pos(sb, nsites);
+        float pv[8], rv[8], qv[8];
+        unit_decode(p[u.unit], ps[u.su], pv);
+        unit_decode(r[u.unit], rs[u.su], rv);
+        unit_decode(q[u.unit], qs[u.su], qv);
+        float4 x0 = xh[2 * u.unit], x1 = xh[2 * u.unit + 1];
+        x0 = make_float4(x0.x + al * pv[0], x0.y + al * pv[1], x0.z + al * pv[2], x0.w + al * pv[3]);
+        x1 = make_float4(x1.x + al * pv[4], x1.y + al * pv[5], x1.z + al * pv[6], x1.w + al * pv[7]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) rv[j] -= al * qv[j];
+        float m;
+        const uint4 code = unit_encode(rv, m);
+        if (u.ok) {
+            xh[2 * u.unit] = x0;
+            xh[2 * u.unit + 1] = x1;
+            r[u.unit] = code;
+            if (u.sub == 0) rs[u.su] = m;
+            // the norm is taken of the stored (coded) residual
+            float dv[8];
+            unit_decode(code, m, dv);
+            double d = 0.0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) d += double(dv[j]) * double(dv[j]);
+            acc += d;
+        }
+    }
+    const double t = block_sum(acc, sm);
+    if (threadIdx.x == 0) rr_new[blockIdx.x] = t;
+}
+
+// beta = sum(rr_new) / sum(rr_prev); p = r + beta p (FP16 re-encoded).
+__global__ void __launch_bounds__(kThreads)
+k_update_p_f16(const uint4 *__restrict__ r, const float *__restrict__ rs, uint4 *__restrict__ p, float *__restrict__ ps,
+               long nsites, const double *__restrict__ rr_prev, const double *__restrict__ rr_new, int np,
+               double *__restrict__ scal) {
+    __shared__ double sm[4];
+    const double rho = sum_partials(rr_prev, np, sm);
+    const double rn = sum_partials(rr_new, np, sm);
+    const double beta = rn / rho;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        scal[3] = beta;
+        scal[4] = rn;
+    }
+    const float be = static_cast<float>(beta);
+    for (long sb = unit_first(); sb < nsites; sb += unit_stride()) {
+        const UnitPos u = unit_pos(sb, nsites);
+        float pv[8], rv[8];
+        unit_decode(p[u.unit], ps[u.su], pv);
+        unit_decode(r[u.unit], rs[u.su], rv);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) pv[j] = rv[j] + be * pv[j];
+        float m;
+        const uint4 code = unit_encode(pv, m);
+        if (u.ok) {
+            p[u.unit] = code;
+            if (u.sub == 0) ps[u.su] = m;
+        }
+    }
+}
+
+// r = b - q (FP64) with |r|^2 partials, and FP16 copies lo (and lo2) with |lo|^2 partials.
+__global__ void __launch_bounds__(kThreads)
+k_residual_f16lo(const double2 *__restrict__ b, const double2 *__restrict__ q, double2 *__restrict__ r, uint4 *__restrict__ lo,
+                 float *__restrict__ los, uint4 *__restrict__ lo2, float *__restrict__ lo2s, long nsites,
+                 double *__restrict__ part, double *__restrict__ part_lo) {
     __shared__ double sm[4];
     double acc = 0.0, acc_lo = 0.0;
-    for (int site = blockIdx.x * kThreads + threadIdx.x; site < n; site += gridDim.x * kThreads) {
-        Cx<double> bv[4][3], qv[4][3];
-        SpF64::load(b, nullptr, site, bv);
-        SpF64::load(q, nullptr, site, qv);
-        double s = 0.0;
+    for (long sb = unit_first(); sb < nsites; sb += unit_stride()) {
+        const UnitPos u = unit_pos(sb, nsites);
+        float v[8];
+        double d = 0.0;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            bv[k / 3][k % 3] = csub(bv[k / 3][k % 3], qv[k / 3][k % 3]);
-            s += bv[k / 3][k % 3].r * bv[k / 3][k % 3].r + bv[k / 3][k % 3].i * bv[k / 3][k % 3].i;
+        for (int j = 0; j < 4; ++j) {
+            const double2 bv = b[4 * u.unit + j], qv = q[4 * u.unit + j];
+            const double2 rv = make_double2(bv.x - qv.x, bv.y - qv.y);
+            if (u.ok) r[4 * u.unit + j] = rv;
+            d += dot2(rv, rv);
+            v[2 * j] = static_cast<float>(rv.x);
+            v[2 * j + 1] = static_cast<float>(rv.y);
         }
-        acc += s;
-        SpF64::store(r, nullptr, site, bv);
-        if (lo) {
-            using CL = typename SL::C;
-            Cx<CL> lv[4][3];
+        float m;
+        const uint4 code = unit_encode(v, m);
+        if (u.ok) {
+            acc += d;
+            lo[u.unit] = code;
+            if (u.sub == 0) los[u.su] = m;
+            if (lo2) {
+                lo2[u.unit] = code;
+                if (u.sub == 0) lo2s[u.su] = m;
+            }
+            float dv[8];
+            unit_decode(code, m, dv);
+            double dl = 0.0;
 #pragma unroll
-            for (int k = 0; k < 12; ++k) lv[k / 3][k % 3] = {static_cast<CL>(bv[k / 3][k % 3].r), static_cast<CL>(bv[k / 3][k % 3].i)};
-            SL::store(lo, los, site, lv);
-            if (lo2) SL::store(lo2, lo2s, site, lv);
-            SL::load(lo, los, site, lv);
-            double sl = 0.0;
-#pragma unroll
-            for (int k = 0; k < 12; ++k)
-                sl += double(lv[k / 3][k % 3].r) * double(lv[k / 3][k % 3].r) + double(lv[k / 3][k % 3].i) * double(lv[k / 3][k % 3].i);
-            acc_lo += sl;
+            for (int j = 0; j < 8; ++j) dl += double(dv[j]) * double(dv[j]);
+            acc_lo += dl;
         }
     }
     double t = block_sum(acc, sm);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
-    if (lo) {
-        t = block_sum(acc_lo, sm);
-        if (threadIdx.x == 0) part_lo[blockIdx.x] = t;
-    }
-}
-
-// x += x_hat (FP32), x_hat = 0.
-__global__ void __launch_bounds__(kThreads) k_accum_x(void *__restrict__ x, void *__restrict__ xh, int n) {
-    for (int site = blockIdx.x * kThreads + threadIdx.x; site < n; site += gridDim.x * kThreads) {
-        Cx<double> xv[4][3];
-        Cx<float> hv[4][3];
-        SpF64::load(x, nullptr, site, xv);
-        SpF32::load(xh, nullptr, site, hv);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            xv[k / 3][k % 3].r += double(hv[k / 3][k % 3].r);
-            xv[k / 3][k % 3].i += double(hv[k / 3][k % 3].i);
-            hv[k / 3][k % 3] = {0.f, 0.f};
-        }
-        SpF64::store(x, nullptr, site, xv);
-        SpF32::store(xh, nullptr, site, hv);
-    }
+    t = block_sum(acc_lo, sm);
+    if (threadIdx.x == 0) part_lo[blockIdx.x] = t;
 }
 
 // Final sum of partials into scal[slot] (one block).
@@ -213,6 +364,79 @@ __global__ void __launch_bounds__(kThreads) k_sum(const double *__restrict__ par
     const double t = sum_partials(part, np, sm);
     if (threadIdx.x == 0) scal[slot] = t;
 }
+
+// Launch helpers per sloppy precision (FP64 mode uses SpF64 for everything).
+template <class SH>
+struct Vec;
+
+template <>
+struct Vec<SpF64> {
+    static void dot(dim3 g, hipStream_t st, const void *a, const float *, const void *b, const float *, long n5, double *part) {
+        hipLaunchKernelGGL(k_dot_flat<double2>, g, dim3(kThreads), 0, st, static_cast<const double2 *>(a),
+                           static_cast<const double2 *>(b), n5 * 12, part);
+    }
+    static void update_xr(dim3 g, hipStream_t st, void *x, const void *p, const float *, void *r, float *, const void *q,
+                          const float *, long n5, const double *rrp, const double *pq, int np, double *rrn, double *scal) {
+        hipLaunchKernelGGL(k_update_xr_flat<double2>, g, dim3(kThreads), 0, st, static_cast<double2 *>(x),
+                           static_cast<const double2 *>(p), static_cast<double2 *>(r), static_cast<const double2 *>(q), n5 * 12,
+                           rrp, pq, np, rrn, scal);
+    }
+    static void update_p(dim3 g, hipStream_t st, const void *r, const float *, void *p, float *, long n5, const double *rrp,
+                         const double *rrn, int np, double *scal) {
+        hipLaunchKernelGGL(k_update_p_flat<double2>, g, dim3(kThreads), 0, st, static_cast<const double2 *>(r),
+                           static_cast<double2 *>(p), n5 * 12, rrp, rrn, np, scal);
+    }
+};
+
+template <>
+struct Vec<SpF32> {
+    static void dot(dim3 g, hipStream_t st, const void *a, const float *, const void *b, const float *, long n5, double *part) {
+        hipLaunchKernelGGL(k_dot_flat<float4>, g, dim3(kThreads), 0, st, static_cast<const float4 *>(a),
+                           static_cast<const float4 *>(b), n5 * 6, part);
+    }
+    static void update_xr(dim3 g, hipStream_t st, void *x, const void *p, const float *, void *r, float *, const void *q,
+                          const float *, long n5, const double *rrp, const double *pq, int np, double *rrn, double *scal) {
+        hipLaunchKernelGGL(k_update_xr_flat<float4>, g, dim3(kThreads), 0, st, static_cast<float4 *>(x),
+                           static_cast<const float4 *>(p), static_cast<float4 *>(r), static_cast<const float4 *>(q), n5 * 6, rrp,
+                           pq, np, rrn, scal);
+    }
+    static void update_p(dim3 g, hipStream_t st, const void *r, const float *, void *p, float *, long n5, const double *rrp,
+                         const double *rrn, int np, double *scal) {
+        hipLaunchKernelGGL(k_update_p_flat<float4>, g, dim3(kThreads), 0, st, static_cast<const float4 *>(r),
+                           static_cast<float4 *>(p), n5 * 6, rrp, rrn, np, scal);
+    }
+    static void residual_lo(dim3 g, hipStream_t st, const void *b, const void *q, void *r, void *lo, float *, void *lo2,
+                            float *, long n5, double *part, double *part_lo) {
+        hipLaunchKernelGGL(k_residual_f32lo, g, dim3(kThreads), 0, st, static_cast<const double2 *>(b),
+                           static_cast<const double2 *>(q), static_cast<double2 *>(r), static_cast<float4 *>(lo),
+                           static_cast<float4 *>(lo2), n5 * 6, part, part_lo);
+    }
+};
+
+template <>
+struct Vec<SpF16S> {
+    static void dot(dim3 g, hipStream_t st, const void *a, const float *as, const void *b, const float *bs, long n5,
+                    double *part) {
+        hipLaunchKernelGGL(k_dot_f16, g, dim3(kThreads), 0, st, static_cast<const uint4 *>(a), as,
+                           static_cast<const uint4 *>(b), bs, n5, part);
+    }
+    static void update_xr(dim3 g, hipStream_t st, void *x, const void *p, const float *ps, void *r, float *rs, const void *q,
+                          const float *qs, long n5, const double *rrp, const double *pq, int np, double *rrn, double *scal) {
+        hipLaunchKernelGGL(k_update_xr_f16, g, dim3(kThreads), 0, st, static_cast<float4 *>(x), static_cast<const uint4 *>(p),
+                           ps, static_cast<uint4 *>(r), rs, static_cast<const uint4 *>(q), qs, n5, rrp, pq, np, rrn, scal);
+    }
+    static void update_p(dim3 g, hipStream_t st, const void *r, const float *rs, void *p, float *ps, long n5,
+                         const double *rrp, const double *rrn, int np, double *scal) {
+        hipLaunchKernelGGL(k_update_p_f16, g, dim3(kThreads), 0, st, static_cast<const uint4 *>(r), rs,
+                           static_cast<uint4 *>(p), ps, n5, rrp, rrn, np, scal);
+    }
+    static void residual_lo(dim3 g, hipStream_t st, const void *b, const void *q, void *r, void *lo, float *los, void *lo2,
+                            float *lo2s, long n5, double *part, double *part_lo) {
+        hipLaunchKernelGGL(k_residual_f16lo, g, dim3(kThreads), 0, st, static_cast<const double2 *>(b),
+                           static_cast<const double2 *>(q), static_cast<double2 *>(r), static_cast<uint4 *>(lo), los,
+                           static_cast<uint4 *>(lo2), lo2s, n5, part, part_lo);
+    }
+};
 
 // --------------------------------------------------------------------------------------------
 // Workspace layout
@@ -362,7 +586,7 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
     hipError_t err;
 
     // |b|
-    hipLaunchKernelGGL((k_dot<SpF64, SpF64>), grid, block, 0, c.st, c.b, nullptr, c.b, nullptr, n, ptrue);
+    Vec<SpF64>::dot(grid, c.st, c.b, nullptr, c.b, nullptr, n, ptrue);
     HIPCHK(hipGetLastError());
     const double bnorm = sqrt(read_scalar(c, ptrue, np, scal, 8, &err));
     HIPCHK(err);
@@ -384,22 +608,24 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
     auto true_residual = [&](bool to_lo, int parity) -> hipError_t {
         HIPCHK(apply_op(c, c.U, GRID_F64, GRID_L18, c.x, nullptr, t, nullptr, 0));
         HIPCHK(apply_op(c, c.U, GRID_F64, GRID_L18, t, nullptr, q, nullptr, 1));
-        if (mixed) {
-            hipLaunchKernelGGL((k_residual<SH>), grid, block, 0, c.st, c.b, q, r, n, ptrue, to_lo ? rh : nullptr,
-                               to_lo ? rhs : nullptr, nullptr, nullptr, rr[parity]);
+        if (mixed && to_lo) {
+            if constexpr (!std::is_same<SH, SpF64>::value)
+                Vec<SH>::residual_lo(grid, c.st, c.b, q, r, rh, rhs, nullptr, nullptr, n, ptrue, rr[parity]);
         } else {
-            hipLaunchKernelGGL((k_residual<SpF64>), grid, block, 0, c.st, c.b, q, r, n, to_lo ? rr[parity] : ptrue,
-                               nullptr, nullptr, nullptr, nullptr, nullptr);
+            hipLaunchKernelGGL(k_residual_f64, grid, block, 0, c.st, static_cast<const double2 *>(c.b),
+                               static_cast<const double2 *>(q), static_cast<double2 *>(r), static_cast<long>(n) * 12,
+                               (!mixed && to_lo) ? rr[parity] : ptrue);
         }
         return hipGetLastError();
     };
     HIPCHK(apply_op(c, c.U, GRID_F64, GRID_L18, c.x, nullptr, t, nullptr, 0));
     HIPCHK(apply_op(c, c.U, GRID_F64, GRID_L18, t, nullptr, q, nullptr, 1));
     if (mixed) {
-        hipLaunchKernelGGL((k_residual<SH>), grid, block, 0, c.st, c.b, q, r, n, ptrue, rh, rhs, ph, phs, rr[1]);
+        if constexpr (!std::is_same<SH, SpF64>::value)
+            Vec<SH>::residual_lo(grid, c.st, c.b, q, r, rh, rhs, ph, phs, n, ptrue, rr[1]);
     } else {
-        hipLaunchKernelGGL((k_residual<SpF64>), grid, block, 0, c.st, c.b, q, r, n, rr[1], nullptr, nullptr, nullptr,
-                           nullptr, nullptr);
+        hipLaunchKernelGGL(k_residual_f64, grid, block, 0, c.st, static_cast<const double2 *>(c.b),
+                           static_cast<const double2 *>(q), static_cast<double2 *>(r), static_cast<long>(n) * 12, rr[1]);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(ph, r, static_cast<size_t>(n) * 192, hipMemcpyDeviceToDevice, c.st));
     }
@@ -416,14 +642,9 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
         // q_hat = A_lo p_hat
         HIPCHK(apply_op(c, ulo, c.sloppy, lo_fmt, ph, phs, th, ths, 0));
         HIPCHK(apply_op(c, ulo, c.sloppy, lo_fmt, th, ths, qh, qhs, 1));
-        hipLaunchKernelGGL((k_dot<SH, SH>), grid, block, 0, c.st, ph, phs, qh, qhs, n, pq);
+        Vec<SH>::dot(grid, c.st, ph, phs, qh, qhs, n, pq);
         HIPCHK(hipGetLastError());
-        if (mixed)
-            hipLaunchKernelGGL((k_update_xr<SpF32, SH, SH, SH>), grid, block, 0, c.st, xh, ph, phs, rh, rhs, qh, qhs, n,
-                               rr[P ^ 1], pq, np, rr[P], scal);
-        else
-            hipLaunchKernelGGL((k_update_xr<SpF64, SpF64, SpF64, SpF64>), grid, block, 0, c.st, c.x, ph, nullptr, rh,
-                               nullptr, qh, nullptr, n, rr[P ^ 1], pq, np, rr[P], scal);
+        Vec<SH>::update_xr(grid, c.st, mixed ? xh : c.x, ph, phs, rh, rhs, qh, qhs, n, rr[P ^ 1], pq, np, rr[P], scal);
         HIPCHK(hipGetLastError());
         ++it;
         if (it % check == 0 || it == c.maxiter) {
@@ -440,7 +661,8 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
             if (small || (mixed && rn < c.delta * maxr)) {
                 // reliable update / residual replacement in FP64
                 if (mixed) {
-                    hipLaunchKernelGGL(k_accum_x, grid, block, 0, c.st, c.x, xh, n);
+                    hipLaunchKernelGGL(k_accum_x, grid, block, 0, c.st, static_cast<double2 *>(c.x),
+                                       static_cast<float4 *>(xh), static_cast<long>(n) * 6);
                     HIPCHK(hipGetLastError());
                 }
                 HIPCHK(true_residual(true, P));
@@ -454,11 +676,12 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
                 maxr = rtrue;
             }
         }
-        hipLaunchKernelGGL((k_update_p<SH, SH>), grid, block, 0, c.st, rh, rhs, ph, phs, n, rr[P ^ 1], rr[P], np, scal);
+        Vec<SH>::update_p(grid, c.st, rh, rhs, ph, phs, n, rr[P ^ 1], rr[P], np, scal);
         HIPCHK(hipGetLastError());
     }
     if (mixed && !converged) {
-        hipLaunchKernelGGL(k_accum_x, grid, block, 0, c.st, c.x, xh, n);
+        hipLaunchKernelGGL(k_accum_x, grid, block, 0, c.st, static_cast<double2 *>(c.x), static_cast<float4 *>(xh),
+                           static_cast<long>(n) * 6);
         HIPCHK(hipGetLastError());
     }
     // final FP64 true residual
