@@ -1,28 +1,362 @@
 // Wilson hopping term, Wilson operator and Shamir domain-wall operator (gfx950).
 //
-// Work decomposition. A thread owns one 5D "column" q = (x, y, z, s) of a time slice (s is the
-// fifth coordinate, fastest, so Ls consecutive lanes share a 4D site and its links; Ls = 1 for
-// 4D fields) and walks T consecutive time slices t0 .. t0 + T - 1. Along the walk the t-hop terms
-// are carried in registers: the backward hop of slice t, U_t(x, t-1)^dagger h(psi(x, t-1)), is
-// computed at step t-1 from the link and spinor that step loads anyway, so each psi record and
-// each U_t link is read once per walk instead of three and two times.
+// Two schedules of the same operator share this file; launch_dhop picks one by field type.
+//
+// Direction-parallel schedule (4D fields in FP64 and FP32). A block owns 32 consecutive 5D sites of a traversal order and runs 8
+// wavefronts, one per hopping direction (mu = 0..3, forward and backward). In phase 1 wavefront d
+// computes, for every site of the block, the spin-projected neighbour h = (1 -/+ gamma_mu) psi and
+// its parallel transport chi = U h (forward) or U^dagger h (backward); two lanes share a site, one
+// per spin of the half-spinor, so every lane does one 3x3 complex matrix-vector product. The
+// eight chi per site meet in LDS, and in phase 2 sixteen lanes per site (twelve active, one per
+// output spin-colour component) reconstruct the lower spins, sum the directions, apply the
+// Wilson or domain-wall diagonal and fifth-dimension terms and store the component. All eight
+// neighbour records and links of a site are in flight at once, which is what feeds HBM when the
+// lattice is small (a 16^4 lattice has only 65536 sites for 256 compute units).
 //
 // Coalescing. The fields are site-major (a site's 12 complex numbers are contiguous), so a lane
 // reading its own neighbour record touches a partial cache line per instruction. Neighbour
-// records are therefore gathered per wavefront through LDS: lane l loads 16-byte chunk
-// c = k*64 + l of the 64 records the wave needs (record c / chunks), i.e. consecutive lanes read
-// consecutive addresses, and writes it to a padded LDS slot; each lane then reads its own record
-// back. This is the MI355X form of Grid's observation (Section 2.1-2.2) that many small matrix-
-// vector products in parallel, one per SIMD lane, need a data layout or staging that feeds the
-// lanes contiguously.
+// records are therefore gathered per wavefront through LDS: consecutive lanes read consecutive
+// 16-byte chunks of the 32 records the wavefront needs and write them to padded LDS slots, from
+// which each lane reads the spins it projects. This is the MI355X form of Grid's observation
+// (Sections 2.1-2.2) that many small matrix-vector products in parallel, one per SIMD lane, need
+// a data layout or staging that feeds the lanes contiguously.
+//
+// Traversal. Blocks are renumbered so that each XCD receives a contiguous range of the traversal
+// order; when Lt is a multiple of 8 that range is a slab of Lt/8 time slices, swept with z
+// slowest, so a record's eight uses fall within a few (x, y, t)-cross-sections of the slab and
+// mostly stay in the XCD's L2. (Halving x, y and z instead, with t swept, measured no better:
+// the slab faces read by two XCDs cost less than the cross-section working set.)
 //
 // Per site: 8 x (spin projection 12 + SU(3) x half-spinor 132) + 7 x 24 reconstruction = 1320
-// flops. Blocks are numbered so that each XCD receives a contiguous range of (time segment,
-// column block) pairs, time segment slowest, i.e. a slab of time slices per XCD.
+// flops, the convention of the flop counts quoted for this operator.
 #include "device.h"
 #include "launch.h"
 
 namespace gridmi {
+
+constexpr int kSites = 32;           // 5D sites per block
+constexpr int kDirs = 8;             // wavefronts per block, one per hopping direction
+constexpr int kBlock = kDirs * 64;   // threads per block
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 16-byte chunk as a native vector type.
+typedef unsigned int chunk_t __attribute__((ext_vector_type(4)));
+
+// Complex number k (spin k / 3, colour k % 3) of a record: staged in LDS or in global memory.
+template <class SP>
+struct Elem;
+
+template <>
+struct Elem<SpF64> {
+    __device__ __forceinline__ static Cx<double> get(const void *rec, int k, float) {
+        const double2 v = reinterpret_cast<const double2 *>(rec)[k];
+        return {v.x, v.y};
+    }
+};
+template <>
+struct Elem<SpF32> {
+    __device__ __forceinline__ static Cx<float> get(const void *rec, int k, float) {
+        const float2 v = reinterpret_cast<const float2 *>(rec)[k];
+        return {v.x, v.y};
+    }
+};
+template <>
+struct Elem<SpF16S> {
+    __device__ __forceinline__ static Cx<float> get(const void *rec, int k, float s) {
+        const uint32_t w = reinterpret_cast<const uint32_t *>(rec)[k];
+        return {half_bits_to_float(w & 0xffffu) * s, half_bits_to_float(w >> 16) * s};
+    }
+};
+
+template <class SP>
+__device__ __forceinline__ Cx<typename SP::C> global_elem(const void *base, const float *scale, size_t rec, int k) {
+    const char *p = reinterpret_cast<const char *>(base) + rec * (SP::kChunks * 16);
+    return Elem<SP>::get(p, k, SP::kScaled ? scale[rec] : 1.0f);
+}
+
+// Store complex k of record rec. FP16 storage: the 16 lanes of a site (12 active) agree on the
+// site scale max |re|, |im| before encoding.
+template <class SP>
+__device__ __forceinline__ void store_elem(void *base, float *scale, size_t rec, int k, Cx<typename SP::C> v, bool live);
+
+template <>
+__device__ __forceinline__ void store_elem<SpF64>(void *base, float *, size_t rec, int k, Cx<double> v, bool live) {
+    if (live) reinterpret_cast<double2 *>(base)[rec * 12 + k] = make_double2(v.r, v.i);
+}
+template <>
+__device__ __forceinline__ void store_elem<SpF32>(void *base, float *, size_t rec, int k, Cx<float> v, bool live) {
+    if (live) reinterpret_cast<float2 *>(base)[rec * 12 + k] = make_float2(v.r, v.i);
+}
+template <>
+__device__ __forceinline__ void store_elem<SpF16S>(void *base, float *scale, size_t rec, int k, Cx<float> v, bool live) {
+    float m = live ? fmaxf(fabsf(v.r), fabsf(v.i)) : 0.f;
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 16));
+    const float inv = m > 0.f ? 1.0f / m : 0.f;
+    const uint32_t w = scaled_half_bits(v.r, inv) | (scaled_half_bits(v.i, inv) << 16);
+    if (live) {
+        reinterpret_cast<uint32_t *>(base)[rec * 12 + k] = w;
+        if (k == 0) scale[rec] = m;
+    }
+}
+
+// Division by a launch-invariant divisor d >= 1 for 0 <= n < 2^31: q = (umulhi(n, m) + n) >> l with
+// l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1 (Granlund and Montgomery's division by
+// invariant integers; n + umulhi(n, m) < 2^32 because n < 2^31).
+struct FastDiv {
+    uint32_t m, l;
+};
+
+static FastDiv make_fastdiv(int d) {
+    uint32_t l = 0;
+    while ((1u << l) < static_cast<uint32_t>(d)) ++l;
+    const uint64_t m = ((uint64_t(1) << 32) * ((uint64_t(1) << l) - static_cast<uint64_t>(d))) / static_cast<uint64_t>(d) + 1;
+    return {static_cast<uint32_t>(m), l};
+}
+
+__device__ __forceinline__ int fdiv(int n, FastDiv f) {
+    return static_cast<int>((__umulhi(static_cast<uint32_t>(n), f.m) + static_cast<uint32_t>(n)) >> f.l);
+}
+
+// Traversal order: s, x, y, t within a slab of nt time slices, z, slab.
+struct Trav {
+    FastDiv ls, lx, ly, nt, lz;
+    int nts;   // nt
+};
+
+// Traversal index j -> coordinates, 4D site and s.
+__device__ __forceinline__ void trav_decode(const GeomDev &g, const Trav &tr, int j, int x[4], int &site4, int &s) {
+    int q = fdiv(j, tr.ls);
+    s = j - q * g.Ls;
+    j = q;
+    q = fdiv(j, tr.lx);
+    x[0] = j - q * g.L[0];
+    j = q;
+    q = fdiv(j, tr.ly);
+    x[1] = j - q * g.L[1];
+    j = q;
+    q = fdiv(j, tr.nt);
+    const int tl = j - q * tr.nts;
+    j = q;
+    q = fdiv(j, tr.lz);
+    x[2] = j - q * g.L[2];
+    x[3] = q * tr.nts + tl;
+    site4 = x[0] + g.L[0] * (x[1] + g.L[1] * (x[2] + g.L[2] * x[3]));
+}
+
+template <int MU>
+__device__ __forceinline__ int stride_of(const GeomDev &g) {
+    return MU == 0 ? 1 : MU == 1 ? g.L[0] : MU == 2 ? g.L[0] * g.L[1] : g.L[0] * g.L[1] * g.L[2];
+}
+
+// Phase 1, direction (MU, BWD): chi = U_mu(x) h(psi(x + mu)) or U_mu(x - mu)^dagger h(psi(x - mu))
+// with h = (1 + E gamma_mu) psi projected; lane spin sp of the half-spinor. The result goes to
+// the wavefront's LDS area as red[site][sp][colour].
+template <class SP, class LK, int MU, bool BWD, int E>
+__device__ __forceinline__ void dir_term(const void *__restrict__ U, const void *__restrict__ psi,
+                                         const float *__restrict__ psi_scale, const GeomDev &g, const int x[4],
+                                         int site4, int s, int sl, int sp, chunk_t *lds) {
+    using C = typename SP::C;
+    constexpr int CH = SP::kChunks, PITCH = CH + 1;
+    const int lane = threadIdx.x & 63;
+    const int L = g.L[MU], st = stride_of<MU>(g);
+    const int nb4 = BWD ? (x[MU] == 0 ? site4 + (L - 1) * st : site4 - st)
+                        : (x[MU] == L - 1 ? site4 - (L - 1) * st : site4 + st);
+    const int rec = nb4 * g.Ls + s;
+    // coalesced fetch of the 32 records (record r is named by lane 2r)
+    const chunk_t *src = reinterpret_cast<const chunk_t *>(psi);
+    constexpr int NCH = kSites * CH, NK = (NCH + 63) / 64;
+    chunk_t w[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        const int c = k * 64 + lane;
+        const int cc = c < NCH ? c : 0;
+        const int r = cc / CH, j = cc - r * CH;
+        const int n = __shfl(rec, 2 * r, 64);
+        w[k] = src[static_cast<size_t>(n) * CH + j];
+    }
+    const float sc = SP::kScaled ? psi_scale[rec] : 1.0f;
+    Cx<C> u[3][3];
+    LK::load(U, static_cast<size_t>(BWD ? nb4 : site4) * 4 + MU, u);
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        const int c = k * 64 + lane;
+        if (c < NCH) {
+            const int r = c / CH, j = c - r * CH;
+            lds[r * PITCH + j] = w[k];
+        }
+    }
+    wave_sync();
+    // h_sp = psi_sp + E * phase * psi_src
+    const chunk_t *rp = lds + sl * PITCH;
+    const int srcs = (MU < 2) ? 3 - sp : 2 + sp;
+    const C e = static_cast<C>(E);
+    const C sg = sp ? C(1) : C(-1);
+    Cx<C> h[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const Cx<C> pu = Elem<SP>::get(rp, sp * 3 + c, sc);
+        const Cx<C> pd = Elem<SP>::get(rp, srcs * 3 + c, sc);
+        if (MU == 0)        // -i
+            h[c] = {pu.r + e * pd.i, pu.i - e * pd.r};
+        else if (MU == 1)   // -1 (sp 0), +1 (sp 1)
+            h[c] = {pu.r + e * sg * pd.r, pu.i + e * sg * pd.i};
+        else if (MU == 2)   // -i (sp 0), +i (sp 1)
+            h[c] = {pu.r - e * sg * pd.i, pu.i + e * sg * pd.r};
+        else
+            h[c] = {pu.r + e * pd.r, pu.i + e * pd.i};
+    }
+    wave_sync();   // every lane has read its record before the area is reused for chi
+    Cx<C> *red = reinterpret_cast<Cx<C> *>(lds);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Cx<C> acc;
+        if (BWD) {
+            acc = cmulc(u[0][a], h[0]);
+            acc = cmacc(acc, u[1][a], h[1]);
+            acc = cmacc(acc, u[2][a], h[2]);
+        } else {
+            acc = cmul(u[a][0], h[0]);
+            acc = cmac(acc, u[a][1], h[1]);
+            acc = cmac(acc, u[a][2], h[2]);
+        }
+        red[(sl * 2 + sp) * 3 + a] = acc;
+    }
+}
+
+template <class SP, class LK, bool DAG, int KIND>
+__global__ void __launch_bounds__(kBlock)
+k_dhop_dir(const void *__restrict__ U, const void *__restrict__ psi, const float *__restrict__ psi_scale,
+       void *__restrict__ out, float *__restrict__ out_scale, GeomDev g, Trav tr, double diag, double mf) {
+    using C = typename SP::C;
+    constexpr int PITCH = SP::kChunks + 1;
+    __shared__ chunk_t sm[kDirs][kSites * PITCH];
+    __shared__ int2 sinfo[kSites];   // (4D site, s) of the block's sites, for phase 2
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int base = xcd_block(blockIdx.x, gridDim.x) * kSites;
+    // H: (1 - gamma) forward, (1 + gamma) backward; H^dagger the opposite.
+    constexpr int EF = DAG ? +1 : -1;
+    {
+        const int sl = lane >> 1, sp = lane & 1;
+        const int j = min(base + sl, g.n5 - 1);   // idle lanes of a ragged block still take part
+        int x[4], site4, s;
+        trav_decode(g, tr, j, x, site4, s);
+        if (wv == 0 && sp == 0) sinfo[sl] = make_int2(site4, s);
+        chunk_t *lds = sm[wv];
+        switch (wv) {
+            case 0: dir_term<SP, LK, 0, false, EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, lds); break;
+            case 1: dir_term<SP, LK, 0, true, -EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, lds); break;
+            case 2: dir_term<SP, LK, 1, false, EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, lds); break;
+            case 3: dir_term<SP, LK, 1, true, -EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, lds); break;
+            case 4: dir_term<SP, LK, 2, false, EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, lds); break;
+            case 5: dir_term<SP, LK, 2, true, -EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, lds); break;
+            case 6: dir_term<SP, LK, 3, false, EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, lds); break;
+            default: dir_term<SP, LK, 3, true, -EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, lds); break;
+        }
+    }
+    __syncthreads();
+    // Phase 2: lane (site sl, component k = 3 a + c); lanes 12..15 of a site are idle.
+    const int sl = threadIdx.x >> 4, k16 = threadIdx.x & 15;
+    const int j = base + sl;
+    const bool live = j < g.n5 && k16 < 12;
+    const int k = k16 < 12 ? k16 : 0;
+    const int a = k / 3, c = k - 3 * (k / 3);
+    const bool up = a < 2;
+    const int a2 = a - 2;
+    const C sgn = up ? C(1) : C(-1);
+    Cx<C> acc = {C(0), C(0)};
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        // upper: chi_f[a] + chi_b[a]; lower: EF * phase * (chi_f - chi_b)[src]
+        int src;
+        C pr, pi;   // phase of the lower reconstruction, times EF
+        if (mu == 0) { src = 1 - a2; pr = 0; pi = EF; }                         // i
+        else if (mu == 1) { src = 1 - a2; pr = a2 ? -EF : EF; pi = 0; }         // +1 / -1
+        else if (mu == 2) { src = a2; pr = 0; pi = a2 ? -EF : EF; }             // i / -i
+        else { src = a2; pr = EF; pi = 0; }                                     // 1
+        if (up) { src = a; pr = 1; pi = 0; }
+        const Cx<C> *rf = reinterpret_cast<const Cx<C> *>(sm[2 * mu]);
+        const Cx<C> *rb = reinterpret_cast<const Cx<C> *>(sm[2 * mu + 1]);
+        const Cx<C> f = rf[(sl * 2 + src) * 3 + c], b = rb[(sl * 2 + src) * 3 + c];
+        const Cx<C> d = {f.r + sgn * b.r, f.i + sgn * b.i};
+        acc = {acc.r + pr * d.r - pi * d.i, acc.i + pr * d.i + pi * d.r};
+    }
+    const int2 si = sinfo[sl];
+    const int site4 = si.x, s = si.y;
+    const size_t q = static_cast<size_t>(site4) * g.Ls + s;
+    if (KIND != GRID_HOP) {
+        // D = (4 + m) - H/2;  M = (5 - M5) - H/2 - (fifth-dimension hopping)
+        const Cx<C> v = global_elem<SP>(psi, psi_scale, q, k);
+        const C dg = static_cast<C>(diag), half = static_cast<C>(0.5);
+        acc = {dg * v.r - half * acc.r, dg * v.i - half * acc.i};
+    }
+    if (KIND == GRID_DWF) {
+        // M:   - P_- psi~_{s+1} - P_+ psi~_{s-1};  M^dagger: - P_+ psi~_{s+1} - P_- psi~_{s-1}
+        // walls: psi~_{Ls} = -mf psi_0, psi~_{-1} = -mf psi_{Ls-1}
+        const int Ls = g.Ls;
+        const int hup = DAG ? 0 : 1;   // chiral half taken from s + 1 (0: spins 0,1; 1: spins 2,3)
+        const bool from_up = (a >> 1) == hup;
+        const int s2 = from_up ? (s == Ls - 1 ? 0 : s + 1) : (s == 0 ? Ls - 1 : s - 1);
+        const C f = from_up ? (s == Ls - 1 ? static_cast<C>(-mf) : C(1)) : (s == 0 ? static_cast<C>(-mf) : C(1));
+        const Cx<C> v = global_elem<SP>(psi, psi_scale, static_cast<size_t>(site4) * Ls + s2, k);
+        acc = {acc.r - f * v.r, acc.i - f * v.i};
+    }
+    store_elem<SP>(out, out_scale, q, k, acc, live);
+}
+
+// Time slices per XCD slab: Lt / 8 when Lt is a multiple of 8, else the whole extent.
+static Trav make_trav(const GeomDev &g) {
+    const int nt = (g.L[3] % 8 == 0) ? g.L[3] / 8 : g.L[3];
+    Trav tr;
+    tr.ls = make_fastdiv(g.Ls);
+    tr.lx = make_fastdiv(g.L[0]);
+    tr.ly = make_fastdiv(g.L[1]);
+    tr.nt = make_fastdiv(nt);
+    tr.lz = make_fastdiv(g.L[2]);
+    tr.nts = nt;
+    return tr;
+}
+
+template <class SP, class LK>
+static hipError_t launch_dir(const DhopArgs &a) {
+    const Trav tr = make_trav(a.g);
+    const long nblocks = (static_cast<long>(a.g.n5) + kSites - 1) / kSites;
+    const dim3 grid(static_cast<unsigned>(nblocks)), block(kBlock);
+    hipStream_t st = a.stream;
+#define GRIDMI_LAUNCH(DAG, KIND)                                                                          \
+    hipLaunchKernelGGL((k_dhop_dir<SP, LK, DAG, KIND>), grid, block, 0, st, a.U, a.psi, a.psi_scale, a.out, \
+                       a.out_scale, a.g, tr, a.diag, a.mf)
+    switch (a.kind * 2 + (a.dag ? 1 : 0)) {
+        case GRID_HOP * 2 + 0: GRIDMI_LAUNCH(false, GRID_HOP); break;
+        case GRID_HOP * 2 + 1: GRIDMI_LAUNCH(true, GRID_HOP); break;
+        case GRID_WILSON * 2 + 0: GRIDMI_LAUNCH(false, GRID_WILSON); break;
+        case GRID_WILSON * 2 + 1: GRIDMI_LAUNCH(true, GRID_WILSON); break;
+        case GRID_DWF * 2 + 0: GRIDMI_LAUNCH(false, GRID_DWF); break;
+        case GRID_DWF * 2 + 1: GRIDMI_LAUNCH(true, GRID_DWF); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef GRIDMI_LAUNCH
+    return hipGetLastError();
+}
+
+// ============================================================================================
+// Column-walk schedule (domain-wall fields and FP16 storage).
+//
+// A thread owns one 5D "column" q = (x, y, z, s) of a time slice (s fastest, so Ls consecutive
+// lanes share a 4D site and its links) and walks T consecutive time slices t0 .. t0 + T - 1.
+// Along the walk the t-hop terms are carried in registers: the backward hop of slice t,
+// U_t(x, t-1)^dagger h(psi(x, t-1)), is computed at step t-1 from the link and spinor that step
+// loads anyway, so each psi record and each U_t link is read once per walk. Neighbour records are
+// gathered per wavefront through LDS (64 records per gather), and the gather of the next record is
+// in flight while the current direction computes. With one thread per 5D site this schedule
+// spends far fewer instructions per site than the direction-parallel one, which is what the
+// ALU-heavy FP16 decode and the Ls-fold link reuse of the fifth dimension need.
+// ============================================================================================
 
 constexpr int kWaves = 4;   // wavefronts per block
 
@@ -40,11 +374,6 @@ __device__ __forceinline__ void neighbours3(const GeomDev &g, int col, int nb[6]
     }
 }
 
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Coalesced wavefront gather of spinor records through LDS, in two phases so that the global
 // loads of the next gather can be in flight while the current direction computes:
@@ -53,9 +382,6 @@ __device__ __forceinline__ void wave_sync() {
 //          consecutive lanes read consecutive addresses;
 //   stage: the chunks go to padded LDS slots and each lane reads its own record back.
 // All 64 lanes must take part with a valid record index.
-// 16-byte chunk as a native vector type (HIP's uint4 wraps a union, which keeps the in-flight
-// chunks from being promoted to registers).
-typedef unsigned int chunk_t __attribute__((ext_vector_type(4)));
 
 template <class SP>
 struct Fetch {
@@ -136,7 +462,7 @@ __device__ __forceinline__ void hop_term(Cx<C> acc[4][3], const Cx<C> p[4][3], c
 
 template <class SP, class LK, bool DAG, int KIND>
 __global__ void __launch_bounds__(256)
-k_dhop(const void *__restrict__ U, const void *__restrict__ psi, const float *__restrict__ psi_scale,
+k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const float *__restrict__ psi_scale,
        void *__restrict__ out, float *__restrict__ out_scale, GeomDev g, int T, double diag, double mf) {
     using C = typename SP::C;
     __shared__ chunk_t sm[kWaves][64 * (SP::kChunks + 1)];
@@ -266,13 +592,13 @@ static int choose_steps(const GeomDev &g) {
 }
 
 template <class SP, class LK>
-static hipError_t launch_T(const DhopArgs &a) {
+static hipError_t launch_walk(const DhopArgs &a) {
     const int T = choose_steps(a.g);
     const long nbc = (static_cast<long>(a.g.L[0]) * a.g.L[1] * a.g.L[2] * a.g.Ls + 255) / 256;
     const dim3 grid(static_cast<unsigned>(nbc * (a.g.L[3] / T))), block(256);
     hipStream_t st = a.stream;
 #define GRIDMI_LAUNCH(DAG, KIND)                                                                          \
-    hipLaunchKernelGGL((k_dhop<SP, LK, DAG, KIND>), grid, block, 0, st, a.U, a.psi, a.psi_scale, a.out, \
+    hipLaunchKernelGGL((k_dhop_walk<SP, LK, DAG, KIND>), grid, block, 0, st, a.U, a.psi, a.psi_scale, a.out, \
                        a.out_scale, a.g, T, a.diag, a.mf)
     switch (a.kind * 2 + (a.dag ? 1 : 0)) {
         case GRID_HOP * 2 + 0: GRIDMI_LAUNCH(false, GRID_HOP); break;
@@ -287,15 +613,22 @@ static hipError_t launch_T(const DhopArgs &a) {
     return hipGetLastError();
 }
 
+// Direction-parallel schedule for 4D fields in FP64 / FP32, column walk otherwise.
+template <class SP, class LK>
+static hipError_t launch_sched(const DhopArgs &a) {
+    if (a.g.Ls == 1 && !SP::kScaled) return launch_dir<SP, LK>(a);
+    return launch_walk<SP, LK>(a);
+}
+
 hipError_t launch_dhop(const DhopArgs &a) {
     if (a.g.n5 == 0) return hipSuccess;
     switch (a.prec * 2 + a.link_fmt) {
-        case GRID_F64 * 2 + GRID_L18: return launch_T<SpF64, LkF64<3>>(a);
-        case GRID_F64 * 2 + GRID_L12: return launch_T<SpF64, LkF64<2>>(a);
-        case GRID_F32 * 2 + GRID_L18: return launch_T<SpF32, LkF32<3>>(a);
-        case GRID_F32 * 2 + GRID_L12: return launch_T<SpF32, LkF32<2>>(a);
-        case GRID_F16S * 2 + GRID_L18: return launch_T<SpF16S, LkF16<3>>(a);
-        case GRID_F16S * 2 + GRID_L12: return launch_T<SpF16S, LkF16<2>>(a);
+        case GRID_F64 * 2 + GRID_L18: return launch_sched<SpF64, LkF64<3>>(a);
+        case GRID_F64 * 2 + GRID_L12: return launch_sched<SpF64, LkF64<2>>(a);
+        case GRID_F32 * 2 + GRID_L18: return launch_sched<SpF32, LkF32<3>>(a);
+        case GRID_F32 * 2 + GRID_L12: return launch_sched<SpF32, LkF32<2>>(a);
+        case GRID_F16S * 2 + GRID_L18: return launch_sched<SpF16S, LkF16<3>>(a);
+        case GRID_F16S * 2 + GRID_L12: return launch_sched<SpF16S, LkF16<2>>(a);
         default: return hipErrorInvalidValue;
     }
 }
