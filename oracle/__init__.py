@@ -1,3 +1,4 @@
 """FP64 CPU oracle (test infrastructure only): see oracle.oracle."""
 from .oracle import *  # noqa: F401,F403
 from .oracle import Op, build, FLOPS_HOP, FLOPS_WILSON, FLOPS_DWF  # noqa: F401
+from . import eo  # noqa: F401,E402
