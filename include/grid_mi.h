@@ -53,7 +53,7 @@ extern "C" {
 
 #define GRID_OK           0
 #define GRID_EINVAL      -1   /* bad enum value, NULL pointer where one is required, aliasing  */
-#define GRID_ESHAPE      -2   /* a lattice extent below 2, Ls below 1, or a size overflow       */
+#define GRID_ESHAPE      -2   /* an extent below 2 (or odd for checkerboards), bad Ls, overflow */
 #define GRID_EDTYPE      -3   /* precision / link-format combination not supported             */
 #define GRID_EALIGN      -4   /* a pointer not 16-byte aligned                                  */
 #define GRID_EHIP        -5   /* a HIP runtime call failed                                      */
@@ -181,6 +181,53 @@ int grid_convert_spinor(const void *src, int src_prec, const float *src_scale, v
  */
 int grid_convert_links(const void *src, void *dst, int dst_prec, int dst_fmt, int reunitarise, long n_links,
                        void *stream);
+
+/*
+ * Even-odd (red-black) preconditioning. Grid objects may be single-checkerboard (Section 2.2):
+ * a checkerboard field holds the sites of one parity p = (x + y + z + t) mod 2, site
+ * (x, y, z, t) at index (x / 2) + (Lx/2)(y + Ly(z + Lz t)) -- the full index divided by two --
+ * with the Ls records of a 4D site contiguous: [Lt][Lz][Ly][Lx/2][Ls][4][3]. Every extent must
+ * be even (GRID_ESHAPE otherwise). Links stay full-lattice.
+ *
+ * grid_dhop_cb -- out = beta * H_{p,1-p} psi + Diag(y) on checkerboard p = out_parity, psi on
+ * checkerboard 1 - p (H with H^+ when op->dag). Diag by op->kind: GRID_HOP none (y must be
+ * NULL); GRID_WILSON (4 + mass) y (Ls must be 1); GRID_DWF the fifth-dimension part of M,
+ * (5 - M5) y_s - P_- y~_{s+1} - P_+ y~_{s-1} (M^+: P_+ and P_- swapped). All three fields in
+ * precision prec (scales for GRID_F16S), n = V Ls / 2 records each. Asynchronous.
+ */
+int grid_dhop_cb(const void *U, const void *psi, const float *psi_scale, const void *y, const float *y_scale,
+                 void *out, float *out_scale, const grid_geom *geom, const grid_op *op, int out_parity,
+                 double beta, int prec, int link_fmt, void *stream);
+
+/*
+ * grid_m5inv -- out = M5^-1 psi, M5 the fifth-dimension part of the domain-wall operator (as in
+ * grid_dhop_cb), or (M5^+)^-1 psi when dag != 0, on n4 4D sites of Ls records each (a full or a
+ * checkerboard field). Applied per site and chirality in closed form (cyclic bidiagonal
+ * system); needs 1 <= Ls <= 64 and |5 - M5| > 1 for a stable recurrence. Asynchronous.
+ */
+int grid_m5inv(const void *psi, const float *psi_scale, void *out, float *out_scale, long n4, int Ls, double M5,
+               double mf, int dag, int prec, void *stream);
+
+/*
+ * grid_solve_eo_workspace_bytes -- device workspace grid_solve_eo needs (0 for invalid input).
+ */
+size_t grid_solve_eo_workspace_bytes(const grid_geom *geom, const grid_cg_params *params);
+
+/*
+ * grid_solve_eo -- solve Op x = b (Op = D or M as in grid_cg; full-lattice FP64 fields) by CG on
+ * the even-odd preconditioned normal equations Mhat^+ Mhat x_e = Mhat^+ bhat with
+ *   Mhat = M_ee - M_eo M_oo^-1 M_oe,  bhat = b_e - M_eo M_oo^-1 b_o,
+ *   x_o  = M_oo^-1 (b_o - M_oe x_e),
+ * M_eo = M_oe = -H/2 between checkerboards and M_ee = M_oo = 4 + mass (Wilson) or the
+ * fifth-dimension part M5 (domain wall). Precision options as grid_cg (params). x on entry is
+ * the initial guess (its even sites are used). The CG stops when the FP64 true residual of the
+ * preconditioned normal equations is <= tol relative to |Mhat^+ bhat|; stats->true_residual is
+ * then |b - Op x| / |b| of the full system, recomputed in FP64, and stats->converged reports the
+ * CG criterion. Synchronous. Returns as grid_cg.
+ */
+int grid_solve_eo(const void *U, const void *b, void *x, const grid_geom *geom, const grid_op *op,
+                  const grid_cg_params *params, void *workspace, size_t ws_bytes, grid_cg_stats *stats,
+                  void *stream);
 
 /* grid_last_error -- message of the calling thread's last failed call ("" if none). */
 const char *grid_last_error(void);

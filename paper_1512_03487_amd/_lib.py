@@ -19,6 +19,7 @@ GRID_HOP, GRID_WILSON, GRID_DWF = 0, 1, 2
 
 #: every symbol include/grid_mi.h declares
 EXPORTS = ("grid_dhop", "grid_dwf_mdag_m", "grid_cg_workspace_bytes", "grid_cg", "grid_dhop_backward",
+           "grid_dhop_cb", "grid_m5inv", "grid_solve_eo_workspace_bytes", "grid_solve_eo",
            "grid_convert_spinor", "grid_convert_links", "grid_last_error", "grid_version")
 
 
@@ -71,6 +72,15 @@ def load():
     lib.grid_cg.restype = I
     lib.grid_dhop_backward.argtypes = [P, P, P, P, P, ctypes.POINTER(GridGeom), ctypes.POINTER(GridOp), I, I, P]
     lib.grid_dhop_backward.restype = I
+    lib.grid_dhop_cb.argtypes = [P, P, P, P, P, P, P, ctypes.POINTER(GridGeom), ctypes.POINTER(GridOp), I, D, I, I, P]
+    lib.grid_dhop_cb.restype = I
+    lib.grid_m5inv.argtypes = [P, P, P, P, ctypes.c_long, I, D, D, I, I, P]
+    lib.grid_m5inv.restype = I
+    lib.grid_solve_eo_workspace_bytes.argtypes = [ctypes.POINTER(GridGeom), ctypes.POINTER(GridCgParams)]
+    lib.grid_solve_eo_workspace_bytes.restype = ctypes.c_size_t
+    lib.grid_solve_eo.argtypes = [P, P, P, ctypes.POINTER(GridGeom), ctypes.POINTER(GridOp),
+                                  ctypes.POINTER(GridCgParams), P, ctypes.c_size_t, ctypes.POINTER(GridCgStats), P]
+    lib.grid_solve_eo.restype = I
     lib.grid_convert_spinor.argtypes = [P, I, P, P, I, P, ctypes.c_long, P]
     lib.grid_convert_spinor.restype = I
     lib.grid_convert_links.argtypes = [P, P, I, I, I, ctypes.c_long, P]

@@ -200,6 +200,81 @@ def cg(U, b, kind="dwf", mass=0.0, M5=1.8, mf=0.01, x0=None, workspace=None, rai
     return x, stats
 
 
+def _geom_cb(U, psi) -> GridGeom:
+    """Geometry of a checkerboard field (x extent Lx / 2) checked against full-lattice links."""
+    g = geom_of(psi)
+    g.dims[0] = 2 * g.dims[0]
+    if tuple(U.shape[:4]) != (g.dims[3], g.dims[2], g.dims[1], g.dims[0]):
+        raise ValueError(f"checkerboard field {tuple(psi.shape)} does not match links {tuple(U.shape)}")
+    return g
+
+
+def dhop_cb(U, psi, out_parity, kind="hop", y=None, beta=1.0, dag=False, mass=0.0, M5=1.8, mf=0.01, out=None):
+    """Checkerboard hopping term: out (parity p) = beta H psi (parity 1 - p) + Diag_kind(y).
+
+    Checkerboard fields have shape (Lt, Lz, Ly, Lx/2[, Ls], 4, 3); see include/grid_mi.h.
+    """
+    prec = spinor_prec(psi)
+    fmt = link_format(U, prec)
+    g = _geom_cb(U, psi)
+    if out is None:
+        out = _empty_like(psi)
+    pd, ps = _data_scale(psi)
+    yd, ys = _data_scale(y) if y is not None else (None, None)
+    od, os_ = _data_scale(out)
+    op = make_op(kind, dag, mass, M5, mf)
+    check(load().grid_dhop_cb(_ptr(U), _ptr(pd), _ptr(ps), _ptr(yd), _ptr(ys), _ptr(od), _ptr(os_), ctypes.byref(g),
+                              ctypes.byref(op), int(out_parity), float(beta), prec, fmt, _stream(pd.device)))
+    return out
+
+
+def m5inv(psi, M5, mf, dag=False, out=None):
+    """Inverse of the domain-wall fifth-dimension operator on a full or checkerboard 5D field."""
+    prec = spinor_prec(psi)
+    shape = psi.shape
+    if len(shape) != 7:
+        raise ValueError("m5inv takes a 5D field (..., Ls, 4, 3)")
+    n4 = int(shape[0]) * int(shape[1]) * int(shape[2]) * int(shape[3])
+    out = _empty_like(psi) if out is None else out
+    pd, ps = _data_scale(psi)
+    od, os_ = _data_scale(out)
+    check(load().grid_m5inv(_ptr(pd), _ptr(ps), _ptr(od), _ptr(os_), n4, int(shape[4]), float(M5), float(mf),
+                            int(bool(dag)), prec, _stream(pd.device)))
+    return out
+
+
+def solve_eo_workspace_bytes(b, **params) -> int:
+    g = geom_of(b)
+    p = cg_params(**params)
+    return int(load().grid_solve_eo_workspace_bytes(ctypes.byref(g), ctypes.byref(p)))
+
+
+def solve_eo(U, b, kind="dwf", mass=0.0, M5=1.8, mf=0.01, x0=None, workspace=None, raise_on_fail=True, **params):
+    """Solve Op x = b (Op = D or M) with even-odd preconditioned CG; FP64 full-lattice U, b, x.
+
+    Returns (x, stats); stats["true_residual"] is |b - Op x| / |b|. Synchronous.
+    """
+    if spinor_prec(b) != GRID_F64 or link_format(U, GRID_F64) != GRID_L18:
+        raise TypeError("solve_eo takes complex128 b and complex128 18-real links")
+    g = geom_of(b)
+    p = cg_params(**params)
+    need = int(load().grid_solve_eo_workspace_bytes(ctypes.byref(g), ctypes.byref(p)))
+    if need == 0:
+        raise ValueError("invalid geometry or parameters for solve_eo (every extent must be even)")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=b.device)
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    op = make_op(kind, False, mass, M5, mf)
+    st = GridCgStats()
+    rc = load().grid_solve_eo(_ptr(U), _ptr(b), _ptr(x), ctypes.byref(g), ctypes.byref(op), ctypes.byref(p),
+                              _ptr(workspace), ctypes.c_size_t(workspace.numel()), ctypes.byref(st), _stream(b.device))
+    stats = {"iterations": st.iterations, "reliable_updates": st.reliable_updates, "converged": bool(st.converged),
+             "true_residual": st.true_residual, "seconds": st.seconds, "status": rc}
+    if rc != 0 and raise_on_fail:
+        check(rc)
+    return x, stats
+
+
 def dhop_backward(U, psi, grad_out, kind="hop", dag=False, mass=0.0, M5=1.8, mf=0.01, want_psi=True, want_U=True,
                   force=False):
     """Gradients of L = Re <grad_out, Op psi>: (Op^dagger grad_out, dL/dU or its su(3) force)."""

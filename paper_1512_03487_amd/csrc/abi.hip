@@ -1,6 +1,7 @@
 // C ABI of libgrid_mi: host-side argument validation, dispatch to the kernel launchers, status
 // codes and a thread-local error message. Every check runs before the first HIP call, so a
 // rejected call has no effect on the device.
+#include <math.h>
 #include <stdarg.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -91,6 +92,29 @@ int check_spinor(const void *p, const float *scale, int prec, const char *name, 
         int rc_ = (x);           \
         if (rc_) return rc_;     \
     } while (0)
+
+// Checkerboard fields need every extent even (the parity of a site is then well defined across
+// the periodic boundary, and x pairs up).
+int check_even(const GeomDev &g) {
+    for (int mu = 0; mu < 4; ++mu)
+        if (g.L[mu] % 2) return fail(GRID_ESHAPE, "checkerboard fields need even extents (dims[%d] = %d)", mu, g.L[mu]);
+    return GRID_OK;
+}
+
+// Operator and parameter checks shared by the solvers.
+int check_solver_args(const GeomDev &g, const grid_op *op, const grid_cg_params *params, const grid_cg_stats *stats) {
+    if (!op || !params || !stats) return fail(GRID_EINVAL, "op, params and stats must not be NULL");
+    if (op->kind != GRID_WILSON && op->kind != GRID_DWF)
+        return fail(GRID_EINVAL, "the solvers take GRID_WILSON or GRID_DWF (got kind %d)", op->kind);
+    if (op->kind == GRID_WILSON && g.Ls != 1) return fail(GRID_ESHAPE, "GRID_WILSON needs Ls == 1 (got %d)", g.Ls);
+    TRY(check_prec(params->sloppy_prec));
+    TRY(check_fmt(params->link_fmt));
+    if (!(params->tol > 0.0) || params->maxiter < 0 || params->check_every < 1)
+        return fail(GRID_EINVAL, "need tol > 0, maxiter >= 0 and check_every >= 1");
+    if (params->sloppy_prec != GRID_F64 && !(params->delta > 0.0 && params->delta < 1.0))
+        return fail(GRID_EINVAL, "reliable-update delta must lie in (0, 1)");
+    return GRID_OK;
+}
 
 }  // namespace
 
@@ -217,16 +241,7 @@ int grid_cg(const void *U, const void *b, void *x, const grid_geom *geom, const 
             void *workspace, size_t ws_bytes, grid_cg_stats *stats, void *stream) {
     GeomDev g;
     TRY(check_geom(geom, &g));
-    if (!op || !params || !stats) return fail(GRID_EINVAL, "op, params and stats must not be NULL");
-    if (op->kind != GRID_WILSON && op->kind != GRID_DWF)
-        return fail(GRID_EINVAL, "grid_cg solves with GRID_WILSON or GRID_DWF (got kind %d)", op->kind);
-    if (op->kind == GRID_WILSON && g.Ls != 1) return fail(GRID_ESHAPE, "GRID_WILSON needs Ls == 1 (got %d)", g.Ls);
-    TRY(check_prec(params->sloppy_prec));
-    TRY(check_fmt(params->link_fmt));
-    if (!(params->tol > 0.0) || params->maxiter < 0 || params->check_every < 1)
-        return fail(GRID_EINVAL, "need tol > 0, maxiter >= 0 and check_every >= 1");
-    if (params->sloppy_prec != GRID_F64 && !(params->delta > 0.0 && params->delta < 1.0))
-        return fail(GRID_EINVAL, "reliable-update delta must lie in (0, 1)");
+    TRY(check_solver_args(g, op, params, stats));
     TRY(check_ptr(U, "U", 16));
     TRY(check_ptr(b, "b", 16));
     TRY(check_ptr(x, "x", 16));
@@ -245,6 +260,121 @@ int grid_cg(const void *U, const void *b, void *x, const grid_geom *geom, const 
     if (e != hipSuccess) return hip_fail(e, "grid_cg");
     if (status == GRID_ENOCONV)
         return fail(GRID_ENOCONV, "CG stopped after %d iterations at true residual %.3e", stats->iterations,
+                    stats->true_residual);
+    if (status == GRID_EBREAKDOWN) return fail(GRID_EBREAKDOWN, "CG breakdown after %d iterations", stats->iterations);
+    return ok();
+}
+
+int grid_dhop_cb(const void *U, const void *psi, const float *psi_scale, const void *y, const float *y_scale, void *out,
+                 float *out_scale, const grid_geom *geom, const grid_op *op, int out_parity, double beta, int prec,
+                 int link_fmt, void *stream) {
+    GeomDev g;
+    TRY(check_geom(geom, &g));
+    TRY(check_even(g));
+    if (!op) return fail(GRID_EINVAL, "op is NULL");
+    TRY(check_prec(prec));
+    TRY(check_fmt(link_fmt));
+    if (op->kind != GRID_HOP && op->kind != GRID_WILSON && op->kind != GRID_DWF)
+        return fail(GRID_EINVAL, "unknown operator kind %d", op->kind);
+    if (op->kind == GRID_WILSON && g.Ls != 1) return fail(GRID_ESHAPE, "GRID_WILSON needs Ls == 1 (got %d)", g.Ls);
+    if (out_parity != 0 && out_parity != 1) return fail(GRID_EINVAL, "out_parity must be 0 or 1");
+    TRY(check_ptr(U, "U", 16));
+    TRY(check_spinor(psi, psi_scale, prec, "psi", "psi_scale"));
+    TRY(check_spinor(out, out_scale, prec, "out", "out_scale"));
+    if (op->kind == GRID_HOP) {
+        if (y || y_scale) return fail(GRID_EINVAL, "y must be NULL for GRID_HOP");
+    } else {
+        TRY(check_spinor(y, y_scale, prec, "y", "y_scale"));
+    }
+    const size_t nh = static_cast<size_t>(g.n5 / 2);
+    const size_t sb = spinor_site_bytes(prec) * nh;
+    const size_t ub = link_bytes(prec, link_fmt) * static_cast<size_t>(g.vol) * 4;
+    const size_t cb = prec == GRID_F16S ? sizeof(float) * nh : 0;
+    if (overlap(out, sb, psi, sb) || overlap(out, sb, U, ub) || overlap(out, sb, y, y ? sb : 0))
+        return fail(GRID_EINVAL, "out overlaps psi, y or U");
+    if (cb && (overlap(out_scale, cb, psi_scale, cb) || overlap(out_scale, cb, y_scale, y_scale ? cb : 0) ||
+               overlap(out_scale, cb, out, sb) || overlap(out_scale, cb, psi, sb)))
+        return fail(GRID_EINVAL, "out_scale overlaps an input or out");
+    DhopArgs a;
+    a.U = U;
+    a.psi = psi;
+    a.psi_scale = psi_scale;
+    a.out = out;
+    a.out_scale = out_scale;
+    a.g = g;
+    a.prec = prec;
+    a.link_fmt = link_fmt;
+    a.kind = op->kind;
+    a.dag = op->dag ? 1 : 0;
+    a.diag = op->kind == GRID_WILSON ? 4.0 + op->mass : (op->kind == GRID_DWF ? 5.0 - op->M5 : 0.0);
+    a.mf = op->mf;
+    a.stream = static_cast<hipStream_t>(stream);
+    a.custom = true;
+    a.cb = out_parity;
+    a.y = y;
+    a.y_scale = y_scale;
+    a.beta = beta;
+    hipError_t e = launch_dhop(a);
+    if (e != hipSuccess) return hip_fail(e, "grid_dhop_cb launch");
+    return ok();
+}
+
+int grid_m5inv(const void *psi, const float *psi_scale, void *out, float *out_scale, long n4, int Ls, double M5,
+               double mf, int dag, int prec, void *stream) {
+    TRY(check_prec(prec));
+    if (Ls < 1 || Ls > 64) return fail(GRID_ESHAPE, "grid_m5inv needs 1 <= Ls <= 64 (got %d)", Ls);
+    if (n4 < 0 || n4 * Ls * 4 >= (long(1) << 31)) return fail(GRID_ESHAPE, "n4 out of range");
+    if (!(fabs(5.0 - M5) > 1.0)) return fail(GRID_EINVAL, "grid_m5inv needs |5 - M5| > 1 (got M5 = %g)", M5);
+    TRY(check_spinor(psi, psi_scale, prec, "psi", "psi_scale"));
+    TRY(check_spinor(out, out_scale, prec, "out", "out_scale"));
+    const size_t sb = spinor_site_bytes(prec) * static_cast<size_t>(n4) * Ls;
+    if (overlap(out, sb, psi, sb)) return fail(GRID_EINVAL, "out overlaps psi");
+    if (out_scale && (overlap(out_scale, 4 * n4 * Ls, psi, sb) || overlap(out_scale, 4 * n4 * Ls, out, sb) ||
+                      overlap(out_scale, 4 * n4 * Ls, psi_scale, psi_scale ? 4 * n4 * Ls : 0)))
+        return fail(GRID_EINVAL, "out_scale overlaps another buffer");
+    hipError_t e = launch_m5inv(psi, psi_scale, out, out_scale, n4, Ls, 5.0 - M5, mf, dag ? 1 : 0, prec,
+                                static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "grid_m5inv launch");
+    return ok();
+}
+
+size_t grid_solve_eo_workspace_bytes(const grid_geom *geom, const grid_cg_params *params) {
+    GeomDev g;
+    if (check_geom(geom, &g) || check_even(g) || !params) return 0;
+    if (check_prec(params->sloppy_prec) || check_fmt(params->link_fmt)) return 0;
+    return solve_eo_workspace_bytes(g, params->sloppy_prec, params->link_fmt);
+}
+
+int grid_solve_eo(const void *U, const void *b, void *x, const grid_geom *geom, const grid_op *op,
+                  const grid_cg_params *params, void *workspace, size_t ws_bytes, grid_cg_stats *stats, void *stream) {
+    GeomDev g;
+    TRY(check_geom(geom, &g));
+    TRY(check_even(g));
+    TRY(check_solver_args(g, op, params, stats));
+    if (op->kind == GRID_DWF) {
+        if (g.Ls > 64) return fail(GRID_ESHAPE, "grid_solve_eo needs Ls <= 64 for the domain-wall M5 inverse");
+        if (!(fabs(5.0 - op->M5) > 1.0)) return fail(GRID_EINVAL, "grid_solve_eo needs |5 - M5| > 1");
+    } else if (!(fabs(4.0 + op->mass) > 0.0)) {
+        return fail(GRID_EINVAL, "grid_solve_eo needs 4 + mass != 0");
+    }
+    TRY(check_ptr(U, "U", 16));
+    TRY(check_ptr(b, "b", 16));
+    TRY(check_ptr(x, "x", 16));
+    TRY(check_ptr(workspace, "workspace", 256));
+    const size_t need = solve_eo_workspace_bytes(g, params->sloppy_prec, params->link_fmt);
+    if (ws_bytes < need) return fail(GRID_ESPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    const size_t sb = static_cast<size_t>(g.n5) * 192, ub = static_cast<size_t>(g.vol) * 4 * 144;
+    if (overlap(x, sb, b, sb) || overlap(x, sb, U, ub) || overlap(workspace, need, x, sb) ||
+        overlap(workspace, need, b, sb) || overlap(workspace, need, U, ub))
+        return fail(GRID_EINVAL, "x, b, U and workspace must not overlap");
+    int status = GRID_OK;
+    memset(stats, 0, sizeof(*stats));
+    const double diag = op->kind == GRID_WILSON ? 4.0 + op->mass : 5.0 - op->M5;
+    hipError_t e = run_solve_eo(U, b, x, g, op->kind, diag, op->mf, *params, workspace, static_cast<hipStream_t>(stream),
+                                stats, &status);
+    if (e != hipSuccess) return hip_fail(e, "grid_solve_eo");
+    if (status == GRID_ENOCONV)
+        return fail(GRID_ENOCONV, "CG stopped after %d iterations (full residual %.3e)", stats->iterations,
                     stats->true_residual);
     if (status == GRID_EBREAKDOWN) return fail(GRID_EBREAKDOWN, "CG breakdown after %d iterations", stats->iterations);
     return ok();

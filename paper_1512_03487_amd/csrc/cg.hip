@@ -26,6 +26,7 @@
 namespace gridmi {
 
 constexpr int kRedBlocks = 1024;   // maximum number of reduction partials
+static_assert(kNormScratch >= kRedBlocks + 1, "norm scratch holds the partials and the sum");
 constexpr int kThreads = 256;
 
 __device__ __forceinline__ double block_sum(double v, double *sm) {
@@ -358,6 +359,20 @@ k_residual_f16lo(const double2 *__restrict__ b, const double2 *__restrict__ q, d
     if (threadIdx.x == 0) part_lo[blockIdx.x] = t;
 }
 
+// Partials of |a - b|^2 over FP64 chunks.
+__global__ void __launch_bounds__(kThreads)
+k_diff_norm2(const double2 *__restrict__ a, const double2 *__restrict__ b, long n, double *__restrict__ part) {
+    __shared__ double sm[4];
+    double acc = 0.0;
+    for (long i = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * kThreads) {
+        const double2 u = a[i], v = b[i];
+        const double dx = u.x - v.x, dy = u.y - v.y;
+        acc += dx * dx + dy * dy;
+    }
+    const double t = block_sum(acc, sm);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
 // Final sum of partials into scal[slot] (one block).
 __global__ void __launch_bounds__(kThreads) k_sum(const double *__restrict__ part, int np, double *__restrict__ scal, int slot) {
     __shared__ double sm[4];
@@ -456,10 +471,10 @@ struct CgLayout {
     size_t total;
 };
 
-static CgLayout cg_layout(const GeomDev &g, int sloppy, int link_fmt) {
+static CgLayout cg_layout(long nsites, long nlinks, int sloppy, int link_fmt) {
     CgLayout L;
     memset(&L, 0, sizeof(L));
-    const size_t n = static_cast<size_t>(g.n5);
+    const size_t n = static_cast<size_t>(nsites);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -486,7 +501,7 @@ static CgLayout cg_layout(const GeomDev &g, int sloppy, int link_fmt) {
         }
         const size_t rows = link_fmt == GRID_L12 ? 2 : 3;
         const size_t cb = sloppy == GRID_F32 ? 8 : 4;
-        L.ulo = take(static_cast<size_t>(g.vol) * 4 * rows * 3 * cb);
+        L.ulo = take(static_cast<size_t>(nlinks) * rows * 3 * cb);
     }
     L.part = take(5 * kRedBlocks * sizeof(double));
     L.scal = take(16 * sizeof(double));
@@ -494,7 +509,13 @@ static CgLayout cg_layout(const GeomDev &g, int sloppy, int link_fmt) {
     return L;
 }
 
-size_t cg_workspace_bytes(const GeomDev &g, int sloppy, int link_fmt) { return cg_layout(g, sloppy, link_fmt).total; }
+size_t cg_workspace_bytes_n(long nsites, long nlinks, int sloppy, int link_fmt) {
+    return cg_layout(nsites, nlinks, sloppy, link_fmt).total;
+}
+
+size_t cg_workspace_bytes(const GeomDev &g, int sloppy, int link_fmt) {
+    return cg_workspace_bytes_n(g.n5, static_cast<long>(g.vol) * 4, sloppy, link_fmt);
+}
 
 // --------------------------------------------------------------------------------------------
 // Driver
@@ -504,9 +525,9 @@ struct CgRun {
     const void *U;
     const void *b;
     void *x;
-    GeomDev g;
-    int kind;            // GRID_WILSON or GRID_DWF
-    double diag, mf;
+    long n;              // 5D sites of the system
+    long nlinks;         // links (for the sloppy copy)
+    CgOp op;             // A = op^dagger op
     double tol;
     int maxiter;
     int sloppy;
@@ -525,20 +546,33 @@ struct CgRun {
 
 static hipError_t apply_op(const CgRun &c, const void *U, int prec, int fmt, const void *in, const float *ins, void *out,
                            float *outs, int dag) {
+    return c.op.apply(c.op.ctx, U, prec, fmt, in, ins, out, outs, dag, c.st);
+}
+
+// The full-lattice operator (Wilson D or domain-wall M).
+struct FullOp {
+    GeomDev g;
+    int kind;
+    double diag, mf;
+};
+
+static hipError_t full_apply(const void *ctx, const void *U, int prec, int fmt, const void *in, const float *ins, void *out,
+                             float *outs, int dag, hipStream_t st) {
+    const FullOp &o = *static_cast<const FullOp *>(ctx);
     DhopArgs a;
     a.U = U;
     a.psi = in;
     a.psi_scale = ins;
     a.out = out;
     a.out_scale = outs;
-    a.g = c.g;
+    a.g = o.g;
     a.prec = prec;
     a.link_fmt = fmt;
-    a.kind = c.kind;
+    a.kind = o.kind;
     a.dag = dag;
-    a.diag = c.diag;
-    a.mf = c.mf;
-    a.stream = c.st;
+    a.diag = o.diag;
+    a.mf = o.mf;
+    a.stream = st;
     return launch_dhop(a);
 }
 
@@ -559,9 +593,9 @@ static double read_scalar(const CgRun &c, const double *part, int np, double *sc
 template <class SH>
 static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
     const bool mixed = c.sloppy != GRID_F64;
-    const CgLayout L = cg_layout(c.g, c.sloppy, c.link_fmt);
+    const CgLayout L = cg_layout(c.n, c.nlinks, c.sloppy, c.link_fmt);
     char *ws = c.ws;
-    const int n = c.g.n5;
+    const int n = static_cast<int>(c.n);
     const int np = static_cast<int>((static_cast<long>(n) + kThreads - 1) / kThreads < kRedBlocks
                                         ? (static_cast<long>(n) + kThreads - 1) / kThreads
                                         : kRedBlocks);
@@ -601,7 +635,7 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
         return hipStreamSynchronize(c.st);
     }
     if (mixed) {
-        HIPCHK(launch_convert_links(c.U, ws + L.ulo, c.sloppy, c.link_fmt, 1, static_cast<long>(c.g.vol) * 4, c.st));
+        HIPCHK(launch_convert_links(c.U, ws + L.ulo, c.sloppy, c.link_fmt, 1, c.nlinks, c.st));
         HIPCHK(hipMemsetAsync(xh, 0, static_cast<size_t>(n) * 96, c.st));
     }
     // r = b - A x;  r_hat = p = lo(r)
@@ -695,16 +729,15 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
     return hipSuccess;
 }
 
-hipError_t run_cg(const void *U, const void *b, void *x, const GeomDev &g, int kind, double diag, double mf,
-                  const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status) {
+hipError_t run_cg_op(const CgOp &op, const void *U, const void *b, void *x, long nsites, long nlinks,
+                     const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status) {
     CgRun c;
     c.U = U;
     c.b = b;
     c.x = x;
-    c.g = g;
-    c.kind = kind;
-    c.diag = diag;
-    c.mf = mf;
+    c.n = nsites;
+    c.nlinks = nlinks;
+    c.op = op;
     c.tol = p.tol;
     c.maxiter = p.maxiter;
     c.sloppy = p.sloppy_prec;
@@ -723,6 +756,44 @@ hipError_t run_cg(const void *U, const void *b, void *x, const GeomDev &g, int k
         e = cg_T<SpF16S>(c, stats, status);
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return e;
+}
+
+hipError_t run_cg(const void *U, const void *b, void *x, const GeomDev &g, int kind, double diag, double mf,
+                  const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status) {
+    FullOp o;
+    o.g = g;
+    o.kind = kind;
+    o.diag = diag;
+    o.mf = mf;
+    CgOp op;
+    op.apply = full_apply;
+    op.ctx = &o;
+    return run_cg_op(op, U, b, x, g.n5, static_cast<long>(g.vol) * 4, p, ws, st, stats, status);
+}
+
+// ||a - b||^2 (b may be NULL) over n FP64 spinor sites, summed deterministically; waits for the
+// stream. `part` holds kRedBlocks + 16 doubles of device scratch.
+hipError_t norm2_diff(const void *a, const void *b, long n, double *part, hipStream_t st, double *result) {
+    const int np = static_cast<int>((n + kThreads - 1) / kThreads < kRedBlocks ? (n + kThreads - 1) / kThreads
+                                                                                : kRedBlocks);
+    if (n == 0) {
+        *result = 0.0;
+        return hipSuccess;
+    }
+    if (b)
+        hipLaunchKernelGGL(k_diff_norm2, dim3(np), dim3(kThreads), 0, st, static_cast<const double2 *>(a),
+                           static_cast<const double2 *>(b), n * 12, part);
+    else
+        hipLaunchKernelGGL(k_dot_flat<double2>, dim3(np), dim3(kThreads), 0, st, static_cast<const double2 *>(a),
+                           static_cast<const double2 *>(a), n * 12, part);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, st, part, np, part + kRedBlocks, 0);
+    HIPCHK(hipGetLastError());
+    double h = 0.0;
+    HIPCHK(hipMemcpyAsync(&h, part + kRedBlocks, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *result = h;
+    return hipSuccess;
 }
 
 }  // namespace gridmi

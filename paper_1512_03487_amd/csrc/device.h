@@ -206,6 +206,68 @@ struct SpF16S {
 };
 
 // ------------------------------------------------------------------------------------------
+// Per-component access to a spinor record (used where lanes own components, not sites).
+// ------------------------------------------------------------------------------------------
+
+// Complex number k (spin k / 3, colour k % 3) of a record: staged in LDS or in global memory.
+template <class SP>
+struct Elem;
+
+template <>
+struct Elem<SpF64> {
+    __device__ __forceinline__ static Cx<double> get(const void *rec, int k, float) {
+        const double2 v = reinterpret_cast<const double2 *>(rec)[k];
+        return {v.x, v.y};
+    }
+};
+template <>
+struct Elem<SpF32> {
+    __device__ __forceinline__ static Cx<float> get(const void *rec, int k, float) {
+        const float2 v = reinterpret_cast<const float2 *>(rec)[k];
+        return {v.x, v.y};
+    }
+};
+template <>
+struct Elem<SpF16S> {
+    __device__ __forceinline__ static Cx<float> get(const void *rec, int k, float s) {
+        const uint32_t w = reinterpret_cast<const uint32_t *>(rec)[k];
+        return {half_bits_to_float(w & 0xffffu) * s, half_bits_to_float(w >> 16) * s};
+    }
+};
+
+template <class SP>
+__device__ __forceinline__ Cx<typename SP::C> global_elem(const void *base, const float *scale, size_t rec, int k) {
+    const char *p = reinterpret_cast<const char *>(base) + rec * (SP::kChunks * 16);
+    return Elem<SP>::get(p, k, SP::kScaled ? scale[rec] : 1.0f);
+}
+
+// Store complex k of record rec. FP16 storage: the 16 lanes of a site (12 active) agree on the
+// site scale max |re|, |im| before encoding.
+template <class SP>
+__device__ __forceinline__ void store_elem(void *base, float *scale, size_t rec, int k, Cx<typename SP::C> v, bool live);
+
+template <>
+__device__ __forceinline__ void store_elem<SpF64>(void *base, float *, size_t rec, int k, Cx<double> v, bool live) {
+    if (live) reinterpret_cast<double2 *>(base)[rec * 12 + k] = make_double2(v.r, v.i);
+}
+template <>
+__device__ __forceinline__ void store_elem<SpF32>(void *base, float *, size_t rec, int k, Cx<float> v, bool live) {
+    if (live) reinterpret_cast<float2 *>(base)[rec * 12 + k] = make_float2(v.r, v.i);
+}
+template <>
+__device__ __forceinline__ void store_elem<SpF16S>(void *base, float *scale, size_t rec, int k, Cx<float> v, bool live) {
+    float m = live ? fmaxf(fabsf(v.r), fabsf(v.i)) : 0.f;
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 16));
+    const float inv = m > 0.f ? 1.0f / m : 0.f;
+    const uint32_t w = scaled_half_bits(v.r, inv) | (scaled_half_bits(v.i, inv) << 16);
+    if (live) {
+        reinterpret_cast<uint32_t *>(base)[rec * 12 + k] = w;
+        if (k == 0) scale[rec] = m;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // Link storage. `link` = site * 4 + mu. Loads fill u[3][3] (row 2 rebuilt for 12-real links).
 // ------------------------------------------------------------------------------------------
 

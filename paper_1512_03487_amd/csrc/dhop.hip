@@ -47,64 +47,6 @@ __device__ __forceinline__ void wave_sync() {
 // 16-byte chunk as a native vector type.
 typedef unsigned int chunk_t __attribute__((ext_vector_type(4)));
 
-// Complex number k (spin k / 3, colour k % 3) of a record: staged in LDS or in global memory.
-template <class SP>
-struct Elem;
-
-template <>
-struct Elem<SpF64> {
-    __device__ __forceinline__ static Cx<double> get(const void *rec, int k, float) {
-        const double2 v = reinterpret_cast<const double2 *>(rec)[k];
-        return {v.x, v.y};
-    }
-};
-template <>
-struct Elem<SpF32> {
-    __device__ __forceinline__ static Cx<float> get(const void *rec, int k, float) {
-        const float2 v = reinterpret_cast<const float2 *>(rec)[k];
-        return {v.x, v.y};
-    }
-};
-template <>
-struct Elem<SpF16S> {
-    __device__ __forceinline__ static Cx<float> get(const void *rec, int k, float s) {
-        const uint32_t w = reinterpret_cast<const uint32_t *>(rec)[k];
-        return {half_bits_to_float(w & 0xffffu) * s, half_bits_to_float(w >> 16) * s};
-    }
-};
-
-template <class SP>
-__device__ __forceinline__ Cx<typename SP::C> global_elem(const void *base, const float *scale, size_t rec, int k) {
-    const char *p = reinterpret_cast<const char *>(base) + rec * (SP::kChunks * 16);
-    return Elem<SP>::get(p, k, SP::kScaled ? scale[rec] : 1.0f);
-}
-
-// Store complex k of record rec. FP16 storage: the 16 lanes of a site (12 active) agree on the
-// site scale max |re|, |im| before encoding.
-template <class SP>
-__device__ __forceinline__ void store_elem(void *base, float *scale, size_t rec, int k, Cx<typename SP::C> v, bool live);
-
-template <>
-__device__ __forceinline__ void store_elem<SpF64>(void *base, float *, size_t rec, int k, Cx<double> v, bool live) {
-    if (live) reinterpret_cast<double2 *>(base)[rec * 12 + k] = make_double2(v.r, v.i);
-}
-template <>
-__device__ __forceinline__ void store_elem<SpF32>(void *base, float *, size_t rec, int k, Cx<float> v, bool live) {
-    if (live) reinterpret_cast<float2 *>(base)[rec * 12 + k] = make_float2(v.r, v.i);
-}
-template <>
-__device__ __forceinline__ void store_elem<SpF16S>(void *base, float *scale, size_t rec, int k, Cx<float> v, bool live) {
-    float m = live ? fmaxf(fabsf(v.r), fabsf(v.i)) : 0.f;
-#pragma unroll
-    for (int o = 8; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 16));
-    const float inv = m > 0.f ? 1.0f / m : 0.f;
-    const uint32_t w = scaled_half_bits(v.r, inv) | (scaled_half_bits(v.i, inv) << 16);
-    if (live) {
-        reinterpret_cast<uint32_t *>(base)[rec * 12 + k] = w;
-        if (k == 0) scale[rec] = m;
-    }
-}
-
 // Division by a launch-invariant divisor d >= 1 for 0 <= n < 2^31: q = (umulhi(n, m) + n) >> l with
 // l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1 (Granlund and Montgomery's division by
 // invariant integers; n + umulhi(n, m) < 2^32 because n < 2^31).
@@ -123,10 +65,14 @@ __device__ __forceinline__ int fdiv(int n, FastDiv f) {
     return static_cast<int>((__umulhi(static_cast<uint32_t>(n), f.m) + static_cast<uint32_t>(n)) >> f.l);
 }
 
-// Traversal order: s, x, y, t within a slab of nt time slices, z, slab.
+// Traversal order: s, x, y, t within a slab of nt time slices, z, slab. For checkerboard output
+// (cbp = 0 / 1) x runs over Lx / 2 and the site of parity cbp in each pair is taken.
 struct Trav {
     FastDiv ls, lx, ly, nt, lz;
-    int nts;   // nt
+    int nts;    // nt
+    int lxn;    // x extent of the traversal (Lx or Lx / 2)
+    int cbp;    // output checkerboard, -1 for the full lattice
+    int nout;   // 5D sites written
 };
 
 // Traversal index j -> coordinates, 4D site and s.
@@ -135,7 +81,7 @@ __device__ __forceinline__ void trav_decode(const GeomDev &g, const Trav &tr, in
     s = j - q * g.Ls;
     j = q;
     q = fdiv(j, tr.lx);
-    x[0] = j - q * g.L[0];
+    x[0] = j - q * tr.lxn;
     j = q;
     q = fdiv(j, tr.ly);
     x[1] = j - q * g.L[1];
@@ -146,6 +92,7 @@ __device__ __forceinline__ void trav_decode(const GeomDev &g, const Trav &tr, in
     q = fdiv(j, tr.lz);
     x[2] = j - q * g.L[2];
     x[3] = q * tr.nts + tl;
+    if (tr.cbp >= 0) x[0] = 2 * x[0] + ((x[1] + x[2] + x[3] + tr.cbp) & 1);
     site4 = x[0] + g.L[0] * (x[1] + g.L[1] * (x[2] + g.L[2] * x[3]));
 }
 
@@ -160,14 +107,14 @@ __device__ __forceinline__ int stride_of(const GeomDev &g) {
 template <class SP, class LK, int MU, bool BWD, int E>
 __device__ __forceinline__ void dir_term(const void *__restrict__ U, const void *__restrict__ psi,
                                          const float *__restrict__ psi_scale, const GeomDev &g, const int x[4],
-                                         int site4, int s, int sl, int sp, chunk_t *lds) {
+                                         int site4, int s, int sl, int sp, int cbin, chunk_t *lds) {
     using C = typename SP::C;
     constexpr int CH = SP::kChunks, PITCH = CH + 1;
     const int lane = threadIdx.x & 63;
     const int L = g.L[MU], st = stride_of<MU>(g);
     const int nb4 = BWD ? (x[MU] == 0 ? site4 + (L - 1) * st : site4 - st)
                         : (x[MU] == L - 1 ? site4 - (L - 1) * st : site4 + st);
-    const int rec = nb4 * g.Ls + s;
+    const int rec = (nb4 >> cbin) * g.Ls + s;   // checkerboard input: half-volume index
     // coalesced fetch of the 32 records (record r is named by lane 2r)
     const chunk_t *src = reinterpret_cast<const chunk_t *>(psi);
     constexpr int NCH = kSites * CH, NK = (NCH + 63) / 64;
@@ -232,7 +179,8 @@ __device__ __forceinline__ void dir_term(const void *__restrict__ U, const void 
 template <class SP, class LK, bool DAG, int KIND>
 __global__ void __launch_bounds__(kBlock)
 k_dhop_dir(const void *__restrict__ U, const void *__restrict__ psi, const float *__restrict__ psi_scale,
-       void *__restrict__ out, float *__restrict__ out_scale, GeomDev g, Trav tr, double diag, double mf) {
+           const void *__restrict__ yv, const float *__restrict__ y_scale, void *__restrict__ out,
+           float *__restrict__ out_scale, GeomDev g, Trav tr, double diag, double mf, double beta) {
     using C = typename SP::C;
     constexpr int PITCH = SP::kChunks + 1;
     __shared__ chunk_t sm[kDirs][kSites * PITCH];
@@ -243,27 +191,28 @@ k_dhop_dir(const void *__restrict__ U, const void *__restrict__ psi, const float
     constexpr int EF = DAG ? +1 : -1;
     {
         const int sl = lane >> 1, sp = lane & 1;
-        const int j = min(base + sl, g.n5 - 1);   // idle lanes of a ragged block still take part
+        const int j = min(base + sl, tr.nout - 1);   // idle lanes of a ragged block still take part
         int x[4], site4, s;
         trav_decode(g, tr, j, x, site4, s);
         if (wv == 0 && sp == 0) sinfo[sl] = make_int2(site4, s);
         chunk_t *lds = sm[wv];
+        const int cbin = tr.cbp >= 0 ? 1 : 0;
         switch (wv) {
-            case 0: dir_term<SP, LK, 0, false, EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, lds); break;
-            case 1: dir_term<SP, LK, 0, true, -EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, lds); break;
-            case 2: dir_term<SP, LK, 1, false, EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, lds); break;
-            case 3: dir_term<SP, LK, 1, true, -EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, lds); break;
-            case 4: dir_term<SP, LK, 2, false, EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, lds); break;
-            case 5: dir_term<SP, LK, 2, true, -EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, lds); break;
-            case 6: dir_term<SP, LK, 3, false, EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, lds); break;
-            default: dir_term<SP, LK, 3, true, -EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, lds); break;
+            case 0: dir_term<SP, LK, 0, false, EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, cbin, lds); break;
+            case 1: dir_term<SP, LK, 0, true, -EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, cbin, lds); break;
+            case 2: dir_term<SP, LK, 1, false, EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, cbin, lds); break;
+            case 3: dir_term<SP, LK, 1, true, -EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, cbin, lds); break;
+            case 4: dir_term<SP, LK, 2, false, EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, cbin, lds); break;
+            case 5: dir_term<SP, LK, 2, true, -EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, cbin, lds); break;
+            case 6: dir_term<SP, LK, 3, false, EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, cbin, lds); break;
+            default: dir_term<SP, LK, 3, true, -EF>(U, psi, psi_scale, g, x, site4, s, sl, sp, cbin, lds); break;
         }
     }
     __syncthreads();
     // Phase 2: lane (site sl, component k = 3 a + c); lanes 12..15 of a site are idle.
     const int sl = threadIdx.x >> 4, k16 = threadIdx.x & 15;
     const int j = base + sl;
-    const bool live = j < g.n5 && k16 < 12;
+    const bool live = j < tr.nout && k16 < 12;
     const int k = k16 < 12 ? k16 : 0;
     const int a = k / 3, c = k - 3 * (k / 3);
     const bool up = a < 2;
@@ -287,13 +236,17 @@ k_dhop_dir(const void *__restrict__ U, const void *__restrict__ psi, const float
         acc = {acc.r + pr * d.r - pi * d.i, acc.i + pr * d.i + pi * d.r};
     }
     const int2 si = sinfo[sl];
-    const int site4 = si.x, s = si.y;
-    const size_t q = static_cast<size_t>(site4) * g.Ls + s;
-    if (KIND != GRID_HOP) {
-        // D = (4 + m) - H/2;  M = (5 - M5) - H/2 - (fifth-dimension hopping)
-        const Cx<C> v = global_elem<SP>(psi, psi_scale, q, k);
-        const C dg = static_cast<C>(diag), half = static_cast<C>(0.5);
-        acc = {dg * v.r - half * acc.r, dg * v.i - half * acc.i};
+    const int site4o = si.x >> (tr.cbp >= 0 ? 1 : 0), s = si.y;   // output (checkerboard) 4D index
+    const size_t q = static_cast<size_t>(site4o) * g.Ls + s;
+    const C bt = static_cast<C>(beta);
+    if (KIND == GRID_HOP) {
+        acc = {bt * acc.r, bt * acc.i};
+    } else {
+        // D = (4 + m) - H/2;  M = (5 - M5) - H/2 - (fifth-dimension hopping); the diagonal part
+        // acts on y (= psi on the full lattice), H is scaled by beta (= -1/2 there)
+        const Cx<C> v = global_elem<SP>(yv, y_scale, q, k);
+        const C dg = static_cast<C>(diag);
+        acc = {dg * v.r + bt * acc.r, dg * v.i + bt * acc.i};
     }
     if (KIND == GRID_DWF) {
         // M:   - P_- psi~_{s+1} - P_+ psi~_{s-1};  M^dagger: - P_+ psi~_{s+1} - P_- psi~_{s-1}
@@ -303,18 +256,21 @@ k_dhop_dir(const void *__restrict__ U, const void *__restrict__ psi, const float
         const bool from_up = (a >> 1) == hup;
         const int s2 = from_up ? (s == Ls - 1 ? 0 : s + 1) : (s == 0 ? Ls - 1 : s - 1);
         const C f = from_up ? (s == Ls - 1 ? static_cast<C>(-mf) : C(1)) : (s == 0 ? static_cast<C>(-mf) : C(1));
-        const Cx<C> v = global_elem<SP>(psi, psi_scale, static_cast<size_t>(site4) * Ls + s2, k);
+        const Cx<C> v = global_elem<SP>(yv, y_scale, static_cast<size_t>(site4o) * Ls + s2, k);
         acc = {acc.r - f * v.r, acc.i - f * v.i};
     }
     store_elem<SP>(out, out_scale, q, k, acc, live);
 }
 
 // Time slices per XCD slab: Lt / 8 when Lt is a multiple of 8, else the whole extent.
-static Trav make_trav(const GeomDev &g) {
+static Trav make_trav(const GeomDev &g, int cb) {
     const int nt = (g.L[3] % 8 == 0) ? g.L[3] / 8 : g.L[3];
     Trav tr;
+    tr.cbp = cb;
+    tr.lxn = cb >= 0 ? g.L[0] / 2 : g.L[0];
+    tr.nout = cb >= 0 ? g.n5 / 2 : g.n5;
     tr.ls = make_fastdiv(g.Ls);
-    tr.lx = make_fastdiv(g.L[0]);
+    tr.lx = make_fastdiv(tr.lxn);
     tr.ly = make_fastdiv(g.L[1]);
     tr.nt = make_fastdiv(nt);
     tr.lz = make_fastdiv(g.L[2]);
@@ -324,13 +280,16 @@ static Trav make_trav(const GeomDev &g) {
 
 template <class SP, class LK>
 static hipError_t launch_dir(const DhopArgs &a) {
-    const Trav tr = make_trav(a.g);
-    const long nblocks = (static_cast<long>(a.g.n5) + kSites - 1) / kSites;
+    const Trav tr = make_trav(a.g, a.custom ? a.cb : -1);
+    const long nblocks = (static_cast<long>(tr.nout) + kSites - 1) / kSites;
+    const void *y = a.custom ? a.y : a.psi;
+    const float *ys = a.custom ? a.y_scale : a.psi_scale;
+    const double beta = a.custom ? a.beta : (a.kind == GRID_HOP ? 1.0 : -0.5);
     const dim3 grid(static_cast<unsigned>(nblocks)), block(kBlock);
     hipStream_t st = a.stream;
 #define GRIDMI_LAUNCH(DAG, KIND)                                                                          \
-    hipLaunchKernelGGL((k_dhop_dir<SP, LK, DAG, KIND>), grid, block, 0, st, a.U, a.psi, a.psi_scale, a.out, \
-                       a.out_scale, a.g, tr, a.diag, a.mf)
+    hipLaunchKernelGGL((k_dhop_dir<SP, LK, DAG, KIND>), grid, block, 0, st, a.U, a.psi, a.psi_scale, y, ys,     \
+                       a.out, a.out_scale, a.g, tr, a.diag, a.mf, beta)
     switch (a.kind * 2 + (a.dag ? 1 : 0)) {
         case GRID_HOP * 2 + 0: GRIDMI_LAUNCH(false, GRID_HOP); break;
         case GRID_HOP * 2 + 1: GRIDMI_LAUNCH(true, GRID_HOP); break;
@@ -613,10 +572,11 @@ static hipError_t launch_walk(const DhopArgs &a) {
     return hipGetLastError();
 }
 
-// Direction-parallel schedule for 4D fields in FP64 / FP32, column walk otherwise.
+// Direction-parallel schedule for 4D fields in FP64 / FP32 and for every even-odd (custom) call,
+// column walk otherwise.
 template <class SP, class LK>
 static hipError_t launch_sched(const DhopArgs &a) {
-    if (a.g.Ls == 1 && !SP::kScaled) return launch_dir<SP, LK>(a);
+    if (a.custom || (a.g.Ls == 1 && !SP::kScaled)) return launch_dir<SP, LK>(a);
     return launch_walk<SP, LK>(a);
 }
 

@@ -1,0 +1,345 @@
+// Even-odd (red-black) preconditioning of the Wilson and domain-wall operators.
+//
+// Grid objects may be single-checkerboard (Section 2.2): a field holding only the sites of one
+// parity p = (x + y + z + t) mod 2. Here such a field stores site (x, y, z, t) at the half-volume
+// index (x / 2) + (Lx / 2)(y + Ly(z + Lz t)), i.e. the full site index divided by two, with the
+// Ls fifth-dimension records of a 4D site contiguous as in full fields; all four extents are even.
+//
+// The hopping term connects the two parities only, so with o = odd, e = even
+//   M = [[M_ee, M_eo], [M_oe, M_oo]],  M_eo = -H_eo / 2,  M_oe = -H_oe / 2,
+//   M_ee = M_oo = (4 + m) for Wilson and the fifth-dimension operator M5 for domain wall,
+// and M x = b is solved through the Schur complement on the even sites
+//   Mhat = M_ee - M_eo M_oo^-1 M_oe = M_ee - H_eo M_oo^-1 H_oe / 4,
+//   bhat = b_e - M_eo M_oo^-1 b_o = b_e + H_eo M_oo^-1 b_o / 2,
+//   Mhat^dagger Mhat x_e = Mhat^dagger bhat (CG),   x_o = M_oo^-1 (b_o + H_oe x_e / 2).
+//
+// M5 per 4D site and chirality is (5 - M5) minus a cyclic shift in s with -m_f on the wrap: the
+// lower spins take psi_{s+1} (psi_{Ls} = -m_f psi_0), the upper spins psi_{s-1}
+// (psi_{-1} = -m_f psi_{Ls-1}); the adjoint swaps the two. Its inverse is applied in closed form:
+// for d y_s - y_{s+1} = b_s (s < Ls-1), d y_{Ls-1} + m_f y_0 = b_{Ls-1},
+//   y_0 = [sum_k b_k d^-(k+1)] / (1 + m_f d^-Ls),  y_{Ls-1} = (b_{Ls-1} - m_f y_0) / d,
+//   y_s = (b_s + y_{s+1}) / d  for s = Ls-2 .. 1,
+// and mirrored in s for the other chirality (the recurrences are stable for |d| > 1).
+#include <chrono>
+#include <string.h>
+
+#include "device.h"
+#include "launch.h"
+
+namespace gridmi {
+
+constexpr int kM5invSites = 4;   // 4D sites per block (16 lanes each, one wavefront)
+constexpr int kM5invMaxLs = 64;
+
+template <class SP>
+__global__ void __launch_bounds__(64)
+k_m5inv(const void *__restrict__ psi, const float *__restrict__ psi_scale, void *__restrict__ out,
+        float *__restrict__ out_scale, long n4, int Ls, double diag, double mf, int dag) {
+    using C = typename SP::C;
+    extern __shared__ unsigned char smem[];   // [kM5invSites][Ls][12] complex
+    const int lane = threadIdx.x;
+    const int sl = lane >> 4, k16 = lane & 15;
+    const long h = static_cast<long>(blockIdx.x) * kM5invSites + sl;
+    const bool live = h < n4 && k16 < 12;
+    const long hh = h < n4 ? h : n4 - 1;
+    const int k = k16 < 12 ? k16 : 0;
+    // non-adjoint: lower spins couple to s + 1, upper spins to s - 1; the adjoint swaps them
+    const bool plus = ((k / 3) >= 2) != (dag != 0);
+    const C d = static_cast<C>(diag), m = static_cast<C>(mf);
+    const C dinv = C(1) / d;
+    C dl = C(1);
+    for (int i = 0; i < Ls; ++i) dl *= dinv;
+    const C den = C(1) + m * dl;
+    Cx<C> *yb = reinterpret_cast<Cx<C> *>(smem) + static_cast<size_t>(sl) * Ls * 12;
+    const size_t base = static_cast<size_t>(hh) * Ls;
+    const bool wr = k16 < 12;
+    auto put = [&](int s, Cx<C> v) {
+        if (wr) yb[s * 12 + k] = v;
+    };
+    if (plus) {
+        Cx<C> S = {C(0), C(0)};
+        for (int s = Ls - 1; s >= 0; --s) {
+            const Cx<C> b = global_elem<SP>(psi, psi_scale, base + s, k);
+            S = {(S.r + b.r) * dinv, (S.i + b.i) * dinv};
+        }
+        const Cx<C> y0 = {S.r / den, S.i / den};
+        put(0, y0);
+        if (Ls > 1) {
+            Cx<C> b = global_elem<SP>(psi, psi_scale, base + Ls - 1, k);
+            Cx<C> y = {(b.r - m * y0.r) * dinv, (b.i - m * y0.i) * dinv};
+            put(Ls - 1, y);
+            for (int s = Ls - 2; s >= 1; --s) {
+                b = global_elem<SP>(psi, psi_scale, base + s, k);
+                y = {(b.r + y.r) * dinv, (b.i + y.i) * dinv};
+                put(s, y);
+            }
+        }
+    } else {
+        Cx<C> S = {C(0), C(0)};
+        for (int s = 0; s < Ls; ++s) {
+            const Cx<C> b = global_elem<SP>(psi, psi_scale, base + s, k);
+            S = {(S.r + b.r) * dinv, (S.i + b.i) * dinv};
+        }
+        const Cx<C> yl = {S.r / den, S.i / den};
+        put(Ls - 1, yl);
+        if (Ls > 1) {
+            Cx<C> b = global_elem<SP>(psi, psi_scale, base, k);
+            Cx<C> y = {(b.r - m * yl.r) * dinv, (b.i - m * yl.i) * dinv};
+            put(0, y);
+            for (int s = 1; s <= Ls - 2; ++s) {
+                b = global_elem<SP>(psi, psi_scale, base + s, k);
+                y = {(b.r + y.r) * dinv, (b.i + y.i) * dinv};
+                put(s, y);
+            }
+        }
+    }
+    __syncthreads();
+    for (int s = 0; s < Ls; ++s) {
+        const Cx<C> v = yb[s * 12 + k];
+        store_elem<SP>(out, out_scale, base + s, k, v, live);
+    }
+}
+
+hipError_t launch_m5inv(const void *psi, const float *psi_scale, void *out, float *out_scale, long n4, int Ls,
+                        double diag, double mf, int dag, int prec, hipStream_t stream) {
+    if (n4 == 0) return hipSuccess;
+    if (Ls < 1 || Ls > kM5invMaxLs) return hipErrorInvalidValue;
+    const dim3 grid(static_cast<unsigned>((n4 + kM5invSites - 1) / kM5invSites)), block(64);
+    const size_t c = prec == GRID_F64 ? sizeof(Cx<double>) : sizeof(Cx<float>);
+    const size_t lds = kM5invSites * static_cast<size_t>(Ls) * 12 * c;
+    if (prec == GRID_F64)
+        hipLaunchKernelGGL(k_m5inv<SpF64>, grid, block, lds, stream, psi, psi_scale, out, out_scale, n4, Ls, diag, mf, dag);
+    else if (prec == GRID_F32)
+        hipLaunchKernelGGL(k_m5inv<SpF32>, grid, block, lds, stream, psi, psi_scale, out, out_scale, n4, Ls, diag, mf, dag);
+    else
+        hipLaunchKernelGGL(k_m5inv<SpF16S>, grid, block, lds, stream, psi, psi_scale, out, out_scale, n4, Ls, diag, mf,
+                           dag);
+    return hipGetLastError();
+}
+
+// Copy between a full FP64 field and one checkerboard of it (to_cb: full -> checkerboard).
+__global__ void __launch_bounds__(256)
+k_cb_copy(const double2 *__restrict__ src, double2 *__restrict__ dst, GeomDev g, int parity, int to_cb, long nchunks) {
+    const long i = static_cast<long>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= nchunks) return;
+    const long rec = i / 12;
+    const int c = static_cast<int>(i - rec * 12);
+    const long h = rec / g.Ls;
+    const int s = static_cast<int>(rec - h * g.Ls);
+    const int lxh = g.L[0] / 2;
+    long r = h / lxh;
+    const int xh = static_cast<int>(h - r * lxh);
+    const int y = static_cast<int>(r % g.L[1]);
+    r /= g.L[1];
+    const int z = static_cast<int>(r % g.L[2]);
+    const int t = static_cast<int>(r / g.L[2]);
+    const int x = 2 * xh + ((y + z + t + parity) & 1);
+    const long full = (x + static_cast<long>(g.L[0]) * (y + static_cast<long>(g.L[1]) * (z + static_cast<long>(g.L[2]) * t))) *
+                          g.Ls + s;
+    if (to_cb)
+        dst[i] = src[full * 12 + c];
+    else
+        dst[full * 12 + c] = src[i];
+}
+
+static hipError_t cb_copy(const void *src, void *dst, const GeomDev &g, int parity, int to_cb, hipStream_t st) {
+    const long n = static_cast<long>(g.n5 / 2) * 12;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cb_copy, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
+                       static_cast<const double2 *>(src), static_cast<double2 *>(dst), g, parity, to_cb, n);
+    return hipGetLastError();
+}
+
+#define EOCHK(x)                                \
+    do {                                        \
+        hipError_t e_ = (x);                    \
+        if (e_ != hipSuccess) return e_;        \
+    } while (0)
+
+// out (checkerboard cb) = diagonal part of `kind` (coefficient dg) on y + beta * H psi.
+static hipError_t hop_cb(const void *U, int prec, int fmt, const GeomDev &g, int kind, int dag, double dg, double mf,
+                         int cb, const void *psi, const float *psis, const void *y, const float *ys, double beta, void *out,
+                         float *outs, hipStream_t st) {
+    DhopArgs a;
+    a.U = U;
+    a.psi = psi;
+    a.psi_scale = psis;
+    a.out = out;
+    a.out_scale = outs;
+    a.g = g;
+    a.prec = prec;
+    a.link_fmt = fmt;
+    a.kind = kind;
+    a.dag = dag;
+    a.diag = dg;
+    a.mf = mf;
+    a.stream = st;
+    a.custom = true;
+    a.cb = cb;
+    a.y = y;
+    a.y_scale = ys;
+    a.beta = beta;
+    return launch_dhop(a);
+}
+
+// The Schur operator Mhat (dag: Mhat^dagger) on even checkerboard fields, with two temporaries
+// per precision class (index 0: FP64, 1: the sloppy precision).
+struct EoOp {
+    GeomDev g;
+    int kind;
+    double diag, mf;
+    void *t1[2], *t2[2];
+    float *t1s, *t2s;   // sloppy FP16 scales
+};
+
+static hipError_t eo_apply(const void *ctx, const void *U, int prec, int fmt, const void *in, const float *ins, void *out,
+                           float *outs, int dag, hipStream_t st) {
+    const EoOp &o = *static_cast<const EoOp *>(ctx);
+    const int ix = prec == GRID_F64 ? 0 : 1;
+    float *t1s = prec == GRID_F16S ? o.t1s : nullptr, *t2s = prec == GRID_F16S ? o.t2s : nullptr;
+    // t1 = H_oe in
+    EOCHK(hop_cb(U, prec, fmt, o.g, GRID_HOP, dag, 0.0, o.mf, 1, in, ins, nullptr, nullptr, 1.0, o.t1[ix], t1s, st));
+    const void *src = o.t1[ix];
+    const float *srcs = t1s;
+    if (o.kind == GRID_DWF) {
+        EOCHK(launch_m5inv(o.t1[ix], t1s, o.t2[ix], t2s, o.g.vol / 2, o.g.Ls, o.diag, o.mf, dag, prec, st));
+        src = o.t2[ix];
+        srcs = t2s;
+    }
+    // out = M_ee in - H_eo M_oo^-1 H_oe in / 4  (Wilson: M_oo^-1 = 1 / (4 + m) folded into beta)
+    const double beta = o.kind == GRID_WILSON ? -0.25 / o.diag : -0.25;
+    return hop_cb(U, prec, fmt, o.g, o.kind, dag, o.diag, o.mf, 0, src, srcs, in, ins, beta, out, outs, st);
+}
+
+static size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct EoLayout {
+    size_t be, bo, bhat, rhs, xe, xo, t1, t2, t1h, t2h, t1hs, t2hs, norm, cg, total;
+};
+
+static EoLayout eo_layout(const GeomDev &g, int sloppy, int link_fmt) {
+    EoLayout L;
+    memset(&L, 0, sizeof(L));
+    const size_t n = static_cast<size_t>(g.n5 / 2);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = al256(off + bytes);
+        return o;
+    };
+    // be and bo adjacent: together they hold a full FP64 field for the final residual
+    L.be = take(2 * n * 192);
+    L.bo = L.be + n * 192;
+    L.bhat = take(n * 192);
+    L.rhs = take(n * 192);
+    L.xe = take(n * 192);
+    L.xo = take(n * 192);
+    L.t1 = take(n * 192);
+    L.t2 = take(n * 192);
+    if (sloppy != GRID_F64) {
+        const size_t sb = sloppy == GRID_F32 ? 96 : 48;
+        L.t1h = take(n * sb);
+        L.t2h = take(n * sb);
+        if (sloppy == GRID_F16S) {
+            L.t1hs = take(n * 4);
+            L.t2hs = take(n * 4);
+        }
+    }
+    L.norm = take(kNormScratch * sizeof(double));
+    L.cg = off;
+    L.total = off + cg_workspace_bytes_n(static_cast<long>(n), static_cast<long>(g.vol) * 4, sloppy, link_fmt);
+    return L;
+}
+
+size_t solve_eo_workspace_bytes(const GeomDev &g, int sloppy, int link_fmt) { return eo_layout(g, sloppy, link_fmt).total; }
+
+hipError_t run_solve_eo(const void *U, const void *b, void *x, const GeomDev &g, int kind, double diag, double mf,
+                        const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const EoLayout L = eo_layout(g, p.sloppy_prec, p.link_fmt);
+    char *w = static_cast<char *>(ws);
+    void *be = w + L.be, *bo = w + L.bo, *bhat = w + L.bhat, *rhs = w + L.rhs, *xe = w + L.xe, *xo = w + L.xo;
+    double *norm = reinterpret_cast<double *>(w + L.norm);
+    const long n = g.n5 / 2;
+    *status = GRID_OK;
+    memset(stats, 0, sizeof(*stats));
+
+    double bb = 0.0;
+    EOCHK(norm2_diff(b, nullptr, g.n5, norm, st, &bb));
+    if (bb == 0.0) {
+        EOCHK(hipMemsetAsync(x, 0, static_cast<size_t>(g.n5) * 192, st));
+        EOCHK(hipStreamSynchronize(st));
+        stats->converged = 1;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return hipSuccess;
+    }
+    EoOp o;
+    o.g = g;
+    o.kind = kind;
+    o.diag = diag;
+    o.mf = mf;
+    o.t1[0] = w + L.t1;
+    o.t2[0] = w + L.t2;
+    o.t1[1] = p.sloppy_prec != GRID_F64 ? w + L.t1h : nullptr;
+    o.t2[1] = p.sloppy_prec != GRID_F64 ? w + L.t2h : nullptr;
+    o.t1s = p.sloppy_prec == GRID_F16S ? reinterpret_cast<float *>(w + L.t1hs) : nullptr;
+    o.t2s = p.sloppy_prec == GRID_F16S ? reinterpret_cast<float *>(w + L.t2hs) : nullptr;
+
+    EOCHK(cb_copy(b, be, g, 0, 1, st));
+    EOCHK(cb_copy(b, bo, g, 1, 1, st));
+    // bhat = b_e + H_eo M_oo^-1 b_o / 2
+    const void *src = bo;
+    double beta = 0.5 / diag;
+    if (kind == GRID_DWF) {
+        EOCHK(launch_m5inv(bo, nullptr, o.t1[0], nullptr, g.vol / 2, g.Ls, diag, mf, 0, GRID_F64, st));
+        src = o.t1[0];
+        beta = 0.5;
+    }
+    EOCHK(hop_cb(U, GRID_F64, GRID_L18, g, GRID_WILSON, 0, 1.0, mf, 0, src, nullptr, be, nullptr, beta, bhat, nullptr, st));
+    // rhs = Mhat^dagger bhat; initial guess: the even part of x
+    EOCHK(eo_apply(&o, U, GRID_F64, GRID_L18, bhat, nullptr, rhs, nullptr, 1, st));
+    EOCHK(cb_copy(x, xe, g, 0, 1, st));
+    CgOp op;
+    op.apply = eo_apply;
+    op.ctx = &o;
+    grid_cg_stats cs;
+    memset(&cs, 0, sizeof(cs));
+    EOCHK(run_cg_op(op, U, rhs, xe, n, static_cast<long>(g.vol) * 4, p, w + L.cg, st, &cs, status));
+    // x_o = M_oo^-1 (b_o + H_oe x_e / 2)
+    if (kind == GRID_DWF) {
+        EOCHK(hop_cb(U, GRID_F64, GRID_L18, g, GRID_WILSON, 0, 1.0, mf, 1, xe, nullptr, bo, nullptr, 0.5, o.t1[0], nullptr,
+                     st));
+        EOCHK(launch_m5inv(o.t1[0], nullptr, xo, nullptr, g.vol / 2, g.Ls, diag, mf, 0, GRID_F64, st));
+    } else {
+        EOCHK(hop_cb(U, GRID_F64, GRID_L18, g, GRID_WILSON, 0, 1.0 / diag, mf, 1, xe, nullptr, bo, nullptr, 0.5 / diag, xo,
+                     nullptr, st));
+    }
+    EOCHK(cb_copy(xe, x, g, 0, 0, st));
+    EOCHK(cb_copy(xo, x, g, 1, 0, st));
+    // true residual of the full system, in FP64 (be|bo now hold M x)
+    DhopArgs a;
+    a.U = U;
+    a.psi = x;
+    a.psi_scale = nullptr;
+    a.out = be;
+    a.out_scale = nullptr;
+    a.g = g;
+    a.prec = GRID_F64;
+    a.link_fmt = GRID_L18;
+    a.kind = kind;
+    a.dag = 0;
+    a.diag = diag;
+    a.mf = mf;
+    a.stream = st;
+    EOCHK(launch_dhop(a));
+    double rr = 0.0;
+    EOCHK(norm2_diff(b, be, g.n5, norm, st, &rr));
+    stats->iterations = cs.iterations;
+    stats->reliable_updates = cs.reliable_updates;
+    stats->converged = cs.converged;
+    stats->true_residual = sqrt(rr / bb);
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return hipSuccess;
+}
+
+}  // namespace gridmi

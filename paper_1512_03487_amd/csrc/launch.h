@@ -24,9 +24,27 @@ struct DhopArgs {
     double diag;   // 4 + mass (Wilson) or 5 - M5 (domain wall)
     double mf;
     hipStream_t stream;
+    // Even-odd form (direction-parallel schedule only): out (checkerboard cb) = beta * H psi
+    // (psi on checkerboard 1 - cb) + the diagonal part of `kind` applied to y (checkerboard cb).
+    // With custom == false: full lattice, y = psi, beta = 1 (HOP) or -1/2 (WILSON, DWF).
+    bool custom = false;
+    int cb = -1;               // output checkerboard 0 / 1, or -1 for full-lattice fields
+    const void *y = nullptr;
+    const float *y_scale = nullptr;
+    double beta = 0.0;
 };
 
 hipError_t launch_dhop(const DhopArgs &a);
+
+// Fifth-dimension operator inverse of the domain-wall operator (eo.hip): out = M5^-1 psi or
+// (M5^dagger)^-1 psi on n4 4D sites of Ls records each (full or checkerboard fields).
+hipError_t launch_m5inv(const void *psi, const float *psi_scale, void *out, float *out_scale, long n4, int Ls,
+                        double diag, double mf, int dag, int prec, hipStream_t stream);
+
+// Even-odd solve of M x = b (eo.hip).
+size_t solve_eo_workspace_bytes(const GeomDev &g, int sloppy, int link_fmt);
+hipError_t run_solve_eo(const void *U, const void *b, void *x, const GeomDev &g, int kind, double diag, double mf,
+                        const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status);
 
 // Link gradient / force of the hopping term (backward.hip).
 struct LinkGradArgs {
@@ -49,9 +67,21 @@ hipError_t launch_convert_spinor(const void *src, int src_prec, const float *src
 hipError_t launch_convert_links(const void *src, void *dst, int dst_prec, int dst_fmt, int reunitarise, long n_links,
                                 hipStream_t stream);
 
-// Conjugate gradient (cg.hip).
+// Conjugate gradient on A = op^dagger op (cg.hip). The operator is applied in the precision and
+// link format asked for (GRID_F64 / GRID_L18 for true residuals, the sloppy ones in iterations).
+struct CgOp {
+    hipError_t (*apply)(const void *ctx, const void *U, int prec, int fmt, const void *in, const float *ins, void *out,
+                        float *outs, int dag, hipStream_t st);
+    const void *ctx;
+};
 size_t cg_workspace_bytes(const GeomDev &g, int sloppy, int link_fmt);
+size_t cg_workspace_bytes_n(long nsites, long nlinks, int sloppy, int link_fmt);
 hipError_t run_cg(const void *U, const void *b, void *x, const GeomDev &g, int kind, double diag, double mf,
                   const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status);
+hipError_t run_cg_op(const CgOp &op, const void *U, const void *b, void *x, long nsites, long nlinks,
+                     const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status);
+// ||a - b||^2 over n FP64 spinor sites (b may be NULL); part: kRedBlocks + 16 doubles of scratch.
+constexpr int kNormScratch = 1024 + 16;
+hipError_t norm2_diff(const void *a, const void *b, long n, double *part, hipStream_t st, double *result);
 
 }  // namespace gridmi

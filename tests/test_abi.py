@@ -109,3 +109,43 @@ def test_cg_workspace_and_validation(lib):
     nodelta = _lib.GridCgParams(1e-10, 100, _lib.GRID_F32, _lib.GRID_L18, 1.5, 10)
     assert lib.grid_cg(*args(A + 0x4000000, w64 * 4, p=nodelta)) == _lib.GRID_EINVAL
     assert _lib.last_error()
+
+
+def test_even_odd_validation(lib):
+    g, go = geom((4, 4, 4, 4), Ls=4), geom((4, 3, 4, 4), Ls=4)
+    o_hop, o_dwf = op(), op(kind=_lib.GRID_DWF)
+    cb = lambda gg=g, oo=o_hop, y=None, par=0, prec=0, ps=None, os_=None: lib.grid_dhop_cb(
+        P(A), P(A + 0x1000000), P(ps), P(y), None, P(A + 0x2000000), P(os_), ctypes.byref(gg), ctypes.byref(oo), par,
+        ctypes.c_double(0.5), prec, 0, None)
+    assert cb(gg=go) == _lib.GRID_ESHAPE and "even" in _lib.last_error()
+    assert cb(par=2) == _lib.GRID_EINVAL
+    assert cb(y=A + 0x3000000) == _lib.GRID_EINVAL                           # y with GRID_HOP
+    assert cb(oo=o_dwf) == _lib.GRID_EINVAL                                  # y missing
+    assert cb(oo=op(kind=_lib.GRID_WILSON), y=A + 0x3000000) == _lib.GRID_ESHAPE   # Wilson needs Ls 1
+    assert cb(prec=_lib.GRID_F16S) == _lib.GRID_EINVAL                       # scales missing
+    m5 = lambda Ls=8, M5=1.8, n4=16: lib.grid_m5inv(P(A), None, P(A + 0x1000000), None, n4, Ls, ctypes.c_double(M5),
+                                                    ctypes.c_double(0.01), 0, 0, None)
+    assert m5(Ls=65) == _lib.GRID_ESHAPE and m5(Ls=0) == _lib.GRID_ESHAPE
+    assert m5(M5=4.5) == _lib.GRID_EINVAL                                    # |5 - M5| <= 1
+    assert m5(n4=-1) == _lib.GRID_ESHAPE
+    assert lib.grid_m5inv(P(A), None, P(A + 16), None, 16, 8, ctypes.c_double(1.8), ctypes.c_double(0.01), 0, 0,
+                          None) == _lib.GRID_EINVAL                          # overlap
+
+
+def test_solve_eo_workspace_and_validation(lib):
+    g = geom((4, 4, 4, 4), Ls=8)
+    n = 4 ** 4 * 8
+    p64 = _lib.GridCgParams(1e-10, 100, _lib.GRID_F64, _lib.GRID_L18, 0.1, 10)
+    w = lib.grid_solve_eo_workspace_bytes(ctypes.byref(g), ctypes.byref(p64))
+    assert w >= 4 * n * 192 + lib.grid_cg_workspace_bytes(ctypes.byref(geom((4, 4, 4, 4), Ls=4)), ctypes.byref(p64))
+    assert lib.grid_solve_eo_workspace_bytes(ctypes.byref(geom((4, 4, 4, 5), Ls=8)), ctypes.byref(p64)) == 0
+    st = _lib.GridCgStats()
+    args = lambda gg=g, oo=op(kind=_lib.GRID_DWF), ws=A + 0x40000000, nbytes=w: (
+        P(A), P(A + 0x10000000), P(A + 0x20000000), ctypes.byref(gg), ctypes.byref(oo), ctypes.byref(p64), P(ws),
+        ctypes.c_size_t(nbytes), ctypes.byref(st), None)
+    assert lib.grid_solve_eo(*args(gg=geom((4, 4, 6, 5), Ls=8))) == _lib.GRID_ESHAPE
+    assert lib.grid_solve_eo(*args(gg=geom((4, 4, 4, 4), Ls=65))) == _lib.GRID_ESHAPE
+    assert lib.grid_solve_eo(*args(oo=op(kind=_lib.GRID_DWF, M5=4.5))) == _lib.GRID_EINVAL
+    assert lib.grid_solve_eo(*args(oo=op(kind=_lib.GRID_HOP))) == _lib.GRID_EINVAL
+    assert lib.grid_solve_eo(*args(nbytes=w - 1)) == _lib.GRID_ESPACE
+    assert lib.grid_solve_eo(*args(ws=A + 0x40000000 + 64)) == _lib.GRID_EALIGN
