@@ -5,7 +5,8 @@ One "step" is one application of the hopping operator H on a 16^4 lattice in FP6
 links exp(0.3 i H) and a Gaussian spinor (1320 flop per site). The timed loop rotates over
 several independent (U, psi, out) buffer sets whose total size exceeds the 256 MB last-level
 cache, so every application streams its inputs from HBM. Further legs (FP32, 32^4, domain wall
-24^4 x 12 in FP32 and FP16 storage, and the CG on 16^4 x 16) are reported alongside.
+24^4 x 12 in FP32 and FP16 storage, the CG on 16^4 x 16, and the even-odd preconditioned solve of
+M x = b on the same lattice against CG on M^dagger M) are reported alongside.
 
 Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--no-cg] [--no-cpu]
 Prints one JSON line.
@@ -153,6 +154,53 @@ def cg_legs():
     return out
 
 
+def eo_legs():
+    """M x = b on the 16^4 x 16 domain-wall workload: CG on M^dagger M (source M^dagger b) against
+    even-odd preconditioned CG, each in FP64 and mixed precision, to a normal-equation residual of
+    1e-10; the full residual |b - M x| / |b| is reported for both."""
+    import torch
+    import paper_1512_03487_amd as gm
+    from paper_1512_03487_amd import fields
+    dev = torch.device("cuda:0")
+    dims, Ls = (16, 16, 16, 16), 16
+    U = torch.from_numpy(fields.gauge_field(dims, seed=1, kind="haar")).to(dev)
+    b = torch.from_numpy(fields.spinor_field(dims, seed=3, Ls=Ls)).to(dev)
+    bn = float(torch.linalg.vector_norm(b))
+    kw = dict(M5=1.8, mf=0.01)
+    out = {"lattice": list(dims), "Ls": Ls, "M5": 1.8, "mf": 0.01, "tol": 1e-10, "system": "M x = b"}
+
+    def full_res(x):
+        return float(torch.linalg.vector_norm(gm.dwf(U, x, **kw) - b)) / bn
+
+    for name, sloppy, fmt in (("fp64", "f64", "L18"), ("mixed_f32", "f32", "L18"), ("mixed_f16s", "f16s", "L12")):
+        ws = torch.empty(gm.cg_workspace_bytes(b, sloppy=sloppy, link_fmt=fmt), dtype=torch.uint8, device=dev)
+        gm.cg(U, b, kind="dwf", tol=1e-10, sloppy=sloppy, link_fmt=fmt, workspace=ws, maxiter=20, raise_on_fail=False,
+              **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c = gm.dwf(U, b, dag=True, **kw)
+        x, st = gm.cg(U, c, kind="dwf", tol=1e-10, sloppy=sloppy, link_fmt=fmt, workspace=ws, **kw)
+        torch.cuda.synchronize()
+        t_full = time.perf_counter() - t0
+        r_full = full_res(x)
+        del ws, x, c
+        ws = torch.empty(gm.solve_eo_workspace_bytes(b, sloppy=sloppy, link_fmt=fmt), dtype=torch.uint8, device=dev)
+        gm.solve_eo(U, b, kind="dwf", tol=1e-10, sloppy=sloppy, link_fmt=fmt, workspace=ws, maxiter=20,
+                    raise_on_fail=False, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, ste = gm.solve_eo(U, b, kind="dwf", tol=1e-10, sloppy=sloppy, link_fmt=fmt, workspace=ws, **kw)
+        torch.cuda.synchronize()
+        t_eo = time.perf_counter() - t0
+        out[name] = {"cgnr": {"seconds": round(t_full, 4), "iterations": st["iterations"],
+                              "full_residual": r_full},
+                     "even_odd": {"seconds": round(t_eo, 4), "iterations": ste["iterations"],
+                                  "full_residual": ste["true_residual"]},
+                     "speedup_even_odd": round(t_full / t_eo, 2)}
+        del ws, x
+    return out
+
+
 def cpu_baseline(seconds_target=15.0):
     """The FP64 oracle's H on the same 16^4 workload, timed on the host cores."""
     from oracle import oracle as orc
@@ -183,7 +231,12 @@ def main():
     ap.add_argument("--no-legs", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy three times (counter calibration)")
+    ap.add_argument("--only-solvers", action="store_true",
+                    help="profiling aid: run only the CG and even-odd solver legs and print them")
     args = ap.parse_args()
+    if args.only_solvers:
+        print(json.dumps({"cg_dwf_16^4x16": cg_legs(), "solve_dwf_16^4x16_even_odd": eo_legs()}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (multi-GPU sharding is not built)",
               file=sys.stderr)
@@ -225,6 +278,7 @@ def main():
         legs["dwf_24^4x12_f16s_L12"] = leg((24, 24, 24, 24), "f16s", "L12", "dwf", 12, 20, 3)
         torch.cuda.empty_cache()
     cg = None if args.no_cg else cg_legs()
+    eo = None if args.no_cg else eo_legs()
     cpu = None if args.no_cpu else cpu_baseline()
 
     traffic = measured_traffic()
@@ -253,6 +307,7 @@ def main():
         "cpu_baseline": cpu,
         "legs": legs,
         "cg_dwf_16^4x16": cg,
+        "solve_dwf_16^4x16_even_odd": eo,
         "wall_s_timed": round(wall, 4),
     }
     print(json.dumps(rec), flush=True)
