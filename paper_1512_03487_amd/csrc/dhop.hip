@@ -22,10 +22,9 @@
 // a data layout or staging that feeds the lanes contiguously.
 //
 // Traversal. Blocks are renumbered so that each XCD receives a contiguous range of the traversal
-// order; when Lt is a multiple of 8 that range is a slab of Lt/8 time slices, swept with z
-// slowest, so a record's eight uses fall within a few (x, y, t)-cross-sections of the slab and
-// mostly stay in the XCD's L2. (Halving x, y and z instead, with t swept, measured no better:
-// the slab faces read by two XCDs cost less than the cross-section working set.)
+// order, which is one of 8 sub-lattices (x, y and z halved) swept along t: a record's eight uses
+// then fall within a few cross-sections of that sub-lattice and mostly stay in the XCD's L2, and
+// only the sub-lattice faces are read by two XCDs.
 //
 // Per site: 8 x (spin projection 12 + SU(3) x half-spinor 132) + 7 x 24 reconstruction = 1320
 // flops, the convention of the flop counts quoted for this operator.
@@ -65,14 +64,19 @@ __device__ __forceinline__ int fdiv(int n, FastDiv f) {
     return static_cast<int>((__umulhi(static_cast<uint32_t>(n), f.m) + static_cast<uint32_t>(n)) >> f.l);
 }
 
-// Traversal order: s, x, y, t within a slab of nt time slices, z, slab. For checkerboard output
-// (cbp = 0 / 1) x runs over Lx / 2 and the site of parity cbp in each pair is taken.
+// Traversal order: 8 XCD domains, one per contiguous eighth of the block order (x halved for
+// checkerboard output).
+//   mode 0: the halves of x, y and z; inside a domain s, x, y, z, t (t slowest, so the domain is
+//           swept along t with an eighth of a time slice as cross-section); domain slowest;
+//   mode 1: slabs of Lt / 8 time slices; inside s, x, y, t, z (z slowest); slab slowest;
+//   mode 2: one domain in memory order s, x, y, z, t.
+// For checkerboard output (cbp = 0 / 1) the site of parity cbp in each x pair is taken.
 struct Trav {
-    FastDiv ls, lx, ly, nt, lz;
-    int nts;    // nt
-    int lxn;    // x extent of the traversal (Lx or Lx / 2)
-    int cbp;    // output checkerboard, -1 for the full lattice
-    int nout;   // 5D sites written
+    FastDiv ls, e0, e1, e2, e3;
+    int en0, en1, en2, en3;   // domain extents
+    int mode;
+    int cbp;                  // output checkerboard, -1 for the full lattice
+    int nout;                 // 5D sites written
 };
 
 // Traversal index j -> coordinates, 4D site and s.
@@ -80,18 +84,30 @@ __device__ __forceinline__ void trav_decode(const GeomDev &g, const Trav &tr, in
     int q = fdiv(j, tr.ls);
     s = j - q * g.Ls;
     j = q;
-    q = fdiv(j, tr.lx);
-    x[0] = j - q * tr.lxn;
+    q = fdiv(j, tr.e0);
+    x[0] = j - q * tr.en0;
     j = q;
-    q = fdiv(j, tr.ly);
-    x[1] = j - q * g.L[1];
+    q = fdiv(j, tr.e1);
+    x[1] = j - q * tr.en1;
     j = q;
-    q = fdiv(j, tr.nt);
-    const int tl = j - q * tr.nts;
-    j = q;
-    q = fdiv(j, tr.lz);
-    x[2] = j - q * g.L[2];
-    x[3] = q * tr.nts + tl;
+    if (tr.mode == 1) {
+        q = fdiv(j, tr.e3);
+        x[3] = j - q * tr.en3;
+        j = q;
+        q = fdiv(j, tr.e2);
+        x[2] = j - q * tr.en2;
+        x[3] += q * tr.en3;
+    } else {
+        q = fdiv(j, tr.e2);
+        x[2] = j - q * tr.en2;
+        j = q;
+        q = fdiv(j, tr.e3);
+        x[3] = j - q * tr.en3;
+        // domain index q (0 in mode 2)
+        x[0] += (q & 1) * tr.en0;
+        x[1] += ((q >> 1) & 1) * tr.en1;
+        x[2] += (q >> 2) * tr.en2;
+    }
     if (tr.cbp >= 0) x[0] = 2 * x[0] + ((x[1] + x[2] + x[3] + tr.cbp) & 1);
     site4 = x[0] + g.L[0] * (x[1] + g.L[1] * (x[2] + g.L[2] * x[3]));
 }
@@ -262,19 +278,33 @@ k_dhop_dir(const void *__restrict__ U, const void *__restrict__ psi, const float
     store_elem<SP>(out, out_scale, q, k, acc, live);
 }
 
-// Time slices per XCD slab: Lt / 8 when Lt is a multiple of 8, else the whole extent.
+// XCD domains: halves of x, y, z when those extents are even (measured best with inputs streamed
+// from HBM), else slabs of t when Lt is a multiple of 8, else a single domain.
 static Trav make_trav(const GeomDev &g, int cb) {
-    const int nt = (g.L[3] % 8 == 0) ? g.L[3] / 8 : g.L[3];
     Trav tr;
     tr.cbp = cb;
-    tr.lxn = cb >= 0 ? g.L[0] / 2 : g.L[0];
     tr.nout = cb >= 0 ? g.n5 / 2 : g.n5;
+    int e[4] = {cb >= 0 ? g.L[0] / 2 : g.L[0], g.L[1], g.L[2], g.L[3]};
+    if (e[0] % 2 == 0 && e[1] % 2 == 0 && e[2] % 2 == 0) {
+        tr.mode = 0;
+        e[0] /= 2;
+        e[1] /= 2;
+        e[2] /= 2;
+    } else if (e[3] % 8 == 0) {
+        tr.mode = 1;
+        e[3] /= 8;
+    } else {
+        tr.mode = 2;
+    }
     tr.ls = make_fastdiv(g.Ls);
-    tr.lx = make_fastdiv(tr.lxn);
-    tr.ly = make_fastdiv(g.L[1]);
-    tr.nt = make_fastdiv(nt);
-    tr.lz = make_fastdiv(g.L[2]);
-    tr.nts = nt;
+    tr.en0 = e[0];
+    tr.en1 = e[1];
+    tr.en2 = e[2];
+    tr.en3 = e[3];
+    tr.e0 = make_fastdiv(e[0]);
+    tr.e1 = make_fastdiv(e[1]);
+    tr.e2 = make_fastdiv(e[2]);
+    tr.e3 = make_fastdiv(e[3]);
     return tr;
 }
 
