@@ -19,6 +19,10 @@
  *   M psi_s   = (5 - M5) psi_s - H psi_s / 2 - P_- psi~_{s+1} - P_+ psi~_{s-1}   (Shamir DWF)
  *               with psi~_{Ls} = -mf psi_0, psi~_{-1} = -mf psi_{Ls-1};
  *   M^+ psi_s = (5 - M5) psi_s - H^+ psi_s / 2 - P_+ psi~_{s+1} - P_- psi~_{s-1}.
+ *   Moebius (the Cayley form of the five-dimensional chiral fermions listed in Section 4):
+ *   M_mob = D_W B + 1 - S,  D_W = (4 - M5) - H/2,  B = b5 + c5 S,
+ *   (S psi)_s = P_- psi~_{s+1} + P_+ psi~_{s-1} (walls as above), S^+ with P_+ and P_- swapped;
+ *   b5 = 1, c5 = 0 is the Shamir M.
  *
  * Data layout (all fields site-major, x fastest, then y, z, t; complex = interleaved re, im):
  *   spinor 4D  [Lt][Lz][Ly][Lx][4 spin][3 colour] complex
@@ -63,7 +67,7 @@ extern "C" {
 
 enum grid_prec { GRID_F64 = 0, GRID_F32 = 1, GRID_F16S = 2 };
 enum grid_link_fmt { GRID_L18 = 0, GRID_L12 = 1 };
-enum grid_op_kind { GRID_HOP = 0, GRID_WILSON = 1, GRID_DWF = 2 };
+enum grid_op_kind { GRID_HOP = 0, GRID_WILSON = 1, GRID_DWF = 2, GRID_MOBIUS = 3 };
 
 /* Lattice extents (dims[0..3] = Lx, Ly, Lz, Lt, each >= 2) and fifth extent Ls (1 for 4D). */
 typedef struct {
@@ -71,14 +75,18 @@ typedef struct {
     int Ls;
 } grid_geom;
 
-/* Operator: kind GRID_HOP (H, applied on each fifth slice when Ls > 1), GRID_WILSON (D, Ls = 1)
- * or GRID_DWF (M); dag != 0 applies the adjoint. mass is D's m; M5, mf are M's parameters. */
+/* Operator: kind GRID_HOP (H, applied on each fifth slice when Ls > 1), GRID_WILSON (D, Ls = 1),
+ * GRID_DWF (Shamir M) or GRID_MOBIUS (M_mob, through grid_mobius and grid_cg only); dag != 0
+ * applies the adjoint. mass is D's m; M5, mf the domain-wall parameters; b5, c5 the Moebius
+ * coefficients (ignored by the other kinds). */
 typedef struct {
     int kind;
     int dag;
     double mass;
     double M5;
     double mf;
+    double b5;
+    double c5;
 } grid_op;
 
 /* Conjugate-gradient parameters. */
@@ -126,6 +134,15 @@ int grid_dwf_mdag_m(const void *U, const void *psi, const float *psi_scale, void
                     int link_fmt, void *stream);
 
 /*
+ * grid_mobius -- out = M_mob psi (M_mob^+ psi when op->dag) for op->kind = GRID_MOBIUS: one
+ * s-local pass (chi = B psi; for the adjoint B^+ after the hop) and one hopping pass. tmp (and
+ * tmp_scale for GRID_F16S) holds the intermediate field and must have psi's size. Same argument
+ * rules as grid_dhop (Ls >= 1, every precision and link format). Asynchronous.
+ */
+int grid_mobius(const void *U, const void *psi, const float *psi_scale, void *out, float *out_scale, void *tmp,
+                float *tmp_scale, const grid_geom *geom, const grid_op *op, int prec, int link_fmt, void *stream);
+
+/*
  * grid_cg_workspace_bytes -- device workspace grid_cg needs for this geometry and parameters.
  * Returns 0 for invalid arguments.
  */
@@ -133,7 +150,7 @@ size_t grid_cg_workspace_bytes(const grid_geom *geom, const grid_cg_params *para
 
 /*
  * grid_cg -- solve Op^+ Op x = b by conjugate gradients (Section 4), Op = D (op->kind =
- * GRID_WILSON) or M (GRID_DWF), in FP64 or in mixed precision with reliable updates: sloppy
+ * GRID_WILSON), M (GRID_DWF) or M_mob (GRID_MOBIUS), in FP64 or in mixed precision with reliable updates: sloppy
  * iterations in FP32 or FP16-storage with FP32 arithmetic, the solution, the source and each
  * recomputed true residual in FP64, inner products and norms accumulated in FP64.
  *

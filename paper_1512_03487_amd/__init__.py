@@ -5,10 +5,10 @@ its thin torch binding. ``fields`` draws seeded synthetic inputs.
 """
 from . import fields  # noqa: F401
 from .api import (F16Spinor, cg, cg_workspace_bytes, convert_links, convert_spinor, dhop,  # noqa: F401
-                  dhop_backward, dhop_cb, dwf, dwf_mdag_m, m5inv, solve_eo, solve_eo_workspace_bytes, version,
+                  dhop_backward, dhop_cb, dwf, dwf_mdag_m, m5inv, mobius, solve_eo, solve_eo_workspace_bytes, version,
                   wilson)
 from .autograd import DhopFn, PseudofermionActionFn  # noqa: F401
 
 __all__ = ["fields", "F16Spinor", "dhop", "wilson", "dwf", "dwf_mdag_m", "cg", "cg_workspace_bytes",
-           "dhop_backward", "dhop_cb", "m5inv", "solve_eo", "solve_eo_workspace_bytes", "convert_spinor",
+           "dhop_backward", "dhop_cb", "m5inv", "mobius", "solve_eo", "solve_eo_workspace_bytes", "convert_spinor",
            "convert_links", "version", "DhopFn", "PseudofermionActionFn"]

@@ -15,10 +15,10 @@ GRID_OK, GRID_EINVAL, GRID_ESHAPE, GRID_EDTYPE, GRID_EALIGN = 0, -1, -2, -3, -4
 GRID_EHIP, GRID_ENOCONV, GRID_EBREAKDOWN, GRID_ESPACE = -5, -6, -7, -8
 GRID_F64, GRID_F32, GRID_F16S = 0, 1, 2
 GRID_L18, GRID_L12 = 0, 1
-GRID_HOP, GRID_WILSON, GRID_DWF = 0, 1, 2
+GRID_HOP, GRID_WILSON, GRID_DWF, GRID_MOBIUS = 0, 1, 2, 3
 
 #: every symbol include/grid_mi.h declares
-EXPORTS = ("grid_dhop", "grid_dwf_mdag_m", "grid_cg_workspace_bytes", "grid_cg", "grid_dhop_backward",
+EXPORTS = ("grid_dhop", "grid_mobius", "grid_dwf_mdag_m", "grid_cg_workspace_bytes", "grid_cg", "grid_dhop_backward",
            "grid_dhop_cb", "grid_m5inv", "grid_solve_eo_workspace_bytes", "grid_solve_eo",
            "grid_convert_spinor", "grid_convert_links", "grid_last_error", "grid_version")
 
@@ -29,7 +29,7 @@ class GridGeom(ctypes.Structure):
 
 class GridOp(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("dag", ctypes.c_int), ("mass", ctypes.c_double),
-                ("M5", ctypes.c_double), ("mf", ctypes.c_double)]
+                ("M5", ctypes.c_double), ("mf", ctypes.c_double), ("b5", ctypes.c_double), ("c5", ctypes.c_double)]
 
 
 class GridCgParams(ctypes.Structure):
@@ -63,6 +63,8 @@ def load():
     P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     lib.grid_dhop.argtypes = [P, P, P, P, P, ctypes.POINTER(GridGeom), ctypes.POINTER(GridOp), I, I, P]
     lib.grid_dhop.restype = I
+    lib.grid_mobius.argtypes = [P, P, P, P, P, P, P, ctypes.POINTER(GridGeom), ctypes.POINTER(GridOp), I, I, P]
+    lib.grid_mobius.restype = I
     lib.grid_dwf_mdag_m.argtypes = [P, P, P, P, P, P, P, ctypes.POINTER(GridGeom), D, D, I, I, P]
     lib.grid_dwf_mdag_m.restype = I
     lib.grid_cg_workspace_bytes.argtypes = [ctypes.POINTER(GridGeom), ctypes.POINTER(GridCgParams)]

@@ -18,10 +18,10 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import (GRID_DWF, GRID_F16S, GRID_F32, GRID_F64, GRID_HOP, GRID_L12, GRID_L18, GRID_WILSON, GridCgParams,
-                   GridCgStats, GridGeom, GridOp, check, load)
+from ._lib import (GRID_DWF, GRID_F16S, GRID_F32, GRID_F64, GRID_HOP, GRID_L12, GRID_L18, GRID_MOBIUS, GRID_WILSON,
+                   GridCgParams, GridCgStats, GridGeom, GridOp, check, load)
 
-_KIND = {"hop": GRID_HOP, "wilson": GRID_WILSON, "dwf": GRID_DWF}
+_KIND = {"hop": GRID_HOP, "wilson": GRID_WILSON, "dwf": GRID_DWF, "mobius": GRID_MOBIUS}
 _PREC = {"f64": GRID_F64, "f32": GRID_F32, "f16s": GRID_F16S}
 _FMT = {"L18": GRID_L18, "L12": GRID_L12}
 
@@ -114,11 +114,12 @@ def _empty_like(psi):
     return torch.empty_like(psi)
 
 
-def make_op(kind="hop", dag=False, mass=0.0, M5=1.8, mf=0.01) -> GridOp:
+def make_op(kind="hop", dag=False, mass=0.0, M5=1.8, mf=0.01, b5=1.0, c5=0.0) -> GridOp:
     op = GridOp()
     op.kind = _KIND[kind] if isinstance(kind, str) else int(kind)
     op.dag = int(bool(dag))
     op.mass, op.M5, op.mf = float(mass), float(M5), float(mf)
+    op.b5, op.c5 = float(b5), float(c5)
     return op
 
 
@@ -143,6 +144,22 @@ def wilson(U, psi, mass, dag=False, out=None):
 
 def dwf(U, psi, M5, mf, dag=False, out=None):
     return dhop(U, psi, "dwf", dag=dag, M5=M5, mf=mf, out=out)
+
+
+def mobius(U, psi, M5, mf, b5, c5, dag=False, out=None, tmp=None):
+    """Moebius domain-wall M psi (or M^dagger psi), M = D_W (b5 + c5 S) + 1 - S; see include/grid_mi.h."""
+    prec = spinor_prec(psi)
+    fmt = link_format(U, prec)
+    g = geom_of(psi)
+    out = _empty_like(psi) if out is None else out
+    tmp = _empty_like(psi) if tmp is None else tmp
+    pd, ps = _data_scale(psi)
+    od, os_ = _data_scale(out)
+    td, ts = _data_scale(tmp)
+    op = make_op("mobius", dag, 0.0, M5, mf, b5, c5)
+    check(load().grid_mobius(_ptr(U), _ptr(pd), _ptr(ps), _ptr(od), _ptr(os_), _ptr(td), _ptr(ts), ctypes.byref(g),
+                             ctypes.byref(op), prec, fmt, _stream(pd.device)))
+    return out
 
 
 def dwf_mdag_m(U, psi, M5, mf, out=None, tmp=None):
@@ -175,8 +192,9 @@ def cg_workspace_bytes(b, **params) -> int:
     return int(load().grid_cg_workspace_bytes(ctypes.byref(g), ctypes.byref(p)))
 
 
-def cg(U, b, kind="dwf", mass=0.0, M5=1.8, mf=0.01, x0=None, workspace=None, raise_on_fail=True, **params):
-    """Solve Op^dagger Op x = b (Op = D for kind "wilson", M for "dwf"); FP64 U, b, x.
+def cg(U, b, kind="dwf", mass=0.0, M5=1.8, mf=0.01, x0=None, workspace=None, raise_on_fail=True, b5=1.0, c5=0.0,
+       **params):
+    """Solve Op^dagger Op x = b (Op = D for kind "wilson", M for "dwf", M_mob for "mobius"); FP64 U, b, x.
 
     ``params``: tol, maxiter, sloppy ("f64" | "f32" | "f16s"), link_fmt ("L18" | "L12"), delta,
     check_every. Returns (x, stats dict). Synchronous.
@@ -189,7 +207,7 @@ def cg(U, b, kind="dwf", mass=0.0, M5=1.8, mf=0.01, x0=None, workspace=None, rai
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=b.device)
     x = torch.zeros_like(b) if x0 is None else x0.clone()
-    op = make_op(kind, False, mass, M5, mf)
+    op = make_op(kind, False, mass, M5, mf, b5, c5)
     st = GridCgStats()
     rc = load().grid_cg(_ptr(U), _ptr(b), _ptr(x), ctypes.byref(g), ctypes.byref(op), ctypes.byref(p),
                         _ptr(workspace), ctypes.c_size_t(workspace.numel()), ctypes.byref(st), _stream(b.device))

@@ -104,8 +104,8 @@ int check_even(const GeomDev &g) {
 // Operator and parameter checks shared by the solvers.
 int check_solver_args(const GeomDev &g, const grid_op *op, const grid_cg_params *params, const grid_cg_stats *stats) {
     if (!op || !params || !stats) return fail(GRID_EINVAL, "op, params and stats must not be NULL");
-    if (op->kind != GRID_WILSON && op->kind != GRID_DWF)
-        return fail(GRID_EINVAL, "the solvers take GRID_WILSON or GRID_DWF (got kind %d)", op->kind);
+    if (op->kind != GRID_WILSON && op->kind != GRID_DWF && op->kind != GRID_MOBIUS)
+        return fail(GRID_EINVAL, "the solvers take GRID_WILSON, GRID_DWF or GRID_MOBIUS (got kind %d)", op->kind);
     if (op->kind == GRID_WILSON && g.Ls != 1) return fail(GRID_ESHAPE, "GRID_WILSON needs Ls == 1 (got %d)", g.Ls);
     TRY(check_prec(params->sloppy_prec));
     TRY(check_fmt(params->link_fmt));
@@ -131,6 +131,7 @@ int grid_dhop(const void *U, const void *psi, const float *psi_scale, void *out,
     if (!op) return fail(GRID_EINVAL, "op is NULL");
     TRY(check_prec(prec));
     TRY(check_fmt(link_fmt));
+    if (op->kind == GRID_MOBIUS) return fail(GRID_EINVAL, "GRID_MOBIUS needs a temporary: use grid_mobius");
     if (op->kind != GRID_HOP && op->kind != GRID_WILSON && op->kind != GRID_DWF)
         return fail(GRID_EINVAL, "unknown operator kind %d", op->kind);
     if (op->kind == GRID_WILSON && g.Ls != 1) return fail(GRID_ESHAPE, "GRID_WILSON needs Ls == 1 (got %d)", g.Ls);
@@ -164,6 +165,46 @@ int grid_dhop(const void *U, const void *psi, const float *psi_scale, void *out,
     return ok();
 }
 
+int grid_mobius(const void *U, const void *psi, const float *psi_scale, void *out, float *out_scale, void *tmp,
+                float *tmp_scale, const grid_geom *geom, const grid_op *op, int prec, int link_fmt, void *stream) {
+    GeomDev g;
+    TRY(check_geom(geom, &g));
+    if (!op) return fail(GRID_EINVAL, "op is NULL");
+    if (op->kind != GRID_MOBIUS) return fail(GRID_EINVAL, "grid_mobius needs op->kind == GRID_MOBIUS");
+    TRY(check_prec(prec));
+    TRY(check_fmt(link_fmt));
+    TRY(check_ptr(U, "U", 16));
+    TRY(check_spinor(psi, psi_scale, prec, "psi", "psi_scale"));
+    TRY(check_spinor(out, out_scale, prec, "out", "out_scale"));
+    TRY(check_spinor(tmp, tmp_scale, prec, "tmp", "tmp_scale"));
+    const size_t sb = spinor_site_bytes(prec) * static_cast<size_t>(g.n5);
+    const size_t ub = link_bytes(prec, link_fmt) * static_cast<size_t>(g.vol) * 4;
+    const size_t cb = prec == GRID_F16S ? sizeof(float) * static_cast<size_t>(g.n5) : 0;
+    if (overlap(out, sb, psi, sb) || overlap(out, sb, U, ub) || overlap(tmp, sb, psi, sb) || overlap(tmp, sb, out, sb) ||
+        overlap(tmp, sb, U, ub))
+        return fail(GRID_EINVAL, "out, tmp, psi and U must not overlap");
+    if (cb && (overlap(out_scale, cb, psi_scale, cb) || overlap(tmp_scale, cb, psi_scale, cb) ||
+               overlap(tmp_scale, cb, out_scale, cb)))
+        return fail(GRID_EINVAL, "scale arrays overlap");
+    DhopArgs a;
+    a.U = U;
+    a.psi = psi;
+    a.psi_scale = psi_scale;
+    a.out = out;
+    a.out_scale = out_scale;
+    a.g = g;
+    a.prec = prec;
+    a.link_fmt = link_fmt;
+    a.kind = GRID_MOBIUS;
+    a.dag = op->dag ? 1 : 0;
+    a.diag = 0.0;
+    a.mf = op->mf;
+    a.stream = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_mobius(a, op->M5, op->b5, op->c5, tmp, tmp_scale);
+    if (e != hipSuccess) return hip_fail(e, "grid_mobius launch");
+    return ok();
+}
+
 int grid_dwf_mdag_m(const void *U, const void *psi, const float *psi_scale, void *out, float *out_scale, void *tmp,
                     float *tmp_scale, const grid_geom *geom, double M5, double mf, int prec, int link_fmt,
                     void *stream) {
@@ -174,7 +215,7 @@ int grid_dwf_mdag_m(const void *U, const void *psi, const float *psi_scale, void
     TRY(check_spinor(tmp, tmp_scale, prec, "tmp", "tmp_scale"));
     const size_t sb = spinor_site_bytes(prec) * static_cast<size_t>(g.n5);
     if (overlap(tmp, sb, psi, sb) || overlap(tmp, sb, out, sb)) return fail(GRID_EINVAL, "tmp overlaps psi or out");
-    grid_op m = {GRID_DWF, 0, 0.0, M5, mf};
+    grid_op m = {GRID_DWF, 0, 0.0, M5, mf, 1.0, 0.0};
     TRY(grid_dhop(U, psi, psi_scale, tmp, tmp_scale, geom, &m, prec, link_fmt, stream));
     m.dag = 1;
     return grid_dhop(U, tmp, tmp_scale, out, out_scale, geom, &m, prec, link_fmt, stream);
@@ -254,9 +295,7 @@ int grid_cg(const void *U, const void *b, void *x, const grid_geom *geom, const 
         return fail(GRID_EINVAL, "x, b, U and workspace must not overlap");
     int status = GRID_OK;
     memset(stats, 0, sizeof(*stats));
-    const double diag = op->kind == GRID_WILSON ? 4.0 + op->mass : 5.0 - op->M5;
-    hipError_t e = run_cg(U, b, x, g, op->kind, diag, op->mf, *params, workspace, static_cast<hipStream_t>(stream),
-                          stats, &status);
+    hipError_t e = run_cg(U, b, x, g, *op, *params, workspace, static_cast<hipStream_t>(stream), stats, &status);
     if (e != hipSuccess) return hip_fail(e, "grid_cg");
     if (status == GRID_ENOCONV)
         return fail(GRID_ENOCONV, "CG stopped after %d iterations at true residual %.3e", stats->iterations,
@@ -351,6 +390,7 @@ int grid_solve_eo(const void *U, const void *b, void *x, const grid_geom *geom, 
     TRY(check_geom(geom, &g));
     TRY(check_even(g));
     TRY(check_solver_args(g, op, params, stats));
+    if (op->kind == GRID_MOBIUS) return fail(GRID_EINVAL, "grid_solve_eo takes GRID_WILSON or GRID_DWF");
     if (op->kind == GRID_DWF) {
         if (g.Ls > 64) return fail(GRID_ESHAPE, "grid_solve_eo needs Ls <= 64 for the domain-wall M5 inverse");
         if (!(fabs(5.0 - op->M5) > 1.0)) return fail(GRID_EINVAL, "grid_solve_eo needs |5 - M5| > 1");

@@ -466,12 +466,13 @@ struct CgLayout {
     size_t ph, rh, qh, th;                // mixed: sloppy vectors
     size_t phs, rhs, qhs, ths;            // mixed F16S: scales
     size_t ulo;                           // mixed: sloppy links
+    size_t u, uh, uhs;                    // operator temporaries (FP64, sloppy, sloppy scales)
     size_t part;                          // partials: rr[2], pq, true, lo  (5 x kRedBlocks)
     size_t scal;                          // 16 doubles
     size_t total;
 };
 
-static CgLayout cg_layout(long nsites, long nlinks, int sloppy, int link_fmt) {
+static CgLayout cg_layout(long nsites, long nlinks, int sloppy, int link_fmt, bool op_tmp) {
     CgLayout L;
     memset(&L, 0, sizeof(L));
     const size_t n = static_cast<size_t>(nsites);
@@ -503,6 +504,13 @@ static CgLayout cg_layout(long nsites, long nlinks, int sloppy, int link_fmt) {
         const size_t cb = sloppy == GRID_F32 ? 8 : 4;
         L.ulo = take(static_cast<size_t>(nlinks) * rows * 3 * cb);
     }
+    if (op_tmp) {
+        L.u = take(n * 192);
+        if (sloppy != GRID_F64) {
+            L.uh = take(n * (sloppy == GRID_F32 ? 96 : 48));
+            if (sloppy == GRID_F16S) L.uhs = take(n * 4);
+        }
+    }
     L.part = take(5 * kRedBlocks * sizeof(double));
     L.scal = take(16 * sizeof(double));
     L.total = off;
@@ -510,11 +518,13 @@ static CgLayout cg_layout(long nsites, long nlinks, int sloppy, int link_fmt) {
 }
 
 size_t cg_workspace_bytes_n(long nsites, long nlinks, int sloppy, int link_fmt) {
-    return cg_layout(nsites, nlinks, sloppy, link_fmt).total;
+    return cg_layout(nsites, nlinks, sloppy, link_fmt, false).total;
 }
 
+// The full-lattice solve keeps one operator temporary per precision (the Moebius operator's
+// intermediate field).
 size_t cg_workspace_bytes(const GeomDev &g, int sloppy, int link_fmt) {
-    return cg_workspace_bytes_n(g.n5, static_cast<long>(g.vol) * 4, sloppy, link_fmt);
+    return cg_layout(g.n5, static_cast<long>(g.vol) * 4, sloppy, link_fmt, true).total;
 }
 
 // --------------------------------------------------------------------------------------------
@@ -536,6 +546,7 @@ struct CgRun {
     int check_every;
     char *ws;
     hipStream_t st;
+    bool op_tmp;         // workspace holds the operator temporaries
 };
 
 #define HIPCHK(x)                               \
@@ -549,11 +560,14 @@ static hipError_t apply_op(const CgRun &c, const void *U, int prec, int fmt, con
     return c.op.apply(c.op.ctx, U, prec, fmt, in, ins, out, outs, dag, c.st);
 }
 
-// The full-lattice operator (Wilson D or domain-wall M).
+// The full-lattice operator (Wilson D, Shamir M or Moebius M).
 struct FullOp {
     GeomDev g;
     int kind;
     double diag, mf;
+    double M5, b5, c5;
+    void *tmp[2];      // Moebius intermediate field: FP64, sloppy
+    float *tmps;       // sloppy FP16 scales
 };
 
 static hipError_t full_apply(const void *ctx, const void *U, int prec, int fmt, const void *in, const float *ins, void *out,
@@ -573,6 +587,8 @@ static hipError_t full_apply(const void *ctx, const void *U, int prec, int fmt, 
     a.diag = o.diag;
     a.mf = o.mf;
     a.stream = st;
+    if (o.kind == GRID_MOBIUS)
+        return launch_mobius(a, o.M5, o.b5, o.c5, o.tmp[prec == GRID_F64 ? 0 : 1], prec == GRID_F16S ? o.tmps : nullptr);
     return launch_dhop(a);
 }
 
@@ -593,7 +609,7 @@ static double read_scalar(const CgRun &c, const double *part, int np, double *sc
 template <class SH>
 static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
     const bool mixed = c.sloppy != GRID_F64;
-    const CgLayout L = cg_layout(c.n, c.nlinks, c.sloppy, c.link_fmt);
+    const CgLayout L = cg_layout(c.n, c.nlinks, c.sloppy, c.link_fmt, c.op_tmp);
     char *ws = c.ws;
     const int n = static_cast<int>(c.n);
     const int np = static_cast<int>((static_cast<long>(n) + kThreads - 1) / kThreads < kRedBlocks
@@ -730,8 +746,10 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
 }
 
 hipError_t run_cg_op(const CgOp &op, const void *U, const void *b, void *x, long nsites, long nlinks,
-                     const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status) {
+                     const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status,
+                     bool op_tmp) {
     CgRun c;
+    c.op_tmp = op_tmp;
     c.U = U;
     c.b = b;
     c.x = x;
@@ -758,17 +776,25 @@ hipError_t run_cg_op(const CgOp &op, const void *U, const void *b, void *x, long
     return e;
 }
 
-hipError_t run_cg(const void *U, const void *b, void *x, const GeomDev &g, int kind, double diag, double mf,
-                  const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status) {
+hipError_t run_cg(const void *U, const void *b, void *x, const GeomDev &g, const grid_op &opd, const grid_cg_params &p,
+                  void *ws, hipStream_t st, grid_cg_stats *stats, int *status) {
     FullOp o;
     o.g = g;
-    o.kind = kind;
-    o.diag = diag;
-    o.mf = mf;
+    o.kind = opd.kind;
+    o.diag = opd.kind == GRID_WILSON ? 4.0 + opd.mass : 5.0 - opd.M5;
+    o.mf = opd.mf;
+    o.M5 = opd.M5;
+    o.b5 = opd.b5;
+    o.c5 = opd.c5;
+    const CgLayout L = cg_layout(g.n5, static_cast<long>(g.vol) * 4, p.sloppy_prec, p.link_fmt, true);
+    char *w = static_cast<char *>(ws);
+    o.tmp[0] = w + L.u;
+    o.tmp[1] = p.sloppy_prec != GRID_F64 ? w + L.uh : nullptr;
+    o.tmps = p.sloppy_prec == GRID_F16S ? reinterpret_cast<float *>(w + L.uhs) : nullptr;
     CgOp op;
     op.apply = full_apply;
     op.ctx = &o;
-    return run_cg_op(op, U, b, x, g.n5, static_cast<long>(g.vol) * 4, p, ws, st, stats, status);
+    return run_cg_op(op, U, b, x, g.n5, static_cast<long>(g.vol) * 4, p, ws, st, stats, status, true);
 }
 
 // ||a - b||^2 (b may be NULL) over n FP64 spinor sites, summed deterministically; waits for the

@@ -196,7 +196,7 @@ template <class SP, class LK, bool DAG, int KIND>
 __global__ void __launch_bounds__(kBlock)
 k_dhop_dir(const void *__restrict__ U, const void *__restrict__ psi, const float *__restrict__ psi_scale,
            const void *__restrict__ yv, const float *__restrict__ y_scale, void *__restrict__ out,
-           float *__restrict__ out_scale, GeomDev g, Trav tr, double diag, double mf, double beta) {
+           float *__restrict__ out_scale, GeomDev g, Trav tr, double diag, double mf, double beta, double cs) {
     using C = typename SP::C;
     constexpr int PITCH = SP::kChunks + 1;
     __shared__ chunk_t sm[kDirs][kSites * PITCH];
@@ -271,7 +271,8 @@ k_dhop_dir(const void *__restrict__ U, const void *__restrict__ psi, const float
         const int hup = DAG ? 0 : 1;   // chiral half taken from s + 1 (0: spins 0,1; 1: spins 2,3)
         const bool from_up = (a >> 1) == hup;
         const int s2 = from_up ? (s == Ls - 1 ? 0 : s + 1) : (s == 0 ? Ls - 1 : s - 1);
-        const C f = from_up ? (s == Ls - 1 ? static_cast<C>(-mf) : C(1)) : (s == 0 ? static_cast<C>(-mf) : C(1));
+        const C f = static_cast<C>(cs) *
+                    (from_up ? (s == Ls - 1 ? static_cast<C>(-mf) : C(1)) : (s == 0 ? static_cast<C>(-mf) : C(1)));
         const Cx<C> v = global_elem<SP>(yv, y_scale, static_cast<size_t>(site4o) * Ls + s2, k);
         acc = {acc.r - f * v.r, acc.i - f * v.i};
     }
@@ -315,11 +316,12 @@ static hipError_t launch_dir(const DhopArgs &a) {
     const void *y = a.custom ? a.y : a.psi;
     const float *ys = a.custom ? a.y_scale : a.psi_scale;
     const double beta = a.custom ? a.beta : (a.kind == GRID_HOP ? 1.0 : -0.5);
+    const double cs = a.custom ? a.cs : 1.0;
     const dim3 grid(static_cast<unsigned>(nblocks)), block(kBlock);
     hipStream_t st = a.stream;
 #define GRIDMI_LAUNCH(DAG, KIND)                                                                          \
     hipLaunchKernelGGL((k_dhop_dir<SP, LK, DAG, KIND>), grid, block, 0, st, a.U, a.psi, a.psi_scale, y, ys,     \
-                       a.out, a.out_scale, a.g, tr, a.diag, a.mf, beta)
+                       a.out, a.out_scale, a.g, tr, a.diag, a.mf, beta, cs)
     switch (a.kind * 2 + (a.dag ? 1 : 0)) {
         case GRID_HOP * 2 + 0: GRIDMI_LAUNCH(false, GRID_HOP); break;
         case GRID_HOP * 2 + 1: GRIDMI_LAUNCH(true, GRID_HOP); break;

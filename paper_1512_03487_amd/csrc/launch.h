@@ -32,9 +32,14 @@ struct DhopArgs {
     const void *y = nullptr;
     const float *y_scale = nullptr;
     double beta = 0.0;
+    double cs = 1.0;           // DWF epilogue: coefficient of the fifth-dimension hopping of y
 };
 
 hipError_t launch_dhop(const DhopArgs &a);
+
+// Moebius domain-wall operator (mobius.hip): out = M_mob psi (dag: M_mob^dagger psi) through the
+// intermediate field tmp (same size and precision as psi). a.diag is unused; M5, b5, c5 given.
+hipError_t launch_mobius(const DhopArgs &a, double M5, double b5, double c5, void *tmp, float *tmp_scale);
 
 // Fifth-dimension operator inverse of the domain-wall operator (eo.hip): out = M5^-1 psi or
 // (M5^dagger)^-1 psi on n4 4D sites of Ls records each (full or checkerboard fields).
@@ -76,10 +81,13 @@ struct CgOp {
 };
 size_t cg_workspace_bytes(const GeomDev &g, int sloppy, int link_fmt);
 size_t cg_workspace_bytes_n(long nsites, long nlinks, int sloppy, int link_fmt);
-hipError_t run_cg(const void *U, const void *b, void *x, const GeomDev &g, int kind, double diag, double mf,
-                  const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status);
+hipError_t run_cg(const void *U, const void *b, void *x, const GeomDev &g, const grid_op &op, const grid_cg_params &p,
+                  void *ws, hipStream_t st, grid_cg_stats *stats, int *status);
+// op_tmp: the workspace was sized with the operator temporaries (cg_workspace_bytes) or not
+// (cg_workspace_bytes_n).
 hipError_t run_cg_op(const CgOp &op, const void *U, const void *b, void *x, long nsites, long nlinks,
-                     const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status);
+                     const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status,
+                     bool op_tmp = false);
 // ||a - b||^2 over n FP64 spinor sites (b may be NULL); part: kRedBlocks + 16 doubles of scratch.
 constexpr int kNormScratch = 1024 + 16;
 hipError_t norm2_diff(const void *a, const void *b, long n, double *part, hipStream_t st, double *result);

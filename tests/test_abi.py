@@ -34,8 +34,8 @@ def geom(dims=(4, 4, 4, 4), Ls=1):
     return g
 
 
-def op(kind=_lib.GRID_HOP, dag=0, mass=0.1, M5=1.8, mf=0.01):
-    return _lib.GridOp(kind, dag, mass, M5, mf)
+def op(kind=_lib.GRID_HOP, dag=0, mass=0.1, M5=1.8, mf=0.01, b5=1.0, c5=0.0):
+    return _lib.GridOp(kind, dag, mass, M5, mf, b5, c5)
 
 
 def dhop(lib, U=A, psi=A + 0x10000000, ps=None, out=A + 0x20000000, os_=None, g=None, o=None, prec=0, fmt=0):
@@ -137,7 +137,8 @@ def test_solve_eo_workspace_and_validation(lib):
     n = 4 ** 4 * 8
     p64 = _lib.GridCgParams(1e-10, 100, _lib.GRID_F64, _lib.GRID_L18, 0.1, 10)
     w = lib.grid_solve_eo_workspace_bytes(ctypes.byref(g), ctypes.byref(p64))
-    assert w >= 4 * n * 192 + lib.grid_cg_workspace_bytes(ctypes.byref(geom((4, 4, 4, 4), Ls=4)), ctypes.byref(p64))
+    # eight checkerboard FP64 fields of its own plus the CG's four on the even checkerboard
+    assert w >= 8 * (n // 2) * 192 + 4 * (n // 2) * 192
     assert lib.grid_solve_eo_workspace_bytes(ctypes.byref(geom((4, 4, 4, 5), Ls=8)), ctypes.byref(p64)) == 0
     st = _lib.GridCgStats()
     args = lambda gg=g, oo=op(kind=_lib.GRID_DWF), ws=A + 0x40000000, nbytes=w: (
@@ -149,3 +150,23 @@ def test_solve_eo_workspace_and_validation(lib):
     assert lib.grid_solve_eo(*args(oo=op(kind=_lib.GRID_HOP))) == _lib.GRID_EINVAL
     assert lib.grid_solve_eo(*args(nbytes=w - 1)) == _lib.GRID_ESPACE
     assert lib.grid_solve_eo(*args(ws=A + 0x40000000 + 64)) == _lib.GRID_EALIGN
+
+
+def test_mobius_validation(lib):
+    g = geom((4, 4, 4, 4), Ls=8)
+    mob = op(kind=_lib.GRID_MOBIUS, b5=1.5, c5=0.5)
+    call = lambda oo=mob, tmp=A + 0x30000000, prec=0, ts=None: lib.grid_mobius(
+        P(A), P(A + 0x10000000), None, P(A + 0x20000000), None, P(tmp), P(ts), ctypes.byref(g), ctypes.byref(oo), prec,
+        0, None)
+    assert call(oo=op(kind=_lib.GRID_DWF)) == _lib.GRID_EINVAL
+    assert call(tmp=0) == _lib.GRID_EINVAL
+    assert call(tmp=A + 0x10000000 + 64) == _lib.GRID_EINVAL                # tmp overlaps psi
+    assert call(prec=_lib.GRID_F16S) == _lib.GRID_EINVAL                     # scales missing
+    assert dhop(lib, o=mob, g=g) == _lib.GRID_EINVAL and "grid_mobius" in _lib.last_error()
+    # the CG takes the Moebius kind; the even-odd solver does not
+    p64 = _lib.GridCgParams(1e-10, 100, _lib.GRID_F64, _lib.GRID_L18, 0.1, 10)
+    st = _lib.GridCgStats()
+    w = lib.grid_solve_eo_workspace_bytes(ctypes.byref(g), ctypes.byref(p64))
+    assert lib.grid_solve_eo(P(A), P(A + 0x10000000), P(A + 0x20000000), ctypes.byref(g), ctypes.byref(mob),
+                             ctypes.byref(p64), P(A + 0x40000000), ctypes.c_size_t(w), ctypes.byref(st),
+                             None) == _lib.GRID_EINVAL
