@@ -114,6 +114,29 @@ def time_dhop(sets, steps, warmup, kind="hop", **kw):
     return e0.elapsed_time(e1) * 1e-3 / steps, wall
 
 
+def mobius_leg(dims, Ls, prec, steps, warmup, b5=1.5, c5=0.5):
+    """Moebius operator (grid_mobius): s-local pass + hopping pass; GB/s on the same algorithmic
+    bytes as the Shamir operator (read psi and the links once, write out once)."""
+    import torch
+    import paper_1512_03487_amd as gm
+    (U, p, o), = make_sets(dims, prec, 1, kind="haar", Ls=Ls)[0]
+    tmp = torch.empty_like(p)
+    for _ in range(warmup):
+        gm.mobius(U, p, 1.8, 0.01, b5, c5, out=o, tmp=tmp)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        gm.mobius(U, p, 1.8, 0.01, b5, c5, out=o, tmp=tmp)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / steps
+    n5 = dims[0] * dims[1] * dims[2] * dims[3] * Ls
+    gbs = alg_bytes_per_site(prec, "L18", Ls) * n5 / t / 1e9
+    return {"lattice": list(dims), "Ls": Ls, "prec": prec, "b5": b5, "c5": c5, "us_per_launch": round(t * 1e6, 2),
+            "alg_gbs": round(gbs, 1), "roofline_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def leg(dims, prec, fmt, kind, Ls, steps, warmup, min_bytes=600e6):
     sb = SPINOR_BYTES[prec] * (Ls or 1) * 2 + 4 * LINK_BYTES[(prec, fmt)]
     vol = dims[0] * dims[1] * dims[2] * dims[3]
@@ -149,6 +172,17 @@ def cg_legs():
                      "reliable_updates": st["reliable_updates"], "true_residual": st["true_residual"],
                      "converged": st["converged"]}
         del ws, x
+    ws = torch.empty(gm.cg_workspace_bytes(b, sloppy="f32"), dtype=torch.uint8, device=dev)
+    gm.cg(U, b, kind="mobius", M5=1.8, mf=0.01, b5=1.5, c5=0.5, tol=1e-10, sloppy="f32", workspace=ws, maxiter=20,
+          raise_on_fail=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st = gm.cg(U, b, kind="mobius", M5=1.8, mf=0.01, b5=1.5, c5=0.5, tol=1e-10, sloppy="f32", workspace=ws)
+    torch.cuda.synchronize()
+    out["mobius_b1.5_c0.5_mixed_f32"] = {"seconds": round(time.perf_counter() - t0, 4), "iterations": st["iterations"],
+                                         "reliable_updates": st["reliable_updates"],
+                                         "true_residual": st["true_residual"], "converged": st["converged"]}
+    del ws, x
     out["speedup_mixed_f32"] = round(out["fp64"]["seconds"] / out["mixed_f32"]["seconds"], 2)
     out["speedup_mixed_f16s"] = round(out["fp64"]["seconds"] / out["mixed_f16s"]["seconds"], 2)
     return out
@@ -276,6 +310,8 @@ def main():
         legs["hop_32^4_f16s_L12"] = leg((32, 32, 32, 32), "f16s", "L12", "hop", None, 50, 5)
         legs["dwf_24^4x12_f32"] = leg((24, 24, 24, 24), "f32", "L18", "dwf", 12, 20, 3)
         legs["dwf_24^4x12_f16s_L12"] = leg((24, 24, 24, 24), "f16s", "L12", "dwf", 12, 20, 3)
+        legs["mobius_16^4x16_f32"] = mobius_leg((16, 16, 16, 16), 16, "f32", 50, 5)
+        legs["mobius_16^4x16_f64"] = mobius_leg((16, 16, 16, 16), 16, "f64", 20, 3)
         torch.cuda.empty_cache()
     cg = None if args.no_cg else cg_legs()
     eo = None if args.no_cg else eo_legs()
