@@ -1,0 +1,105 @@
+"""Pins of the HMC oracle pieces (oracle.hmc): plaquette, gauge force, su(3) exponential,
+leapfrog integrator. Fixed by closed forms (unit links), gauge invariance, finite differences of
+the action, a Taylor series, and the integrator's reversibility and second-order energy error.
+"""
+import numpy as np
+import pytest
+
+import oracle.oracle as O
+from oracle import hmc
+from paper_1512_03487_amd import fields as F
+
+
+def _gauge_rotate(U, g):
+    out = np.empty_like(U)
+    for mu, ax in ((0, 3), (1, 2), (2, 1), (3, 0)):
+        gp = np.roll(g, -1, axis=ax)
+        out[..., mu, :, :] = np.einsum("...ij,...jk,...lk->...il", g, U[..., mu, :, :], gp.conj())
+    return out
+
+
+def test_plaquette_unit_links_and_gauge_invariance():
+    dims = (4, 4, 2, 4)
+    assert hmc.plaquette(F.gauge_field(dims, kind="unit")) == pytest.approx(1.0, abs=1e-15)
+    U = F.gauge_field(dims, seed=1, kind="weak")
+    g = F.gauge_transform(dims, seed=4)
+    assert abs(hmc.plaquette(_gauge_rotate(U, g)) - hmc.plaquette(U)) < 1e-14
+    assert 0.5 < hmc.plaquette(U) < 1.0
+    # Haar links: plaquette average near 0 (random), bounded by 1
+    assert abs(hmc.plaquette(F.gauge_field(dims, seed=1, kind="haar"))) < 0.1
+
+
+def test_staples_close_the_plaquettes():
+    """sum_mu Re tr(U_mu A_mu) counts every plaquette four times."""
+    dims = (2, 4, 2, 4)
+    U = F.gauge_field(dims, seed=1, kind="weak")
+    tot = sum(float(np.einsum("...ij,...ji->...", U[..., mu, :, :], hmc.staples(U, mu)).real.sum()) for mu in range(4))
+    V = int(np.prod(dims))
+    assert tot == pytest.approx(4 * 3 * 6 * V * hmc.plaquette(U), rel=1e-13)
+
+
+def test_gauge_force_finite_differences():
+    """d/de S_G(exp(e X) U)|0 = Re tr(F^dagger X) summed over links, central differences."""
+    dims, beta = (2, 2, 2, 4), 5.5
+    U = F.gauge_field(dims, seed=1, kind="weak")
+    X = F.random_su3_algebra(dims, seed=6)
+    Fg = hmc.gauge_force(U, beta)
+    # F is traceless anti-Hermitian
+    assert np.max(np.abs(Fg + np.conj(np.swapaxes(Fg, -1, -2)))) < 1e-13
+    assert np.max(np.abs(np.trace(Fg, axis1=-2, axis2=-1))) < 1e-13
+    h = 1e-4
+    def S(e):
+        return hmc.gauge_action(np.einsum("...ij,...jk->...ik", hmc.su3_exp(e * X), U), beta)
+    fd = (S(h) - S(-h)) / (2 * h)
+    an = float(np.sum(np.conj(Fg) * X).real)
+    assert abs(fd - an) < 1e-7 * abs(an)
+
+
+def test_su3_exp_against_taylor_series():
+    X = F.random_su3_algebra((2, 2, 2, 2), seed=9) * 0.7
+    E = hmc.su3_exp(X)
+    T = np.zeros_like(X)
+    term = np.broadcast_to(np.eye(3, dtype=complex), X.shape).copy()
+    for k in range(1, 40):
+        T += term
+        term = np.einsum("...ij,...jk->...ik", term, X) / k
+    assert np.max(np.abs(E - T)) < 1e-14
+    assert np.max(np.abs(np.einsum("...ji,...jk->...ik", E.conj(), E) - np.eye(3))) < 1e-14
+    assert np.max(np.abs(np.linalg.det(E) - 1)) < 1e-14
+
+
+def _fermion(dims, Ls=4):
+    U = F.gauge_field(dims, seed=1, kind="weak")
+    phi = F.spinor_field(dims, seed=5, Ls=Ls)
+    return U, (O.Op.dwf(Ls, 1.8, 0.2), phi)
+
+
+@pytest.mark.parametrize("with_fermion", [False, True])
+def test_leapfrog_reversible(with_fermion):
+    dims, beta = (2, 2, 2, 4), 5.5
+    U0, ferm = _fermion(dims)
+    ferm = ferm if with_fermion else None
+    P0 = F.random_su3_algebra(dims, seed=7)
+    U1, P1 = hmc.leapfrog(U0, P0, beta, 0.05, 4, ferm)
+    U2, P2 = hmc.leapfrog(U1, -P1, beta, 0.05, 4, ferm)
+    tol = 1e-12 if not with_fermion else 1e-10
+    assert np.max(np.abs(U2 - U0)) < tol and np.max(np.abs(P2 + P0)) < tol
+    assert np.max(np.abs(U1 - U0)) > 1e-3   # it moved
+
+
+@pytest.mark.parametrize("with_fermion", [False, True])
+def test_leapfrog_energy_error_is_second_order(with_fermion):
+    dims, beta, tau = (2, 2, 2, 4), 5.5, 0.4
+    U0, ferm = _fermion(dims)
+    ferm = ferm if with_fermion else None
+    P0 = F.random_su3_algebra(dims, seed=7)
+    H0 = hmc.hamiltonian(U0, P0, beta, ferm)
+    dH = []
+    for n in (4, 8):
+        U1, P1 = hmc.leapfrog(U0, P0, beta, tau / n, n, ferm)
+        dH.append(abs(hmc.hamiltonian(U1, P1, beta, ferm) - H0))
+    assert 3.0 < dH[0] / dH[1] < 5.0, dH
+    # and a force with the wrong normalisation does not conserve H
+    Ub, Pb = U0.copy(), P0 - 0.2 * hmc.md_force(U0, beta, ferm)
+    Ub = np.einsum("...ij,...jk->...ik", hmc.su3_exp(0.4 * Pb), Ub)
+    assert abs(hmc.hamiltonian(Ub, Pb - 0.2 * hmc.md_force(Ub, beta, ferm), beta, ferm) - H0) > 10 * dH[0]
