@@ -246,6 +246,58 @@ int grid_solve_eo(const void *U, const void *b, void *x, const grid_geom *geom, 
                   const grid_cg_params *params, void *workspace, size_t ws_bytes, grid_cg_stats *stats,
                   void *stream);
 
+/*
+ * Hybrid Monte Carlo molecular dynamics (HMC, Section 4), FP64, links [V][4][3][3].
+ *   S_G = beta sum_{x, mu<nu} (1 - Re tr P_munu(x) / 3),
+ *   P_munu(x) = U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+;
+ *   S_F = phi^+ (Op^+ Op)^-1 phi (two flavours, Op = D or the Shamir M of `fermion`);
+ *   forces F = TA(G U^+) with G = dS/dRe U + i dS/dIm U (as grid_dhop_backward);
+ *   momenta P in su(3) per link ([V][4][3][3], anti-Hermitian traceless), K = sum tr(P^+ P);
+ *   dU/dt = P U, dP/dt = -F/2, leapfrog: P -= (eps/2) F/2, then n_steps times
+ *   { U <- exp(eps P) U; P -= eps F/2 } with the last momentum step halved.
+ * Random momenta and pseudofermion sources are drawn by the caller.
+ */
+typedef struct {
+    double beta;            /* Wilson gauge coupling                                            */
+    double eps;             /* leapfrog step size                                               */
+    int n_steps;            /* leapfrog steps                                                   */
+    grid_op fermion;        /* GRID_WILSON or GRID_DWF pseudofermion operator (phi != NULL)     */
+    grid_cg_params cg;      /* the solves inside every fermion-force evaluation                 */
+} grid_md_params;
+
+typedef struct {
+    int solves;             /* fermion solves performed                                         */
+    int cg_iterations;      /* their total CG iterations                                        */
+    int failed_solves;      /* solves that stopped short of cg.tol                              */
+    double seconds;         /* wall time of the call                                            */
+} grid_md_stats;
+
+/* grid_md_workspace_bytes -- device workspace of grid_md_leapfrog / grid_hmc_energy (0: invalid). */
+size_t grid_md_workspace_bytes(const grid_geom *geom, const grid_md_params *params);
+
+/* grid_gauge_force -- F = the su(3) force of S_G on every link. Asynchronous. */
+int grid_gauge_force(const void *U, void *F, const grid_geom *geom, double beta, void *stream);
+
+/* grid_link_exp -- U <- exp(eps P) U on n_links links (P in su(3)), in place. Asynchronous. */
+int grid_link_exp(void *U, const void *P, double eps, long n_links, void *stream);
+
+/*
+ * grid_md_leapfrog -- integrate (U, P) in place over n_steps leapfrog steps of size eps; phi
+ * (FP64, the 4D or 5D pseudofermion of `fermion`) adds the fermion force, NULL integrates the pure
+ * gauge system. Synchronous. Returns GRID_OK or an argument / HIP error; stats->failed_solves
+ * counts force solves that did not reach cg.tol.
+ */
+int grid_md_leapfrog(void *U, void *P, const void *phi, const grid_geom *geom, const grid_md_params *params,
+                     void *workspace, size_t ws_bytes, grid_md_stats *stats, void *stream);
+
+/*
+ * grid_hmc_energy -- energies[0..3] = K, S_G, S_F (0 when phi is NULL), H = K + S_G + S_F, in FP64.
+ * Synchronous.
+ */
+int grid_hmc_energy(const void *U, const void *P, const void *phi, const grid_geom *geom,
+                    const grid_md_params *params, void *workspace, size_t ws_bytes, double energies[4],
+                    grid_md_stats *stats, void *stream);
+
 /* grid_last_error -- message of the calling thread's last failed call ("" if none). */
 const char *grid_last_error(void);
 

@@ -5,10 +5,11 @@ its thin torch binding. ``fields`` draws seeded synthetic inputs.
 """
 from . import fields  # noqa: F401
 from .api import (F16Spinor, cg, cg_workspace_bytes, convert_links, convert_spinor, dhop,  # noqa: F401
-                  dhop_backward, dhop_cb, dwf, dwf_mdag_m, m5inv, mobius, solve_eo, solve_eo_workspace_bytes, version,
+                  dhop_backward, dhop_cb, dwf, dwf_mdag_m, gauge_force, hmc_energy, link_exp, m5inv, md_leapfrog, mobius, solve_eo, solve_eo_workspace_bytes, version,
                   wilson)
 from .autograd import DhopFn, PseudofermionActionFn  # noqa: F401
+from . import hmc  # noqa: F401,E402
 
 __all__ = ["fields", "F16Spinor", "dhop", "wilson", "dwf", "dwf_mdag_m", "cg", "cg_workspace_bytes",
-           "dhop_backward", "dhop_cb", "m5inv", "mobius", "solve_eo", "solve_eo_workspace_bytes", "convert_spinor",
+           "dhop_backward", "dhop_cb", "m5inv", "mobius", "gauge_force", "link_exp", "md_leapfrog", "hmc_energy", "solve_eo", "solve_eo_workspace_bytes", "convert_spinor",
            "convert_links", "version", "DhopFn", "PseudofermionActionFn"]

@@ -20,6 +20,7 @@ GRID_HOP, GRID_WILSON, GRID_DWF, GRID_MOBIUS = 0, 1, 2, 3
 #: every symbol include/grid_mi.h declares
 EXPORTS = ("grid_dhop", "grid_mobius", "grid_dwf_mdag_m", "grid_cg_workspace_bytes", "grid_cg", "grid_dhop_backward",
            "grid_dhop_cb", "grid_m5inv", "grid_solve_eo_workspace_bytes", "grid_solve_eo",
+           "grid_md_workspace_bytes", "grid_gauge_force", "grid_link_exp", "grid_md_leapfrog", "grid_hmc_energy",
            "grid_convert_spinor", "grid_convert_links", "grid_last_error", "grid_version")
 
 
@@ -40,6 +41,16 @@ class GridCgParams(ctypes.Structure):
 class GridCgStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("reliable_updates", ctypes.c_int), ("converged", ctypes.c_int),
                 ("true_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+class GridMdParams(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("eps", ctypes.c_double), ("n_steps", ctypes.c_int), ("fermion", GridOp),
+                ("cg", GridCgParams)]
+
+
+class GridMdStats(ctypes.Structure):
+    _fields_ = [("solves", ctypes.c_int), ("cg_iterations", ctypes.c_int), ("failed_solves", ctypes.c_int),
+                ("seconds", ctypes.c_double)]
 
 
 class GridError(RuntimeError):
@@ -83,6 +94,18 @@ def load():
     lib.grid_solve_eo.argtypes = [P, P, P, ctypes.POINTER(GridGeom), ctypes.POINTER(GridOp),
                                   ctypes.POINTER(GridCgParams), P, ctypes.c_size_t, ctypes.POINTER(GridCgStats), P]
     lib.grid_solve_eo.restype = I
+    lib.grid_md_workspace_bytes.argtypes = [ctypes.POINTER(GridGeom), ctypes.POINTER(GridMdParams)]
+    lib.grid_md_workspace_bytes.restype = ctypes.c_size_t
+    lib.grid_gauge_force.argtypes = [P, P, ctypes.POINTER(GridGeom), D, P]
+    lib.grid_gauge_force.restype = I
+    lib.grid_link_exp.argtypes = [P, P, D, ctypes.c_long, P]
+    lib.grid_link_exp.restype = I
+    lib.grid_md_leapfrog.argtypes = [P, P, P, ctypes.POINTER(GridGeom), ctypes.POINTER(GridMdParams), P,
+                                     ctypes.c_size_t, ctypes.POINTER(GridMdStats), P]
+    lib.grid_md_leapfrog.restype = I
+    lib.grid_hmc_energy.argtypes = [P, P, P, ctypes.POINTER(GridGeom), ctypes.POINTER(GridMdParams), P,
+                                    ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(GridMdStats), P]
+    lib.grid_hmc_energy.restype = I
     lib.grid_convert_spinor.argtypes = [P, I, P, P, I, P, ctypes.c_long, P]
     lib.grid_convert_spinor.restype = I
     lib.grid_convert_links.argtypes = [P, P, I, I, I, ctypes.c_long, P]

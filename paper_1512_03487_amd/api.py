@@ -19,7 +19,7 @@ import torch
 
 from . import _lib
 from ._lib import (GRID_DWF, GRID_F16S, GRID_F32, GRID_F64, GRID_HOP, GRID_L12, GRID_L18, GRID_MOBIUS, GRID_WILSON,
-                   GridCgParams, GridCgStats, GridGeom, GridOp, check, load)
+                   GridCgParams, GridCgStats, GridGeom, GridMdParams, GridMdStats, GridOp, check, load)
 
 _KIND = {"hop": GRID_HOP, "wilson": GRID_WILSON, "dwf": GRID_DWF, "mobius": GRID_MOBIUS}
 _PREC = {"f64": GRID_F64, "f32": GRID_F32, "f16s": GRID_F16S}
@@ -291,6 +291,76 @@ def solve_eo(U, b, kind="dwf", mass=0.0, M5=1.8, mf=0.01, x0=None, workspace=Non
     if rc != 0 and raise_on_fail:
         check(rc)
     return x, stats
+
+
+def _geom_links(U, Ls=1) -> GridGeom:
+    if U.dtype != torch.complex128 or tuple(U.shape[4:]) != (4, 3, 3):
+        raise TypeError("HMC takes complex128 links (Lt, Lz, Ly, Lx, 4, 3, 3)")
+    _need_cuda(U, "U")
+    g = GridGeom()
+    g.dims[:] = [int(U.shape[3]), int(U.shape[2]), int(U.shape[1]), int(U.shape[0])]
+    g.Ls = int(Ls)
+    return g
+
+
+def gauge_force(U, beta):
+    """su(3) force of the Wilson plaquette action on every link."""
+    g = _geom_links(U)
+    F = torch.empty_like(U)
+    check(load().grid_gauge_force(_ptr(U), _ptr(F), ctypes.byref(g), float(beta), _stream(U.device)))
+    return F
+
+
+def link_exp(U, P, eps):
+    """U <- exp(eps P) U in place (returns U)."""
+    _geom_links(U)
+    if P.shape != U.shape or P.dtype != U.dtype:
+        raise ValueError("P must match U")
+    check(load().grid_link_exp(_ptr(U), _ptr(P), float(eps), U.numel() // 9, _stream(U.device)))
+    return U
+
+
+def md_params(beta, eps=0.1, n_steps=10, kind="dwf", mass=0.0, M5=1.8, mf=0.01, **cg) -> GridMdParams:
+    p = GridMdParams()
+    p.beta, p.eps, p.n_steps = float(beta), float(eps), int(n_steps)
+    p.fermion = make_op(kind, False, mass, M5, mf)
+    p.cg = cg_params(**cg)
+    return p
+
+
+def _md_setup(U, phi, workspace, p):
+    Ls = 1
+    if phi is not None:
+        if spinor_prec(phi) != GRID_F64:
+            raise TypeError("phi must be complex128")
+        Ls = geom_of(phi).Ls
+    g = _geom_links(U, Ls)
+    need = int(load().grid_md_workspace_bytes(ctypes.byref(g), ctypes.byref(p)))
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=U.device)
+    return g, workspace
+
+
+def md_leapfrog(U, P, beta, eps, n_steps, phi=None, workspace=None, **kw):
+    """Leapfrog molecular dynamics of (U, P) in place; phi adds the pseudofermion force. Returns stats."""
+    p = md_params(beta, eps, n_steps, **kw)
+    g, workspace = _md_setup(U, phi, workspace, p)
+    st = GridMdStats()
+    check(load().grid_md_leapfrog(_ptr(U), _ptr(P), _ptr(phi), ctypes.byref(g), ctypes.byref(p), _ptr(workspace),
+                                  ctypes.c_size_t(workspace.numel()), ctypes.byref(st), _stream(U.device)))
+    return {"solves": st.solves, "cg_iterations": st.cg_iterations, "failed_solves": st.failed_solves,
+            "seconds": st.seconds}
+
+
+def hmc_energy(U, P, beta, phi=None, workspace=None, **kw):
+    """{"K", "S_G", "S_F", "H"} in FP64."""
+    p = md_params(beta, **kw)
+    g, workspace = _md_setup(U, phi, workspace, p)
+    st = GridMdStats()
+    e = (ctypes.c_double * 4)()
+    check(load().grid_hmc_energy(_ptr(U), _ptr(P), _ptr(phi), ctypes.byref(g), ctypes.byref(p), _ptr(workspace),
+                                 ctypes.c_size_t(workspace.numel()), e, ctypes.byref(st), _stream(U.device)))
+    return {"K": e[0], "S_G": e[1], "S_F": e[2], "H": e[3]}
 
 
 def dhop_backward(U, psi, grad_out, kind="hop", dag=False, mass=0.0, M5=1.8, mf=0.01, want_psi=True, want_U=True,

@@ -116,6 +116,38 @@ int check_solver_args(const GeomDev &g, const grid_op *op, const grid_cg_params 
     return GRID_OK;
 }
 
+// Molecular-dynamics parameter and buffer checks.
+int check_md(const GeomDev &g, const grid_md_params *p, const void *phi) {
+    if (!p) return fail(GRID_EINVAL, "params is NULL");
+    if (!isfinite(p->beta) || !isfinite(p->eps) || p->n_steps < 0)
+        return fail(GRID_EINVAL, "need finite beta and eps and n_steps >= 0");
+    if (phi) {
+        if (p->fermion.kind != GRID_WILSON && p->fermion.kind != GRID_DWF)
+            return fail(GRID_EINVAL, "the fermion force takes GRID_WILSON or GRID_DWF (got kind %d)", p->fermion.kind);
+        grid_cg_stats dummy;
+        TRY(check_solver_args(g, &p->fermion, &p->cg, &dummy));
+    } else {
+        TRY(check_prec(p->cg.sloppy_prec));
+        TRY(check_fmt(p->cg.link_fmt));
+    }
+    return GRID_OK;
+}
+
+int check_md_buffers(const GeomDev &g, const grid_md_params *p, const void *U, const void *P, const void *phi,
+                     const void *ws, size_t ws_bytes) {
+    TRY(check_ptr(U, "U", 16));
+    TRY(check_ptr(P, "P", 16));
+    if (phi) TRY(check_ptr(phi, "phi", 16));
+    TRY(check_ptr(ws, "workspace", 256));
+    const size_t need = md_workspace_bytes(g, *p);
+    if (ws_bytes < need) return fail(GRID_ESPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    const size_t lb = static_cast<size_t>(g.vol) * 4 * 144, sb = static_cast<size_t>(g.n5) * 192;
+    if (overlap(U, lb, P, lb) || overlap(ws, need, U, lb) || overlap(ws, need, P, lb) ||
+        (phi && (overlap(phi, sb, U, lb) || overlap(phi, sb, P, lb) || overlap(ws, need, phi, sb))))
+        return fail(GRID_EINVAL, "U, P, phi and workspace must not overlap");
+    return GRID_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -417,6 +449,61 @@ int grid_solve_eo(const void *U, const void *b, void *x, const grid_geom *geom, 
         return fail(GRID_ENOCONV, "CG stopped after %d iterations (full residual %.3e)", stats->iterations,
                     stats->true_residual);
     if (status == GRID_EBREAKDOWN) return fail(GRID_EBREAKDOWN, "CG breakdown after %d iterations", stats->iterations);
+    return ok();
+}
+
+// ---- Hybrid Monte Carlo ----
+
+size_t grid_md_workspace_bytes(const grid_geom *geom, const grid_md_params *params) {
+    GeomDev g;
+    if (check_geom(geom, &g) || !params) return 0;
+    if (check_prec(params->cg.sloppy_prec) || check_fmt(params->cg.link_fmt)) return 0;
+    return md_workspace_bytes(g, *params);
+}
+
+int grid_gauge_force(const void *U, void *F, const grid_geom *geom, double beta, void *stream) {
+    GeomDev g;
+    TRY(check_geom(geom, &g));
+    TRY(check_ptr(U, "U", 16));
+    TRY(check_ptr(F, "F", 16));
+    const size_t lb = static_cast<size_t>(g.vol) * 4 * 144;
+    if (overlap(U, lb, F, lb)) return fail(GRID_EINVAL, "F overlaps U");
+    hipError_t e = launch_gauge_force(U, F, g, beta, 1.0, 0, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "grid_gauge_force launch");
+    return ok();
+}
+
+int grid_link_exp(void *U, const void *P, double eps, long n_links, void *stream) {
+    if (n_links < 0 || n_links >= (long(1) << 31)) return fail(GRID_ESHAPE, "n_links out of range");
+    TRY(check_ptr(U, "U", 16));
+    TRY(check_ptr(P, "P", 16));
+    if (overlap(U, 144 * n_links, P, 144 * n_links)) return fail(GRID_EINVAL, "P overlaps U");
+    hipError_t e = launch_link_exp(U, P, eps, n_links, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "grid_link_exp launch");
+    return ok();
+}
+
+int grid_md_leapfrog(void *U, void *P, const void *phi, const grid_geom *geom, const grid_md_params *params,
+                     void *workspace, size_t ws_bytes, grid_md_stats *stats, void *stream) {
+    GeomDev g;
+    TRY(check_geom(geom, &g));
+    TRY(check_md(g, params, phi));
+    if (!stats) return fail(GRID_EINVAL, "stats is NULL");
+    TRY(check_md_buffers(g, params, U, P, phi, workspace, ws_bytes));
+    hipError_t e = run_md_leapfrog(U, P, phi, g, *params, workspace, static_cast<hipStream_t>(stream), stats);
+    if (e != hipSuccess) return hip_fail(e, "grid_md_leapfrog");
+    return ok();
+}
+
+int grid_hmc_energy(const void *U, const void *P, const void *phi, const grid_geom *geom, const grid_md_params *params,
+                    void *workspace, size_t ws_bytes, double energies[4], grid_md_stats *stats, void *stream) {
+    GeomDev g;
+    TRY(check_geom(geom, &g));
+    TRY(check_md(g, params, phi));
+    if (!stats || !energies) return fail(GRID_EINVAL, "stats and energies must not be NULL");
+    TRY(check_md_buffers(g, params, U, P, phi, workspace, ws_bytes));
+    hipError_t e = run_hmc_energy(U, P, phi, g, *params, workspace, static_cast<hipStream_t>(stream), energies, stats);
+    if (e != hipSuccess) return hip_fail(e, "grid_hmc_energy");
     return ok();
 }
 

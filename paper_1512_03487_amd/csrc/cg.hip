@@ -797,6 +797,25 @@ hipError_t run_cg(const void *U, const void *b, void *x, const GeomDev &g, const
     return run_cg_op(op, U, b, x, g.n5, static_cast<long>(g.vol) * 4, p, ws, st, stats, status, true);
 }
 
+hipError_t dot_re(const void *a, const void *b, long n, double *part, hipStream_t st, double *result) {
+    const int np = static_cast<int>((n + kThreads - 1) / kThreads < kRedBlocks ? (n + kThreads - 1) / kThreads
+                                                                                : kRedBlocks);
+    if (n == 0) {
+        *result = 0.0;
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL(k_dot_flat<double2>, dim3(np), dim3(kThreads), 0, st, static_cast<const double2 *>(a),
+                       static_cast<const double2 *>(b), n * 12, part);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, st, part, np, part + kRedBlocks, 0);
+    HIPCHK(hipGetLastError());
+    double h = 0.0;
+    HIPCHK(hipMemcpyAsync(&h, part + kRedBlocks, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *result = h;
+    return hipSuccess;
+}
+
 // ||a - b||^2 (b may be NULL) over n FP64 spinor sites, summed deterministically; waits for the
 // stream. `part` holds kRedBlocks + 16 doubles of device scratch.
 hipError_t norm2_diff(const void *a, const void *b, long n, double *part, hipStream_t st, double *result) {

@@ -91,5 +91,17 @@ hipError_t run_cg_op(const CgOp &op, const void *U, const void *b, void *x, long
 // ||a - b||^2 over n FP64 spinor sites (b may be NULL); part: kRedBlocks + 16 doubles of scratch.
 constexpr int kNormScratch = 1024 + 16;
 hipError_t norm2_diff(const void *a, const void *b, long n, double *part, hipStream_t st, double *result);
+// Re <a, b> over n FP64 spinor sites, deterministic; waits for the stream.
+hipError_t dot_re(const void *a, const void *b, long n, double *part, hipStream_t st, double *result);
+
+// Hybrid Monte Carlo (hmc.hip).
+hipError_t launch_gauge_force(const void *U, void *F, const GeomDev &g, double beta, double scale, int accumulate,
+                              hipStream_t st);
+hipError_t launch_link_exp(void *U, const void *P, double eps, long nlinks, hipStream_t st);
+size_t md_workspace_bytes(const GeomDev &g, const grid_md_params &p);
+hipError_t run_md_leapfrog(void *U, void *P, const void *phi, const GeomDev &g, const grid_md_params &p, void *ws,
+                           hipStream_t st, grid_md_stats *stats);
+hipError_t run_hmc_energy(const void *U, const void *P, const void *phi, const GeomDev &g, const grid_md_params &p,
+                          void *ws, hipStream_t st, double energies[4], grid_md_stats *stats);
 
 }  // namespace gridmi

@@ -170,3 +170,23 @@ def test_mobius_validation(lib):
     assert lib.grid_solve_eo(P(A), P(A + 0x10000000), P(A + 0x20000000), ctypes.byref(g), ctypes.byref(mob),
                              ctypes.byref(p64), P(A + 0x40000000), ctypes.c_size_t(w), ctypes.byref(st),
                              None) == _lib.GRID_EINVAL
+
+
+def test_md_validation(lib):
+    g = geom((4, 4, 4, 4), Ls=4)
+    cg = _lib.GridCgParams(1e-10, 100, _lib.GRID_F64, _lib.GRID_L18, 0.1, 10)
+    p = _lib.GridMdParams(5.5, 0.05, 4, op(kind=_lib.GRID_DWF), cg)
+    w = lib.grid_md_workspace_bytes(ctypes.byref(g), ctypes.byref(p))
+    assert w >= 2 * 4 ** 4 * 4 * 144 + 2 * 4 ** 4 * 4 * 192
+    st = _lib.GridMdStats()
+    call = lambda pp=p, phi=A + 0x20000000, ws=A + 0x40000000, nb=w: lib.grid_md_leapfrog(
+        P(A), P(A + 0x10000000), P(phi), ctypes.byref(g), ctypes.byref(pp), P(ws), ctypes.c_size_t(nb),
+        ctypes.byref(st), None)
+    assert call(nb=w - 1) == _lib.GRID_ESPACE
+    assert call(ws=A + 0x40000000 + 32) == _lib.GRID_EALIGN
+    assert call(pp=_lib.GridMdParams(5.5, 0.05, 4, op(kind=_lib.GRID_MOBIUS), cg)) == _lib.GRID_EINVAL
+    assert call(pp=_lib.GridMdParams(5.5, 0.05, -1, op(kind=_lib.GRID_DWF), cg)) == _lib.GRID_EINVAL
+    assert call(pp=_lib.GridMdParams(float("nan"), 0.05, 4, op(kind=_lib.GRID_DWF), cg)) == _lib.GRID_EINVAL
+    assert call(phi=A + 0x10000000 + 64) == _lib.GRID_EINVAL                  # phi overlaps P
+    assert lib.grid_link_exp(P(A), P(A + 16), ctypes.c_double(0.1), 16, None) == _lib.GRID_EINVAL
+    assert lib.grid_gauge_force(P(A), P(A + 16), ctypes.byref(geom()), ctypes.c_double(5.5), None) == _lib.GRID_EINVAL
