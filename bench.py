@@ -235,6 +235,45 @@ def eo_legs():
     return out
 
 
+def hmc_legs():
+    """Molecular-dynamics kernels on 16^4 (FP64): gauge force and link update per launch, and one
+    5-step leapfrog with a two-flavour Ls = 8 domain-wall pseudofermion (FP32-sloppy solves)."""
+    import torch
+    import paper_1512_03487_amd as gm
+    from paper_1512_03487_amd import fields
+    dev = torch.device("cuda:0")
+    dims = (16, 16, 16, 16)
+    vol = 16 ** 4
+    U = torch.from_numpy(fields.gauge_field(dims, seed=1, kind="weak")).to(dev)
+    P = torch.from_numpy(fields.random_su3_algebra(dims, seed=7)).to(dev)
+    out = {"lattice": list(dims)}
+
+    def timed(fn, n=20):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / n
+
+    F = torch.empty_like(U)
+    t = timed(lambda: gm.gauge_force(U, 5.7, out=F))
+    out["gauge_force"] = {"us_per_launch": round(t * 1e6, 2), "alg_gbs": round(2 * 576 * vol / t / 1e9, 1)}
+    Uc = U.clone()
+    t = timed(lambda: gm.link_exp(Uc, P, 1e-3))
+    out["link_exp"] = {"us_per_launch": round(t * 1e6, 2), "alg_gbs": round(3 * 576 * vol / t / 1e9, 1)}
+    Ls = 8
+    phi = torch.from_numpy(fields.spinor_field(dims, seed=5, Ls=Ls)).to(dev)
+    U1, P1 = U.clone(), P.clone()
+    st = gm.md_leapfrog(U1, P1, 5.7, 0.02, 5, phi, kind="dwf", M5=1.8, mf=0.1, tol=1e-8, sloppy="f32")
+    out["leapfrog_5_steps_dwf_ls8"] = {"seconds": round(st["seconds"], 4), "solves": st["solves"],
+                                      "cg_iterations": st["cg_iterations"], "failed_solves": st["failed_solves"]}
+    return out
+
+
 def cpu_baseline(seconds_target=15.0):
     """The FP64 oracle's H on the same 16^4 workload, timed on the host cores."""
     from oracle import oracle as orc
@@ -315,6 +354,7 @@ def main():
         torch.cuda.empty_cache()
     cg = None if args.no_cg else cg_legs()
     eo = None if args.no_cg else eo_legs()
+    md = None if args.no_legs else hmc_legs()
     cpu = None if args.no_cpu else cpu_baseline()
 
     traffic = measured_traffic()
@@ -344,6 +384,7 @@ def main():
         "legs": legs,
         "cg_dwf_16^4x16": cg,
         "solve_dwf_16^4x16_even_odd": eo,
+        "hmc_16^4": md,
         "wall_s_timed": round(wall, 4),
     }
     print(json.dumps(rec), flush=True)

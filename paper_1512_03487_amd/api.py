@@ -303,10 +303,10 @@ def _geom_links(U, Ls=1) -> GridGeom:
     return g
 
 
-def gauge_force(U, beta):
+def gauge_force(U, beta, out=None):
     """su(3) force of the Wilson plaquette action on every link."""
     g = _geom_links(U)
-    F = torch.empty_like(U)
+    F = torch.empty_like(U) if out is None else out
     check(load().grid_gauge_force(_ptr(U), _ptr(F), ctypes.byref(g), float(beta), _stream(U.device)))
     return F
 
