@@ -3,8 +3,8 @@ time to a true residual of 1e-10 in FP64 and in mixed precision.
 
 One "step" is one application of the hopping operator H on a 16^4 lattice in FP64 with weak-field
 links exp(0.3 i H) and a Gaussian spinor (1320 flop per site). The timed loop rotates over
-several independent (U, psi, out) buffer sets whose total size exceeds the 256 MB last-level
-cache, so every application streams its inputs from HBM. Further legs (FP32, 32^4, domain wall
+several independent (U, psi, out) buffer sets whose inputs alone exceed twice the 256 MB
+last-level cache, so every application streams its inputs from HBM. Further legs (FP32, 32^4, domain wall
 24^4 x 12 in FP32 and FP16 storage, the CG on 16^4 x 16, and the even-odd preconditioned solve of
 M x = b on the same lattice against CG on M^dagger M) are reported alongside.
 
@@ -138,7 +138,7 @@ def mobius_leg(dims, Ls, prec, steps, warmup, b5=1.5, c5=0.5):
 
 
 def leg(dims, prec, fmt, kind, Ls, steps, warmup, min_bytes=600e6):
-    sb = SPINOR_BYTES[prec] * (Ls or 1) * 2 + 4 * LINK_BYTES[(prec, fmt)]
+    sb = SPINOR_BYTES[prec] * (Ls or 1) + 4 * LINK_BYTES[(prec, fmt)]     # input bytes per site
     vol = dims[0] * dims[1] * dims[2] * dims[3]
     nsets = max(1, int(min_bytes // (sb * vol)) + 1)
     sets, _ = make_sets(dims, prec, nsets, kind="haar", Ls=Ls, fmt=fmt)
@@ -318,7 +318,10 @@ def main():
     import torch
     dims = (16, 16, 16, 16)
     vol = 16 ** 4
-    nsets = 5                                   # 5 x 63 MB > 256 MB MALL
+    # 12 x 50.3 MB of inputs (links + psi) = 604 MB, over twice the 256 MB MALL, so every
+    # application streams its inputs from HBM (the outputs are written non-temporally and do not
+    # occupy the MALL, so the inputs alone must exceed it)
+    nsets = 12
     sets, _ = make_sets(dims, "f64", nsets)
     t, wall = time_dhop(sets, args.steps, args.warmup)
     del sets

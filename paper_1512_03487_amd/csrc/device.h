@@ -241,18 +241,27 @@ __device__ __forceinline__ Cx<typename SP::C> global_elem(const void *base, cons
     return Elem<SP>::get(p, k, SP::kScaled ? scale[rec] : 1.0f);
 }
 
-// Store complex k of record rec. FP16 storage: the 16 lanes of a site (12 active) agree on the
-// site scale max |re|, |im| before encoding.
+// Store complex k of record rec, non-temporal (the output is not re-read by the kernel; keeping
+// it out of L2 leaves room for the inputs' reuse, measured 3-10 % faster). FP16 storage: the 16
+// lanes of a site (12 active) agree on the site scale max |re|, |im| before encoding.
+typedef double ntd2 __attribute__((ext_vector_type(2)));
+typedef float ntf2 __attribute__((ext_vector_type(2)));
 template <class SP>
 __device__ __forceinline__ void store_elem(void *base, float *scale, size_t rec, int k, Cx<typename SP::C> v, bool live);
 
 template <>
 __device__ __forceinline__ void store_elem<SpF64>(void *base, float *, size_t rec, int k, Cx<double> v, bool live) {
-    if (live) reinterpret_cast<double2 *>(base)[rec * 12 + k] = make_double2(v.r, v.i);
+    if (live) {
+        const ntd2 w = {v.r, v.i};
+        __builtin_nontemporal_store(w, reinterpret_cast<ntd2 *>(base) + rec * 12 + k);
+    }
 }
 template <>
 __device__ __forceinline__ void store_elem<SpF32>(void *base, float *, size_t rec, int k, Cx<float> v, bool live) {
-    if (live) reinterpret_cast<float2 *>(base)[rec * 12 + k] = make_float2(v.r, v.i);
+    if (live) {
+        const ntf2 w = {v.r, v.i};
+        __builtin_nontemporal_store(w, reinterpret_cast<ntf2 *>(base) + rec * 12 + k);
+    }
 }
 template <>
 __device__ __forceinline__ void store_elem<SpF16S>(void *base, float *scale, size_t rec, int k, Cx<float> v, bool live) {

@@ -66,8 +66,9 @@ __device__ __forceinline__ int fdiv(int n, FastDiv f) {
 
 // Traversal order: 8 XCD domains, one per contiguous eighth of the block order (x halved for
 // checkerboard output).
-//   mode 0: the halves of x, y and z; inside a domain s, x, y, z, t (t slowest, so the domain is
-//           swept along t with an eighth of a time slice as cross-section); domain slowest;
+//   mode 0: the halves of x, y and z (z in quarters for 5D fields: 16 domains, two per XCD);
+//           inside a domain s, x, y, z, t (t slowest, so the domain is swept along t with a
+//           fraction of a time slice as cross-section); domain slowest;
 //   mode 1: slabs of Lt / 8 time slices; inside s, x, y, t, z (z slowest); slab slowest;
 //   mode 2: one domain in memory order s, x, y, z, t.
 // For checkerboard output (cbp = 0 / 1) the site of parity cbp in each x pair is taken.
@@ -106,7 +107,7 @@ __device__ __forceinline__ void trav_decode(const GeomDev &g, const Trav &tr, in
         // domain index q (0 in mode 2)
         x[0] += (q & 1) * tr.en0;
         x[1] += ((q >> 1) & 1) * tr.en1;
-        x[2] += (q >> 2) * tr.en2;
+        x[2] += (q >> 2) * tr.en2;   // up to 3 when z is quartered
     }
     if (tr.cbp >= 0) x[0] = 2 * x[0] + ((x[1] + x[2] + x[3] + tr.cbp) & 1);
     site4 = x[0] + g.L[0] * (x[1] + g.L[1] * (x[2] + g.L[2] * x[3]));
@@ -280,13 +281,21 @@ k_dhop_dir(const void *__restrict__ U, const void *__restrict__ psi, const float
 }
 
 // XCD domains: halves of x, y, z when those extents are even (measured best with inputs streamed
-// from HBM), else slabs of t when Lt is a multiple of 8, else a single domain.
+// from HBM; z in quarters for 5D fields), else slabs of t when Lt is a multiple of 8, else a single
+// domain.
 static Trav make_trav(const GeomDev &g, int cb) {
     Trav tr;
     tr.cbp = cb;
     tr.nout = cb >= 0 ? g.n5 / 2 : g.n5;
     int e[4] = {cb >= 0 ? g.L[0] / 2 : g.L[0], g.L[1], g.L[2], g.L[3]};
-    if (e[0] % 2 == 0 && e[1] % 2 == 0 && e[2] % 2 == 0) {
+    if (e[0] % 2 == 0 && e[1] % 2 == 0 && e[2] % 4 == 0 && g.Ls > 1) {
+        // fifth dimension: 16 domains (z quartered), two consecutive ones per XCD, which halves
+        // the cross-section an XCD sweeps (its Ls records per 4D site multiply the working set)
+        tr.mode = 0;
+        e[0] /= 2;
+        e[1] /= 2;
+        e[2] /= 4;
+    } else if (e[0] % 2 == 0 && e[1] % 2 == 0 && e[2] % 2 == 0) {
         tr.mode = 0;
         e[0] /= 2;
         e[1] /= 2;
@@ -604,11 +613,12 @@ static hipError_t launch_walk(const DhopArgs &a) {
     return hipGetLastError();
 }
 
-// Direction-parallel schedule for 4D fields in FP64 / FP32 and for every even-odd (custom) call,
-// column walk otherwise.
+// Direction-parallel schedule for 4D fields in FP64 / FP32, 5D fields in FP64 and every even-odd
+// or Moebius (custom) call; column walk for FP16 storage and 5D fields in FP32 (measured faster).
 template <class SP, class LK>
 static hipError_t launch_sched(const DhopArgs &a) {
-    if (a.custom || (a.g.Ls == 1 && !SP::kScaled)) return launch_dir<SP, LK>(a);
+    constexpr bool f64 = sizeof(typename SP::C) == 8;
+    if (a.custom || (!SP::kScaled && (a.g.Ls == 1 || f64))) return launch_dir<SP, LK>(a);
     return launch_walk<SP, LK>(a);
 }
 
