@@ -254,7 +254,9 @@ int grid_solve_eo(const void *U, const void *b, void *x, const grid_geom *geom, 
  *   forces F = TA(G U^+) with G = dS/dRe U + i dS/dIm U (as grid_dhop_backward);
  *   momenta P in su(3) per link ([V][4][3][3], anti-Hermitian traceless), K = sum tr(P^+ P);
  *   dU/dt = P U, dP/dt = -F/2, leapfrog: P -= (eps/2) F/2, then n_steps times
- *   { U <- exp(eps P) U; P -= eps F/2 } with the last momentum step halved.
+ *   { U <- exp(eps P) U; P -= eps F/2 } with the last momentum step halved; Omelyan (second-order
+ *   minimum norm, l = 0.1931833275037836) per step: P -= l eps F/2; U <- exp(eps/2 P) U;
+ *   P -= (1 - 2 l) eps F/2; U <- exp(eps/2 P) U; P -= l eps F/2.
  * Random momenta and pseudofermion sources are drawn by the caller.
  */
 typedef struct {
@@ -263,7 +265,10 @@ typedef struct {
     int n_steps;            /* leapfrog steps                                                   */
     grid_op fermion;        /* GRID_WILSON or GRID_DWF pseudofermion operator (phi != NULL)     */
     grid_cg_params cg;      /* the solves inside every fermion-force evaluation                 */
+    int integrator;         /* GRID_LEAPFROG or GRID_OMELYAN                                    */
 } grid_md_params;
+
+enum grid_integrator { GRID_LEAPFROG = 0, GRID_OMELYAN = 1 };
 
 typedef struct {
     int solves;             /* fermion solves performed                                         */
@@ -282,7 +287,8 @@ int grid_gauge_force(const void *U, void *F, const grid_geom *geom, double beta,
 int grid_link_exp(void *U, const void *P, double eps, long n_links, void *stream);
 
 /*
- * grid_md_leapfrog -- integrate (U, P) in place over n_steps leapfrog steps of size eps; phi
+ * grid_md_leapfrog -- integrate (U, P) in place over n_steps steps of size eps with the integrator
+ * params->integrator names (leapfrog or Omelyan); phi
  * (FP64, the 4D or 5D pseudofermion of `fermion`) adds the fermion force, NULL integrates the pure
  * gauge system. Synchronous. Returns GRID_OK or an argument / HIP error; stats->failed_solves
  * counts force solves that did not reach cg.tol.

@@ -119,6 +119,26 @@ def hamiltonian(U, P, beta, fermion=None) -> float:
     return H
 
 
+OMELYAN_LAMBDA = 0.1931833275037836   # Omelyan, Mryglod and Folk's second-order minimum-norm value
+
+
+def omelyan(U, P, beta: float, eps: float, n: int, fermion=None):
+    """Second-order minimum-norm integrator: per step P -= l e F/2; U <- exp(e/2 P) U;
+    P -= (1 - 2 l) e F/2; U <- exp(e/2 P) U; P -= l e F/2 (l = OMELYAN_LAMBDA)."""
+    lam = OMELYAN_LAMBDA
+    U, P = np.array(U, dtype=np.complex128), np.array(P, dtype=np.complex128)
+
+    def drift(U, P):
+        return np.einsum("...ij,...jk->...ik", su3_exp(0.5 * eps * P), U)
+    for _ in range(n):
+        P = P - lam * eps * md_force(U, beta, fermion)
+        U = drift(U, P)
+        P = P - (1.0 - 2.0 * lam) * eps * md_force(U, beta, fermion)
+        U = drift(U, P)
+        P = P - lam * eps * md_force(U, beta, fermion)
+    return U, P
+
+
 def leapfrog(U, P, beta: float, eps: float, n: int, fermion=None):
     U, P = np.array(U, dtype=np.complex128), np.array(P, dtype=np.complex128)
     P = P - 0.5 * eps * md_force(U, beta, fermion)

@@ -1,7 +1,7 @@
 // Hybrid Monte Carlo molecular dynamics (HMC is among the algorithms the paper lists, Section 4):
 // Wilson plaquette gauge action and its force, the su(3) exponential link update, the kinetic
-// energy, and a leapfrog integrator whose fermion force is the pseudofermion force of the
-// hopping-term adjoint (CG solve recomputed at every force evaluation).
+// energy, and leapfrog and Omelyan integrators whose fermion force is the pseudofermion force of
+// the hopping-term adjoint (CG solve recomputed at every force evaluation).
 //
 // Conventions (shared with the fermion force of grid_dhop_backward):
 //   S_G = beta sum_{x, mu<nu} (1 - Re tr P_munu(x) / 3),
@@ -362,6 +362,25 @@ hipError_t run_md_leapfrog(void *U, void *P, const void *phi, const GeomDev &g, 
     memset(stats, 0, sizeof(*stats));
     const long nd = static_cast<long>(g.vol) * 4 * 18;
     if (phi) HMCCHK(hipMemsetAsync(r.ws + r.L.X, 0, static_cast<size_t>(g.n5) * 192, st));
+    if (p.integrator == GRID_OMELYAN) {
+        // the closing kick of a step and the opening kick of the next act at the same U and are
+        // merged: 2 n + 1 force evaluations
+        constexpr double lam = 0.1931833275037836;
+        const long nl = static_cast<long>(g.vol) * 4;
+        HMCCHK(total_force(r));
+        HMCCHK(daxpy(P, r.ws + r.L.F, -0.5 * lam * p.eps, nd, st));
+        for (int i = 0; i < p.n_steps; ++i) {
+            HMCCHK(launch_link_exp(U, P, 0.5 * p.eps, nl, st));
+            HMCCHK(total_force(r));
+            HMCCHK(daxpy(P, r.ws + r.L.F, -0.5 * (1.0 - 2.0 * lam) * p.eps, nd, st));
+            HMCCHK(launch_link_exp(U, P, 0.5 * p.eps, nl, st));
+            HMCCHK(total_force(r));
+            HMCCHK(daxpy(P, r.ws + r.L.F, -0.5 * (i == p.n_steps - 1 ? lam : 2.0 * lam) * p.eps, nd, st));
+        }
+        HMCCHK(hipStreamSynchronize(st));
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return hipSuccess;
+    }
     // P -= (eps / 2) F / 2
     HMCCHK(total_force(r));
     HMCCHK(daxpy(P, r.ws + r.L.F, -0.25 * p.eps, nd, st));

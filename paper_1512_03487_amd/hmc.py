@@ -24,10 +24,10 @@ def gaussian_spinor(shape, rng: np.random.Generator) -> np.ndarray:
     return ((rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2.0)).astype(np.complex128)
 
 
-def trajectory(U, beta, eps, n_steps, rng, fermion=None, **cg):
+def trajectory(U, beta, eps, n_steps, rng, fermion=None, integrator="leapfrog", **cg):
     """One HMC trajectory. fermion: None (pure gauge) or dict(kind, Ls, mass / M5, mf) for a
-    two-flavour pseudofermion phi = Op^dagger eta. Returns (U_new, accepted, dH, info); U is not
-    modified."""
+    two-flavour pseudofermion phi = Op^dagger eta; integrator "leapfrog" or "omelyan". Returns
+    (U_new, accepted, dH, info); U is not modified."""
     dev = U.device
     shape4 = tuple(U.shape[:4])
     P = torch.from_numpy(gaussian_momenta(shape4, rng)).to(dev)
@@ -42,7 +42,7 @@ def trajectory(U, beta, eps, n_steps, rng, fermion=None, **cg):
                        mf=kw.get("mf", 0.01))
     e0 = api.hmc_energy(U, P, beta, phi, **kw, **cg)
     U1, P1 = U.clone(), P.clone()
-    st = api.md_leapfrog(U1, P1, beta, eps, n_steps, phi, **kw, **cg)
+    st = api.md_leapfrog(U1, P1, beta, eps, n_steps, phi, integrator=integrator, **kw, **cg)
     e1 = api.hmc_energy(U1, P1, beta, phi, **kw, **cg)
     dH = e1["H"] - e0["H"]
     accepted = bool(rng.uniform() < np.exp(-dH))

@@ -124,3 +124,41 @@ def test_hmc_trajectories_pure_gauge(gpu):
         assert abs(dH) < 1.0
     assert acc >= 3
     assert abs(OH.plaquette(U.cpu().numpy()) - OH.plaquette(U0)) > 1e-3
+
+
+@pytest.mark.parametrize("with_fermion", [False, True])
+def test_omelyan_matches_oracle(gpu, with_fermion):
+    from tests.gpu_util import dev, host, rel
+    gm = _gm()
+    dims, Ls, beta = (2, 2, 2, 4), 4, 5.5
+    U = F.gauge_field(dims, seed=1, kind="weak")
+    P = F.random_su3_algebra(dims, seed=7)
+    phi = F.spinor_field(dims, seed=5, Ls=Ls) if with_fermion else None
+    Ud, Pd = dev(U), dev(P)
+    st = gm.md_leapfrog(Ud, Pd, beta, 0.1, 3, dev(phi) if with_fermion else None, tol=1e-12, integrator="omelyan",
+                        **DWF)
+    ferm = (O.Op.dwf(Ls, 1.8, 0.2), phi) if with_fermion else None
+    Ur, Pr = OH.omelyan(U, P, beta, 0.1, 3, ferm)
+    tol = 1e-12 if not with_fermion else 1e-8
+    assert rel(host(Ud), Ur) <= tol and rel(host(Pd), Pr) <= tol
+    assert st["solves"] == (7 if with_fermion else 0)
+
+
+def test_omelyan_trajectory_and_reversibility(gpu):
+    """A trajectory with the Omelyan integrator: dH equals the oracle's for the same momenta, and
+    integrating back with -P returns to the start."""
+    import paper_1512_03487_amd.hmc as H
+    from tests.gpu_util import dev, host, rel
+    gm = _gm()
+    dims, beta, eps, n = (4, 4, 4, 4), 5.7, 0.05, 10
+    U0 = F.gauge_field(dims, seed=1, kind="weak")
+    P0 = H.gaussian_momenta(dims[::-1], np.random.default_rng(321))
+    U1, P1 = OH.omelyan(U0, P0, beta, eps, n)
+    dH_ref = OH.hamiltonian(U1, P1, beta) - OH.hamiltonian(U0, P0, beta)
+    _, _, dH, _ = H.trajectory(dev(U0), beta, eps, n, np.random.default_rng(321), integrator="omelyan")
+    assert dH == pytest.approx(dH_ref, rel=1e-8, abs=1e-10)
+    Ud, Pd = dev(U0), dev(P0)
+    gm.md_leapfrog(Ud, Pd, beta, eps, n, integrator="omelyan")
+    Pd.neg_()
+    gm.md_leapfrog(Ud, Pd, beta, eps, n, integrator="omelyan")
+    assert rel(host(Ud), U0) <= 1e-12 and rel(host(Pd), -P0) <= 1e-12

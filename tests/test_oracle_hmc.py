@@ -103,3 +103,25 @@ def test_leapfrog_energy_error_is_second_order(with_fermion):
     Ub, Pb = U0.copy(), P0 - 0.2 * hmc.md_force(U0, beta, ferm)
     Ub = np.einsum("...ij,...jk->...ik", hmc.su3_exp(0.4 * Pb), Ub)
     assert abs(hmc.hamiltonian(Ub, Pb - 0.2 * hmc.md_force(Ub, beta, ferm), beta, ferm) - H0) > 10 * dH[0]
+
+
+@pytest.mark.parametrize("with_fermion", [False, True])
+def test_omelyan_reversible_second_order_and_more_accurate(with_fermion):
+    dims, beta, tau = (2, 2, 2, 4), 5.5, 0.4
+    U0, ferm = _fermion(dims)
+    ferm = ferm if with_fermion else None
+    P0 = F.random_su3_algebra(dims, seed=7)
+    U1, P1 = hmc.omelyan(U0, P0, beta, 0.1, 4, ferm)
+    U2, P2 = hmc.omelyan(U1, -P1, beta, 0.1, 4, ferm)
+    tol = 1e-12 if not with_fermion else 1e-10
+    assert np.max(np.abs(U2 - U0)) < tol and np.max(np.abs(P2 + P0)) < tol
+    H0 = hmc.hamiltonian(U0, P0, beta, ferm)
+    dH = []
+    for n in (4, 8):
+        Un, Pn = hmc.omelyan(U0, P0, beta, tau / n, n, ferm)
+        dH.append(abs(hmc.hamiltonian(Un, Pn, beta, ferm) - H0))
+    assert 3.0 < dH[0] / dH[1] < 5.0, dH
+    # and beats leapfrog at twice the step count (about the same number of force evaluations once
+    # consecutive outer kicks are merged)
+    Ul, Pl = hmc.leapfrog(U0, P0, beta, tau / 16, 16, ferm)
+    assert dH[1] < 0.5 * abs(hmc.hamiltonian(Ul, Pl, beta, ferm) - H0)
