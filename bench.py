@@ -5,8 +5,9 @@ One "step" is one application of the hopping operator H on a 16^4 lattice in FP6
 links exp(0.3 i H) and a Gaussian spinor (1320 flop per site). The timed loop rotates over
 several independent (U, psi, out) buffer sets whose inputs alone exceed twice the 256 MB
 last-level cache, so every application streams its inputs from HBM. Further legs (FP32, 32^4, domain wall
-24^4 x 12 in FP32 and FP16 storage, the CG on 16^4 x 16, and the even-odd preconditioned solve of
-M x = b on the same lattice against CG on M^dagger M) are reported alongside.
+24^4 x 12 in FP32 and FP16 storage, the CG on 16^4 x 16, the even-odd preconditioned solve of
+M x = b on the same lattice against CG on M^dagger M, and the throughput of graph-recorded sloppy CG
+iterations at 32^4 and 24^4 x 12) are reported alongside.
 
 Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--no-cg] [--no-cpu]
 Prints one JSON line.
@@ -235,6 +236,59 @@ def eo_legs():
     return out
 
 
+# CG vector-kernel bytes per 5D site and sloppy iteration (dot <p,q>; x, r update; p update)
+CG_VEC_BYTES = {"f32": 192 + 576 + 288, "f16s": 104 + 400 + 156}
+OP_FLOPS = {"wilson": 1368, "dwf": 1416}
+
+
+def cg_iteration_legs():
+    """Throughput of sloppy CG iterations (two operator applications and the three vector kernels)
+    on Wilson D^dagger D at 32^4 and domain-wall M^dagger M at 24^4 x 12, Haar links, FP32 and
+    FP16-storage spinors, with the iterations between host checks replayed from recorded HIP graphs
+    and, for comparison, launched directly. Per-iteration time = (t(120 its) - t(20 its)) / 100, so
+    the setup, the initial and final FP64 residuals and the workspace touch drop out; no reliable
+    update occurs (delta = tol = 1e-30)."""
+    import torch
+    import paper_1512_03487_amd as gm
+    from paper_1512_03487_amd import fields
+    dev = torch.device("cuda:0")
+    out = {}
+    for name, dims, Ls, kind, kw in (("wilson_32^4", (32, 32, 32, 32), None, "wilson", dict(mass=0.1)),
+                                     ("dwf_24^4x12", (24, 24, 24, 24), 12, "dwf", dict(M5=1.8, mf=0.01))):
+        U = torch.from_numpy(fields.gauge_field(dims, seed=1, kind="haar")).to(dev)
+        b = torch.from_numpy(fields.spinor_field(dims, seed=3, Ls=Ls)).to(dev)
+        n5 = dims[0] * dims[1] * dims[2] * dims[3] * (Ls or 1)
+        res = {"lattice": list(dims), "Ls": Ls or 1, "op": f"{kind} normal operator", **kw}
+        for sloppy, fmt in (("f32", "L18"), ("f16s", "L12")):
+            ws = torch.empty(gm.cg_workspace_bytes(b, sloppy=sloppy, link_fmt=fmt), dtype=torch.uint8, device=dev)
+            per = {}
+            for graph in (True, False):
+                def run(n):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    x, st = gm.cg(U, b, kind=kind, tol=1e-30, delta=1e-30, maxiter=n, sloppy=sloppy, link_fmt=fmt,
+                                  check_every=10, graph=graph, workspace=ws, raise_on_fail=False, **kw)
+                    torch.cuda.synchronize()
+                    assert st["iterations"] == n and st["reliable_updates"] == 0
+                    return time.perf_counter() - t0
+                run(20)
+                t_it = (run(120) - run(20)) / 100
+                per["graph" if graph else "direct"] = t_it
+            t_it = per["graph"]
+            nbytes = (2 * alg_bytes_per_site(sloppy, fmt, Ls or 1) + CG_VEC_BYTES[sloppy]) * n5
+            res[f"{sloppy}_{fmt}"] = {
+                "ms_per_iteration": round(t_it * 1e3, 4),
+                "ms_per_iteration_direct_launches": round(per["direct"] * 1e3, 4),
+                "alg_bytes_per_iteration": int(nbytes),
+                "alg_gbs": round(nbytes / t_it / 1e9, 1), "roofline_frac": round(nbytes / t_it / 1e9 / HBM_PEAK_GBS, 4),
+                "op_gflops": round(2 * OP_FLOPS[kind] * n5 / t_it / 1e9, 1)}
+            del ws
+        out[name] = res
+        del U, b
+        torch.cuda.empty_cache()
+    return out
+
+
 def hmc_legs():
     """Molecular-dynamics kernels on 16^4 (FP64): gauge force and link update per launch, and one
     5-step leapfrog with a two-flavour Ls = 8 domain-wall pseudofermion (FP32-sloppy solves)."""
@@ -306,9 +360,14 @@ def main():
                     help="also run a plain 256 MiB device copy three times (counter calibration)")
     ap.add_argument("--only-solvers", action="store_true",
                     help="profiling aid: run only the CG and even-odd solver legs and print them")
+    ap.add_argument("--only-cg-iterations", action="store_true",
+                    help="profiling aid: run only the recorded-graph CG iteration legs and print them")
     args = ap.parse_args()
     if args.only_solvers:
         print(json.dumps({"cg_dwf_16^4x16": cg_legs(), "solve_dwf_16^4x16_even_odd": eo_legs()}), flush=True)
+        return
+    if args.only_cg_iterations:
+        print(json.dumps({"cg_iterations_graph": cg_iteration_legs()}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (multi-GPU sharding is not built)",
@@ -357,6 +416,7 @@ def main():
         torch.cuda.empty_cache()
     cg = None if args.no_cg else cg_legs()
     eo = None if args.no_cg else eo_legs()
+    cgi = None if args.no_cg else cg_iteration_legs()
     md = None if args.no_legs else hmc_legs()
     cpu = None if args.no_cpu else cpu_baseline()
 
@@ -387,6 +447,7 @@ def main():
         "legs": legs,
         "cg_dwf_16^4x16": cg,
         "solve_dwf_16^4x16_even_odd": eo,
+        "cg_iterations_graph": cgi,
         "hmc_16^4": md,
         "wall_s_timed": round(wall, 4),
     }

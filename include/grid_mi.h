@@ -97,6 +97,11 @@ typedef struct {
     int link_fmt;      /* link format of the sloppy operator (GRID_L18 or GRID_L12)                */
     double delta;      /* reliable-update threshold (mixed modes), e.g. 0.1                       */
     int check_every;   /* iterations between host reads of the residual norm (>= 1), e.g. 10     */
+    int graph;         /* nonzero: the check_every iterations between two host reads are recorded
+                          once into a HIP graph (per starting parity, on a stream of the library's
+                          own) and replayed on the caller's stream, one graph launch in place of
+                          about six kernel launches per iteration; same kernels, same arguments,
+                          bit-identical results                                                   */
 } grid_cg_params;
 
 /* CG results. */

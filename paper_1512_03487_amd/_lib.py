@@ -36,7 +36,8 @@ class GridOp(ctypes.Structure):
 
 class GridCgParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("sloppy_prec", ctypes.c_int),
-                ("link_fmt", ctypes.c_int), ("delta", ctypes.c_double), ("check_every", ctypes.c_int)]
+                ("link_fmt", ctypes.c_int), ("delta", ctypes.c_double), ("check_every", ctypes.c_int),
+                ("graph", ctypes.c_int)]
 
 
 class GridCgStats(ctypes.Structure):

@@ -177,12 +177,14 @@ def dwf_mdag_m(U, psi, M5, mf, out=None, tmp=None):
     return out
 
 
-def cg_params(tol=1e-10, maxiter=20000, sloppy="f64", link_fmt="L18", delta=0.1, check_every=10) -> GridCgParams:
+def cg_params(tol=1e-10, maxiter=20000, sloppy="f64", link_fmt="L18", delta=0.1, check_every=10,
+              graph=False) -> GridCgParams:
     p = GridCgParams()
     p.tol, p.maxiter = float(tol), int(maxiter)
     p.sloppy_prec = _PREC[sloppy] if isinstance(sloppy, str) else int(sloppy)
     p.link_fmt = _FMT[link_fmt] if isinstance(link_fmt, str) else int(link_fmt)
     p.delta, p.check_every = float(delta), int(check_every)
+    p.graph = 1 if graph else 0
     return p
 
 

@@ -15,6 +15,12 @@
 // performs a reliable update (x += x_hat, r = b - A x in FP64, r_hat = lo(r)) when the sloppy
 // residual fell below delta times its maximum since the last update, or below the target.
 // The solve stops only on an FP64 true residual <= tol |b|.
+//
+// With params.graph the check_every iterations between two host reads (their last p update
+// excepted, which follows the check) are recorded once into a HIP graph per starting parity on a
+// stream of the driver's own, then replayed on the caller's stream: one launch per segment in
+// place of about six per iteration. The recorded kernels and arguments are those of the direct
+// path (all workspace pointers are fixed for the solve), so results are bitwise identical.
 #include <chrono>
 #include <type_traits>
 #include <math.h>
@@ -544,9 +550,28 @@ struct CgRun {
     int link_fmt;
     double delta;
     int check_every;
+    bool graph;          // replay recorded iteration segments
     char *ws;
     hipStream_t st;
     bool op_tmp;         // workspace holds the operator temporaries
+};
+
+// Recorded iteration segments of one solve, by starting parity; released with the solve.
+// The caller's stream is drained before the executables are destroyed (the normal exits have
+// already synchronised it; an error exit may leave replays in flight).
+struct SegmentGraphs {
+    hipStream_t user;
+    hipStream_t cs = nullptr;
+    hipGraphExec_t ex[2] = {nullptr, nullptr};
+    explicit SegmentGraphs(hipStream_t s) : user(s) {}
+    SegmentGraphs(const SegmentGraphs &) = delete;
+    SegmentGraphs &operator=(const SegmentGraphs &) = delete;
+    ~SegmentGraphs() {
+        if (ex[0] || ex[1]) (void)hipStreamSynchronize(user);
+        for (hipGraphExec_t e : ex)
+            if (e) (void)hipGraphExecDestroy(e);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
 };
 
 #define HIPCHK(x)                               \
@@ -687,16 +712,50 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
     int it = 0;
     const int check = c.check_every < 1 ? 1 : c.check_every;
 
+    // one sloppy step on stream s (q_hat = A_lo p_hat, alpha, x_hat and r_hat), parity P
+    auto step_xr = [&](hipStream_t s, int P) -> hipError_t {
+        CgRun cs = c;
+        cs.st = s;
+        HIPCHK(apply_op(cs, ulo, c.sloppy, lo_fmt, ph, phs, th, ths, 0));
+        HIPCHK(apply_op(cs, ulo, c.sloppy, lo_fmt, th, ths, qh, qhs, 1));
+        Vec<SH>::dot(grid, s, ph, phs, qh, qhs, n, pq);
+        HIPCHK(hipGetLastError());
+        Vec<SH>::update_xr(grid, s, mixed ? xh : c.x, ph, phs, rh, rhs, qh, qhs, n, rr[P ^ 1], pq, np, rr[P], scal);
+        return hipGetLastError();
+    };
+    auto step_p = [&](hipStream_t s, int P) -> hipError_t {
+        Vec<SH>::update_p(grid, s, rh, rhs, ph, phs, n, rr[P ^ 1], rr[P], np, scal);
+        return hipGetLastError();
+    };
+    // record the segment of `check` steps starting at parity P0
+    SegmentGraphs seg(c.st);
+    auto record = [&](int P0) -> hipError_t {
+        if (!seg.cs) HIPCHK(hipStreamCreateWithFlags(&seg.cs, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(seg.cs, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < check && e == hipSuccess; ++i) {
+            e = step_xr(seg.cs, (P0 + i) & 1);
+            if (e == hipSuccess && i + 1 < check) e = step_p(seg.cs, (P0 + i) & 1);
+        }
+        hipGraph_t gr = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(seg.cs, &gr);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&seg.ex[P0], gr, nullptr, nullptr, 0);
+        if (gr) (void)hipGraphDestroy(gr);
+        return e;
+    };
+
     while (!converged && it < c.maxiter) {
-        const int P = it & 1;
-        // q_hat = A_lo p_hat
-        HIPCHK(apply_op(c, ulo, c.sloppy, lo_fmt, ph, phs, th, ths, 0));
-        HIPCHK(apply_op(c, ulo, c.sloppy, lo_fmt, th, ths, qh, qhs, 1));
-        Vec<SH>::dot(grid, c.st, ph, phs, qh, qhs, n, pq);
-        HIPCHK(hipGetLastError());
-        Vec<SH>::update_xr(grid, c.st, mixed ? xh : c.x, ph, phs, rh, rhs, qh, qhs, n, rr[P ^ 1], pq, np, rr[P], scal);
-        HIPCHK(hipGetLastError());
-        ++it;
+        int P = it & 1;
+        if (c.graph && it % check == 0 && it + check <= c.maxiter) {
+            if (!seg.ex[P]) HIPCHK(record(P));
+            HIPCHK(hipGraphLaunch(seg.ex[P], c.st));
+            it += check;
+            P = (it - 1) & 1;
+        } else {
+            HIPCHK(step_xr(c.st, P));
+            ++it;
+        }
         if (it % check == 0 || it == c.maxiter) {
             double sc[16];
             const double rn = sqrt(read_scalar(c, rr[P], np, scal, 10, &err, sc));
@@ -726,8 +785,7 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
                 maxr = rtrue;
             }
         }
-        Vec<SH>::update_p(grid, c.st, rh, rhs, ph, phs, n, rr[P ^ 1], rr[P], np, scal);
-        HIPCHK(hipGetLastError());
+        HIPCHK(step_p(c.st, P));
     }
     if (mixed && !converged) {
         hipLaunchKernelGGL(k_accum_x, grid, block, 0, c.st, static_cast<double2 *>(c.x), static_cast<float4 *>(xh),
@@ -762,6 +820,7 @@ hipError_t run_cg_op(const CgOp &op, const void *U, const void *b, void *x, long
     c.link_fmt = p.link_fmt;
     c.delta = p.delta;
     c.check_every = p.check_every;
+    c.graph = p.graph != 0;
     c.ws = static_cast<char *>(ws);
     c.st = st;
     const auto t0 = std::chrono::steady_clock::now();

@@ -190,3 +190,32 @@ def test_md_validation(lib):
     assert call(phi=A + 0x10000000 + 64) == _lib.GRID_EINVAL                  # phi overlaps P
     assert lib.grid_link_exp(P(A), P(A + 16), ctypes.c_double(0.1), 16, None) == _lib.GRID_EINVAL
     assert lib.grid_gauge_force(P(A), P(A + 16), ctypes.byref(geom()), ctypes.c_double(5.5), None) == _lib.GRID_EINVAL
+
+
+def test_ctypes_structs_match_the_c_header(tmp_path):
+    """Every struct of include/grid_mi.h has the size and field offsets of its ctypes mirror, as a
+    C compiler lays it out (gcc on the header itself)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"grid_geom": _lib.GridGeom, "grid_op": _lib.GridOp, "grid_cg_params": _lib.GridCgParams,
+               "grid_cg_stats": _lib.GridCgStats, "grid_md_params": _lib.GridMdParams,
+               "grid_md_stats": _lib.GridMdStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "grid_mi.h"', 'int main(void) {']
+    for cname, py in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict((" ".join(l.split()[:2]), int(l.split()[2]))
+               for l in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines())
+    for cname, py in mirrors.items():
+        assert got[f"{cname} size"] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[f"{cname} {fname}"] == getattr(py, fname).offset, (cname, fname)

@@ -102,3 +102,30 @@ def test_config2_dwf_16_4_ls16(gpu, sloppy):
     print(f"config2 {sloppy}: {st['iterations']} it, {st['reliable_updates']} RU, {st['seconds']:.3f} s, "
           f"oracle residual {res:.3e}", flush=True)
     assert st["converged"] and res <= RES_SLACK * TOL
+
+
+@pytest.mark.parametrize("solver,kind,sloppy,check", [
+    ("cg", "dwf", "f64", 10), ("cg", "dwf", "f32", 3), ("cg", "dwf", "f16s", 4), ("cg", "wilson", "f32", 7),
+    ("cg", "mobius", "f32", 5), ("eo", "dwf", "f32", 3), ("eo", "wilson", "f16s", 6)])
+def test_graph_segments_match_direct_launches(gpu, solver, kind, sloppy, check):
+    """Recorded iteration segments (grid_cg_params.graph) replay the direct path's kernels with the
+    same arguments: the solution, iteration count, reliable updates and residual are identical.
+    Each solve replays a segment tens of times with the driver's own checks, reliable updates and
+    synchronisations in between; an odd check_every exercises both starting parities."""
+    import paper_1512_03487_amd as gm
+    from tests.gpu_util import dev
+    dims, Ls = (4, 4, 4, 8), (1 if kind == "wilson" else 8)
+    U = dev(F.gauge_field(dims, seed=1, kind="haar"))
+    b = dev(F.spinor_field(dims, seed=3, Ls=Ls) if Ls > 1 else F.spinor_field(dims, seed=3))
+    kw = dict(kind=kind, mass=0.1, M5=1.8, mf=0.05, tol=TOL, sloppy=sloppy, check_every=check)
+    if kind == "mobius":
+        kw.update(b5=1.5, c5=0.5)
+    run = gm.cg if solver == "cg" else gm.solve_eo
+    out = [run(U, b, graph=g, **kw) for g in (False, True, True)]
+    (x0, s0), (x1, s1), (x2, s2) = out
+    for x, s in ((x1, s1), (x2, s2)):
+        assert s["converged"] and s["iterations"] == s0["iterations"]
+        assert s.get("reliable_updates") == s0.get("reliable_updates")
+        assert s["true_residual"] == s0["true_residual"]
+        assert bool((x == x0).all()), "graph replay differs from direct launches"
+    assert s0["iterations"] > 2 * check
