@@ -309,6 +309,81 @@ int grid_hmc_energy(const void *U, const void *P, const void *phi, const grid_ge
                     const grid_md_params *params, void *workspace, size_t ws_bytes, double energies[4],
                     grid_md_stats *stats, void *stream);
 
+/*
+ * Generic coarse stencil and two-level multigrid for the Wilson operator D (Section 2.4's stencil
+ * example is the coarse-grid operator of an adaptive multigrid inverter; Section 4 lists
+ * multigrid-preconditioned GCR). FP64 throughout.
+ *
+ *   aggregates   blocks of block[mu] fine sites; coarse extents Lc = L / block (periodic), coarse
+ *                site index xc0 + Lc0 (xc1 + Lc1 (xc2 + Lc2 xc3));
+ *   basis vecs   nvec fine fields [nvec][V][4][3] complex double; after grid_mg_basis they are
+ *                orthonormal on every aggregate and chirality (spins 0,1 and 2,3);
+ *   coarse field [Vc][N] complex double, N = 2 nvec, component n = chi nvec + k;
+ *   R, P         (R psi)(xc)[chi nvec + k] = sum over the aggregate and the spins of chi of
+ *                conj(phi_k) psi; (P v)(x) = sum_k phi_k(x)|chi v(xc)[chi nvec + k];
+ *   coarse op    A_c = R D P as the 9-point stencil (A_c v)(xc) = sum_d A_d(xc) v(xc + e_d),
+ *                d = 0 (self), 1 + 2 mu (+mu), 2 + 2 mu (-mu); hops of D from fine x in +mu
+ *                with x_mu mod block[mu] = block[mu] - 1 (in -mu with x_mu mod block[mu] = 0)
+ *                make A_{1+2mu} (A_{2+2mu}), all other terms A_0. Layout [Vc][9][N][N] with
+ *                element (row i, column j) of A_d(xc) at [xc][d][j][i].
+ */
+typedef struct {
+    int block[4];       /* aggregate extents (bx, by, bz, bt), each dividing the lattice extent  */
+    int nvec;           /* basis vectors (1..32; N = 2 nvec coarse components per site)          */
+    int setup_rounds;   /* grid_mg_basis: rounds of near-null improvement (0: orthonormalise)  */
+    int setup_iters;    /* CG iterations on D^+ D per vector and round, from zero, then unit norm */
+    int coarse_iters;   /* cap on the coarse CGNR iterations per cycle                           */
+    double coarse_tol;  /* the coarse CGNR stops below coarse_tol times its starting residual    */
+    int smooth_iters;   /* minimal-residual steps on D z = r after the coarse correction         */
+    int restart;        /* GCR restart length (1..64)                                           */
+    int maxiter;        /* cap on GCR iterations                                                */
+    double tol;         /* target |b - D x| / |b|                                               */
+} grid_mg_params;
+
+/*
+ * grid_coarse_stencil -- out = A v (dag: A^+ v, (A^+ v)(xc) = sum_d A_d(xc - e_d)^+ v(xc - e_d)) for
+ * any 9-point stencil A in the layout above; coarse_dims = Lc (each >= 1), N in 1..64.
+ * out must not overlap v. Asynchronous.
+ */
+int grid_coarse_stencil(const void *A, const void *v, void *out, const int coarse_dims[4], int N, int dag,
+                        void *stream);
+
+/* grid_mg_workspace_bytes -- device workspace of grid_mg_basis / grid_mg_coarse_op / grid_mg_solve. */
+size_t grid_mg_workspace_bytes(const grid_geom *geom, const grid_mg_params *params);
+
+/*
+ * grid_mg_basis -- in place on vecs: setup_rounds times { every vector <- setup_iters CG iterations
+ * on D^+ D x = vector from x = 0, normalised to 1 }, then Gram-Schmidt in the order k = 0, 1, ...
+ * on every aggregate and chirality. The starting vectors (random) are the caller's. op: GRID_WILSON
+ * (op->mass). Synchronous.
+ */
+int grid_mg_basis(const void *U, void *vecs, const grid_geom *geom, const grid_op *op, const grid_mg_params *params,
+                  void *workspace, size_t ws_bytes, void *stream);
+
+/* grid_mg_coarse_op -- A = R D P for the basis vecs (orthonormalised). Asynchronous. */
+int grid_mg_coarse_op(const void *U, const void *vecs, void *A, const grid_geom *geom, const grid_op *op,
+                      const grid_mg_params *params, void *workspace, size_t ws_bytes, void *stream);
+
+/* grid_mg_restrict / grid_mg_prolong -- vc = R psi, psi = P vc. Asynchronous. */
+int grid_mg_restrict(const void *vecs, const void *psi, void *vc, const grid_geom *geom, const grid_mg_params *params,
+                     void *stream);
+int grid_mg_prolong(const void *vecs, const void *vc, void *psi, const grid_geom *geom, const grid_mg_params *params,
+                    void *stream);
+
+/*
+ * grid_mg_solve -- D x = b by flexible GCR(restart) preconditioned with one two-level cycle:
+ * r_c = R r; CGNR on A_c from zero (A_c^+ = G5 A_c G5, G5 = +1 / -1 on the two chiralities) for
+ * at most coarse_iters iterations, stopping below coarse_tol times the starting normal residual;
+ * z = P e_c; smooth_iters minimal-residual steps on D z = r. The GCR orthogonalises w = D z by
+ * modified Gram-Schmidt and recomputes r = b - D x at every restart and at the end. x holds the
+ * initial guess on entry. stats: iterations (GCR), reliable_updates (restarts), true_residual,
+ * converged, seconds. Synchronous. Returns GRID_OK, GRID_ENOCONV, GRID_EBREAKDOWN or an argument /
+ * HIP error.
+ */
+int grid_mg_solve(const void *U, const void *vecs, const void *A, const void *b, void *x, const grid_geom *geom,
+                  const grid_op *op, const grid_mg_params *params, void *workspace, size_t ws_bytes,
+                  grid_cg_stats *stats, void *stream);
+
 /* grid_last_error -- message of the calling thread's last failed call ("" if none). */
 const char *grid_last_error(void);
 

@@ -22,7 +22,9 @@ GRID_LEAPFROG, GRID_OMELYAN = 0, 1
 EXPORTS = ("grid_dhop", "grid_mobius", "grid_dwf_mdag_m", "grid_cg_workspace_bytes", "grid_cg", "grid_dhop_backward",
            "grid_dhop_cb", "grid_m5inv", "grid_solve_eo_workspace_bytes", "grid_solve_eo",
            "grid_md_workspace_bytes", "grid_gauge_force", "grid_link_exp", "grid_md_leapfrog", "grid_hmc_energy",
-           "grid_convert_spinor", "grid_convert_links", "grid_last_error", "grid_version")
+           "grid_convert_spinor", "grid_convert_links", "grid_coarse_stencil", "grid_mg_workspace_bytes",
+           "grid_mg_basis", "grid_mg_coarse_op", "grid_mg_restrict", "grid_mg_prolong", "grid_mg_solve",
+           "grid_last_error", "grid_version")
 
 
 class GridGeom(ctypes.Structure):
@@ -53,6 +55,13 @@ class GridMdParams(ctypes.Structure):
 class GridMdStats(ctypes.Structure):
     _fields_ = [("solves", ctypes.c_int), ("cg_iterations", ctypes.c_int), ("failed_solves", ctypes.c_int),
                 ("seconds", ctypes.c_double)]
+
+
+class GridMgParams(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int * 4), ("nvec", ctypes.c_int), ("setup_rounds", ctypes.c_int),
+                ("setup_iters", ctypes.c_int), ("coarse_iters", ctypes.c_int), ("coarse_tol", ctypes.c_double),
+                ("smooth_iters", ctypes.c_int), ("restart", ctypes.c_int), ("maxiter", ctypes.c_int),
+                ("tol", ctypes.c_double)]
 
 
 class GridError(RuntimeError):
@@ -112,6 +121,22 @@ def load():
     lib.grid_convert_spinor.restype = I
     lib.grid_convert_links.argtypes = [P, P, I, I, I, ctypes.c_long, P]
     lib.grid_convert_links.restype = I
+    G, MP = ctypes.POINTER(GridGeom), ctypes.POINTER(GridMgParams)
+    lib.grid_coarse_stencil.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_int), I, I, P]
+    lib.grid_coarse_stencil.restype = I
+    lib.grid_mg_workspace_bytes.argtypes = [G, MP]
+    lib.grid_mg_workspace_bytes.restype = ctypes.c_size_t
+    lib.grid_mg_basis.argtypes = [P, P, G, ctypes.POINTER(GridOp), MP, P, ctypes.c_size_t, P]
+    lib.grid_mg_basis.restype = I
+    lib.grid_mg_coarse_op.argtypes = [P, P, P, G, ctypes.POINTER(GridOp), MP, P, ctypes.c_size_t, P]
+    lib.grid_mg_coarse_op.restype = I
+    lib.grid_mg_restrict.argtypes = [P, P, P, G, MP, P]
+    lib.grid_mg_restrict.restype = I
+    lib.grid_mg_prolong.argtypes = [P, P, P, G, MP, P]
+    lib.grid_mg_prolong.restype = I
+    lib.grid_mg_solve.argtypes = [P, P, P, P, P, G, ctypes.POINTER(GridOp), MP, P, ctypes.c_size_t,
+                                  ctypes.POINTER(GridCgStats), P]
+    lib.grid_mg_solve.restype = I
     lib.grid_last_error.argtypes = []
     lib.grid_last_error.restype = ctypes.c_char_p
     lib.grid_version.argtypes = []

@@ -19,7 +19,8 @@ import torch
 
 from . import _lib
 from ._lib import (GRID_DWF, GRID_F16S, GRID_F32, GRID_F64, GRID_HOP, GRID_L12, GRID_L18, GRID_MOBIUS, GRID_WILSON,
-                   GridCgParams, GridCgStats, GridGeom, GridMdParams, GridMdStats, GridOp, check, load)
+                   GridCgParams, GridCgStats, GridGeom, GridMdParams, GridMdStats, GridMgParams, GridOp, check,
+                   load)
 
 _KIND = {"hop": GRID_HOP, "wilson": GRID_WILSON, "dwf": GRID_DWF, "mobius": GRID_MOBIUS}
 _PREC = {"f64": GRID_F64, "f32": GRID_F32, "f16s": GRID_F16S}
@@ -424,3 +425,129 @@ def convert_links(U, prec="f32", fmt="L18", reunitarise=False):
 
 def version() -> int:
     return int(load().grid_version())
+
+
+# --------------------------------------------------------------------------------------------
+# Generic coarse stencil and two-level multigrid for the Wilson operator (FP64).
+# Coarse fields are (Lct, Lcz, Lcy, Lcx, N) complex128; the coarse operator is
+# (Lct, Lcz, Lcy, Lcx, 9, N, N) with A[..., d, j, i] = element (row i, column j) of A_d.
+# --------------------------------------------------------------------------------------------
+
+def mg_params(block=(2, 2, 2, 2), nvec=6, setup_rounds=2, setup_iters=8, coarse_iters=40, coarse_tol=0.05,
+              smooth_iters=2, restart=8, maxiter=500, tol=1e-10) -> GridMgParams:
+    p = GridMgParams()
+    for mu in range(4):
+        p.block[mu] = int(block[mu])
+    p.nvec, p.setup_rounds, p.setup_iters = int(nvec), int(setup_rounds), int(setup_iters)
+    p.coarse_iters, p.coarse_tol, p.smooth_iters = int(coarse_iters), float(coarse_tol), int(smooth_iters)
+    p.restart, p.maxiter, p.tol = int(restart), int(maxiter), float(tol)
+    return p
+
+
+def _coarse_shape(psi_or_U, block, N):
+    lt, lz, ly, lx = psi_or_U.shape[:4]
+    bx, by, bz, bt = block
+    return (lt // bt, lz // bz, ly // by, lx // bx, N)
+
+
+def _mg_ws(U, p, workspace):
+    g = geom_of_links(U)
+    need = int(load().grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(p)))
+    if need == 0:
+        check(load().grid_mg_restrict(None, None, None, ctypes.byref(g), ctypes.byref(p), None))
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=U.device)
+    return g, workspace
+
+
+def geom_of_links(U) -> GridGeom:
+    if U.dtype != torch.complex128 or tuple(U.shape[4:]) != (4, 3, 3):
+        raise TypeError("multigrid takes complex128 links (Lt, Lz, Ly, Lx, 4, 3, 3)")
+    g = GridGeom()
+    lt, lz, ly, lx = U.shape[:4]
+    g.dims[:] = [lx, ly, lz, lt]
+    g.Ls = 1
+    return g
+
+
+def coarse_stencil(A, v, dag=False, out=None):
+    """out = A v (dag: A^dagger v) for a 9-point coarse stencil (see the layout above)."""
+    _need_cuda(A, "A")
+    _need_cuda(v, "v")
+    N = int(v.shape[-1])
+    if A.dtype != torch.complex128 or v.dtype != torch.complex128 or tuple(A.shape) != tuple(v.shape[:4]) + (9, N, N):
+        raise ValueError("A must be complex128 (Lct, Lcz, Lcy, Lcx, 9, N, N) and v (Lct, Lcz, Lcy, Lcx, N)")
+    out = torch.empty_like(v) if out is None else out
+    lt, lz, ly, lx = v.shape[:4]
+    cd = (ctypes.c_int * 4)(lx, ly, lz, lt)
+    check(load().grid_coarse_stencil(_ptr(A), _ptr(v), _ptr(out), cd, N, int(bool(dag)), _stream(v.device)))
+    return out
+
+
+def mg_basis(U, vecs, mass, workspace=None, **params):
+    """In place: near-null improvement of the caller's vecs (nvec, Lt, Lz, Ly, Lx, 4, 3) and blockwise
+    Gram-Schmidt. Returns vecs."""
+    p = mg_params(nvec=int(vecs.shape[0]), **params)
+    _need_cuda(vecs, "vecs")
+    g, workspace = _mg_ws(U, p, workspace)
+    op = make_op("wilson", False, mass)
+    check(load().grid_mg_basis(_ptr(U), _ptr(vecs), ctypes.byref(g), ctypes.byref(op), ctypes.byref(p), _ptr(workspace),
+                               ctypes.c_size_t(workspace.numel()), _stream(U.device)))
+    return vecs
+
+
+def mg_coarse_op(U, vecs, mass, workspace=None, out=None, **params):
+    """Galerkin coarse operator R D P as a (Lct, Lcz, Lcy, Lcx, 9, N, N) complex128 tensor."""
+    nvec = int(vecs.shape[0])
+    p = mg_params(nvec=nvec, **params)
+    g, workspace = _mg_ws(U, p, workspace)
+    cs = _coarse_shape(U, p.block, 2 * nvec)
+    A = torch.empty(cs[:4] + (9, 2 * nvec, 2 * nvec), dtype=torch.complex128, device=U.device) if out is None else out
+    op = make_op("wilson", False, mass)
+    check(load().grid_mg_coarse_op(_ptr(U), _ptr(vecs), _ptr(A), ctypes.byref(g), ctypes.byref(op), ctypes.byref(p),
+                                   _ptr(workspace), ctypes.c_size_t(workspace.numel()), _stream(U.device)))
+    return A
+
+
+def mg_restrict(vecs, psi, block):
+    nvec = int(vecs.shape[0])
+    p = mg_params(block=block, nvec=nvec)
+    g = geom_of(psi)
+    vc = torch.empty(_coarse_shape(psi, block, 2 * nvec), dtype=torch.complex128, device=psi.device)
+    check(load().grid_mg_restrict(_ptr(vecs), _ptr(psi), _ptr(vc), ctypes.byref(g), ctypes.byref(p),
+                                  _stream(psi.device)))
+    return vc
+
+
+def mg_prolong(vecs, vc, block):
+    nvec = int(vecs.shape[0])
+    p = mg_params(block=block, nvec=nvec)
+    psi = torch.empty(tuple(vecs.shape[1:]), dtype=torch.complex128, device=vecs.device)
+    g = geom_of(psi)
+    check(load().grid_mg_prolong(_ptr(vecs), _ptr(vc), _ptr(psi), ctypes.byref(g), ctypes.byref(p),
+                                 _stream(psi.device)))
+    return psi
+
+
+def mg_solve(U, vecs, A, b, mass, x0=None, workspace=None, raise_on_fail=True, **params):
+    """D x = b by multigrid-preconditioned flexible GCR. Returns (x, stats)."""
+    nvec = int(vecs.shape[0])
+    p = mg_params(nvec=nvec, **params)
+    g, workspace = _mg_ws(U, p, workspace)
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    op = make_op("wilson", False, mass)
+    st = GridCgStats()
+    rc = load().grid_mg_solve(_ptr(U), _ptr(vecs), _ptr(A), _ptr(b), _ptr(x), ctypes.byref(g), ctypes.byref(op),
+                              ctypes.byref(p), _ptr(workspace), ctypes.c_size_t(workspace.numel()), ctypes.byref(st),
+                              _stream(b.device))
+    stats = {"iterations": st.iterations, "restarts": st.reliable_updates, "converged": bool(st.converged),
+             "true_residual": st.true_residual, "seconds": st.seconds, "status": rc}
+    if rc != 0 and raise_on_fail:
+        check(rc)
+    return x, stats
+
+
+def mg_workspace_bytes(U, **params) -> int:
+    p = mg_params(**params)
+    g = geom_of_links(U)
+    return int(load().grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(p)))

@@ -150,6 +150,33 @@ int check_md_buffers(const GeomDev &g, const grid_md_params *p, const void *U, c
     return GRID_OK;
 }
 
+// Multigrid parameters and buffers (4D Wilson, FP64).
+int check_mg(const GeomDev &g, const grid_op *op, const grid_mg_params *p) {
+    if (!p) return fail(GRID_EINVAL, "params is NULL");
+    if (g.Ls != 1) return fail(GRID_ESHAPE, "multigrid takes 4D fields (Ls = %d)", g.Ls);
+    if (op && op->kind != GRID_WILSON) return fail(GRID_EINVAL, "multigrid takes GRID_WILSON (got kind %d)", op->kind);
+    int64_t nb = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        if (p->block[mu] < 1 || g.L[mu] % p->block[mu])
+            return fail(GRID_ESHAPE, "block[%d] = %d does not divide dims[%d] = %d", mu, p->block[mu], mu, g.L[mu]);
+        nb *= p->block[mu];
+    }
+    if (p->nvec < 1 || p->nvec > 32) return fail(GRID_EINVAL, "nvec = %d outside 1..32", p->nvec);
+    if (p->nvec > 6 * nb) return fail(GRID_EINVAL, "nvec = %d exceeds the 6 x %d dimensions of an aggregate chirality",
+                                      p->nvec, (int)nb);
+    if (p->setup_rounds < 0 || p->setup_iters < 0 || p->coarse_iters < 0 || p->smooth_iters < 0 || p->maxiter < 0)
+        return fail(GRID_EINVAL, "iteration counts must be >= 0");
+    if (p->restart < 1 || p->restart > 64) return fail(GRID_EINVAL, "restart = %d outside 1..64", p->restart);
+    if (!(p->tol > 0.0) || !(p->coarse_tol >= 0.0)) return fail(GRID_EINVAL, "need tol > 0 and coarse_tol >= 0");
+    return GRID_OK;
+}
+
+int check_ws(const void *ws, size_t bytes, size_t need) {
+    TRY(check_ptr(ws, "workspace", 256));
+    if (bytes < need) return fail(GRID_EINVAL, "workspace of %zu bytes, %zu needed", bytes, need);
+    return GRID_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -538,6 +565,128 @@ int grid_convert_links(const void *src, void *dst, int dst_prec, int dst_fmt, in
         return fail(GRID_EINVAL, "dst overlaps src");
     hipError_t e = launch_convert_links(src, dst, dst_prec, dst_fmt, reunitarise, n_links, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "grid_convert_links launch");
+    return ok();
+}
+
+int grid_coarse_stencil(const void *A, const void *v, void *out, const int coarse_dims[4], int N, int dag,
+                        void *stream) {
+    if (!coarse_dims) return fail(GRID_EINVAL, "coarse_dims is NULL");
+    int64_t vc = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        if (coarse_dims[mu] < 1) return fail(GRID_ESHAPE, "coarse_dims[%d] = %d is below 1", mu, coarse_dims[mu]);
+        vc *= coarse_dims[mu];
+        if (vc > (int64_t(1) << 24)) return fail(GRID_ESHAPE, "coarse volume too large");
+    }
+    if (N < 1 || N > 64) return fail(GRID_EINVAL, "N = %d outside 1..64", N);
+    TRY(check_ptr(A, "A", 16));
+    TRY(check_ptr(v, "v", 16));
+    TRY(check_ptr(out, "out", 16));
+    const size_t vb = static_cast<size_t>(vc) * N * 16;
+    if (overlap(v, vb, out, vb) || overlap(A, vb * 9 * N, out, vb)) return fail(GRID_EINVAL, "out overlaps an input");
+    hipError_t e = launch_coarse_stencil(A, v, out, coarse_dims, N, dag ? 1 : 0, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "grid_coarse_stencil launch");
+    return ok();
+}
+
+size_t grid_mg_workspace_bytes(const grid_geom *geom, const grid_mg_params *params) {
+    GeomDev g;
+    if (check_geom(geom, &g) || check_mg(g, nullptr, params)) return 0;
+    return mg_workspace_bytes(g, *params);
+}
+
+int grid_mg_basis(const void *U, void *vecs, const grid_geom *geom, const grid_op *op, const grid_mg_params *params,
+                  void *workspace, size_t ws_bytes, void *stream) {
+    GeomDev g;
+    TRY(check_geom(geom, &g));
+    if (!op) return fail(GRID_EINVAL, "op is NULL");
+    TRY(check_mg(g, op, params));
+    TRY(check_ptr(U, "U", 16));
+    TRY(check_ptr(vecs, "vecs", 16));
+    TRY(check_ws(workspace, ws_bytes, mg_workspace_bytes(g, *params)));
+    const size_t fb = static_cast<size_t>(g.vol) * 192;
+    if (overlap(vecs, fb * params->nvec, workspace, ws_bytes) || overlap(vecs, fb * params->nvec, U, 4 * 144 * g.vol))
+        return fail(GRID_EINVAL, "vecs overlaps U or the workspace");
+    hipError_t e = run_mg_basis(U, vecs, g, op->mass, *params, workspace, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "grid_mg_basis");
+    return ok();
+}
+
+int grid_mg_coarse_op(const void *U, const void *vecs, void *A, const grid_geom *geom, const grid_op *op,
+                      const grid_mg_params *params, void *workspace, size_t ws_bytes, void *stream) {
+    GeomDev g;
+    TRY(check_geom(geom, &g));
+    if (!op) return fail(GRID_EINVAL, "op is NULL");
+    TRY(check_mg(g, op, params));
+    TRY(check_ptr(U, "U", 16));
+    TRY(check_ptr(vecs, "vecs", 16));
+    TRY(check_ptr(A, "A", 16));
+    TRY(check_ws(workspace, ws_bytes, mg_workspace_bytes(g, *params)));
+    int64_t vc = 1;
+    for (int mu = 0; mu < 4; ++mu) vc *= g.L[mu] / params->block[mu];
+    const size_t N = 2 * static_cast<size_t>(params->nvec);
+    const size_t ab = static_cast<size_t>(vc) * 9 * N * N * 16;
+    if (overlap(A, ab, vecs, static_cast<size_t>(g.vol) * 192 * params->nvec) || overlap(A, ab, workspace, ws_bytes) ||
+        overlap(A, ab, U, 4 * 144 * static_cast<size_t>(g.vol)))
+        return fail(GRID_EINVAL, "A overlaps another buffer");
+    hipError_t e = run_mg_coarse_op(U, vecs, A, g, op->mass, *params, workspace, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "grid_mg_coarse_op");
+    return ok();
+}
+
+int grid_mg_restrict(const void *vecs, const void *psi, void *vc, const grid_geom *geom, const grid_mg_params *params,
+                     void *stream) {
+    GeomDev g;
+    TRY(check_geom(geom, &g));
+    TRY(check_mg(g, nullptr, params));
+    TRY(check_ptr(vecs, "vecs", 16));
+    TRY(check_ptr(psi, "psi", 16));
+    TRY(check_ptr(vc, "vc", 16));
+    hipError_t e = launch_mg_restrict(vecs, psi, vc, g, *params, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "grid_mg_restrict launch");
+    return ok();
+}
+
+int grid_mg_prolong(const void *vecs, const void *vc, void *psi, const grid_geom *geom, const grid_mg_params *params,
+                    void *stream) {
+    GeomDev g;
+    TRY(check_geom(geom, &g));
+    TRY(check_mg(g, nullptr, params));
+    TRY(check_ptr(vecs, "vecs", 16));
+    TRY(check_ptr(vc, "vc", 16));
+    TRY(check_ptr(psi, "psi", 16));
+    if (overlap(psi, static_cast<size_t>(g.vol) * 192, vecs, static_cast<size_t>(g.vol) * 192 * params->nvec))
+        return fail(GRID_EINVAL, "psi overlaps vecs");
+    hipError_t e = launch_mg_prolong(vecs, vc, psi, g, *params, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "grid_mg_prolong launch");
+    return ok();
+}
+
+int grid_mg_solve(const void *U, const void *vecs, const void *A, const void *b, void *x, const grid_geom *geom,
+                  const grid_op *op, const grid_mg_params *params, void *workspace, size_t ws_bytes,
+                  grid_cg_stats *stats, void *stream) {
+    GeomDev g;
+    TRY(check_geom(geom, &g));
+    if (!op || !stats) return fail(GRID_EINVAL, "op and stats must not be NULL");
+    TRY(check_mg(g, op, params));
+    TRY(check_ptr(U, "U", 16));
+    TRY(check_ptr(vecs, "vecs", 16));
+    TRY(check_ptr(A, "A", 16));
+    TRY(check_ptr(b, "b", 16));
+    TRY(check_ptr(x, "x", 16));
+    TRY(check_ws(workspace, ws_bytes, mg_workspace_bytes(g, *params)));
+    const size_t fb = static_cast<size_t>(g.vol) * 192;
+    if (overlap(x, fb, b, fb) || overlap(x, fb, workspace, ws_bytes) || overlap(x, fb, vecs, fb * params->nvec))
+        return fail(GRID_EINVAL, "x overlaps another buffer");
+    memset(stats, 0, sizeof(*stats));
+    int status = GRID_OK;
+    hipError_t e = run_mg_solve(U, vecs, A, b, x, g, op->mass, *params, workspace, static_cast<hipStream_t>(stream),
+                                stats, &status);
+    if (e != hipSuccess) return hip_fail(e, "grid_mg_solve");
+    if (status == GRID_ENOCONV)
+        return fail(GRID_ENOCONV, "GCR stopped at relative residual %.3e after %d iterations", stats->true_residual,
+                    stats->iterations);
+    if (status == GRID_EBREAKDOWN) return fail(GRID_EBREAKDOWN, "GCR breakdown after %d iterations", stats->iterations);
     return ok();
 }
 

@@ -104,4 +104,20 @@ hipError_t run_md_leapfrog(void *U, void *P, const void *phi, const GeomDev &g, 
 hipError_t run_hmc_energy(const void *U, const void *P, const void *phi, const GeomDev &g, const grid_md_params &p,
                           void *ws, hipStream_t st, double energies[4], grid_md_stats *stats);
 
+// Coarse stencil and two-level multigrid for the Wilson operator (mg.hip); arguments validated.
+hipError_t launch_coarse_stencil(const void *A, const void *v, void *out, const int Lc[4], int N, int dag,
+                                 hipStream_t st);
+size_t mg_workspace_bytes(const GeomDev &g, const grid_mg_params &p);
+hipError_t run_mg_basis(const void *U, void *vecs, const GeomDev &g, double mass, const grid_mg_params &p, void *ws,
+                        hipStream_t st);
+hipError_t run_mg_coarse_op(const void *U, const void *vecs, void *A, const GeomDev &g, double mass,
+                            const grid_mg_params &p, void *ws, hipStream_t st);
+hipError_t launch_mg_restrict(const void *vecs, const void *psi, void *vc, const GeomDev &g, const grid_mg_params &p,
+                              hipStream_t st);
+hipError_t launch_mg_prolong(const void *vecs, const void *vc, void *psi, const GeomDev &g, const grid_mg_params &p,
+                             hipStream_t st);
+hipError_t run_mg_solve(const void *U, const void *vecs, const void *A, const void *b, void *x, const GeomDev &g,
+                        double mass, const grid_mg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats,
+                        int *status);
+
 }  // namespace gridmi

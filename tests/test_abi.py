@@ -202,7 +202,7 @@ def test_ctypes_structs_match_the_c_header(tmp_path):
         pytest.skip("no C compiler")
     mirrors = {"grid_geom": _lib.GridGeom, "grid_op": _lib.GridOp, "grid_cg_params": _lib.GridCgParams,
                "grid_cg_stats": _lib.GridCgStats, "grid_md_params": _lib.GridMdParams,
-               "grid_md_stats": _lib.GridMdStats}
+               "grid_md_stats": _lib.GridMdStats, "grid_mg_params": _lib.GridMgParams}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "grid_mi.h"', 'int main(void) {']
     for cname, py in mirrors.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -219,3 +219,39 @@ def test_ctypes_structs_match_the_c_header(tmp_path):
         assert got[f"{cname} size"] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[f"{cname} {fname}"] == getattr(py, fname).offset, (cname, fname)
+
+
+def mg_params(**kw):
+    p = _lib.GridMgParams()
+    for mu, b in enumerate(kw.get("block", (2, 2, 2, 2))):
+        p.block[mu] = b
+    p.nvec = kw.get("nvec", 4)
+    p.setup_rounds, p.setup_iters = 1, 4
+    p.coarse_iters, p.coarse_tol, p.smooth_iters = 10, 0.1, 1
+    p.restart, p.maxiter, p.tol = kw.get("restart", 4), 10, 1e-8
+    return p
+
+
+def test_multigrid_validation(lib):
+    g = geom()
+    ok = mg_params()
+    assert lib.grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(ok)) > 0
+    for bad in (mg_params(block=(3, 2, 2, 2)), mg_params(block=(0, 2, 2, 2)), mg_params(nvec=0), mg_params(nvec=33),
+                mg_params(restart=0), mg_params(restart=65), mg_params(block=(1, 1, 1, 1), nvec=7)):
+        assert lib.grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(bad)) == 0
+    op = _lib.GridOp(_lib.GRID_WILSON, 0, 0.1, 1.8, 0.01, 1.0, 0.0)
+    dwf = _lib.GridOp(_lib.GRID_DWF, 0, 0.1, 1.8, 0.01, 1.0, 0.0)
+    need = lib.grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(ok))
+    st = _lib.GridCgStats()
+    assert lib.grid_mg_solve(P(A), P(A + 2**30), P(A + 2**31), P(A + 3 * 2**30), P(A + 2**32), ctypes.byref(g),
+                             ctypes.byref(dwf), ctypes.byref(ok), P(A + 2**33), need, ctypes.byref(st), None) == _lib.GRID_EINVAL
+    assert lib.grid_mg_solve(P(A), P(A + 2**30), P(A + 2**31), P(A + 3 * 2**30), P(A + 2**32), ctypes.byref(g),
+                             ctypes.byref(op), ctypes.byref(ok), P(A + 2**33), need - 1, ctypes.byref(st), None) == _lib.GRID_EINVAL
+    assert "workspace" in _lib.last_error()
+    assert lib.grid_mg_basis(P(A), P(A + 2**30), ctypes.byref(geom(Ls=4)), ctypes.byref(op), ctypes.byref(ok),
+                             P(A + 2**33), need, None) == _lib.GRID_ESHAPE
+    cd = (ctypes.c_int * 4)(2, 2, 2, 2)
+    assert lib.grid_coarse_stencil(P(A), P(A + 2**30), P(A + 2**31), cd, 65, 0, None) == _lib.GRID_EINVAL
+    assert lib.grid_coarse_stencil(P(A), P(A + 2**30), P(A + 2**30), cd, 8, 0, None) == _lib.GRID_EINVAL
+    cd0 = (ctypes.c_int * 4)(2, 0, 2, 2)
+    assert lib.grid_coarse_stencil(P(A), P(A + 2**30), P(A + 2**31), cd0, 8, 0, None) == _lib.GRID_ESHAPE

@@ -1,0 +1,154 @@
+"""GPU parity of the coarse stencil and the multigrid entry points (grid_coarse_stencil,
+grid_mg_basis, grid_mg_restrict, grid_mg_prolong, grid_mg_coarse_op, grid_mg_solve) against the
+FP64 oracle (oracle.mg), through the C ABI.
+
+Tolerances: the linear maps (stencil, R, P, Galerkin operator, Gram-Schmidt of a given set)
+1e-13 relative (FP64, summation order only); the setup's near-null vectors 1e-9 (sixteen CG
+iterations on each side, different summation orders); GCR iterates after three steps 1e-9; the
+full solve is gated on the oracle-recomputed true residual and the iteration count.
+"""
+import numpy as np
+import pytest
+
+import oracle.oracle as O
+from oracle import mg
+from paper_1512_03487_amd import fields as F
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _announce():
+    print("\n[gpu] test_gpu_mg", flush=True)
+
+
+def _gm():
+    import paper_1512_03487_amd as gm
+    return gm
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _vecs(dims, nvec, seed=11):
+    return np.stack([F.spinor_field(dims, seed=seed + k) for k in range(nvec)])
+
+
+@pytest.mark.parametrize("cdims,N", [((4, 2, 3, 2), 12), ((2, 1, 3, 4), 24), ((3, 3, 1, 1), 64), ((1, 1, 1, 2), 1)])
+def test_coarse_stencil(gpu, cdims, N):
+    from tests.gpu_util import dev, host
+    gm = _gm()
+    rng = np.random.default_rng(7)
+    shp = (cdims[3], cdims[2], cdims[1], cdims[0])
+    A = rng.standard_normal(shp + (9, N, N)) + 1j * rng.standard_normal(shp + (9, N, N))
+    v = rng.standard_normal(shp + (N,)) + 1j * rng.standard_normal(shp + (N,))
+    A_nat = np.ascontiguousarray(np.swapaxes(A, -1, -2))    # device layout [d][j][i] -> oracle [d][i][j]
+    for dag in (False, True):
+        got = host(gm.coarse_stencil(dev(A), dev(v), dag=dag))
+        assert _rel(got, mg.coarse_apply(A_nat, v, dag=dag)) <= 1e-13, dag
+
+
+@pytest.mark.parametrize("dims,block,nvec", [((4, 4, 4, 4), (2, 2, 2, 2), 6), ((4, 6, 2, 4), (1, 3, 2, 2), 3),
+                                             ((4, 4, 2, 2), (4, 2, 2, 1), 1)])
+def test_orthonormalise_restrict_prolong(gpu, dims, block, nvec):
+    from tests.gpu_util import dev, host
+    gm = _gm()
+    U = F.gauge_field(dims, seed=1, kind="haar")
+    v = _vecs(dims, nvec)
+    vd = dev(v)
+    gm.mg_basis(dev(U), vd, 0.1, block=block, setup_rounds=0)
+    q = mg.orthonormalise(v, block)
+    assert _rel(host(vd), q) <= 1e-13
+    psi = F.spinor_field(dims, seed=2)
+    vc = host(gm.mg_restrict(dev(q), dev(psi), block))
+    assert _rel(vc, mg.restrict(q, psi, block)) <= 1e-13
+    back = host(gm.mg_prolong(dev(q), dev(vc), block))
+    assert _rel(back, mg.prolong(q, vc, block)) <= 1e-13
+
+
+def test_near_null_setup(gpu):
+    from tests.gpu_util import dev, host
+    gm = _gm()
+    dims, block, nvec, m = (4, 4, 4, 4), (2, 2, 2, 2), 4, 0.2
+    U = F.gauge_field(dims, seed=1, kind="weak")
+    v = _vecs(dims, nvec)
+    vd = dev(v)
+    gm.mg_basis(dev(U), vd, m, block=block, setup_rounds=2, setup_iters=8)
+    ref = mg.orthonormalise(mg.near_null(U, v, m, 2, 8), block)
+    assert _rel(host(vd), ref) <= 1e-9
+
+
+@pytest.mark.parametrize("dims,block,nvec,kind", [((8, 4, 2, 4), (2, 2, 2, 2), 3, "haar"),
+                                                  ((4, 6, 4, 2), (1, 3, 2, 2), 4, "weak"),
+                                                  ((4, 4, 4, 4), (4, 2, 1, 2), 2, "haar")])
+def test_coarse_operator(gpu, dims, block, nvec, kind):
+    from tests.gpu_util import dev, host
+    gm = _gm()
+    m = 0.1
+    U = F.gauge_field(dims, seed=1, kind=kind)
+    q = mg.orthonormalise(_vecs(dims, nvec), block)
+    A = host(gm.mg_coarse_op(dev(U), dev(q), m, block=block))
+    ref = mg.coarse_operator(U, q, m, block)
+    assert np.max(np.abs(np.swapaxes(A, -1, -2) - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def _setup(dims, block, nvec, m, kind="weak"):
+    U = F.gauge_field(dims, seed=1, kind=kind)
+    q = mg.orthonormalise(mg.near_null(U, _vecs(dims, nvec), m, 2, 8), block)
+    return U, q, mg.coarse_operator(U, q, m, block)
+
+
+def test_gcr_iterates_match_the_oracle(gpu):
+    """Three preconditioned GCR steps (no convergence): the iterate equals the oracle's."""
+    from tests.gpu_util import dev, host
+    gm = _gm()
+    dims, block, nvec, m = (4, 4, 4, 4), (2, 2, 2, 2), 6, 0.2
+    U, q, A = _setup(dims, block, nvec, m)
+    b = F.spinor_field(dims, seed=3)
+    kw = dict(block=block, restart=2, coarse_iters=30, coarse_tol=0.05, smooth_iters=2)
+    x, st = gm.mg_solve(dev(U), dev(q), dev(np.ascontiguousarray(np.swapaxes(A, -1, -2))), dev(b), m, maxiter=3,
+                        raise_on_fail=False, **kw)
+    xo, ito, _ = mg.fgcr(U, q, A, b, m, block, tol=1e-10, maxiter=3, restart=2, coarse_iters=30, coarse_tol=0.05,
+                         smooth_iters=2)
+    assert st["iterations"] == ito == 3
+    assert _rel(host(x), xo) <= 1e-9
+
+
+@pytest.mark.parametrize("dims,block,nvec,restart", [((4, 4, 4, 4), (2, 2, 2, 2), 6, 8), ((8, 4, 4, 4), (2, 2, 2, 2), 4, 4)])
+def test_mg_solve(gpu, dims, block, nvec, restart):
+    from tests.gpu_util import dev, host
+    gm = _gm()
+    m = 0.2
+    U, q, A = _setup(dims, block, nvec, m)
+    b = F.spinor_field(dims, seed=3)
+    Ud, qd = dev(U), dev(q)
+    Ad = gm.mg_coarse_op(Ud, qd, m, block=block)
+    x, st = gm.mg_solve(Ud, qd, Ad, dev(b), m, block=block, restart=restart, coarse_iters=40, tol=1e-10)
+    assert st["converged"]
+    res = float(np.linalg.norm(b - O.wilson(U, host(x), m)) / np.linalg.norm(b))
+    assert res <= 1.05e-10 and abs(res - st["true_residual"]) <= 1e-3 * res
+    _, ito, _ = mg.fgcr(U, q, A, b, m, block, tol=1e-10, restart=restart, coarse_iters=40, coarse_tol=0.05,
+                        smooth_iters=2)
+    assert abs(st["iterations"] - ito) <= 1, (st["iterations"], ito)
+
+
+def test_mg_full_pipeline_on_device(gpu):
+    """Setup, coarse operator and solve all on the device from the same random vectors: solves
+    D x = b to 1e-10 in fewer outer iterations than with an unimproved (random) basis."""
+    from tests.gpu_util import dev, host
+    gm = _gm()
+    dims, block, nvec, m = (8, 8, 8, 8), (4, 4, 4, 4), 8, 0.05
+    U = F.gauge_field(dims, seed=1, kind="weak")
+    b = F.spinor_field(dims, seed=3)
+    Ud = dev(U)
+    its = {}
+    for rounds in (0, 3):
+        qd = dev(_vecs(dims, nvec))
+        gm.mg_basis(Ud, qd, m, block=block, setup_rounds=rounds, setup_iters=10)
+        Ad = gm.mg_coarse_op(Ud, qd, m, block=block)
+        x, st = gm.mg_solve(Ud, qd, Ad, dev(b), m, block=block, restart=8, coarse_iters=50, coarse_tol=0.05)
+        res = float(np.linalg.norm(b - O.wilson(U, host(x), m)) / np.linalg.norm(b))
+        assert st["converged"] and res <= 1.05e-10
+        its[rounds] = st["iterations"]
+    assert its[3] < its[0], its
