@@ -289,6 +289,79 @@ def cg_iteration_legs():
     return out
 
 
+def mg_legs(mass=0.01, nvec=12, block=(4, 4, 4, 4)):
+    """Multigrid: (1) the generic coarse stencil on the 8^4 coarse lattice of a 32^4 lattice with
+    4^4 aggregates, N = 24 (its bytes are the 9 N^2 matrices per coarse site plus v and out);
+    (2) the Wilson system D x = b at 16^4, weak-field links, m = 0.01, to |b - D x| / |b| <= 1e-10:
+    setup (near-null vectors and the Galerkin operator) and multigrid-preconditioned GCR against
+    FP64 CG on D^dagger D x = D^dagger b."""
+    import numpy as np
+    import torch
+    import paper_1512_03487_amd as gm
+    from paper_1512_03487_amd import fields
+    dev = torch.device("cuda:0")
+    out = {}
+    N = 2 * nvec
+    cshape = (8, 8, 8, 8)
+    g = torch.Generator(device="cpu").manual_seed(5)
+    A = torch.complex(torch.randn(cshape + (9, N, N), generator=g, dtype=torch.float64),
+                      torch.randn(cshape + (9, N, N), generator=g, dtype=torch.float64)).to(dev)
+    v = torch.complex(torch.randn(cshape + (N,), generator=g, dtype=torch.float64),
+                      torch.randn(cshape + (N,), generator=g, dtype=torch.float64)).to(dev)
+    o = torch.empty_like(v)
+    for _ in range(3):
+        gm.coarse_stencil(A, v, out=o)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(50):
+        gm.coarse_stencil(A, v, out=o)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / 50
+    nbytes = (A.numel() + 2 * v.numel()) * 16
+    out["coarse_stencil_8^4_N24"] = {"us_per_launch": round(t * 1e6, 2), "alg_bytes": int(nbytes),
+                                     "alg_gbs": round(nbytes / t / 1e9, 1),
+                                     "roofline_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4),
+                                     "gflops": round(8 * 9 * N * N * np.prod(cshape) / t / 1e9, 1)}
+    del A, v, o
+    dims = (16, 16, 16, 16)
+    U = torch.from_numpy(fields.gauge_field(dims, seed=1, kind="weak")).to(dev)
+    b = torch.from_numpy(fields.spinor_field(dims, seed=3)).to(dev)
+    vec0 = torch.from_numpy(np.stack([fields.spinor_field(dims, seed=11 + k) for k in range(nvec)])).to(dev)
+    kw = dict(block=block, restart=8, coarse_iters=30, coarse_tol=0.1, smooth_iters=2, tol=1e-10)
+    ws = torch.empty(gm.mg_workspace_bytes(U, nvec=nvec, **kw), dtype=torch.uint8, device=dev)
+    res = {"lattice": list(dims), "mass": mass, "links": "weak field exp(0.3 i H)", "block": list(block), "nvec": nvec,
+           "tol": 1e-10}
+    vecs = vec0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gm.mg_basis(U, vecs, mass, workspace=ws, setup_rounds=3, setup_iters=20, **kw)
+    Ac = gm.mg_coarse_op(U, vecs, mass, workspace=ws, **kw)
+    torch.cuda.synchronize()
+    res["setup_seconds"] = round(time.perf_counter() - t0, 4)
+    gm.mg_solve(U, vecs, Ac, b, mass, workspace=ws, raise_on_fail=False, **dict(kw, maxiter=2))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st = gm.mg_solve(U, vecs, Ac, b, mass, workspace=ws, **kw)
+    torch.cuda.synchronize()
+    res["mg_gcr"] = {"seconds": round(time.perf_counter() - t0, 4), "iterations": st["iterations"],
+                     "true_residual": st["true_residual"]}
+    del ws
+    c = gm.wilson(U, b, mass=mass, dag=True)
+    wsc = torch.empty(gm.cg_workspace_bytes(c), dtype=torch.uint8, device=dev)
+    gm.cg(U, c, kind="wilson", mass=mass, tol=1e-10, workspace=wsc, maxiter=20, raise_on_fail=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xc, stc = gm.cg(U, c, kind="wilson", mass=mass, tol=1e-10, workspace=wsc)
+    torch.cuda.synchronize()
+    full = float(torch.linalg.vector_norm(gm.wilson(U, xc, mass=mass) - b) / torch.linalg.vector_norm(b))
+    res["cg_normal_fp64"] = {"seconds": round(time.perf_counter() - t0, 4), "iterations": stc["iterations"],
+                             "full_residual": full}
+    out["wilson_16^4_solve"] = res
+    return out
+
+
 def hmc_legs():
     """Molecular-dynamics kernels on 16^4 (FP64): gauge force and link update per launch, and one
     5-step leapfrog with a two-flavour Ls = 8 domain-wall pseudofermion (FP32-sloppy solves)."""
@@ -360,11 +433,15 @@ def main():
                     help="also run a plain 256 MiB device copy three times (counter calibration)")
     ap.add_argument("--only-solvers", action="store_true",
                     help="profiling aid: run only the CG and even-odd solver legs and print them")
+    ap.add_argument("--only-mg", action="store_true", help="profiling aid: run only the multigrid legs")
     ap.add_argument("--only-cg-iterations", action="store_true",
                     help="profiling aid: run only the recorded-graph CG iteration legs and print them")
     args = ap.parse_args()
     if args.only_solvers:
         print(json.dumps({"cg_dwf_16^4x16": cg_legs(), "solve_dwf_16^4x16_even_odd": eo_legs()}), flush=True)
+        return
+    if args.only_mg:
+        print(json.dumps({"multigrid": mg_legs()}), flush=True)
         return
     if args.only_cg_iterations:
         print(json.dumps({"cg_iterations_graph": cg_iteration_legs()}), flush=True)
@@ -417,6 +494,7 @@ def main():
     cg = None if args.no_cg else cg_legs()
     eo = None if args.no_cg else eo_legs()
     cgi = None if args.no_cg else cg_iteration_legs()
+    mgl = None if args.no_cg else mg_legs()
     md = None if args.no_legs else hmc_legs()
     cpu = None if args.no_cpu else cpu_baseline()
 
@@ -448,6 +526,7 @@ def main():
         "cg_dwf_16^4x16": cg,
         "solve_dwf_16^4x16_even_odd": eo,
         "cg_iterations_graph": cgi,
+        "multigrid": mgl,
         "hmc_16^4": md,
         "wall_s_timed": round(wall, 4),
     }
