@@ -384,12 +384,14 @@ k_zdot_part(const double2 *__restrict__ a, const double2 *__restrict__ b, long n
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
-__global__ void k_zsum(const double2 *__restrict__ part, int np, double2 *__restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double2 s = {0.0, 0.0};
-        for (int i = 0; i < np; ++i) s = add2(s, part[i]);
-        *out = s;
-    }
+// One block: thread t adds partials t, t + 256, ... then a tree sum (fixed order).
+__global__ void __launch_bounds__(kMgThreads)
+k_zsum(const double2 *__restrict__ part, int np, double2 *__restrict__ out) {
+    __shared__ double2 sm[kMgThreads];
+    double2 s = {0.0, 0.0};
+    for (int i = threadIdx.x; i < np; i += kMgThreads) s = add2(s, part[i]);
+    s = block_sum2(s, sm);
+    if (threadIdx.x == 0) *out = s;
 }
 
 // y += a x; if x2: y2 += a2 x2 (two independent updates in one pass)
@@ -589,7 +591,7 @@ struct MgCtx {
         const int nb = vec_blocks(n);
         hipLaunchKernelGGL(k_zdot_part, dim3(nb), dim3(kMgThreads), 0, st, a, b, n, part());
         MGCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_zsum, dim3(1), dim3(64), 0, st, part(), nb, scal());
+        hipLaunchKernelGGL(k_zsum, dim3(1), dim3(kMgThreads), 0, st, part(), nb, scal());
         MGCHK(hipGetLastError());
         MGCHK(hipMemcpyAsync(res, scal(), sizeof(double2), hipMemcpyDeviceToHost, st));
         return hipStreamSynchronize(st);
