@@ -3,7 +3,7 @@
 // source and true residuals).
 //
 // Device side: streaming vector kernels fused as
-//   dot:       <p, q>                                  -> per-block FP64 partial sums
+//   dot:       <p, A p> as |op p|^2 = <t, t>           -> per-block FP64 partial sums
 //   update_xr: alpha = rho / <p,q>; x += alpha p; r -= alpha q; |r|^2 partials
 //   update_p:  beta = |r_new|^2 / |r_old|^2; p = r + beta p
 // Every block of update_xr / update_p first re-sums the partials of the previous kernel in the
@@ -718,7 +718,8 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
         cs.st = s;
         HIPCHK(apply_op(cs, ulo, c.sloppy, lo_fmt, ph, phs, th, ths, 0));
         HIPCHK(apply_op(cs, ulo, c.sloppy, lo_fmt, th, ths, qh, qhs, 1));
-        Vec<SH>::dot(grid, s, ph, phs, qh, qhs, n, pq);
+        // <p, A p> = <p, op^+ op p> = |op p|^2 = |t|^2: one vector read instead of two
+        Vec<SH>::dot(grid, s, th, ths, th, ths, n, pq);
         HIPCHK(hipGetLastError());
         Vec<SH>::update_xr(grid, s, mixed ? xh : c.x, ph, phs, rh, rhs, qh, qhs, n, rr[P ^ 1], pq, np, rr[P], scal);
         return hipGetLastError();
