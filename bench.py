@@ -289,12 +289,13 @@ def cg_iteration_legs():
     return out
 
 
-def mg_legs(mass=0.01, nvec=12, block=(4, 4, 4, 4)):
+def mg_legs(mass=-0.1, nvec=12, block=(4, 4, 4, 4)):
     """Multigrid: (1) the generic coarse stencil on the 8^4 coarse lattice of a 32^4 lattice with
     4^4 aggregates, N = 24 (its bytes are the 9 N^2 matrices per coarse site plus v and out);
-    (2) the Wilson system D x = b at 16^4, weak-field links, m = 0.01, to |b - D x| / |b| <= 1e-10:
-    setup (near-null vectors and the Galerkin operator) and multigrid-preconditioned GCR against
-    FP64 CG on D^dagger D x = D^dagger b."""
+    (2) the Wilson system D x = b at 24^4, weak-field links, m = -0.1, to |b - D x| / |b| <= 1e-10:
+    setup (near-null vectors and the Galerkin operator) and multigrid-preconditioned GCR (coarse
+    CGNR <= 8 iterations to 0.25, four MR smoothing steps) against FP64 CG on
+    D^dagger D x = D^dagger b."""
     import numpy as np
     import torch
     import paper_1512_03487_amd as gm
@@ -325,11 +326,11 @@ def mg_legs(mass=0.01, nvec=12, block=(4, 4, 4, 4)):
                                      "roofline_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4),
                                      "gflops": round(8 * 9 * N * N * np.prod(cshape) / t / 1e9, 1)}
     del A, v, o
-    dims = (16, 16, 16, 16)
+    dims = (24, 24, 24, 24)
     U = torch.from_numpy(fields.gauge_field(dims, seed=1, kind="weak")).to(dev)
     b = torch.from_numpy(fields.spinor_field(dims, seed=3)).to(dev)
     vec0 = torch.from_numpy(np.stack([fields.spinor_field(dims, seed=11 + k) for k in range(nvec)])).to(dev)
-    kw = dict(block=block, restart=8, coarse_iters=30, coarse_tol=0.1, smooth_iters=2, tol=1e-10)
+    kw = dict(block=block, restart=8, coarse_iters=8, coarse_tol=0.25, smooth_iters=4, tol=1e-10)
     ws = torch.empty(gm.mg_workspace_bytes(U, nvec=nvec, **kw), dtype=torch.uint8, device=dev)
     res = {"lattice": list(dims), "mass": mass, "links": "weak field exp(0.3 i H)", "block": list(block), "nvec": nvec,
            "tol": 1e-10}
@@ -363,7 +364,7 @@ def mg_legs(mass=0.01, nvec=12, block=(4, 4, 4, 4)):
                              "full_residual": full}
     res["speedup_mg"] = round(min(t_cg) / min(t_mg), 2)
     del ws, wsc
-    out["wilson_16^4_solve"] = res
+    out["wilson_24^4_solve"] = res
     return out
 
 

@@ -338,6 +338,8 @@ typedef struct {
     int restart;        /* GCR restart length (1..64)                                           */
     int maxiter;        /* cap on GCR iterations                                                */
     double tol;         /* target |b - D x| / |b|                                               */
+    int graph;          /* nonzero: the coarse solve of a cycle is recorded once per grid_mg_solve
+                           into a HIP graph and replayed (same kernels, same results)             */
 } grid_mg_params;
 
 /*

@@ -19,6 +19,8 @@
 //               minimal-residual steps on D z = r;
 //   solver      flexible GCR(m) with K, modified Gram-Schmidt on the w = D z, true residual at
 //               every restart and at the end.
+// With params.graph the coarse solve of a cycle (a fixed kernel sequence: its control stays on the
+// device) is recorded once per solve and replayed in every cycle.
 //
 // The coarse CGNR keeps its scalars on the device (per-block partial sums re-summed in a fixed
 // order by every block of the next kernel, a stop flag read by every kernel), so a cycle costs
@@ -384,6 +386,25 @@ k_zdot_part(const double2 *__restrict__ a, const double2 *__restrict__ b, long n
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
+// Two inner products in one pass: part[b] = <a1, b1>, part[kMgParts + b] = <a2, b2>.
+__global__ void __launch_bounds__(kMgThreads)
+k_zdot2_part(const double2 *__restrict__ a1, const double2 *__restrict__ b1, const double2 *__restrict__ a2,
+             const double2 *__restrict__ b2, long n, double2 *__restrict__ part) {
+    __shared__ double2 sm[kMgThreads];
+    double2 c1 = {0.0, 0.0}, c2 = {0.0, 0.0};
+    for (long i = static_cast<long>(blockIdx.x) * kMgThreads + threadIdx.x; i < n;
+         i += static_cast<long>(gridDim.x) * kMgThreads) {
+        c1 = add2(c1, cmulc2(a1[i], b1[i]));
+        c2 = add2(c2, cmulc2(a2[i], b2[i]));
+    }
+    c1 = block_sum2(c1, sm);
+    c2 = block_sum2(c2, sm);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = c1;
+        part[kMgParts + blockIdx.x] = c2;
+    }
+}
+
 // One block: thread t adds partials t, t + 256, ... then a tree sum (fixed order).
 __global__ void __launch_bounds__(kMgThreads)
 k_zsum(const double2 *__restrict__ part, int np, double2 *__restrict__ out) {
@@ -444,6 +465,16 @@ k_cdot_re(const double2 *__restrict__ a, const double2 *__restrict__ b, long n, 
         acc.x += a[i].x * b[i].x + a[i].y * b[i].y;
     acc = block_sum2(acc, sm);
     if (threadIdx.x == 0) part[blockIdx.x] = acc.x;
+}
+
+// p = r; e = 0 (a kernel rather than a copy and a fill, so the sequence can be recorded)
+__global__ void __launch_bounds__(kMgThreads)
+k_ccg_start(double2 *__restrict__ p, const double2 *__restrict__ r, double2 *__restrict__ e, long n) {
+    for (long i = static_cast<long>(blockIdx.x) * kMgThreads + threadIdx.x; i < n;
+         i += static_cast<long>(gridDim.x) * kMgThreads) {
+        p[i] = r[i];
+        e[i] = {0.0, 0.0};
+    }
 }
 
 // rho_0 = sum of parts; ctl[0] = tol^2 rho_0; ctl[1] = rho_0
@@ -564,6 +595,9 @@ struct MgCtx {
     MgLayout L;
     hipStream_t st;
     long nf, ncv;   // complex elements of a fine / coarse vector
+    // the coarse solve recorded once per solve (params.graph): executable and recording stream
+    hipGraphExec_t coarse_exec = nullptr;
+    hipStream_t rec = nullptr;
 
     double2 *f(size_t off) const { return reinterpret_cast<double2 *>(ws + off); }
     double2 *part() const { return f(L.part); }
@@ -594,6 +628,19 @@ struct MgCtx {
         hipLaunchKernelGGL(k_zsum, dim3(1), dim3(kMgThreads), 0, st, part(), nb, scal());
         MGCHK(hipGetLastError());
         MGCHK(hipMemcpyAsync(res, scal(), sizeof(double2), hipMemcpyDeviceToHost, st));
+        return hipStreamSynchronize(st);
+    }
+    // <a1, b1> and <a2, b2> in one pass and one read-back
+    hipError_t zdot2(const double2 *a1, const double2 *b1, const double2 *a2, const double2 *b2, long n,
+                     double2 res[2]) const {
+        const int nb = vec_blocks(n);
+        hipLaunchKernelGGL(k_zdot2_part, dim3(nb), dim3(kMgThreads), 0, st, a1, b1, a2, b2, n, part());
+        MGCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_zsum, dim3(1), dim3(kMgThreads), 0, st, part(), nb, scal());
+        MGCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_zsum, dim3(1), dim3(kMgThreads), 0, st, part() + kMgParts, nb, scal() + 1);
+        MGCHK(hipGetLastError());
+        MGCHK(hipMemcpyAsync(res, scal(), 2 * sizeof(double2), hipMemcpyDeviceToHost, st));
         return hipStreamSynchronize(st);
     }
     hipError_t axpy2(double2 *y, const double2 *x, double2 a, double2 *y2, const double2 *x2, double2 a2, long n) const {
@@ -746,27 +793,49 @@ static hipError_t mg_cycle(const MgCtx &c, const void *U, const double2 *V, cons
     double *pq = reinterpret_cast<double *>(c.part()), *rr = pq + kMgParts;
     const long n = c.ncv;
     const int nb = vec_blocks(n);
-    // r_c = R r; cr = A^+ r_c = G5 A G5 r_c; cp = cr; ec = 0
+    // r_c = R r
     hipLaunchKernelGGL(k_mg_restrict, dim3(m.vc), dim3(kMgThreads), 0, c.st, V, r, rc, m);
     MGCHK(hipGetLastError());
-    MGCHK(coarse_stencil(A, rc, cr, cg, 0, 1, nullptr, 0, c.st));
-    MGCHK(hipMemcpyAsync(cp, cr, static_cast<size_t>(n) * sizeof(double2), hipMemcpyDeviceToDevice, c.st));
-    MGCHK(hipMemsetAsync(ec, 0, static_cast<size_t>(n) * sizeof(double2), c.st));
-    hipLaunchKernelGGL(k_cdot_re, dim3(nb), dim3(kMgThreads), 0, c.st, cr, cr, n, rr, static_cast<const double *>(nullptr),
-                       0);
-    MGCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_ccg_init, dim3(1), dim3(64), 0, c.st, rr, nb, c.p->coarse_tol, ctl);
-    MGCHK(hipGetLastError());
-    for (int i = 0; i < c.p->coarse_iters; ++i) {
-        const int P = i & 1;
-        MGCHK(coarse_stencil(A, cp, cq1, cg, 0, 0, ctl, P, c.st));
-        MGCHK(coarse_stencil(A, cq1, cq, cg, 0, 1, ctl, P, c.st));
-        hipLaunchKernelGGL(k_cdot_re, dim3(nb), dim3(kMgThreads), 0, c.st, cp, cq, n, pq, ctl, P);
+    // coarse CGNR from e_c = 0: cr = A^+ r_c = G5 A G5 r_c; cp = cr; then the iterations, every
+    // scalar on the device (the same kernels and arguments in every cycle of the solve)
+    auto coarse_solve = [&](hipStream_t s) -> hipError_t {
+        MGCHK(coarse_stencil(A, rc, cr, cg, 0, 1, nullptr, 0, s));
+        hipLaunchKernelGGL(k_ccg_start, dim3(nb), dim3(kMgThreads), 0, s, cp, cr, ec, n);
         MGCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_ccg_update, dim3(nb), dim3(kMgThreads), 0, c.st, ec, cr, cp, cq, n, pq, rr, nb, ctl, P);
+        hipLaunchKernelGGL(k_cdot_re, dim3(nb), dim3(kMgThreads), 0, s, cr, cr, n, rr, static_cast<const double *>(nullptr),
+                           0);
         MGCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_ccg_p, dim3(nb), dim3(kMgThreads), 0, c.st, cp, cr, n, rr, nb, ctl, P);
+        hipLaunchKernelGGL(k_ccg_init, dim3(1), dim3(64), 0, s, rr, nb, c.p->coarse_tol, ctl);
         MGCHK(hipGetLastError());
+        for (int i = 0; i < c.p->coarse_iters; ++i) {
+            const int P = i & 1;
+            MGCHK(coarse_stencil(A, cp, cq1, cg, 0, 0, ctl, P, s));
+            MGCHK(coarse_stencil(A, cq1, cq, cg, 0, 1, ctl, P, s));
+            hipLaunchKernelGGL(k_cdot_re, dim3(nb), dim3(kMgThreads), 0, s, cp, cq, n, pq, ctl, P);
+            MGCHK(hipGetLastError());
+            hipLaunchKernelGGL(k_ccg_update, dim3(nb), dim3(kMgThreads), 0, s, ec, cr, cp, cq, n, pq, rr, nb, ctl, P);
+            MGCHK(hipGetLastError());
+            hipLaunchKernelGGL(k_ccg_p, dim3(nb), dim3(kMgThreads), 0, s, cp, cr, n, rr, nb, ctl, P);
+            MGCHK(hipGetLastError());
+        }
+        return hipSuccess;
+    };
+    if (!c.p->graph) {
+        MGCHK(coarse_solve(c.st));
+    } else {
+        if (!c.coarse_exec) {
+            MgCtx &mc = const_cast<MgCtx &>(c);
+            if (!mc.rec) MGCHK(hipStreamCreateWithFlags(&mc.rec, hipStreamNonBlocking));
+            MGCHK(hipStreamBeginCapture(mc.rec, hipStreamCaptureModeThreadLocal));
+            hipError_t e = coarse_solve(mc.rec);
+            hipGraph_t gr = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(mc.rec, &gr);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&mc.coarse_exec, gr, nullptr, nullptr, 0);
+            if (gr) (void)hipGraphDestroy(gr);
+            MGCHK(e);
+        }
+        MGCHK(hipGraphLaunch(c.coarse_exec, c.st));
     }
     // z = P e_c
     const long nf = c.nf;
@@ -780,9 +849,9 @@ static hipError_t mg_cycle(const MgCtx &c, const void *U, const double2 *V, cons
         MGCHK(c.sub(s, r, t, nf));
         for (int it = 0; it < c.p->smooth_iters; ++it) {
             MGCHK(c.D(U, s, t));
-            double2 ts, tt;
-            MGCHK(c.zdot(t, s, nf, &ts));
-            MGCHK(c.zdot(t, t, nf, &tt));
+            double2 d2[2];
+            MGCHK(c.zdot2(t, s, t, t, nf, d2));
+            const double2 ts = d2[0], tt = d2[1];
             const double2 alpha = {ts.x / tt.x, ts.y / tt.x};
             MGCHK(c.axpy2(z, s, alpha, s, t, {-alpha.x, -alpha.y}, nf));
         }
@@ -795,6 +864,16 @@ hipError_t run_mg_solve(const void *U, const void *vecs, const void *A, const vo
                         int *status) {
     const auto t0 = std::chrono::steady_clock::now();
     MgCtx c;
+    struct Release {   // the recorded coarse solve, after the caller's stream has drained
+        MgCtx &c;
+        ~Release() {
+            if (c.coarse_exec) {
+                (void)hipStreamSynchronize(c.st);
+                (void)hipGraphExecDestroy(c.coarse_exec);
+            }
+            if (c.rec) (void)hipStreamDestroy(c.rec);
+        }
+    } release{c};
     mg_dims(g, p, &c.m);
     c.g = g;
     c.mass = mass;
@@ -835,16 +914,18 @@ hipError_t run_mg_solve(const void *U, const void *vecs, const void *A, const vo
             MGCHK(c.zdot(W(j), wk, nf, &beta));
             MGCHK(c.axpy2(wk, W(j), {-beta.x, -beta.y}, zk, Z(j), {-beta.x, -beta.y}, nf));
         }
-        double2 nw;
-        MGCHK(c.zdot(wk, wk, nf, &nw));
-        if (!(nw.x > 0.0) || !isfinite(nw.x)) {
+        // |w|^2 and <w, r> in one pass; w, z scaled to |w| = 1, alpha = <w, r> / |w|
+        double2 d2[2];
+        MGCHK(c.zdot2(wk, wk, wk, r, nf, d2));
+        const double nw = d2[0].x;
+        if (!(nw > 0.0) || !isfinite(nw)) {
             *status = GRID_EBREAKDOWN;
             break;
         }
-        hipLaunchKernelGGL(k_zscale2, dim3(vec_blocks(nf)), dim3(kMgThreads), 0, st, wk, zk, 1.0 / sqrt(nw.x), nf);
+        const double inv = 1.0 / sqrt(nw);
+        hipLaunchKernelGGL(k_zscale2, dim3(vec_blocks(nf)), dim3(kMgThreads), 0, st, wk, zk, inv, nf);
         MGCHK(hipGetLastError());
-        double2 alpha;
-        MGCHK(c.zdot(wk, r, nf, &alpha));
+        const double2 alpha = {d2[1].x * inv, d2[1].y * inv};
         MGCHK(c.axpy2(xx, zk, alpha, r, wk, {-alpha.x, -alpha.y}, nf));
         ++it;
         ++k;

@@ -152,3 +152,21 @@ def test_mg_full_pipeline_on_device(gpu):
         assert st["converged"] and res <= 1.05e-10
         its[rounds] = st["iterations"]
     assert its[3] < its[0], its
+
+
+def test_recorded_coarse_solve_matches_direct_launches(gpu):
+    """grid_mg_params.graph replays the coarse solve recorded once per solve: x, the iteration count
+    and the residual equal those of direct launches bit for bit, for two solves in a row."""
+    from tests.gpu_util import dev
+    gm = _gm()
+    dims, block, nvec, m = (8, 4, 4, 4), (2, 2, 2, 2), 4, 0.2
+    U, q, A = _setup(dims, block, nvec, m)
+    Ud, qd = dev(U), dev(q)
+    Ad = gm.mg_coarse_op(Ud, qd, m, block=block)
+    for seed in (3, 4):
+        b = dev(F.spinor_field(dims, seed=seed))
+        kw = dict(block=block, restart=4, coarse_iters=25, coarse_tol=0.05)
+        x0, s0 = gm.mg_solve(Ud, qd, Ad, b, m, graph=False, **kw)
+        x1, s1 = gm.mg_solve(Ud, qd, Ad, b, m, graph=True, **kw)
+        assert s0["iterations"] == s1["iterations"] and s0["true_residual"] == s1["true_residual"]
+        assert bool((x0 == x1).all())
