@@ -18,6 +18,8 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace gridmi {
 
 template <typename C>
@@ -288,6 +290,39 @@ __device__ __forceinline__ void rebuild_row2(Cx<C> u[3][3]) {
     u[2][2] = cconj(csub(cmul(u[0][0], u[1][1]), cmul(u[0][1], u[1][0])));
 }
 
+// Split link load for kernels in which lanes l and l + 32 of a wavefront need the same link: the
+// two half-wavefronts load alternate elements, so one load instruction reads each link's bytes
+// once instead of twice, and v_permlane32_swap (gfx950) exchanges them: with both operands equal
+// to x it returns [x(lanes 0-31) | x(lanes 0-31)] and [x(lanes 32-63) | x(lanes 32-63)].
+// issue() only loads; finish() exchanges, so the loads can be in flight across other work.
+template <class E, int N>
+struct SplitLoad {
+    static_assert(sizeof(E) % 4 == 0, "element of whole dwords");
+    static constexpr int NP = N / 2, W = sizeof(E) / 4;
+    E v[NP + (N & 1)];
+    __device__ __forceinline__ void issue(const E *__restrict__ q, int half) {
+#pragma unroll
+        for (int m = 0; m < NP; ++m) v[m] = q[2 * m + half];
+        if (N & 1) v[NP] = q[N - 1];
+    }
+    __device__ __forceinline__ void finish(E out[N]) const {
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+            uint32_t d[W], lo[W], hi[W];
+            __builtin_memcpy(d, &v[m], sizeof(E));
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const auto r = __builtin_amdgcn_permlane32_swap(d[w], d[w], false, false);
+                lo[w] = r[0];
+                hi[w] = r[1];
+            }
+            __builtin_memcpy(&out[2 * m], lo, sizeof(E));
+            __builtin_memcpy(&out[2 * m + 1], hi, sizeof(E));
+        }
+        if (N & 1) out[N - 1] = v[NP];
+    }
+};
+
 template <int ROWS>
 struct LkF64 {
     using C = double;
@@ -300,6 +335,17 @@ struct LkF64 {
             double2 v = q[k];
             u[k / 3][k % 3] = {v.x, v.y};
         }
+        if (ROWS == 2) rebuild_row2(u);
+    }
+    // raw elements of a link and their decoding (for SplitLoad)
+    using E = double2;
+    static constexpr int kN = ROWS * 3;
+    __device__ __forceinline__ static const E *elems(const void *base, size_t link) {
+        return reinterpret_cast<const E *>(base) + link * kN;
+    }
+    __device__ __forceinline__ static void decode(const E e[kN], Cx<C> u[3][3]) {
+#pragma unroll
+        for (int k = 0; k < kN; ++k) u[k / 3][k % 3] = {e[k].x, e[k].y};
         if (ROWS == 2) rebuild_row2(u);
     }
 };

@@ -6,7 +6,9 @@
 // wavefronts, one per hopping direction (mu = 0..3, forward and backward). In phase 1 wavefront d
 // computes, for every site of the block, the spin-projected neighbour h = (1 -/+ gamma_mu) psi and
 // its parallel transport chi = U h (forward) or U^dagger h (backward); two lanes share a site, one
-// per spin of the half-spinor, so every lane does one 3x3 complex matrix-vector product. The
+// per spin of the half-spinor, so every lane does one 3x3 complex matrix-vector product. In FP64
+// the two lanes of a site are l and l + 32 and split the link's loads between them (measured
+// faster for FP64, slower for FP32, which keeps lanes 2 l and 2 l + 1 and whole-link loads). The
 // eight chi per site meet in LDS, and in phase 2 sixteen lanes per site (twelve active, one per
 // output spin-colour component) reconstruct the lower spins, sum the directions, apply the
 // Wilson or domain-wall diagonal and fifth-dimension terms and store the component. All eight
@@ -118,6 +120,16 @@ __device__ __forceinline__ int stride_of(const GeomDev &g) {
     return MU == 0 ? 1 : MU == 1 ? g.L[0] : MU == 2 ? g.L[0] * g.L[1] : g.L[0] * g.L[1] * g.L[2];
 }
 
+// The split link load of a link type (FP64 links only; a placeholder otherwise).
+template <class LK, bool S>
+struct SplitOf {
+    using type = SplitLoad<uint32_t, 1>;
+};
+template <class LK>
+struct SplitOf<LK, true> {
+    using type = SplitLoad<typename LK::E, LK::kN>;
+};
+
 // Phase 1, direction (MU, BWD): chi = U_mu(x) h(psi(x + mu)) or U_mu(x - mu)^dagger h(psi(x - mu))
 // with h = (1 + E gamma_mu) psi projected; lane spin sp of the half-spinor. The result goes to
 // the wavefront's LDS area as red[site][sp][colour].
@@ -132,7 +144,8 @@ __device__ __forceinline__ void dir_term(const void *__restrict__ U, const void 
     const int nb4 = BWD ? (x[MU] == 0 ? site4 + (L - 1) * st : site4 - st)
                         : (x[MU] == L - 1 ? site4 - (L - 1) * st : site4 + st);
     const int rec = (nb4 >> cbin) * g.Ls + s;   // checkerboard input: half-volume index
-    // coalesced fetch of the 32 records (record r is named by lane 2r)
+    // coalesced fetch of the 32 records (record r is named by lane r (split) or 2r)
+    constexpr bool kSplit = sizeof(C) == 8;
     const chunk_t *src = reinterpret_cast<const chunk_t *>(psi);
     constexpr int NCH = kSites * CH, NK = (NCH + 63) / 64;
     chunk_t w[NK];
@@ -141,12 +154,20 @@ __device__ __forceinline__ void dir_term(const void *__restrict__ U, const void 
         const int c = k * 64 + lane;
         const int cc = c < NCH ? c : 0;
         const int r = cc / CH, j = cc - r * CH;
-        const int n = __shfl(rec, 2 * r, 64);
+        const int n = __shfl(rec, kSplit ? r : 2 * r, 64);
         w[k] = src[static_cast<size_t>(n) * CH + j];
     }
     const float sc = SP::kScaled ? psi_scale[rec] : 1.0f;
+    const size_t link = static_cast<size_t>(BWD ? nb4 : site4) * 4 + MU;
     Cx<C> u[3][3];
-    LK::load(U, static_cast<size_t>(BWD ? nb4 : site4) * 4 + MU, u);
+    [[maybe_unused]] typename SplitOf<LK, kSplit>::type lk;
+    if constexpr (kSplit) {
+        lk.issue(LK::elems(U, link), sp);
+        // every load of this direction is issued before anything waits on one
+        __builtin_amdgcn_sched_barrier(0);
+    } else {
+        LK::load(U, link, u);
+    }
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
         const int c = k * 64 + lane;
@@ -176,6 +197,11 @@ __device__ __forceinline__ void dir_term(const void *__restrict__ U, const void 
             h[c] = {pu.r + e * pd.r, pu.i + e * pd.i};
     }
     wave_sync();   // every lane has read its record before the area is reused for chi
+    if constexpr (kSplit) {
+        typename LK::E e[LK::kN];
+        lk.finish(e);
+        LK::decode(e, u);
+    }
     Cx<C> *red = reinterpret_cast<Cx<C> *>(lds);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -207,7 +233,8 @@ k_dhop_dir(const void *__restrict__ U, const void *__restrict__ psi, const float
     // H: (1 - gamma) forward, (1 + gamma) backward; H^dagger the opposite.
     constexpr int EF = DAG ? +1 : -1;
     {
-        const int sl = lane >> 1, sp = lane & 1;
+        constexpr bool kSplit = sizeof(C) == 8;   // lanes l, l + 32 share site l in FP64
+        const int sl = kSplit ? (lane & 31) : (lane >> 1), sp = kSplit ? (lane >> 5) : (lane & 1);
         const int j = min(base + sl, tr.nout - 1);   // idle lanes of a ragged block still take part
         int x[4], site4, s;
         trav_decode(g, tr, j, x, site4, s);
@@ -583,7 +610,7 @@ k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const floa
 // Steps per thread: the longest walk (a divisor of Lt) that still leaves enough blocks to fill
 // the chip; small lattices use T = 1.
 static int choose_steps(const GeomDev &g) {
-    constexpr long kMinBlocks = 1024;
+    constexpr long kMinBlocks = 2048;   // measured: shorter walks over more blocks are faster
     const long nbc = (static_cast<long>(g.L[0]) * g.L[1] * g.L[2] * g.Ls + 255) / 256;
     int best = 1;
     for (int T = 1; T <= g.L[3]; ++T)
