@@ -610,11 +610,19 @@ k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const floa
 // Steps per thread: the longest walk (a divisor of Lt) that still leaves enough blocks to fill
 // the chip; small lattices use T = 1.
 static int choose_steps(const GeomDev &g) {
-    constexpr long kMinBlocks = 2048;   // measured: shorter walks over more blocks are faster
+    // Measured: the longest walk that still gives >= 4096 blocks, but at least two slices (a walk
+    // of one slice cannot carry the backward t-hop and reads twice the records).
+    constexpr long kMinBlocks = 4096;
     const long nbc = (static_cast<long>(g.L[0]) * g.L[1] * g.L[2] * g.Ls + 255) / 256;
     int best = 1;
     for (int T = 1; T <= g.L[3]; ++T)
         if (g.L[3] % T == 0 && nbc * (g.L[3] / T) >= kMinBlocks) best = T;
+    if (best < 2)
+        for (int T = 2; T <= g.L[3]; ++T)
+            if (g.L[3] % T == 0) {
+                if (nbc * (g.L[3] / T) >= 1024) best = T;
+                break;
+            }
     return best;
 }
 
