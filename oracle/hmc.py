@@ -139,6 +139,25 @@ def omelyan(U, P, beta: float, eps: float, n: int, fermion=None):
     return U, P
 
 
+def force_gradient(U, P, beta: float, eps: float, n: int, fermion=None):
+    """Force-gradient integrator (Omelyan, Mryglod and Folk's fourth-order PQPQP scheme with the
+    force-gradient term, in the Hessian-free form of Yin and Mawhinney): per step
+    P -= e/6 f(U); U <- exp(e/2 P) U; P -= 2e/3 f(U'), U' = exp(-(e^2/24) f(U)) U;
+    U <- exp(e/2 P) U; P -= e/6 f(U), with f = md_force (dP/dt = -f)."""
+    U, P = np.array(U, dtype=np.complex128), np.array(P, dtype=np.complex128)
+
+    def drift(U, P, t):
+        return np.einsum("...ij,...jk->...ik", su3_exp(t * P), U)
+    for _ in range(n):
+        P = P - (eps / 6.0) * md_force(U, beta, fermion)
+        U = drift(U, P, 0.5 * eps)
+        Ud = drift(U, md_force(U, beta, fermion), -eps * eps / 24.0)
+        P = P - (2.0 * eps / 3.0) * md_force(Ud, beta, fermion)
+        U = drift(U, P, 0.5 * eps)
+        P = P - (eps / 6.0) * md_force(U, beta, fermion)
+    return U, P
+
+
 def leapfrog(U, P, beta: float, eps: float, n: int, fermion=None):
     U, P = np.array(U, dtype=np.complex128), np.array(P, dtype=np.complex128)
     P = P - 0.5 * eps * md_force(U, beta, fermion)

@@ -125,3 +125,25 @@ def test_omelyan_reversible_second_order_and_more_accurate(with_fermion):
     # consecutive outer kicks are merged)
     Ul, Pl = hmc.leapfrog(U0, P0, beta, tau / 16, 16, ferm)
     assert dH[1] < 0.5 * abs(hmc.hamiltonian(Ul, Pl, beta, ferm) - H0)
+
+
+@pytest.mark.parametrize("with_fermion", [False, True])
+def test_force_gradient_reversible_and_fourth_order(with_fermion):
+    """The force-gradient step is reversible and its energy error falls by ~16 when the step
+    halves (fourth order; the Hessian-free displacement -(e^2/24) f must have exactly this size,
+    since a wrong one leaves a second-order term)."""
+    dims, beta, tau = (2, 2, 2, 4), 5.5, 0.4
+    U0, ferm = _fermion(dims)
+    ferm = ferm if with_fermion else None
+    P0 = F.random_su3_algebra(dims, seed=7)
+    U1, P1 = hmc.force_gradient(U0, P0, beta, 0.1, 2, ferm)
+    U2, P2 = hmc.force_gradient(U1, -P1, beta, 0.1, 2, ferm)
+    tol = 1e-12 if not with_fermion else 1e-10
+    assert np.max(np.abs(U2 - U0)) < tol and np.max(np.abs(P2 + P0)) < tol
+    H0 = hmc.hamiltonian(U0, P0, beta, ferm)
+    steps = (4, 8) if not with_fermion else (8, 16)
+    dH = []
+    for n in steps:
+        Un, Pn = hmc.force_gradient(U0, P0, beta, tau / n, n, ferm)
+        dH.append(abs(hmc.hamiltonian(Un, Pn, beta, ferm) - H0))
+    assert 10.0 < dH[0] / dH[1] < 25.0, dH
