@@ -261,7 +261,11 @@ int grid_solve_eo(const void *U, const void *b, void *x, const grid_geom *geom, 
  *   dU/dt = P U, dP/dt = -F/2, leapfrog: P -= (eps/2) F/2, then n_steps times
  *   { U <- exp(eps P) U; P -= eps F/2 } with the last momentum step halved; Omelyan (second-order
  *   minimum norm, l = 0.1931833275037836) per step: P -= l eps F/2; U <- exp(eps/2 P) U;
- *   P -= (1 - 2 l) eps F/2; U <- exp(eps/2 P) U; P -= l eps F/2.
+ *   P -= (1 - 2 l) eps F/2; U <- exp(eps/2 P) U; P -= l eps F/2; force gradient (fourth order;
+ *   Omelyan, Mryglod and Folk's scheme with the force-gradient term taken, as Yin and Mawhinney
+ *   do, as the force at displaced links) per step: P -= eps/6 F(U)/2; U <- exp(eps/2 P) U;
+ *   P -= 2 eps/3 F(U')/2 with U' = exp(-(eps^2/24) F(U)/2) U; U <- exp(eps/2 P) U;
+ *   P -= eps/6 F(U)/2.
  * Random momenta and pseudofermion sources are drawn by the caller.
  */
 typedef struct {
@@ -270,10 +274,10 @@ typedef struct {
     int n_steps;            /* leapfrog steps                                                   */
     grid_op fermion;        /* GRID_WILSON or GRID_DWF pseudofermion operator (phi != NULL)     */
     grid_cg_params cg;      /* the solves inside every fermion-force evaluation                 */
-    int integrator;         /* GRID_LEAPFROG or GRID_OMELYAN                                    */
+    int integrator;         /* GRID_LEAPFROG, GRID_OMELYAN or GRID_FORCE_GRADIENT               */
 } grid_md_params;
 
-enum grid_integrator { GRID_LEAPFROG = 0, GRID_OMELYAN = 1 };
+enum grid_integrator { GRID_LEAPFROG = 0, GRID_OMELYAN = 1, GRID_FORCE_GRADIENT = 2 };
 
 typedef struct {
     int solves;             /* fermion solves performed                                         */

@@ -16,7 +16,7 @@ GRID_EHIP, GRID_ENOCONV, GRID_EBREAKDOWN, GRID_ESPACE = -5, -6, -7, -8
 GRID_F64, GRID_F32, GRID_F16S = 0, 1, 2
 GRID_L18, GRID_L12 = 0, 1
 GRID_HOP, GRID_WILSON, GRID_DWF, GRID_MOBIUS = 0, 1, 2, 3
-GRID_LEAPFROG, GRID_OMELYAN = 0, 1
+GRID_LEAPFROG, GRID_OMELYAN, GRID_FORCE_GRADIENT = 0, 1, 2
 
 #: every symbol include/grid_mi.h declares
 EXPORTS = ("grid_dhop", "grid_mobius", "grid_dwf_mdag_m", "grid_cg_workspace_bytes", "grid_cg", "grid_dhop_backward",

@@ -327,7 +327,7 @@ def md_params(beta, eps=0.1, n_steps=10, kind="dwf", mass=0.0, M5=1.8, mf=0.01, 
               **cg) -> GridMdParams:
     p = GridMdParams()
     p.beta, p.eps, p.n_steps = float(beta), float(eps), int(n_steps)
-    p.integrator = {"leapfrog": 0, "omelyan": 1}[integrator]
+    p.integrator = {"leapfrog": 0, "omelyan": 1, "force_gradient": 2}[integrator]
     p.fermion = make_op(kind, False, mass, M5, mf)
     p.cg = cg_params(**cg)
     return p
@@ -347,8 +347,8 @@ def _md_setup(U, phi, workspace, p):
 
 
 def md_leapfrog(U, P, beta, eps, n_steps, phi=None, workspace=None, **kw):
-    """Molecular dynamics of (U, P) in place (integrator="leapfrog" | "omelyan" in kw); phi adds the
-    pseudofermion force. Returns stats."""
+    """Molecular dynamics of (U, P) in place (integrator="leapfrog" | "omelyan" | "force_gradient" in
+    kw); phi adds the pseudofermion force. Returns stats."""
     p = md_params(beta, eps, n_steps, **kw)
     g, workspace = _md_setup(U, phi, workspace, p)
     st = GridMdStats()

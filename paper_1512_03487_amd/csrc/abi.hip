@@ -121,7 +121,7 @@ int check_md(const GeomDev &g, const grid_md_params *p, const void *phi) {
     if (!p) return fail(GRID_EINVAL, "params is NULL");
     if (!isfinite(p->beta) || !isfinite(p->eps) || p->n_steps < 0)
         return fail(GRID_EINVAL, "need finite beta and eps and n_steps >= 0");
-    if (p->integrator != GRID_LEAPFROG && p->integrator != GRID_OMELYAN)
+    if (p->integrator != GRID_LEAPFROG && p->integrator != GRID_OMELYAN && p->integrator != GRID_FORCE_GRADIENT)
         return fail(GRID_EINVAL, "unknown integrator %d", p->integrator);
     if (phi) {
         if (p->fermion.kind != GRID_WILSON && p->fermion.kind != GRID_DWF)

@@ -1,7 +1,7 @@
 // Hybrid Monte Carlo molecular dynamics (HMC is among the algorithms the paper lists, Section 4):
 // Wilson plaquette gauge action and its force, the su(3) exponential link update, the kinetic
-// energy, and leapfrog and Omelyan integrators whose fermion force is the pseudofermion force of
-// the hopping-term adjoint (CG solve recomputed at every force evaluation).
+// energy, and leapfrog, Omelyan and force-gradient integrators whose fermion force is the
+// pseudofermion force of the hopping-term adjoint (CG solve recomputed at every force evaluation).
 //
 // Conventions (shared with the fermion force of grid_dhop_backward):
 //   S_G = beta sum_{x, mu<nu} (1 - Re tr P_munu(x) / 3),
@@ -264,7 +264,7 @@ static hipError_t daxpy(void *y, const void *x, double a, long n, hipStream_t st
 static size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct MdLayout {
-    size_t F, Ff, X, Y, part, cg, total;
+    size_t F, Ff, X, Y, Ud, part, cg, total;   // Ud: displaced links (force-gradient integrator)
 };
 
 static MdLayout md_layout(const GeomDev &g, const grid_md_params &p) {
@@ -282,6 +282,7 @@ static MdLayout md_layout(const GeomDev &g, const grid_md_params &p) {
     L.Ff = take(lb);
     L.X = take(sb);
     L.Y = take(sb);
+    L.Ud = p.integrator == GRID_FORCE_GRADIENT ? take(lb) : 0;
     L.part = take((kHmcParts + 16) * sizeof(double));
     L.cg = off;
     L.total = off + cg_workspace_bytes(g, p.cg.sloppy_prec, p.cg.link_fmt);
@@ -362,6 +363,32 @@ hipError_t run_md_leapfrog(void *U, void *P, const void *phi, const GeomDev &g, 
     memset(stats, 0, sizeof(*stats));
     const long nd = static_cast<long>(g.vol) * 4 * 18;
     if (phi) HMCCHK(hipMemsetAsync(r.ws + r.L.X, 0, static_cast<size_t>(g.n5) * 192, st));
+    if (p.integrator == GRID_FORCE_GRADIENT) {
+        // per step: P -= e/6 f(U); U <- exp(e/2 P) U; P -= 2e/3 f(U'), U' = exp(-(e^2/24) f(U)) U;
+        // U <- exp(e/2 P) U; P -= e/6 f(U), f = F/2; consecutive outer kicks merged: 3 n + 1
+        // force evaluations
+        const long nl = static_cast<long>(g.vol) * 4;
+        void *Ud = r.ws + r.L.Ud;
+        HMCCHK(total_force(r));
+        HMCCHK(daxpy(P, r.ws + r.L.F, -0.5 * p.eps / 6.0, nd, st));
+        for (int i = 0; i < p.n_steps; ++i) {
+            HMCCHK(launch_link_exp(U, P, 0.5 * p.eps, nl, st));
+            HMCCHK(total_force(r));
+            HMCCHK(hipMemcpyAsync(Ud, U, static_cast<size_t>(nl) * 144, hipMemcpyDeviceToDevice, st));
+            HMCCHK(launch_link_exp(Ud, r.ws + r.L.F, -0.5 * p.eps * p.eps / 24.0, nl, st));
+            r.U = Ud;   // the force at the displaced links
+            const hipError_t e = total_force(r);
+            r.U = U;
+            HMCCHK(e);
+            HMCCHK(daxpy(P, r.ws + r.L.F, -0.5 * 2.0 * p.eps / 3.0, nd, st));
+            HMCCHK(launch_link_exp(U, P, 0.5 * p.eps, nl, st));
+            HMCCHK(total_force(r));
+            HMCCHK(daxpy(P, r.ws + r.L.F, -0.5 * (i == p.n_steps - 1 ? 1.0 : 2.0) * p.eps / 6.0, nd, st));
+        }
+        HMCCHK(hipStreamSynchronize(st));
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return hipSuccess;
+    }
     if (p.integrator == GRID_OMELYAN) {
         // the closing kick of a step and the opening kick of the next act at the same U and are
         // merged: 2 n + 1 force evaluations

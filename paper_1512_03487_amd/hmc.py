@@ -26,7 +26,8 @@ def gaussian_spinor(shape, rng: np.random.Generator) -> np.ndarray:
 
 def trajectory(U, beta, eps, n_steps, rng, fermion=None, integrator="leapfrog", **cg):
     """One HMC trajectory. fermion: None (pure gauge) or dict(kind, Ls, mass / M5, mf) for a
-    two-flavour pseudofermion phi = Op^dagger eta; integrator "leapfrog" or "omelyan". Returns
+    two-flavour pseudofermion phi = Op^dagger eta; integrator "leapfrog", "omelyan" or
+    "force_gradient". Returns
     (U_new, accepted, dH, info); U is not modified."""
     dev = U.device
     shape4 = tuple(U.shape[:4])

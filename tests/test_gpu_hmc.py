@@ -162,3 +162,26 @@ def test_omelyan_trajectory_and_reversibility(gpu):
     Pd.neg_()
     gm.md_leapfrog(Ud, Pd, beta, eps, n, integrator="omelyan")
     assert rel(host(Ud), U0) <= 1e-12 and rel(host(Pd), -P0) <= 1e-12
+
+
+@pytest.mark.parametrize("with_fermion", [False, True])
+def test_force_gradient_matches_oracle(gpu, with_fermion):
+    """Force-gradient steps equal the oracle's (which keeps consecutive outer kicks separate), with
+    3 n + 1 force evaluations (solves) on the device, and integrating back with -P returns."""
+    from tests.gpu_util import dev, host, rel
+    gm = _gm()
+    dims, Ls, beta = (2, 2, 2, 4), 4, 5.5
+    U = F.gauge_field(dims, seed=1, kind="weak")
+    P = F.random_su3_algebra(dims, seed=7)
+    phi = F.spinor_field(dims, seed=5, Ls=Ls) if with_fermion else None
+    Ud, Pd = dev(U), dev(P)
+    kw = dict(tol=1e-12, integrator="force_gradient", **DWF)
+    st = gm.md_leapfrog(Ud, Pd, beta, 0.1, 3, dev(phi) if with_fermion else None, **kw)
+    ferm = (O.Op.dwf(Ls, 1.8, 0.2), phi) if with_fermion else None
+    Ur, Pr = OH.force_gradient(U, P, beta, 0.1, 3, ferm)
+    tol = 1e-12 if not with_fermion else 1e-8
+    assert rel(host(Ud), Ur) <= tol and rel(host(Pd), Pr) <= tol
+    assert st["solves"] == (10 if with_fermion else 0)
+    Pd.neg_()
+    gm.md_leapfrog(Ud, Pd, beta, 0.1, 3, dev(phi) if with_fermion else None, **kw)
+    assert rel(host(Ud), U) <= 10 * tol and rel(host(Pd), -P) <= 10 * tol
