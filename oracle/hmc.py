@@ -158,6 +158,29 @@ def force_gradient(U, P, beta: float, eps: float, n: int, fermion=None):
     return U, P
 
 
+def gauge_md_force(U, beta):
+    return 0.5 * gauge_force(U, beta)
+
+
+def fermion_md_force(U, fermion):
+    return np.zeros_like(U) if fermion is None else 0.5 * fermion_force(U, fermion)[1]
+
+
+def nested_leapfrog(U, P, beta: float, eps: float, n: int, fermion, n_inner: int):
+    """Two time scales (Sexton and Weingarten): per outer step P -= e/2 f_F(U), then n_inner
+    leapfrog steps of size e / n_inner with the gauge force alone, then P -= e/2 f_F(U)."""
+    U, P = np.array(U, dtype=np.complex128), np.array(P, dtype=np.complex128)
+    h = eps / n_inner
+    for _ in range(n):
+        P = P - 0.5 * eps * fermion_md_force(U, fermion)
+        for _ in range(n_inner):
+            P = P - 0.5 * h * gauge_md_force(U, beta)
+            U = np.einsum("...ij,...jk->...ik", su3_exp(h * P), U)
+            P = P - 0.5 * h * gauge_md_force(U, beta)
+        P = P - 0.5 * eps * fermion_md_force(U, fermion)
+    return U, P
+
+
 def leapfrog(U, P, beta: float, eps: float, n: int, fermion=None):
     U, P = np.array(U, dtype=np.complex128), np.array(P, dtype=np.complex128)
     P = P - 0.5 * eps * md_force(U, beta, fermion)

@@ -147,3 +147,28 @@ def test_force_gradient_reversible_and_fourth_order(with_fermion):
         Un, Pn = hmc.force_gradient(U0, P0, beta, tau / n, n, ferm)
         dH.append(abs(hmc.hamiltonian(Un, Pn, beta, ferm) - H0))
     assert 10.0 < dH[0] / dH[1] < 25.0, dH
+
+
+def test_nested_leapfrog():
+    """Two time scales: one inner step reproduces the plain leapfrog (the kicks commute); the
+    scheme is reversible and second order; with a dominant gauge force, four inner steps cut the
+    energy error at the same number of fermion solves."""
+    dims, beta, tau = (2, 2, 2, 4), 5.5, 0.4
+    U0, ferm = _fermion(dims)
+    P0 = F.random_su3_algebra(dims, seed=7)
+    Ua, Pa = hmc.nested_leapfrog(U0, P0, beta, 0.05, 3, ferm, 1)
+    Ub, Pb = hmc.leapfrog(U0, P0, beta, 0.05, 3, ferm)
+    assert np.max(np.abs(Ua - Ub)) < 1e-12 and np.max(np.abs(Pa - Pb)) < 1e-11
+    U1, P1 = hmc.nested_leapfrog(U0, P0, beta, 0.1, 2, ferm, 3)
+    U2, P2 = hmc.nested_leapfrog(U1, -P1, beta, 0.1, 2, ferm, 3)
+    assert np.max(np.abs(U2 - U0)) < 1e-10 and np.max(np.abs(P2 + P0)) < 1e-10
+    beta2 = 12.0
+    ferm2 = (O.Op.dwf(4, 1.8, 0.5), ferm[1])
+    H0 = hmc.hamiltonian(U0, P0, beta2, ferm2)
+    dH = {}
+    for ni in (1, 4):
+        for n in (4, 8):
+            Un, Pn = hmc.nested_leapfrog(U0, P0, beta2, tau / n, n, ferm2, ni)
+            dH[(ni, n)] = abs(hmc.hamiltonian(Un, Pn, beta2, ferm2) - H0)
+    assert 3.0 < dH[(4, 4)] / dH[(4, 8)] < 5.0, dH
+    assert dH[(4, 8)] < 0.5 * dH[(1, 8)], dH
