@@ -275,6 +275,10 @@ typedef struct {
     grid_op fermion;        /* GRID_WILSON or GRID_DWF pseudofermion operator (phi != NULL)     */
     grid_cg_params cg;      /* the solves inside every fermion-force evaluation                 */
     int integrator;         /* GRID_LEAPFROG, GRID_OMELYAN or GRID_FORCE_GRADIENT               */
+    int n_inner;            /* > 1: two time scales (needs GRID_LEAPFROG): per step
+                               P -= eps/2 F_F/2; n_inner leapfrog steps of eps / n_inner with the
+                               gauge force alone; P -= eps/2 F_F/2 (Sexton and Weingarten);
+                               0 or 1: the integrator with the total force                       */
 } grid_md_params;
 
 enum grid_integrator { GRID_LEAPFROG = 0, GRID_OMELYAN = 1, GRID_FORCE_GRADIENT = 2 };

@@ -49,7 +49,7 @@ class GridCgStats(ctypes.Structure):
 
 class GridMdParams(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("eps", ctypes.c_double), ("n_steps", ctypes.c_int), ("fermion", GridOp),
-                ("cg", GridCgParams), ("integrator", ctypes.c_int)]
+                ("cg", GridCgParams), ("integrator", ctypes.c_int), ("n_inner", ctypes.c_int)]
 
 
 class GridMdStats(ctypes.Structure):

@@ -328,10 +328,8 @@ static hipError_t fermion_solve(MdRun &r) {
     return launch_dhop(a);
 }
 
-// F = gauge force + fermion force (su(3), the convention above) into the F buffer.
-static hipError_t total_force(MdRun &r) {
-    HMCCHK(launch_gauge_force(r.U, r.ws + r.L.F, r.g, r.p.beta, 1.0, 0, r.st));
-    if (!r.phi) return hipSuccess;
+// The pseudofermion force into the Ff buffer (phi != NULL).
+static hipError_t fermion_force(MdRun &r) {
     HMCCHK(fermion_solve(r));
     LinkGradArgs a;
     a.U = r.U;
@@ -344,7 +342,14 @@ static hipError_t total_force(MdRun &r) {
     a.force_mode = 1;
     a.coef = 1.0;   // dS_F/dU = -2 G_{c=-1/2} = G_{c=1}
     a.stream = r.st;
-    HMCCHK(launch_link_grad(a));
+    return launch_link_grad(a);
+}
+
+// F = gauge force + fermion force (su(3), the convention above) into the F buffer.
+static hipError_t total_force(MdRun &r) {
+    HMCCHK(launch_gauge_force(r.U, r.ws + r.L.F, r.g, r.p.beta, 1.0, 0, r.st));
+    if (!r.phi) return hipSuccess;
+    HMCCHK(fermion_force(r));
     return daxpy(r.ws + r.L.F, r.ws + r.L.Ff, 1.0, static_cast<long>(r.g.vol) * 4 * 18, r.st);
 }
 
@@ -363,6 +368,34 @@ hipError_t run_md_leapfrog(void *U, void *P, const void *phi, const GeomDev &g, 
     memset(stats, 0, sizeof(*stats));
     const long nd = static_cast<long>(g.vol) * 4 * 18;
     if (phi) HMCCHK(hipMemsetAsync(r.ws + r.L.X, 0, static_cast<size_t>(g.n5) * 192, st));
+    if (p.n_inner > 1) {
+        // two time scales (leapfrog outer steps): P -= e/2 f_F(U); n_inner leapfrog steps of
+        // h = e / n_inner with the gauge force; P -= e/2 f_F(U). Consecutive fermion kicks and,
+        // inside an outer step, consecutive gauge kicks are merged: n + 1 fermion and
+        // n (n_inner + 1) gauge force evaluations.
+        const long nl = static_cast<long>(g.vol) * 4;
+        const double h = p.eps / p.n_inner;
+        if (phi) {
+            HMCCHK(fermion_force(r));
+            HMCCHK(daxpy(P, r.ws + r.L.Ff, -0.25 * p.eps, nd, st));
+        }
+        for (int i = 0; i < p.n_steps; ++i) {
+            HMCCHK(launch_gauge_force(U, r.ws + r.L.F, g, p.beta, 1.0, 0, st));
+            HMCCHK(daxpy(P, r.ws + r.L.F, -0.25 * h, nd, st));
+            for (int j = 0; j < p.n_inner; ++j) {
+                HMCCHK(launch_link_exp(U, P, h, nl, st));
+                HMCCHK(launch_gauge_force(U, r.ws + r.L.F, g, p.beta, 1.0, 0, st));
+                HMCCHK(daxpy(P, r.ws + r.L.F, (j == p.n_inner - 1 ? -0.25 : -0.5) * h, nd, st));
+            }
+            if (phi) {
+                HMCCHK(fermion_force(r));
+                HMCCHK(daxpy(P, r.ws + r.L.Ff, (i == p.n_steps - 1 ? -0.25 : -0.5) * p.eps, nd, st));
+            }
+        }
+        HMCCHK(hipStreamSynchronize(st));
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return hipSuccess;
+    }
     if (p.integrator == GRID_FORCE_GRADIENT) {
         // per step: P -= e/6 f(U); U <- exp(e/2 P) U; P -= 2e/3 f(U'), U' = exp(-(e^2/24) f(U)) U;
         // U <- exp(e/2 P) U; P -= e/6 f(U), f = F/2; consecutive outer kicks merged: 3 n + 1

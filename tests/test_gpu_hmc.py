@@ -185,3 +185,24 @@ def test_force_gradient_matches_oracle(gpu, with_fermion):
     Pd.neg_()
     gm.md_leapfrog(Ud, Pd, beta, 0.1, 3, dev(phi) if with_fermion else None, **kw)
     assert rel(host(Ud), U) <= 10 * tol and rel(host(Pd), -P) <= 10 * tol
+
+
+@pytest.mark.parametrize("with_fermion", [False, True])
+def test_nested_time_scales_match_oracle(gpu, with_fermion):
+    """Two time scales (n_inner = 3) equal the oracle's nested leapfrog, with n + 1 fermion
+    solves; n_inner > 1 with another integrator is rejected."""
+    from tests.gpu_util import dev, host, rel
+    gm = _gm()
+    dims, Ls, beta = (2, 2, 2, 4), 4, 5.5
+    U = F.gauge_field(dims, seed=1, kind="weak")
+    P = F.random_su3_algebra(dims, seed=7)
+    phi = F.spinor_field(dims, seed=5, Ls=Ls) if with_fermion else None
+    Ud, Pd = dev(U), dev(P)
+    st = gm.md_leapfrog(Ud, Pd, beta, 0.1, 3, dev(phi) if with_fermion else None, tol=1e-12, n_inner=3, **DWF)
+    ferm = (O.Op.dwf(Ls, 1.8, 0.2), phi) if with_fermion else None
+    Ur, Pr = OH.nested_leapfrog(U, P, beta, 0.1, 3, ferm, 3)
+    tol = 1e-12 if not with_fermion else 1e-8
+    assert rel(host(Ud), Ur) <= tol and rel(host(Pd), Pr) <= tol
+    assert st["solves"] == (4 if with_fermion else 0)
+    with pytest.raises(Exception):
+        gm.md_leapfrog(dev(U), dev(P), beta, 0.1, 1, None, n_inner=2, integrator="omelyan", **DWF)
