@@ -71,7 +71,7 @@ def test_config1_16_4_weak_field_100_applications(gpu, prec):
     assert rel(host(out), O.hop(Ur, pr)) <= TOL[prec]
 
 
-@pytest.mark.parametrize("Ls", [1, 2, 5, 8])
+@pytest.mark.parametrize("Ls", [1, 2, 5, 8, 16])
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
 def test_dwf_parity(gpu, Ls, prec):
     from tests.gpu_util import as_prec, host, rel
@@ -86,6 +86,20 @@ def test_dwf_parity(gpu, Ls, prec):
         # Ls-replicated hopping term on the 5D field
         got = host(gm.dhop(Uk, pk, "hop", dag=dag))
         assert rel(got, O.hop(Ur, pr, dag)) <= TOL[prec], (Ls, prec, dag)
+
+
+@pytest.mark.parametrize("prec,fmt", [("f32", "L12"), ("f16s", "L12"), ("f32", "L18")])
+def test_dwf_ls16_link_formats(gpu, prec, fmt):
+    """Ls = 16 (one column of s-lanes per 16-lane row) on a lattice of several column blocks."""
+    from tests.gpu_util import as_prec, host, rel
+    gm = _gm()
+    dims, Ls = (8, 4, 4, 6), 16
+    U = F.gauge_field(dims, seed=4, kind="haar")
+    psi = F.spinor_field(dims, seed=5, Ls=Ls)
+    Uk, pk, Ur, pr = as_prec(U, psi, prec, fmt)
+    for dag in (False, True):
+        got = host(gm.dwf(Uk, pk, 1.8, 0.01, dag=dag))
+        assert rel(got, O.dwf(Ur, pr, 1.8, 0.01, dag)) <= TOL[prec], (prec, fmt, dag)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
