@@ -11,6 +11,14 @@
 // the |r|^2 partials are double-buffered by iteration parity. No atomics: results are bitwise
 // reproducible run to run.
 //
+// Wilson / domain-wall operators (full lattice and the even-odd Schur operator) fuse the vector
+// work into the operator's last kernel instead:
+//   t = op p with the |t|^2 partials (one block sum -> <p,Ap>),
+//   r -= alpha op^dagger t in the second application's epilogue with the |r|^2 partials (block
+//        sum -> rho), so A p is never stored or re-read,
+//   update_px: x += alpha p; p = r + beta p (alpha, beta from the device scalars),
+// moving 6 vectors of streaming traffic per iteration where the unfused sequence moves 10.
+//
 // Host side: launches the iteration, reads |r|^2 back once every `check_every` iterations, and
 // performs a reliable update (x += x_hat, r = b - A x in FP64, r_hat = lo(r)) when the sloppy
 // residual fell below delta times its maximum since the last update, or below the target.
@@ -121,6 +129,21 @@ k_update_p_flat(const V *__restrict__ r, V *__restrict__ p, long n, const double
     }
     for (long i = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * kThreads)
         p[i] = axpy2(beta, p[i], r[i]);
+}
+
+// Fused sequence: alpha = scal[so] / scal[sq], beta = scal[sn] / scal[so];
+// mode bit 0: x += alpha p; bit 1: p = r + beta p (p read once for both).
+template <typename V>
+__global__ void __launch_bounds__(kThreads)
+k_update_px_flat(V *__restrict__ x, V *__restrict__ p, const V *__restrict__ r, long n, const double *__restrict__ scal,
+                 int so, int sn, int sq, int mode) {
+    const double rho = scal[so];
+    const double alpha = rho / scal[sq], beta = scal[sn] / rho;
+    for (long i = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * kThreads) {
+        const V pv = p[i];
+        if (mode & 1) x[i] = axpy2(alpha, pv, x[i]);
+        if (mode & 2) p[i] = axpy2(beta, pv, r[i]);
+    }
 }
 
 // r = b - q in FP64 (flat, one complex per chunk), |r|^2 partials.
@@ -321,6 +344,37 @@ k_update_p_f16(const uint4 *__restrict__ r, const float *__restrict__ rs, uint4 
     }
 }
 
+// FP16-storage form of k_update_px_flat (x_hat in FP32, p re-encoded).
+__global__ void __launch_bounds__(kThreads)
+k_update_px_f16(float4 *__restrict__ xh, uint4 *__restrict__ p, float *__restrict__ ps, const uint4 *__restrict__ r,
+                const float *__restrict__ rs, long nsites, const double *__restrict__ scal, int so, int sn, int sq,
+                int mode) {
+    const double rho = scal[so];
+    const float al = static_cast<float>(rho / scal[sq]), be = static_cast<float>(scal[sn] / rho);
+    for (long sb = unit_first(); sb < nsites; sb += unit_stride()) {
+        const UnitPos u = unit_pos(sb, nsites);
+        float pv[8];
+        unit_decode(p[u.unit], ps[u.su], pv);
+        if ((mode & 1) && u.ok) {
+            float4 x0 = xh[2 * u.unit], x1 = xh[2 * u.unit + 1];
+            xh[2 * u.unit] = make_float4(x0.x + al * pv[0], x0.y + al * pv[1], x0.z + al * pv[2], x0.w + al * pv[3]);
+            xh[2 * u.unit + 1] = make_float4(x1.x + al * pv[4], x1.y + al * pv[5], x1.z + al * pv[6], x1.w + al * pv[7]);
+        }
+        if (mode & 2) {
+            float rv[8];
+            unit_decode(r[u.unit], rs[u.su], rv);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) pv[j] = rv[j] + be * pv[j];
+            float m;
+            const uint4 code = unit_encode(pv, m);
+            if (u.ok) {
+                p[u.unit] = code;
+                if (u.sub == 0) ps[u.su] = m;
+            }
+        }
+    }
+}
+
 // r = b - q (FP64) with |r|^2 partials, and FP16 copies lo (and lo2) with |lo|^2 partials.
 __global__ void __launch_bounds__(kThreads)
 k_residual_f16lo(const double2 *__restrict__ b, const double2 *__restrict__ q, double2 *__restrict__ r, uint4 *__restrict__ lo,
@@ -386,6 +440,32 @@ __global__ void __launch_bounds__(kThreads) k_sum(const double *__restrict__ par
     if (threadIdx.x == 0) scal[slot] = t;
 }
 
+// Final sum of many partials (the fused epilogues write one per operator block, up to tens of
+// thousands): 1024 threads with eight independent accumulators each keep the loads in flight.
+// The order is fixed, so the sum is reproducible.
+constexpr int kWideThreads = 1024;
+__global__ void __launch_bounds__(kWideThreads)
+k_sum_wide(const double *__restrict__ part, int np, double *__restrict__ scal, int slot) {
+    __shared__ double sm[kWideThreads / 64];
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int k = threadIdx.x;
+    for (; k + 7 * kWideThreads < np; k += 8 * kWideThreads) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] += part[k + j * kWideThreads];
+    }
+    for (; k < np; k += kWideThreads) a[0] += part[k];
+    double v = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kWideThreads / 64; ++w) t += sm[w];
+        scal[slot] = t;
+    }
+}
+
 // Launch helpers per sloppy precision (FP64 mode uses SpF64 for everything).
 template <class SH>
 struct Vec;
@@ -407,6 +487,11 @@ struct Vec<SpF64> {
         hipLaunchKernelGGL(k_update_p_flat<double2>, g, dim3(kThreads), 0, st, static_cast<const double2 *>(r),
                            static_cast<double2 *>(p), n5 * 12, rrp, rrn, np, scal);
     }
+    static void update_px(dim3 g, hipStream_t st, void *x, void *p, float *, const void *r, const float *, long n5,
+                          const double *scal, int so, int sn, int sq, int mode) {
+        hipLaunchKernelGGL(k_update_px_flat<double2>, g, dim3(kThreads), 0, st, static_cast<double2 *>(x),
+                           static_cast<double2 *>(p), static_cast<const double2 *>(r), n5 * 12, scal, so, sn, sq, mode);
+    }
 };
 
 template <>
@@ -425,6 +510,11 @@ struct Vec<SpF32> {
                          const double *rrn, int np, double *scal) {
         hipLaunchKernelGGL(k_update_p_flat<float4>, g, dim3(kThreads), 0, st, static_cast<const float4 *>(r),
                            static_cast<float4 *>(p), n5 * 6, rrp, rrn, np, scal);
+    }
+    static void update_px(dim3 g, hipStream_t st, void *x, void *p, float *, const void *r, const float *, long n5,
+                          const double *scal, int so, int sn, int sq, int mode) {
+        hipLaunchKernelGGL(k_update_px_flat<float4>, g, dim3(kThreads), 0, st, static_cast<float4 *>(x),
+                           static_cast<float4 *>(p), static_cast<const float4 *>(r), n5 * 6, scal, so, sn, sq, mode);
     }
     static void residual_lo(dim3 g, hipStream_t st, const void *b, const void *q, void *r, void *lo, float *, void *lo2,
                             float *, long n5, double *part, double *part_lo) {
@@ -451,6 +541,11 @@ struct Vec<SpF16S> {
         hipLaunchKernelGGL(k_update_p_f16, g, dim3(kThreads), 0, st, static_cast<const uint4 *>(r), rs,
                            static_cast<uint4 *>(p), ps, n5, rrp, rrn, np, scal);
     }
+    static void update_px(dim3 g, hipStream_t st, void *x, void *p, float *ps, const void *r, const float *rs, long n5,
+                          const double *scal, int so, int sn, int sq, int mode) {
+        hipLaunchKernelGGL(k_update_px_f16, g, dim3(kThreads), 0, st, static_cast<float4 *>(x), static_cast<uint4 *>(p),
+                           ps, static_cast<const uint4 *>(r), rs, n5, scal, so, sn, sq, mode);
+    }
     static void residual_lo(dim3 g, hipStream_t st, const void *b, const void *q, void *r, void *lo, float *los, void *lo2,
                             float *lo2s, long n5, double *part, double *part_lo) {
         hipLaunchKernelGGL(k_residual_f16lo, g, dim3(kThreads), 0, st, static_cast<const double2 *>(b),
@@ -474,11 +569,12 @@ struct CgLayout {
     size_t ulo;                           // mixed: sloppy links
     size_t u, uh, uhs;                    // operator temporaries (FP64, sloppy, sloppy scales)
     size_t part;                          // partials: rr[2], pq, true, lo  (5 x kRedBlocks)
+    size_t opp;                           // fused-epilogue partials (one per operator block)
     size_t scal;                          // 16 doubles
     size_t total;
 };
 
-static CgLayout cg_layout(long nsites, long nlinks, int sloppy, int link_fmt, bool op_tmp) {
+static CgLayout cg_layout(long nsites, long nlinks, int sloppy, int link_fmt, bool op_tmp, long nparts) {
     CgLayout L;
     memset(&L, 0, sizeof(L));
     const size_t n = static_cast<size_t>(nsites);
@@ -518,19 +614,20 @@ static CgLayout cg_layout(long nsites, long nlinks, int sloppy, int link_fmt, bo
         }
     }
     L.part = take(5 * kRedBlocks * sizeof(double));
+    if (nparts > 0) L.opp = take(static_cast<size_t>(nparts) * sizeof(double));
     L.scal = take(16 * sizeof(double));
     L.total = off;
     return L;
 }
 
-size_t cg_workspace_bytes_n(long nsites, long nlinks, int sloppy, int link_fmt) {
-    return cg_layout(nsites, nlinks, sloppy, link_fmt, false).total;
+size_t cg_workspace_bytes_n(long nsites, long nlinks, int sloppy, int link_fmt, long nparts) {
+    return cg_layout(nsites, nlinks, sloppy, link_fmt, false, nparts).total;
 }
 
 // The full-lattice solve keeps one operator temporary per precision (the Moebius operator's
-// intermediate field).
+// intermediate field) and room for the fused epilogues' partial sums.
 size_t cg_workspace_bytes(const GeomDev &g, int sloppy, int link_fmt) {
-    return cg_layout(g.n5, static_cast<long>(g.vol) * 4, sloppy, link_fmt, true).total;
+    return cg_layout(g.n5, static_cast<long>(g.vol) * 4, sloppy, link_fmt, true, dhop_blocks_max(g.n5, g.L[3])).total;
 }
 
 // --------------------------------------------------------------------------------------------
@@ -554,6 +651,7 @@ struct CgRun {
     char *ws;
     hipStream_t st;
     bool op_tmp;         // workspace holds the operator temporaries
+    long nparts;         // room for fused-epilogue partials (0: unfused sequence)
 };
 
 // Recorded iteration segments of one solve, by starting parity; released with the solve.
@@ -595,9 +693,8 @@ struct FullOp {
     float *tmps;       // sloppy FP16 scales
 };
 
-static hipError_t full_apply(const void *ctx, const void *U, int prec, int fmt, const void *in, const float *ins, void *out,
-                             float *outs, int dag, hipStream_t st) {
-    const FullOp &o = *static_cast<const FullOp *>(ctx);
+static DhopArgs full_args(const FullOp &o, const void *U, int prec, int fmt, const void *in, const float *ins,
+                          void *out, float *outs, int dag, hipStream_t st) {
     DhopArgs a;
     a.U = U;
     a.psi = in;
@@ -612,8 +709,28 @@ static hipError_t full_apply(const void *ctx, const void *U, int prec, int fmt, 
     a.diag = o.diag;
     a.mf = o.mf;
     a.stream = st;
+    return a;
+}
+
+static hipError_t full_apply(const void *ctx, const void *U, int prec, int fmt, const void *in, const float *ins, void *out,
+                             float *outs, int dag, hipStream_t st) {
+    const FullOp &o = *static_cast<const FullOp *>(ctx);
+    const DhopArgs a = full_args(o, U, prec, fmt, in, ins, out, outs, dag, st);
     if (o.kind == GRID_MOBIUS)
         return launch_mobius(a, o.M5, o.b5, o.c5, o.tmp[prec == GRID_F64 ? 0 : 1], prec == GRID_F16S ? o.tmps : nullptr);
+    return launch_dhop(a);
+}
+
+// Wilson / Shamir domain-wall operator with a fused epilogue (the kernels' own block sums).
+static hipError_t full_apply_fused(const void *ctx, const void *U, int prec, int fmt, const void *in, const float *ins,
+                                   void *out, float *outs, int dag, int fuse, const FuseDev &fz, long *nparts,
+                                   hipStream_t st) {
+    const FullOp &o = *static_cast<const FullOp *>(ctx);
+    if (o.kind != GRID_WILSON && o.kind != GRID_DWF) return hipErrorInvalidValue;
+    DhopArgs a = full_args(o, U, prec, fmt, in, ins, out, outs, dag, st);
+    a.fuse = fuse;
+    a.fz = fz;
+    *nparts = dhop_blocks(a);
     return launch_dhop(a);
 }
 
@@ -634,7 +751,7 @@ static double read_scalar(const CgRun &c, const double *part, int np, double *sc
 template <class SH>
 static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
     const bool mixed = c.sloppy != GRID_F64;
-    const CgLayout L = cg_layout(c.n, c.nlinks, c.sloppy, c.link_fmt, c.op_tmp);
+    const CgLayout L = cg_layout(c.n, c.nlinks, c.sloppy, c.link_fmt, c.op_tmp, c.nparts);
     char *ws = c.ws;
     const int n = static_cast<int>(c.n);
     const int np = static_cast<int>((static_cast<long>(n) + kThreads - 1) / kThreads < kRedBlocks
@@ -659,6 +776,15 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
     const void *ulo = mixed ? ws + L.ulo : c.U;
     const int lo_fmt = mixed ? c.link_fmt : GRID_L18;
     hipError_t err;
+    // fused sequence: device scalars <p,Ap> and rho (by iteration parity), operator partials
+    const bool fused = c.op.apply_fused != nullptr && c.nparts > 0;
+    constexpr int kSlotPQ = 11, kSlotRho = 12;
+    double *opp = fused ? reinterpret_cast<double *>(ws + L.opp) : nullptr;
+    void *xs = mixed ? xh : c.x;   // the vector the iterations update
+    auto sum_to = [&](hipStream_t s, const double *pp, long cnt, int slot) -> hipError_t {
+        hipLaunchKernelGGL(k_sum_wide, dim3(1), dim3(kWideThreads), 0, s, pp, static_cast<int>(cnt), scal, slot);
+        return hipGetLastError();
+    };
 
     // |b|
     Vec<SpF64>::dot(grid, c.st, c.b, nullptr, c.b, nullptr, n, ptrue);
@@ -705,6 +831,7 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
         HIPCHK(hipMemcpyAsync(ph, r, static_cast<size_t>(n) * 192, hipMemcpyDeviceToDevice, c.st));
     }
     HIPCHK(hipGetLastError());
+    if (fused) HIPCHK(sum_to(c.st, rr[1], np, kSlotRho + 1));
     double rtrue = sqrt(read_scalar(c, mixed ? ptrue : rr[1], np, scal, 9, &err));
     HIPCHK(err);
     double maxr = rtrue;
@@ -714,6 +841,23 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
 
     // one sloppy step on stream s (q_hat = A_lo p_hat, alpha, x_hat and r_hat), parity P
     auto step_xr = [&](hipStream_t s, int P) -> hipError_t {
+        if (fused) {
+            // t = op p with |t|^2 = <p, A p>; r -= alpha op^dagger t with |r|^2 (x waits for step_p)
+            long nb = 0;
+            FuseDev f1;
+            f1.part = opp;
+            HIPCHK(c.op.apply_fused(c.op.ctx, ulo, c.sloppy, lo_fmt, ph, phs, th, ths, 0, kFuseNorm, f1, &nb, s));
+            HIPCHK(sum_to(s, opp, nb, kSlotPQ));
+            FuseDev f2;
+            f2.r = rh;
+            f2.r_scale = rhs;
+            f2.scal = scal;
+            f2.num = kSlotRho + (P ^ 1);
+            f2.den = kSlotPQ;
+            f2.part = opp;
+            HIPCHK(c.op.apply_fused(c.op.ctx, ulo, c.sloppy, lo_fmt, th, ths, rh, rhs, 1, kFuseAxpy, f2, &nb, s));
+            return sum_to(s, opp, nb, kSlotRho + P);
+        }
         CgRun cs = c;
         cs.st = s;
         HIPCHK(apply_op(cs, ulo, c.sloppy, lo_fmt, ph, phs, th, ths, 0));
@@ -724,7 +868,13 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
         Vec<SH>::update_xr(grid, s, mixed ? xh : c.x, ph, phs, rh, rhs, qh, qhs, n, rr[P ^ 1], pq, np, rr[P], scal);
         return hipGetLastError();
     };
+    // fused: mode 3 = x += alpha p and p = r + beta p; mode 1 / 2 = either half
+    auto step_px = [&](hipStream_t s, int P, int mode) -> hipError_t {
+        Vec<SH>::update_px(grid, s, xs, ph, phs, rh, rhs, n, scal, kSlotRho + (P ^ 1), kSlotRho + P, kSlotPQ, mode);
+        return hipGetLastError();
+    };
     auto step_p = [&](hipStream_t s, int P) -> hipError_t {
+        if (fused) return step_px(s, P, 3);
         Vec<SH>::update_p(grid, s, rh, rhs, ph, phs, n, rr[P ^ 1], rr[P], np, scal);
         return hipGetLastError();
     };
@@ -757,11 +907,21 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
             HIPCHK(step_xr(c.st, P));
             ++it;
         }
+        bool x_done = false;   // fused: alpha p already added to x
         if (it % check == 0 || it == c.maxiter) {
             double sc[16];
-            const double rn = sqrt(read_scalar(c, rr[P], np, scal, 10, &err, sc));
-            HIPCHK(err);
-            const double pqh = sc[1];
+            double rn;
+            if (fused) {
+                // |r|^2 is already summed on the device
+                for (int k = 0; k < 16; ++k) sc[k] = NAN;
+                HIPCHK(hipMemcpyAsync(sc, scal, sizeof(sc), hipMemcpyDeviceToHost, c.st));
+                HIPCHK(hipStreamSynchronize(c.st));
+                rn = sqrt(sc[kSlotRho + P]);
+            } else {
+                rn = sqrt(read_scalar(c, rr[P], np, scal, 10, &err, sc));
+                HIPCHK(err);
+            }
+            const double pqh = sc[fused ? kSlotPQ : 1];
             if (!isfinite(rn) || !(pqh > 0.0) || !isfinite(pqh)) {
                 *status = GRID_EBREAKDOWN;
                 break;
@@ -770,12 +930,17 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
             const bool small = rn <= c.tol * bnorm;
             if (small || (mixed && rn < c.delta * maxr)) {
                 // reliable update / residual replacement in FP64
+                if (fused) {
+                    HIPCHK(step_px(c.st, P, 1));
+                    x_done = true;
+                }
                 if (mixed) {
                     hipLaunchKernelGGL(k_accum_x, grid, block, 0, c.st, static_cast<double2 *>(c.x),
                                        static_cast<float4 *>(xh), static_cast<long>(n) * 6);
                     HIPCHK(hipGetLastError());
                 }
                 HIPCHK(true_residual(true, P));
+                if (fused) HIPCHK(sum_to(c.st, rr[P], np, kSlotRho + P));
                 ++stats->reliable_updates;
                 rtrue = sqrt(read_scalar(c, mixed ? ptrue : rr[P], np, scal, 9, &err));
                 HIPCHK(err);
@@ -786,7 +951,10 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
                 maxr = rtrue;
             }
         }
-        HIPCHK(step_p(c.st, P));
+        if (fused && x_done)
+            HIPCHK(step_px(c.st, P, 2));
+        else
+            HIPCHK(step_p(c.st, P));
     }
     if (mixed && !converged) {
         hipLaunchKernelGGL(k_accum_x, grid, block, 0, c.st, static_cast<double2 *>(c.x), static_cast<float4 *>(xh),
@@ -806,9 +974,10 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
 
 hipError_t run_cg_op(const CgOp &op, const void *U, const void *b, void *x, long nsites, long nlinks,
                      const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status,
-                     bool op_tmp) {
+                     bool op_tmp, long nparts) {
     CgRun c;
     c.op_tmp = op_tmp;
+    c.nparts = nparts;
     c.U = U;
     c.b = b;
     c.x = x;
@@ -846,7 +1015,8 @@ hipError_t run_cg(const void *U, const void *b, void *x, const GeomDev &g, const
     o.M5 = opd.M5;
     o.b5 = opd.b5;
     o.c5 = opd.c5;
-    const CgLayout L = cg_layout(g.n5, static_cast<long>(g.vol) * 4, p.sloppy_prec, p.link_fmt, true);
+    const long nparts = dhop_blocks_max(g.n5, g.L[3]);
+    const CgLayout L = cg_layout(g.n5, static_cast<long>(g.vol) * 4, p.sloppy_prec, p.link_fmt, true, nparts);
     char *w = static_cast<char *>(ws);
     o.tmp[0] = w + L.u;
     o.tmp[1] = p.sloppy_prec != GRID_F64 ? w + L.uh : nullptr;
@@ -854,7 +1024,8 @@ hipError_t run_cg(const void *U, const void *b, void *x, const GeomDev &g, const
     CgOp op;
     op.apply = full_apply;
     op.ctx = &o;
-    return run_cg_op(op, U, b, x, g.n5, static_cast<long>(g.vol) * 4, p, ws, st, stats, status, true);
+    if (opd.kind == GRID_WILSON || opd.kind == GRID_DWF) op.apply_fused = full_apply_fused;
+    return run_cg_op(op, U, b, x, g.n5, static_cast<long>(g.vol) * 4, p, ws, st, stats, status, true, nparts);
 }
 
 hipError_t dot_re(const void *a, const void *b, long n, double *part, hipStream_t st, double *result) {

@@ -95,6 +95,14 @@ struct SpF64 {
 #pragma unroll
         for (int k = 0; k < 12; ++k) q[k] = make_double2(p[k / 3][k % 3].r, p[k / 3][k % 3].i);
     }
+    // store, returning the squared norm of the stored site
+    __device__ __forceinline__ static double store_n2(void *base, float *scale, size_t site, const Cx<C> p[4][3]) {
+        store(base, scale, site, p);
+        double n = 0.0;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) n += p[k / 3][k % 3].r * p[k / 3][k % 3].r + p[k / 3][k % 3].i * p[k / 3][k % 3].i;
+        return n;
+    }
 };
 
 struct SpF32 {
@@ -137,6 +145,16 @@ struct SpF32 {
             const Cx<C> a = p[(2 * k) / 3][(2 * k) % 3], b = p[(2 * k + 1) / 3][(2 * k + 1) % 3];
             q[k] = make_float4(a.r, a.i, b.r, b.i);
         }
+    }
+    __device__ __forceinline__ static double store_n2(void *base, float *scale, size_t site, const Cx<C> p[4][3]) {
+        store(base, scale, site, p);
+        double n = 0.0;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const double r = p[k / 3][k % 3].r, i = p[k / 3][k % 3].i;
+            n += r * r + i * i;
+        }
+        return n;
     }
 };
 
@@ -189,23 +207,86 @@ struct SpF16S {
                                                   half_bits_to_float(v.y >> 16) * s};
         }
     }
-    __device__ __forceinline__ static void store(void *base, float *scale, size_t site, const Cx<C> p[4][3]) {
+    __device__ __forceinline__ static float encode(const Cx<C> p[4][3], uint32_t w[12]) {
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(p[k / 3][k % 3].r), fabsf(p[k / 3][k % 3].i)));
         const float inv = m > 0.f ? 1.0f / m : 0.f;
-        uint32_t w[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             w[k] = scaled_half_bits(p[k / 3][k % 3].r, inv) | (scaled_half_bits(p[k / 3][k % 3].i, inv) << 16);
         }
+        return m;
+    }
+    __device__ __forceinline__ static void put(void *base, float *scale, size_t site, const uint32_t w[12], float m) {
         uint4 *q = reinterpret_cast<uint4 *>(base) + site * 3;
         q[0] = make_uint4(w[0], w[1], w[2], w[3]);
         q[1] = make_uint4(w[4], w[5], w[6], w[7]);
         q[2] = make_uint4(w[8], w[9], w[10], w[11]);
         scale[site] = m;
     }
+    __device__ __forceinline__ static void store(void *base, float *scale, size_t site, const Cx<C> p[4][3]) {
+        uint32_t w[12];
+        const float m = encode(p, w);
+        put(base, scale, site, w, m);
+    }
+    // store, returning the squared norm of the stored (coded) site
+    __device__ __forceinline__ static double store_n2(void *base, float *scale, size_t site, const Cx<C> p[4][3]) {
+        uint32_t w[12];
+        const float m = encode(p, w);
+        put(base, scale, site, w, m);
+        double n = 0.0;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const double r = half_bits_to_float(w[k] & 0xffffu) * m, i = half_bits_to_float(w[k] >> 16) * m;
+            n += r * r + i * i;
+        }
+        return n;
+    }
 };
+
+// ------------------------------------------------------------------------------------------
+// Reductions inside one 16-lane DPP row / one wavefront with DPP moves (VALU) instead of the
+// LDS-path lane permutes. Each step pairs a lane with one of the other group: xor 1 and xor 2
+// (quad_perm [1,0,3,2] and [2,3,0,1]), then the mirror inside each half-row and inside the row,
+// after which every lane of the row holds the row's result. All lanes must be active.
+// ------------------------------------------------------------------------------------------
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(b), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+// max over the 16 lanes of each row (exact: any pairing order gives the same maximum)
+__device__ __forceinline__ float row_max16(float m) {
+    m = fmaxf(m, dpp_f32<kDppXor1>(m));
+    m = fmaxf(m, dpp_f32<kDppXor2>(m));
+    m = fmaxf(m, dpp_f32<kDppHalfMirror>(m));
+    return fmaxf(m, dpp_f32<kDppMirror>(m));
+}
+
+// sum over the wavefront, in a fixed order (the same in every lane and every run)
+__device__ __forceinline__ double wave_sum64(double v) {
+    v += dpp_f64<kDppXor1>(v);
+    v += dpp_f64<kDppXor2>(v);
+    v += dpp_f64<kDppHalfMirror>(v);
+    v += dpp_f64<kDppMirror>(v);
+    auto lane_val = [&](int l) {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
+        const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+        return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+    };
+    return (lane_val(0) + lane_val(16)) + (lane_val(32) + lane_val(48));
+}
 
 // ------------------------------------------------------------------------------------------
 // Per-component access to a spinor record (used where lanes own components, not sites).
@@ -267,15 +348,28 @@ __device__ __forceinline__ void store_elem<SpF32>(void *base, float *, size_t re
 }
 template <>
 __device__ __forceinline__ void store_elem<SpF16S>(void *base, float *scale, size_t rec, int k, Cx<float> v, bool live) {
-    float m = live ? fmaxf(fabsf(v.r), fabsf(v.i)) : 0.f;
-#pragma unroll
-    for (int o = 8; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 16));
+    const float m = row_max16(live ? fmaxf(fabsf(v.r), fabsf(v.i)) : 0.f);
     const float inv = m > 0.f ? 1.0f / m : 0.f;
     const uint32_t w = scaled_half_bits(v.r, inv) | (scaled_half_bits(v.i, inv) << 16);
     if (live) {
         reinterpret_cast<uint32_t *>(base)[rec * 12 + k] = w;
         if (k == 0) scale[rec] = m;
     }
+}
+
+// |v|^2 of complex k as store_elem will store it (0 for idle lanes; FP16 storage: of the coded
+// value, with the same site scale), without storing: a block can reduce it before its stores.
+template <class SP>
+__device__ __forceinline__ double stored_n2(Cx<typename SP::C> v, bool live) {
+    return live ? double(v.r) * double(v.r) + double(v.i) * double(v.i) : 0.0;
+}
+template <>
+__device__ __forceinline__ double stored_n2<SpF16S>(Cx<float> v, bool live) {
+    const float m = row_max16(live ? fmaxf(fabsf(v.r), fabsf(v.i)) : 0.f);
+    const float inv = m > 0.f ? 1.0f / m : 0.f;
+    const uint32_t w = scaled_half_bits(v.r, inv) | (scaled_half_bits(v.i, inv) << 16);
+    const double r = half_bits_to_float(w & 0xffffu) * m, i = half_bits_to_float(w >> 16) * m;
+    return live ? r * r + i * i : 0.0;
 }
 
 // ------------------------------------------------------------------------------------------

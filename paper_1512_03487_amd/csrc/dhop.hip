@@ -219,15 +219,17 @@ __device__ __forceinline__ void dir_term(const void *__restrict__ U, const void 
     }
 }
 
-template <class SP, class LK, bool DAG, int KIND>
+template <class SP, class LK, bool DAG, int KIND, int FUSE>
 __global__ void __launch_bounds__(kBlock)
 k_dhop_dir(const void *__restrict__ U, const void *__restrict__ psi, const float *__restrict__ psi_scale,
-           const void *__restrict__ yv, const float *__restrict__ y_scale, void *__restrict__ out,
-           float *__restrict__ out_scale, GeomDev g, Trav tr, double diag, double mf, double beta, double cs) {
+           const void *__restrict__ yv, const float *__restrict__ y_scale, void *out, float *out_scale, GeomDev g,
+           Trav tr, double diag, double mf, double beta, double cs, FuseDev fz) {
     using C = typename SP::C;
     constexpr int PITCH = SP::kChunks + 1;
     __shared__ chunk_t sm[kDirs][kSites * PITCH];
     __shared__ int2 sinfo[kSites];   // (4D site, s) of the block's sites, for phase 2
+    __shared__ double fred[kDirs];   // fused epilogue: per-wavefront sums and their arrival count
+    __shared__ int fcount;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int base = xcd_block(blockIdx.x, gridDim.x) * kSites;
     // H: (1 - gamma) forward, (1 + gamma) backward; H^dagger the opposite.
@@ -239,6 +241,7 @@ k_dhop_dir(const void *__restrict__ U, const void *__restrict__ psi, const float
         int x[4], site4, s;
         trav_decode(g, tr, j, x, site4, s);
         if (wv == 0 && sp == 0) sinfo[sl] = make_int2(site4, s);
+        if (FUSE != kFuseNone && threadIdx.x == 0) fcount = 0;
         chunk_t *lds = sm[wv];
         const int cbin = tr.cbp >= 0 ? 1 : 0;
         switch (wv) {
@@ -304,7 +307,30 @@ k_dhop_dir(const void *__restrict__ U, const void *__restrict__ psi, const float
         const Cx<C> v = global_elem<SP>(yv, y_scale, static_cast<size_t>(site4o) * Ls + s2, k);
         acc = {acc.r - f * v.r, acc.i - f * v.i};
     }
-    store_elem<SP>(out, out_scale, q, k, acc, live);
+    if constexpr (FUSE == kFuseNone) {
+        store_elem<SP>(out, out_scale, q, k, acc, live);
+    } else {
+        if constexpr (FUSE == kFuseAxpy) {
+            // r - alpha op psi; r may alias out: this lane reads its own element (and the site
+            // scale) before any lane of the site stores
+            const Cx<C> rv = global_elem<SP>(fz.r, fz.r_scale, q, k);
+            const C al = static_cast<C>(fz.scal[fz.num] / fz.scal[fz.den]);
+            acc = {rv.r - al * acc.r, rv.i - al * acc.i};
+        }
+        // Block sum without a block barrier: each wavefront posts its sum and counts itself in;
+        // the last one to arrive adds the eight in a fixed order (reproducible whichever it is).
+        const double n2 = wave_sum64(stored_n2<SP>(acc, live));
+        if (lane == 0) {
+            fred[wv] = n2;
+            if (__hip_atomic_fetch_add(&fcount, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == kDirs - 1) {
+                double t = 0.0;
+#pragma unroll
+                for (int w = 0; w < kDirs; ++w) t += fred[w];
+                fz.part[blockIdx.x] = t;
+            }
+        }
+        store_elem<SP>(out, out_scale, q, k, acc, live);
+    }
 }
 
 // XCD domains: halves of x, y, z when those extents are even (measured best with inputs streamed
@@ -355,16 +381,26 @@ static hipError_t launch_dir(const DhopArgs &a) {
     const double cs = a.custom ? a.cs : 1.0;
     const dim3 grid(static_cast<unsigned>(nblocks)), block(kBlock);
     hipStream_t st = a.stream;
-#define GRIDMI_LAUNCH(DAG, KIND)                                                                          \
-    hipLaunchKernelGGL((k_dhop_dir<SP, LK, DAG, KIND>), grid, block, 0, st, a.U, a.psi, a.psi_scale, y, ys,     \
-                       a.out, a.out_scale, a.g, tr, a.diag, a.mf, beta, cs)
+#define GRIDMI_LAUNCH(DAG, KIND, FUSE)                                                                    \
+    hipLaunchKernelGGL((k_dhop_dir<SP, LK, DAG, KIND, FUSE>), grid, block, 0, st, a.U, a.psi, a.psi_scale, y, ys, \
+                       a.out, a.out_scale, a.g, tr, a.diag, a.mf, beta, cs, a.fz)
+    if (a.fuse != kFuseNone) {
+        switch (a.kind * 4 + a.fuse * 2 + (a.dag ? 1 : 0)) {
+            case GRID_WILSON * 4 + kFuseNorm * 2 + 0: GRIDMI_LAUNCH(false, GRID_WILSON, kFuseNorm); break;
+            case GRID_DWF * 4 + kFuseNorm * 2 + 0: GRIDMI_LAUNCH(false, GRID_DWF, kFuseNorm); break;
+            case GRID_WILSON * 4 + kFuseAxpy * 2 + 1: GRIDMI_LAUNCH(true, GRID_WILSON, kFuseAxpy); break;
+            case GRID_DWF * 4 + kFuseAxpy * 2 + 1: GRIDMI_LAUNCH(true, GRID_DWF, kFuseAxpy); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (a.kind * 2 + (a.dag ? 1 : 0)) {
-        case GRID_HOP * 2 + 0: GRIDMI_LAUNCH(false, GRID_HOP); break;
-        case GRID_HOP * 2 + 1: GRIDMI_LAUNCH(true, GRID_HOP); break;
-        case GRID_WILSON * 2 + 0: GRIDMI_LAUNCH(false, GRID_WILSON); break;
-        case GRID_WILSON * 2 + 1: GRIDMI_LAUNCH(true, GRID_WILSON); break;
-        case GRID_DWF * 2 + 0: GRIDMI_LAUNCH(false, GRID_DWF); break;
-        case GRID_DWF * 2 + 1: GRIDMI_LAUNCH(true, GRID_DWF); break;
+        case GRID_HOP * 2 + 0: GRIDMI_LAUNCH(false, GRID_HOP, kFuseNone); break;
+        case GRID_HOP * 2 + 1: GRIDMI_LAUNCH(true, GRID_HOP, kFuseNone); break;
+        case GRID_WILSON * 2 + 0: GRIDMI_LAUNCH(false, GRID_WILSON, kFuseNone); break;
+        case GRID_WILSON * 2 + 1: GRIDMI_LAUNCH(true, GRID_WILSON, kFuseNone); break;
+        case GRID_DWF * 2 + 0: GRIDMI_LAUNCH(false, GRID_DWF, kFuseNone); break;
+        case GRID_DWF * 2 + 1: GRIDMI_LAUNCH(true, GRID_DWF, kFuseNone); break;
         default: return hipErrorInvalidValue;
     }
 #undef GRIDMI_LAUNCH
@@ -487,10 +523,10 @@ __device__ __forceinline__ void hop_term(Cx<C> acc[4][3], const Cx<C> p[4][3], c
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <class SP, class LK, bool DAG, int KIND>
+template <class SP, class LK, bool DAG, int KIND, int FUSE>
 __global__ void __launch_bounds__(256)
 k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const float *__restrict__ psi_scale,
-       void *__restrict__ out, float *__restrict__ out_scale, GeomDev g, int T, double diag, double mf) {
+       void *out, float *out_scale, GeomDev g, int T, double diag, double mf, FuseDev fz) {
     using C = typename SP::C;
     __shared__ chunk_t sm[kWaves][64 * (SP::kChunks + 1)];
     chunk_t *lds = sm[threadIdx.x >> 6];
@@ -527,6 +563,7 @@ k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const floa
     // centre psi(x, t) for the Wilson / domain-wall epilogue. The next record's loads are issued
     // before the current direction computes.
     constexpr int NREC = (KIND == GRID_HOP) ? 7 : 8;
+    [[maybe_unused]] double n2 = 0.0;   // fused epilogue: this thread's |out|^2
 #pragma unroll 1
     for (int k = 0; k < T; ++k) {
         const int t = t0 + k;
@@ -603,7 +640,29 @@ k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const floa
                 o = {o.r - fm * qh[j / 3][j % 3].r, o.i - fm * qh[j / 3][j % 3].i};
             }
         }
-        if (live) SP::store(out, out_scale, static_cast<size_t>(off) + q, acc);
+        if constexpr (FUSE == kFuseAxpy) {
+            // r - alpha op psi; r may alias out: the wavefront gathers its own records before storing
+            Cx<C> rv[4][3];
+            gather<SP>(fz.r, fz.r_scale, off + qq, lds, rv);
+            const C al = static_cast<C>(fz.scal[fz.num] / fz.scal[fz.den]);
+#pragma unroll
+            for (int j = 0; j < 12; ++j) {
+                const Cx<C> a = acc[j / 3][j % 3], b = rv[j / 3][j % 3];
+                acc[j / 3][j % 3] = {b.r - al * a.r, b.i - al * a.i};
+            }
+        }
+        if constexpr (FUSE == kFuseNone) {
+            if (live) SP::store(out, out_scale, static_cast<size_t>(off) + q, acc);
+        } else {
+            if (live) n2 += SP::store_n2(out, out_scale, static_cast<size_t>(off) + q, acc);
+        }
+    }
+    if constexpr (FUSE != kFuseNone) {
+        n2 = wave_sum64(n2);
+        __shared__ double fred[4];
+        if ((threadIdx.x & 63) == 0) fred[threadIdx.x >> 6] = n2;
+        __syncthreads();
+        if (threadIdx.x == 0) fz.part[blockIdx.x] = (fred[0] + fred[1]) + (fred[2] + fred[3]);
     }
 }
 
@@ -632,16 +691,26 @@ static hipError_t launch_walk(const DhopArgs &a) {
     const long nbc = (static_cast<long>(a.g.L[0]) * a.g.L[1] * a.g.L[2] * a.g.Ls + 255) / 256;
     const dim3 grid(static_cast<unsigned>(nbc * (a.g.L[3] / T))), block(256);
     hipStream_t st = a.stream;
-#define GRIDMI_LAUNCH(DAG, KIND)                                                                          \
-    hipLaunchKernelGGL((k_dhop_walk<SP, LK, DAG, KIND>), grid, block, 0, st, a.U, a.psi, a.psi_scale, a.out, \
-                       a.out_scale, a.g, T, a.diag, a.mf)
+#define GRIDMI_LAUNCH(DAG, KIND, FUSE)                                                                    \
+    hipLaunchKernelGGL((k_dhop_walk<SP, LK, DAG, KIND, FUSE>), grid, block, 0, st, a.U, a.psi, a.psi_scale, a.out, \
+                       a.out_scale, a.g, T, a.diag, a.mf, a.fz)
+    if (a.fuse != kFuseNone) {
+        switch (a.kind * 4 + a.fuse * 2 + (a.dag ? 1 : 0)) {
+            case GRID_WILSON * 4 + kFuseNorm * 2 + 0: GRIDMI_LAUNCH(false, GRID_WILSON, kFuseNorm); break;
+            case GRID_DWF * 4 + kFuseNorm * 2 + 0: GRIDMI_LAUNCH(false, GRID_DWF, kFuseNorm); break;
+            case GRID_WILSON * 4 + kFuseAxpy * 2 + 1: GRIDMI_LAUNCH(true, GRID_WILSON, kFuseAxpy); break;
+            case GRID_DWF * 4 + kFuseAxpy * 2 + 1: GRIDMI_LAUNCH(true, GRID_DWF, kFuseAxpy); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (a.kind * 2 + (a.dag ? 1 : 0)) {
-        case GRID_HOP * 2 + 0: GRIDMI_LAUNCH(false, GRID_HOP); break;
-        case GRID_HOP * 2 + 1: GRIDMI_LAUNCH(true, GRID_HOP); break;
-        case GRID_WILSON * 2 + 0: GRIDMI_LAUNCH(false, GRID_WILSON); break;
-        case GRID_WILSON * 2 + 1: GRIDMI_LAUNCH(true, GRID_WILSON); break;
-        case GRID_DWF * 2 + 0: GRIDMI_LAUNCH(false, GRID_DWF); break;
-        case GRID_DWF * 2 + 1: GRIDMI_LAUNCH(true, GRID_DWF); break;
+        case GRID_HOP * 2 + 0: GRIDMI_LAUNCH(false, GRID_HOP, kFuseNone); break;
+        case GRID_HOP * 2 + 1: GRIDMI_LAUNCH(true, GRID_HOP, kFuseNone); break;
+        case GRID_WILSON * 2 + 0: GRIDMI_LAUNCH(false, GRID_WILSON, kFuseNone); break;
+        case GRID_WILSON * 2 + 1: GRIDMI_LAUNCH(true, GRID_WILSON, kFuseNone); break;
+        case GRID_DWF * 2 + 0: GRIDMI_LAUNCH(false, GRID_DWF, kFuseNone); break;
+        case GRID_DWF * 2 + 1: GRIDMI_LAUNCH(true, GRID_DWF, kFuseNone); break;
         default: return hipErrorInvalidValue;
     }
 #undef GRIDMI_LAUNCH
@@ -650,11 +719,28 @@ static hipError_t launch_walk(const DhopArgs &a) {
 
 // Direction-parallel schedule for 4D fields in FP64 / FP32, 5D fields in FP64 and every even-odd
 // or Moebius (custom) call; column walk for FP16 storage and 5D fields in FP32 (measured faster).
+static bool use_walk(const DhopArgs &a) {
+    return !a.custom && (a.prec == GRID_F16S || (a.prec == GRID_F32 && a.g.Ls > 1));
+}
+
 template <class SP, class LK>
 static hipError_t launch_sched(const DhopArgs &a) {
-    constexpr bool f64 = sizeof(typename SP::C) == 8;
-    if (a.custom || (!SP::kScaled && (a.g.Ls == 1 || f64))) return launch_dir<SP, LK>(a);
-    return launch_walk<SP, LK>(a);
+    if (use_walk(a)) return launch_walk<SP, LK>(a);
+    return launch_dir<SP, LK>(a);
+}
+
+long dhop_blocks(const DhopArgs &a) {
+    if (use_walk(a)) {
+        const long nbc = (static_cast<long>(a.g.L[0]) * a.g.L[1] * a.g.L[2] * a.g.Ls + 255) / 256;
+        return nbc * (a.g.L[3] / choose_steps(a.g));
+    }
+    const Trav tr = make_trav(a.g, a.custom ? a.cb : -1);
+    return (static_cast<long>(tr.nout) + kSites - 1) / kSites;
+}
+
+long dhop_blocks_max(long n5, int Lt) {
+    // direction-parallel: ceil(n5 / 32); column walk: at most ceil(n5 / Lt / 256) * Lt
+    return (n5 + kSites - 1) / kSites + Lt;
 }
 
 hipError_t launch_dhop(const DhopArgs &a) {

@@ -159,7 +159,8 @@ static hipError_t cb_copy(const void *src, void *dst, const GeomDev &g, int pari
 // out (checkerboard cb) = diagonal part of `kind` (coefficient dg) on y + beta * H psi.
 static hipError_t hop_cb(const void *U, int prec, int fmt, const GeomDev &g, int kind, int dag, double dg, double mf,
                          int cb, const void *psi, const float *psis, const void *y, const float *ys, double beta, void *out,
-                         float *outs, hipStream_t st) {
+                         float *outs, hipStream_t st, int fuse = kFuseNone, const FuseDev *fz = nullptr,
+                         long *nparts = nullptr) {
     DhopArgs a;
     a.U = U;
     a.psi = psi;
@@ -179,6 +180,11 @@ static hipError_t hop_cb(const void *U, int prec, int fmt, const GeomDev &g, int
     a.y = y;
     a.y_scale = ys;
     a.beta = beta;
+    if (fuse != kFuseNone) {
+        a.fuse = fuse;
+        a.fz = *fz;
+        *nparts = dhop_blocks(a);
+    }
     return launch_dhop(a);
 }
 
@@ -192,8 +198,9 @@ struct EoOp {
     float *t1s, *t2s;   // sloppy FP16 scales
 };
 
-static hipError_t eo_apply(const void *ctx, const void *U, int prec, int fmt, const void *in, const float *ins, void *out,
-                           float *outs, int dag, hipStream_t st) {
+static hipError_t eo_apply_fz(const void *ctx, const void *U, int prec, int fmt, const void *in, const float *ins,
+                              void *out, float *outs, int dag, int fuse, const FuseDev *fz, long *nparts,
+                              hipStream_t st) {
     const EoOp &o = *static_cast<const EoOp *>(ctx);
     const int ix = prec == GRID_F64 ? 0 : 1;
     float *t1s = prec == GRID_F16S ? o.t1s : nullptr, *t2s = prec == GRID_F16S ? o.t2s : nullptr;
@@ -208,7 +215,20 @@ static hipError_t eo_apply(const void *ctx, const void *U, int prec, int fmt, co
     }
     // out = M_ee in - H_eo M_oo^-1 H_oe in / 4  (Wilson: M_oo^-1 = 1 / (4 + m) folded into beta)
     const double beta = o.kind == GRID_WILSON ? -0.25 / o.diag : -0.25;
-    return hop_cb(U, prec, fmt, o.g, o.kind, dag, o.diag, o.mf, 0, src, srcs, in, ins, beta, out, outs, st);
+    return hop_cb(U, prec, fmt, o.g, o.kind, dag, o.diag, o.mf, 0, src, srcs, in, ins, beta, out, outs, st, fuse, fz,
+                  nparts);
+}
+
+static hipError_t eo_apply(const void *ctx, const void *U, int prec, int fmt, const void *in, const float *ins, void *out,
+                           float *outs, int dag, hipStream_t st) {
+    return eo_apply_fz(ctx, U, prec, fmt, in, ins, out, outs, dag, kFuseNone, nullptr, nullptr, st);
+}
+
+// Mhat with the conjugate gradient's fused epilogue on its last kernel.
+static hipError_t eo_apply_fused(const void *ctx, const void *U, int prec, int fmt, const void *in, const float *ins,
+                                 void *out, float *outs, int dag, int fuse, const FuseDev &fz, long *nparts,
+                                 hipStream_t st) {
+    return eo_apply_fz(ctx, U, prec, fmt, in, ins, out, outs, dag, fuse, &fz, nparts, st);
 }
 
 static size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -247,7 +267,8 @@ static EoLayout eo_layout(const GeomDev &g, int sloppy, int link_fmt) {
     }
     L.norm = take(kNormScratch * sizeof(double));
     L.cg = off;
-    L.total = off + cg_workspace_bytes_n(static_cast<long>(n), static_cast<long>(g.vol) * 4, sloppy, link_fmt);
+    L.total = off + cg_workspace_bytes_n(static_cast<long>(n), static_cast<long>(g.vol) * 4, sloppy, link_fmt,
+                                         dhop_blocks_max(static_cast<long>(n), g.L[3]));
     return L;
 }
 
@@ -301,10 +322,12 @@ hipError_t run_solve_eo(const void *U, const void *b, void *x, const GeomDev &g,
     EOCHK(cb_copy(x, xe, g, 0, 1, st));
     CgOp op;
     op.apply = eo_apply;
+    op.apply_fused = eo_apply_fused;
     op.ctx = &o;
     grid_cg_stats cs;
     memset(&cs, 0, sizeof(cs));
-    EOCHK(run_cg_op(op, U, rhs, xe, n, static_cast<long>(g.vol) * 4, p, w + L.cg, st, &cs, status));
+    EOCHK(run_cg_op(op, U, rhs, xe, n, static_cast<long>(g.vol) * 4, p, w + L.cg, st, &cs, status, false,
+                    dhop_blocks_max(static_cast<long>(n), g.L[3])));
     // x_o = M_oo^-1 (b_o + H_oe x_e / 2)
     if (kind == GRID_DWF) {
         EOCHK(hop_cb(U, GRID_F64, GRID_L18, g, GRID_WILSON, 0, 1.0, mf, 1, xe, nullptr, bo, nullptr, 0.5, o.t1[0], nullptr,

@@ -10,6 +10,20 @@
 
 namespace gridmi {
 
+// Fused epilogue of the full-lattice Wilson / domain-wall operator, for the conjugate gradient:
+//   kFuseNorm: out = op psi as usual, plus per-block partial sums of |out|^2;
+//   kFuseAxpy: out = r - alpha op psi with alpha = scal[num] / scal[den] (device scalars), plus the
+//              partials of |out|^2. r may be out itself (each site is read before it is written).
+// The partials (FP16 storage: of the coded values) go to part[0 .. nblocks), nblocks the grid size.
+enum { kFuseNone = 0, kFuseNorm = 1, kFuseAxpy = 2 };
+struct FuseDev {
+    const void *r = nullptr;
+    const float *r_scale = nullptr;
+    const double *scal = nullptr;
+    int num = 0, den = 0;
+    double *part = nullptr;
+};
+
 struct DhopArgs {
     const void *U;
     const void *psi;
@@ -33,9 +47,17 @@ struct DhopArgs {
     const float *y_scale = nullptr;
     double beta = 0.0;
     double cs = 1.0;           // DWF epilogue: coefficient of the fifth-dimension hopping of y
+    // Fused epilogue (kind WILSON or DWF; full lattice or the custom even-odd form): kFuseNorm
+    // with dag = 0, kFuseAxpy with dag = 1.
+    int fuse = kFuseNone;
+    FuseDev fz;
 };
 
 hipError_t launch_dhop(const DhopArgs &a);
+// Number of blocks (= partial sums written by a fused epilogue) launch_dhop uses for `a`.
+long dhop_blocks(const DhopArgs &a);
+// Upper bound of dhop_blocks over all schedules for a field of n5 sites and time extent Lt.
+long dhop_blocks_max(long n5, int Lt);
 
 // Moebius domain-wall operator (mobius.hip): out = M_mob psi (dag: M_mob^dagger psi) through the
 // intermediate field tmp (same size and precision as psi). a.diag is unused; M5, b5, c5 given.
@@ -78,16 +100,22 @@ struct CgOp {
     hipError_t (*apply)(const void *ctx, const void *U, int prec, int fmt, const void *in, const float *ins, void *out,
                         float *outs, int dag, hipStream_t st);
     const void *ctx;
+    // Optional: apply with a fused epilogue (kFuseNorm with dag 0, kFuseAxpy with dag 1), setting
+    // *nparts to the number of partial sums written.
+    hipError_t (*apply_fused)(const void *ctx, const void *U, int prec, int fmt, const void *in, const float *ins,
+                              void *out, float *outs, int dag, int fuse, const FuseDev &fz, long *nparts,
+                              hipStream_t st) = nullptr;
 };
 size_t cg_workspace_bytes(const GeomDev &g, int sloppy, int link_fmt);
-size_t cg_workspace_bytes_n(long nsites, long nlinks, int sloppy, int link_fmt);
+size_t cg_workspace_bytes_n(long nsites, long nlinks, int sloppy, int link_fmt, long nparts = 0);
 hipError_t run_cg(const void *U, const void *b, void *x, const GeomDev &g, const grid_op &op, const grid_cg_params &p,
                   void *ws, hipStream_t st, grid_cg_stats *stats, int *status);
 // op_tmp: the workspace was sized with the operator temporaries (cg_workspace_bytes) or not
-// (cg_workspace_bytes_n).
+// (cg_workspace_bytes_n); nparts: room for that many fused-epilogue partials (full-lattice
+// operators, cg_workspace_bytes), else 0 and op.apply_fused unused.
 hipError_t run_cg_op(const CgOp &op, const void *U, const void *b, void *x, long nsites, long nlinks,
                      const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status,
-                     bool op_tmp = false);
+                     bool op_tmp = false, long nparts = 0);
 // ||a - b||^2 over n FP64 spinor sites (b may be NULL); part: kRedBlocks + 16 doubles of scratch.
 constexpr int kNormScratch = 1024 + 16;
 hipError_t norm2_diff(const void *a, const void *b, long n, double *part, hipStream_t st, double *result);

@@ -40,6 +40,27 @@ def test_wilson_fp64_cg_4444(gpu):
     assert abs(st["iterations"] - ito) <= max(3, ito // 20)
 
 
+@pytest.mark.parametrize("sloppy", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("kind", ["wilson", "dwf"])
+def test_cg_ragged_blocks(gpu, kind, sloppy):
+    """Full-lattice Wilson / domain-wall solves (operator epilogues carry r -= alpha A p and the
+    norms) on a lattice whose site count fills neither operator schedule's blocks evenly."""
+    import paper_1512_03487_amd as gm
+    from tests.gpu_util import dev
+    dims, Ls = (6, 4, 5, 6), (1 if kind == "wilson" else 3)
+    U = F.gauge_field(dims, seed=7, kind="haar")
+    b = F.spinor_field(dims, seed=8, Ls=Ls) if Ls > 1 else F.spinor_field(dims, seed=8)
+    kw = dict(mass=0.1) if kind == "wilson" else dict(M5=1.8, mf=0.05)
+    x, st = gm.cg(dev(U), dev(b), kind=kind, tol=TOL, sloppy=sloppy, check_every=4, **kw)
+    op = O.Op.wilson(0.1) if kind == "wilson" else O.Op.dwf(Ls, 1.8, 0.05)
+    res = O.true_residual(op, U, b, x.cpu().numpy())
+    print(f"{kind} {sloppy} ragged: {st['iterations']} it, {st['reliable_updates']} RU, oracle residual {res:.2e}")
+    assert st["converged"] and res <= RES_SLACK * TOL
+    if sloppy == "f64":
+        _, sto, ito, _ = O.cg(op, U, b, tol=TOL)
+        assert sto == 0 and abs(st["iterations"] - ito) <= max(3, ito // 20), (st["iterations"], ito)
+
+
 @pytest.mark.parametrize("sloppy,fmt", [("f64", "L18"), ("f32", "L18"), ("f32", "L12"), ("f16s", "L18"),
                                         ("f16s", "L12")])
 def test_dwf_cg_modes(gpu, sloppy, fmt):
