@@ -236,13 +236,16 @@ def eo_legs():
     return out
 
 
-# CG vector-kernel bytes per 5D site and sloppy iteration (dot <p,q>; x, r update; p update)
-CG_VEC_BYTES = {"f32": 192 + 576 + 288, "f16s": 104 + 400 + 156}
+# Bytes per 5D site and sloppy iteration beyond the two operator applications (each: input,
+# output, links): the second one also reads r (its output is r - alpha op^dagger t), and the x/p
+# update reads x_hat (FP32), p, r and writes x_hat, p. Spinors: FP32 96, FP16 storage 52 bytes.
+CG_VEC_BYTES = {"f32": 96 + (2 * 96 + 2 * 96 + 96), "f16s": 52 + (2 * 96 + 2 * 52 + 52)}
 OP_FLOPS = {"wilson": 1368, "dwf": 1416}
 
 
 def cg_iteration_legs():
-    """Throughput of sloppy CG iterations (two operator applications and the three vector kernels)
+    """Throughput of sloppy CG iterations (two operator applications, the second carrying the r
+    update, and the x/p update)
     on Wilson D^dagger D at 32^4 and domain-wall M^dagger M at 24^4 x 12, Haar links, FP32 and
     FP16-storage spinors, with the iterations between host checks replayed from recorded HIP graphs
     and, for comparison, launched directly. Per-iteration time = (t(120 its) - t(20 its)) / 100, so
