@@ -11,13 +11,14 @@
 // the |r|^2 partials are double-buffered by iteration parity. No atomics: results are bitwise
 // reproducible run to run.
 //
-// Wilson / domain-wall operators (full lattice and the even-odd Schur operator) fuse the vector
-// work into the operator's last kernel instead:
+// Wilson, Shamir and Moebius domain-wall operators (full lattice) and the even-odd Schur operator
+// fuse the vector work into the operator's last kernel instead:
 //   t = op p with the |t|^2 partials (one block sum -> <p,Ap>),
 //   r -= alpha op^dagger t in the second application's epilogue with the |r|^2 partials (block
 //        sum -> rho), so A p is never stored or re-read,
 //   update_px: x += alpha p; p = r + beta p (alpha, beta from the device scalars),
-// moving 6 vectors of streaming traffic per iteration where the unfused sequence moves 10.
+// moving 6 vectors of streaming traffic per iteration where the unfused sequence moves 10. (The
+// Moebius operator's last kernel is its s-local pass, which carries the same epilogues.)
 //
 // Host side: launches the iteration, reads |r|^2 back once every `check_every` iterations, and
 // performs a reliable update (x += x_hat, r = b - A x in FP64, r_hat = lo(r)) when the sloppy
@@ -627,7 +628,7 @@ size_t cg_workspace_bytes_n(long nsites, long nlinks, int sloppy, int link_fmt, 
 // The full-lattice solve keeps one operator temporary per precision (the Moebius operator's
 // intermediate field) and room for the fused epilogues' partial sums.
 size_t cg_workspace_bytes(const GeomDev &g, int sloppy, int link_fmt) {
-    return cg_layout(g.n5, static_cast<long>(g.vol) * 4, sloppy, link_fmt, true, dhop_blocks_max(g.n5, g.L[3])).total;
+    return cg_layout(g.n5, static_cast<long>(g.vol) * 4, sloppy, link_fmt, true, fused_parts_max(g.n5, g.L[3])).total;
 }
 
 // --------------------------------------------------------------------------------------------
@@ -721,15 +722,18 @@ static hipError_t full_apply(const void *ctx, const void *U, int prec, int fmt, 
     return launch_dhop(a);
 }
 
-// Wilson / Shamir domain-wall operator with a fused epilogue (the kernels' own block sums).
+// Wilson / Shamir / Moebius domain-wall operator with a fused epilogue on its last kernel.
 static hipError_t full_apply_fused(const void *ctx, const void *U, int prec, int fmt, const void *in, const float *ins,
                                    void *out, float *outs, int dag, int fuse, const FuseDev &fz, long *nparts,
                                    hipStream_t st) {
     const FullOp &o = *static_cast<const FullOp *>(ctx);
-    if (o.kind != GRID_WILSON && o.kind != GRID_DWF) return hipErrorInvalidValue;
+    if (o.kind != GRID_WILSON && o.kind != GRID_DWF && o.kind != GRID_MOBIUS) return hipErrorInvalidValue;
     DhopArgs a = full_args(o, U, prec, fmt, in, ins, out, outs, dag, st);
     a.fuse = fuse;
     a.fz = fz;
+    if (o.kind == GRID_MOBIUS)
+        return launch_mobius(a, o.M5, o.b5, o.c5, o.tmp[prec == GRID_F64 ? 0 : 1], prec == GRID_F16S ? o.tmps : nullptr,
+                             nparts);
     *nparts = dhop_blocks(a);
     return launch_dhop(a);
 }
@@ -1015,7 +1019,7 @@ hipError_t run_cg(const void *U, const void *b, void *x, const GeomDev &g, const
     o.M5 = opd.M5;
     o.b5 = opd.b5;
     o.c5 = opd.c5;
-    const long nparts = dhop_blocks_max(g.n5, g.L[3]);
+    const long nparts = fused_parts_max(g.n5, g.L[3]);
     const CgLayout L = cg_layout(g.n5, static_cast<long>(g.vol) * 4, p.sloppy_prec, p.link_fmt, true, nparts);
     char *w = static_cast<char *>(ws);
     o.tmp[0] = w + L.u;
@@ -1024,7 +1028,7 @@ hipError_t run_cg(const void *U, const void *b, void *x, const GeomDev &g, const
     CgOp op;
     op.apply = full_apply;
     op.ctx = &o;
-    if (opd.kind == GRID_WILSON || opd.kind == GRID_DWF) op.apply_fused = full_apply_fused;
+    if (opd.kind == GRID_WILSON || opd.kind == GRID_DWF || opd.kind == GRID_MOBIUS) op.apply_fused = full_apply_fused;
     return run_cg_op(op, U, b, x, g.n5, static_cast<long>(g.vol) * 4, p, ws, st, stats, status, true, nparts);
 }
 

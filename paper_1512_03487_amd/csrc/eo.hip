@@ -268,7 +268,7 @@ static EoLayout eo_layout(const GeomDev &g, int sloppy, int link_fmt) {
     L.norm = take(kNormScratch * sizeof(double));
     L.cg = off;
     L.total = off + cg_workspace_bytes_n(static_cast<long>(n), static_cast<long>(g.vol) * 4, sloppy, link_fmt,
-                                         dhop_blocks_max(static_cast<long>(n), g.L[3]));
+                                         fused_parts_max(static_cast<long>(n), g.L[3]));
     return L;
 }
 
@@ -327,7 +327,7 @@ hipError_t run_solve_eo(const void *U, const void *b, void *x, const GeomDev &g,
     grid_cg_stats cs;
     memset(&cs, 0, sizeof(cs));
     EOCHK(run_cg_op(op, U, rhs, xe, n, static_cast<long>(g.vol) * 4, p, w + L.cg, st, &cs, status, false,
-                    dhop_blocks_max(static_cast<long>(n), g.L[3])));
+                    fused_parts_max(static_cast<long>(n), g.L[3])));
     // x_o = M_oo^-1 (b_o + H_oe x_e / 2)
     if (kind == GRID_DWF) {
         EOCHK(hop_cb(U, GRID_F64, GRID_L18, g, GRID_WILSON, 0, 1.0, mf, 1, xe, nullptr, bo, nullptr, 0.5, o.t1[0], nullptr,

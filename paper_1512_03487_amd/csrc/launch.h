@@ -61,7 +61,12 @@ long dhop_blocks_max(long n5, int Lt);
 
 // Moebius domain-wall operator (mobius.hip): out = M_mob psi (dag: M_mob^dagger psi) through the
 // intermediate field tmp (same size and precision as psi). a.diag is unused; M5, b5, c5 given.
-hipError_t launch_mobius(const DhopArgs &a, double M5, double b5, double c5, void *tmp, float *tmp_scale);
+// a.fuse (kFuseNorm with dag = 0, kFuseAxpy with dag = 1) applies to the last kernel, whose
+// partial count goes to *nparts.
+hipError_t launch_mobius(const DhopArgs &a, double M5, double b5, double c5, void *tmp, float *tmp_scale,
+                         long *nparts = nullptr);
+// Upper bound of the partial sums any fused epilogue writes for n5 sites (hopping or s-local kernel).
+long fused_parts_max(long n5, int Lt);
 
 // Fifth-dimension operator inverse of the domain-wall operator (eo.hip): out = M5^-1 psi or
 // (M5^dagger)^-1 psi on n4 4D sites of Ls records each (full or checkerboard fields).
