@@ -666,6 +666,161 @@ k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const floa
     }
 }
 
+// Column walk on checkerboard fields (the even-odd form): out (parity cb) = Diag(y) + beta H psi,
+// psi of parity 1 - cb, y and out of parity cb. A checkerboard field holds one site per x-pair, at
+// (full 4D index) / 2. A thread owns (xh, y, z, s) and walks T slices; its physical x shifts with
+// t (x = 2 xh + ((cb + y + z + t) & 1)), so the backward t-hop cannot be carried from the previous
+// step and both t-neighbours are gathered: 8 neighbour records (+ y) and 8 links per step.
+template <class SP, class LK, bool DAG, int KIND, int FUSE>
+__global__ void __launch_bounds__(256)
+k_dhop_walk_cb(const void *__restrict__ U, const void *__restrict__ psi, const float *__restrict__ psi_scale,
+               const void *__restrict__ yv, const float *__restrict__ y_scale, void *out, float *out_scale, GeomDev g,
+               int T, int cbp, double diag, double mf, double beta, double cs, FuseDev fz) {
+    using C = typename SP::C;
+    __shared__ chunk_t sm[kWaves][64 * (SP::kChunks + 1)];
+    chunk_t *lds = sm[threadIdx.x >> 6];
+
+    const int Ls = g.Ls, Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
+    const int Lxh = Lx / 2;
+    const int V3h = Lxh * Ly * Lz;          // checkerboard sites per slice
+    const int nq = V3h * Ls;                // 5D checkerboard sites per slice
+    const int nbc = (nq + 255) / 256;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int seg = lb / nbc, cbk = lb - seg * nbc;
+    const int q = cbk * 256 + threadIdx.x;
+    const bool live = q < nq;
+    const int qq = live ? q : 0;            // idle lanes still take part in the wave's gathers
+    const int colh = qq / Ls, s = qq - (qq / Ls) * Ls;
+    const int xh = colh % Lxh, yz = colh / Lxh;
+    const int y = yz % Ly, z = yz / Ly;
+    const int rowh = yz * Lxh;              // checkerboard index of the row (0, y, z)
+    const int yp = (y == Ly - 1) ? 0 : y + 1, ym = (y == 0) ? Ly - 1 : y - 1;
+    const int zp = (z == Lz - 1) ? 0 : z + 1, zm = (z == 0) ? Lz - 1 : z - 1;
+    const int V3 = Lx * Ly * Lz;
+    const int t0 = seg * T;
+    constexpr int EF = DAG ? +1 : -1;
+    constexpr int NREC = (KIND == GRID_HOP) ? 8 : 9;
+    [[maybe_unused]] double n2 = 0.0;   // fused epilogue: this thread's |out|^2
+
+    Cx<C> p[4][3], u[3][3];
+#pragma unroll 1
+    for (int k = 0; k < T; ++k) {
+        const int t = t0 + k;
+        const int tn = (t == Lt - 1) ? 0 : t + 1, tm = (t == 0) ? Lt - 1 : t - 1;
+        const int x = 2 * xh + ((cbp + y + z + t) & 1);
+        const int xp = (x == Lx - 1) ? 0 : x + 1, xm = (x == 0) ? Lx - 1 : x - 1;
+        const int offh = t * V3h;
+        const int oq = (offh + colh) * Ls + s;   // output (and y) record
+        // records: +t, -t, +x, -x, +y, -y, +z, -z (the input field), then y
+        int rec[NREC];
+        rec[0] = (tn * V3h + colh) * Ls + s;
+        rec[1] = (tm * V3h + colh) * Ls + s;
+        rec[2] = (offh + rowh + (xp >> 1)) * Ls + s;
+        rec[3] = (offh + rowh + (xm >> 1)) * Ls + s;
+        rec[4] = (offh + (z * Ly + yp) * Lxh + xh) * Ls + s;
+        rec[5] = (offh + (z * Ly + ym) * Lxh + xh) * Ls + s;
+        rec[6] = (offh + (zp * Ly + y) * Lxh + xh) * Ls + s;
+        rec[7] = (offh + (zm * Ly + y) * Lxh + xh) * Ls + s;
+        if (KIND != GRID_HOP) rec[8] = oq;
+        // links, full-lattice index: U_mu(x) forward, U_mu(x - mu) backward
+        const size_t f4 = (static_cast<size_t>(t) * Lz + z) * Ly * Lx + static_cast<size_t>(y) * Lx + x;
+        const size_t row4 = f4 - x;
+        size_t lk[8];
+        lk[0] = f4 * 4 + 3;
+        lk[1] = ((static_cast<size_t>(tm) * Lz + z) * Ly * Lx + static_cast<size_t>(y) * Lx + x) * 4 + 3;
+        lk[2] = f4 * 4 + 0;
+        lk[3] = (row4 + xm) * 4 + 0;
+        lk[4] = f4 * 4 + 1;
+        lk[5] = (f4 - static_cast<size_t>(y) * Lx + static_cast<size_t>(ym) * Lx) * 4 + 1;
+        lk[6] = f4 * 4 + 2;
+        lk[7] = (f4 - static_cast<size_t>(z) * Ly * Lx + static_cast<size_t>(zm) * Ly * Lx) * 4 + 2;
+        Fetch<SP> f;
+        fetch<SP>(psi, psi_scale, rec[0], f);
+        Cx<C> acc[4][3];
+#pragma unroll
+        for (int j = 0; j < 12; ++j) acc[j / 3][j % 3] = {C(0), C(0)};
+#pragma unroll
+        for (int i = 0; i < NREC; ++i) {
+            stage<SP>(f, lds, p);
+            // link of this direction first, then the next record: loads complete in issue order
+            if (i < 8) LK::load(U, lk[i], u);
+            if (i + 1 < 8)
+                fetch<SP>(psi, psi_scale, rec[i + 1], f);
+            else if (i + 1 < NREC)
+                fetch<SP>(yv, y_scale, rec[i + 1], f);
+            if (i == 0) hop_term<3, EF, false>(acc, p, u);
+            else if (i == 1) hop_term<3, -EF, true>(acc, p, u);
+            else if (i == 2) hop_term<0, EF, false>(acc, p, u);
+            else if (i == 3) hop_term<0, -EF, true>(acc, p, u);
+            else if (i == 4) hop_term<1, EF, false>(acc, p, u);
+            else if (i == 5) hop_term<1, -EF, true>(acc, p, u);
+            else if (i == 6) hop_term<2, EF, false>(acc, p, u);
+            else if (i == 7) hop_term<2, -EF, true>(acc, p, u);
+            else {
+                // the diagonal part of `kind` on y, H scaled by beta
+                const C dg = static_cast<C>(diag), bt = static_cast<C>(beta);
+#pragma unroll
+                for (int j = 0; j < 12; ++j) {
+                    const Cx<C> a = acc[j / 3][j % 3], v = p[j / 3][j % 3];
+                    acc[j / 3][j % 3] = {dg * v.r + bt * a.r, dg * v.i + bt * a.i};
+                }
+            }
+        }
+        if (KIND == GRID_HOP) {
+            const C bt = static_cast<C>(beta);
+#pragma unroll
+            for (int j = 0; j < 12; ++j) acc[j / 3][j % 3] = {bt * acc[j / 3][j % 3].r, bt * acc[j / 3][j % 3].i};
+        }
+        if (KIND == GRID_DWF) {
+            // - cs (P_- y~_{s+1} + P_+ y~_{s-1}) (M; P_+ and P_- exchanged for M^dagger), walls -mf
+            const int sp = (s == Ls - 1) ? 0 : s + 1;
+            const int sm1 = (s == 0) ? Ls - 1 : s - 1;
+            const C csc = static_cast<C>(cs);
+            const C fp = csc * ((s == Ls - 1) ? static_cast<C>(-mf) : C(1));
+            const C fm = csc * ((s == 0) ? static_cast<C>(-mf) : C(1));
+            const int hup = DAG ? 0 : 1;   // chiral half taken from s + 1 (0: spins 0,1; 1: spins 2,3)
+            const int hdn = 1 - hup;
+            const size_t site4 = static_cast<size_t>(offh + colh) * Ls;
+            Cx<C> qh[2][3];
+            SP::load_half(yv, y_scale, site4 + sp, hup, qh);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                Cx<C> &o = acc[2 * hup + j / 3][j % 3];
+                o = {o.r - fp * qh[j / 3][j % 3].r, o.i - fp * qh[j / 3][j % 3].i};
+            }
+            SP::load_half(yv, y_scale, site4 + sm1, hdn, qh);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                Cx<C> &o = acc[2 * hdn + j / 3][j % 3];
+                o = {o.r - fm * qh[j / 3][j % 3].r, o.i - fm * qh[j / 3][j % 3].i};
+            }
+        }
+        if constexpr (FUSE == kFuseAxpy) {
+            // r - alpha op psi; r may alias out: the wavefront gathers its own records before storing
+            Cx<C> rv[4][3];
+            gather<SP>(fz.r, fz.r_scale, oq, lds, rv);
+            const C al = static_cast<C>(fz.scal[fz.num] / fz.scal[fz.den]);
+#pragma unroll
+            for (int j = 0; j < 12; ++j) {
+                const Cx<C> a = acc[j / 3][j % 3], b = rv[j / 3][j % 3];
+                acc[j / 3][j % 3] = {b.r - al * a.r, b.i - al * a.i};
+            }
+        }
+        if constexpr (FUSE == kFuseNone) {
+            if (live) SP::store(out, out_scale, static_cast<size_t>(oq), acc);
+        } else {
+            if (live) n2 += SP::store_n2(out, out_scale, static_cast<size_t>(oq), acc);
+        }
+    }
+    if constexpr (FUSE != kFuseNone) {
+        n2 = wave_sum64(n2);
+        __shared__ double fred[4];
+        if ((threadIdx.x & 63) == 0) fred[threadIdx.x >> 6] = n2;
+        __syncthreads();
+        if (threadIdx.x == 0) fz.part[blockIdx.x] = (fred[0] + fred[1]) + (fred[2] + fred[3]);
+    }
+}
+
 // Steps per thread: the longest walk (a divisor of Lt) that still leaves enough blocks to fill
 // the chip; small lattices use T = 1.
 static int choose_steps(const GeomDev &g) {
@@ -717,15 +872,60 @@ static hipError_t launch_walk(const DhopArgs &a) {
     return hipGetLastError();
 }
 
-// Direction-parallel schedule for 4D fields in FP64 / FP32, 5D fields in FP64 and every even-odd
-// or Moebius (custom) call; column walk for FP16 storage and 5D fields in FP32 (measured faster).
-static bool use_walk(const DhopArgs &a) {
-    return !a.custom && (a.prec == GRID_F16S || (a.prec == GRID_F32 && a.g.Ls > 1));
+// Checkerboard walk: blocks of 256 column sites, walks of the longest divisor of Lt that keeps at
+// least 2048 blocks (no carried term, so a longer walk only amortises the index set-up).
+static long walk_cb_nbc(const GeomDev &g) {
+    return (static_cast<long>(g.L[0] / 2) * g.L[1] * g.L[2] * g.Ls + 255) / 256;
 }
+static int choose_steps_cb(const GeomDev &g) {
+    const long nbc = walk_cb_nbc(g);
+    int best = 1;
+    for (int T = 1; T <= g.L[3]; ++T)
+        if (g.L[3] % T == 0 && nbc * (g.L[3] / T) >= 2048) best = T;
+    return best;
+}
+
+template <class SP, class LK>
+static hipError_t launch_walk_cb(const DhopArgs &a) {
+    const int T = choose_steps_cb(a.g);
+    const dim3 grid(static_cast<unsigned>(walk_cb_nbc(a.g) * (a.g.L[3] / T))), block(256);
+    hipStream_t st = a.stream;
+#define GRIDMI_LAUNCH(DAG, KIND, FUSE)                                                                    \
+    hipLaunchKernelGGL((k_dhop_walk_cb<SP, LK, DAG, KIND, FUSE>), grid, block, 0, st, a.U, a.psi, a.psi_scale, \
+                       a.y, a.y_scale, a.out, a.out_scale, a.g, T, a.cb, a.diag, a.mf, a.beta, a.cs, a.fz)
+    if (a.fuse != kFuseNone) {
+        switch (a.kind * 4 + a.fuse * 2 + (a.dag ? 1 : 0)) {
+            case GRID_WILSON * 4 + kFuseNorm * 2 + 0: GRIDMI_LAUNCH(false, GRID_WILSON, kFuseNorm); break;
+            case GRID_DWF * 4 + kFuseNorm * 2 + 0: GRIDMI_LAUNCH(false, GRID_DWF, kFuseNorm); break;
+            case GRID_WILSON * 4 + kFuseAxpy * 2 + 1: GRIDMI_LAUNCH(true, GRID_WILSON, kFuseAxpy); break;
+            case GRID_DWF * 4 + kFuseAxpy * 2 + 1: GRIDMI_LAUNCH(true, GRID_DWF, kFuseAxpy); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    switch (a.kind * 2 + (a.dag ? 1 : 0)) {
+        case GRID_HOP * 2 + 0: GRIDMI_LAUNCH(false, GRID_HOP, kFuseNone); break;
+        case GRID_HOP * 2 + 1: GRIDMI_LAUNCH(true, GRID_HOP, kFuseNone); break;
+        case GRID_WILSON * 2 + 0: GRIDMI_LAUNCH(false, GRID_WILSON, kFuseNone); break;
+        case GRID_WILSON * 2 + 1: GRIDMI_LAUNCH(true, GRID_WILSON, kFuseNone); break;
+        case GRID_DWF * 2 + 0: GRIDMI_LAUNCH(false, GRID_DWF, kFuseNone); break;
+        case GRID_DWF * 2 + 1: GRIDMI_LAUNCH(true, GRID_DWF, kFuseNone); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef GRIDMI_LAUNCH
+    return hipGetLastError();
+}
+
+// Schedules: column walk for FP16 storage and 5D FP32 fields (full lattice, or checkerboard
+// fields in the even-odd form), direction-parallel otherwise (measured faster there).
+static bool walk_prec(const DhopArgs &a) { return a.prec == GRID_F16S || (a.prec == GRID_F32 && a.g.Ls > 1); }
+static bool use_walk(const DhopArgs &a) { return !a.custom && walk_prec(a); }
+static bool use_walk_cb(const DhopArgs &a) { return a.custom && a.cb >= 0 && walk_prec(a); }
 
 template <class SP, class LK>
 static hipError_t launch_sched(const DhopArgs &a) {
     if (use_walk(a)) return launch_walk<SP, LK>(a);
+    if (use_walk_cb(a)) return launch_walk_cb<SP, LK>(a);
     return launch_dir<SP, LK>(a);
 }
 
@@ -734,12 +934,13 @@ long dhop_blocks(const DhopArgs &a) {
         const long nbc = (static_cast<long>(a.g.L[0]) * a.g.L[1] * a.g.L[2] * a.g.Ls + 255) / 256;
         return nbc * (a.g.L[3] / choose_steps(a.g));
     }
+    if (use_walk_cb(a)) return walk_cb_nbc(a.g) * (a.g.L[3] / choose_steps_cb(a.g));
     const Trav tr = make_trav(a.g, a.custom ? a.cb : -1);
     return (static_cast<long>(tr.nout) + kSites - 1) / kSites;
 }
 
 long dhop_blocks_max(long n5, int Lt) {
-    // direction-parallel: ceil(n5 / 32); column walk: at most ceil(n5 / Lt / 256) * Lt
+    // direction-parallel: ceil(n5 / 32); column walks: at most ceil(n5 / Lt / 256) * Lt
     return (n5 + kSites - 1) / kSites + Lt;
 }
 

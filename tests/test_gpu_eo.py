@@ -49,6 +49,55 @@ def test_dhop_cb(gpu, dims, Ls, prec):
             assert rel(got, ref) <= TOL[prec], (p, dag, "diag")
 
 
+def _pick_dev(x, p):
+    """Parity-p checkerboard (Lt, Lz, Ly, Lx/2, ...) of a full device field (Lt, Lz, Ly, Lx, ...)."""
+    import torch
+    Lt, Lz, Ly, Lx = x.shape[:4]
+    ar = lambda n: torch.arange(n, device=x.device)
+    xs = 2 * ar(Lx // 2).view(1, 1, 1, -1) + ((p + ar(Lt).view(-1, 1, 1, 1) + ar(Lz).view(1, -1, 1, 1)
+                                                 + ar(Ly).view(1, 1, -1, 1)) & 1)
+    idx = xs.view(xs.shape + (1,) * (x.dim() - 4)).expand((Lt, Lz, Ly, Lx // 2) + tuple(x.shape[4:]))
+    return torch.gather(x, 3, idx).contiguous()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16s"])
+def test_dhop_cb_long_walks_match_full_lattice(gpu, prec):
+    """24^4 x 12 (checkerboard walks of three slices over many blocks): H couples only opposite
+    parities and the diagonal and fifth-dimension parts are parity-local, so the checkerboard
+    operator on (psi of parity 1 - p, y of parity p) equals the full-lattice operator on the field
+    holding both, restricted to parity p. The two sides run different kernels."""
+    import torch
+    from tests.gpu_util import cached
+    gm = _gm()
+    dev = torch.device("cuda:0")
+    dims, Ls = (24, 24, 24, 24), 12
+    U = torch.from_numpy(cached("gauge", dims, 1, kind="haar")).to(dev)
+    g = torch.Generator(device=dev).manual_seed(11)
+    shape = (dims[3], dims[2], dims[1], dims[0], Ls, 4, 3)
+    full = torch.complex(torch.randn(shape, generator=g, device=dev), torch.randn(shape, generator=g, device=dev))
+    if prec == "f32":
+        Uk, fk = U.to(torch.complex64), full
+        pick = _pick_dev
+        as32 = lambda v: v
+        tol = 1e-5
+    else:
+        Uk, fk = gm.convert_links(U, "f16s", "L12"), gm.convert_spinor(full, "f16s")
+        pick = lambda v, p: gm.F16Spinor(_pick_dev(v.codes, p), _pick_dev(v.scale, p))
+        as32 = lambda v: gm.convert_spinor(v, "f32")
+        tol = 4e-3
+    for dag in (False, True):
+        ref_full = as32(gm.dwf(Uk, fk, 1.8, 0.05, dag=dag))
+        hop_full = as32(gm.dhop(Uk, fk, "hop", dag=dag))
+        for p in (0, 1):
+            got = as32(gm.dhop_cb(Uk, pick(fk, 1 - p), p, "dwf", y=pick(fk, p), beta=-0.5, M5=1.8, mf=0.05, dag=dag))
+            ref = _pick_dev(ref_full, p)
+            assert float((got - ref).norm() / ref.norm()) <= tol, (prec, dag, p, "dwf")
+            # the hopping term alone: at parity-p sites H sees only the parity 1 - p part
+            got = as32(gm.dhop_cb(Uk, pick(fk, 1 - p), p, "hop", dag=dag))
+            ref = _pick_dev(hop_full, p)
+            assert float((got - ref).norm() / ref.norm()) <= tol, (prec, dag, p, "hop")
+
+
 @pytest.mark.parametrize("prec", ["f32", "f16s"])
 def test_dhop_cb_compressed_links(gpu, prec):
     from tests.gpu_util import as_prec, host, rel
