@@ -31,17 +31,55 @@ namespace gridmi {
 constexpr int kM5invSites = 4;   // 4D sites per block (16 lanes each, one wavefront)
 constexpr int kM5invMaxLs = 64;
 
+typedef unsigned int m5chunk_t __attribute__((ext_vector_type(4)));
+
+// LDS of one block: the block's 4 x Ls input records as stored (16-byte chunks), then, for FP16
+// storage only, the FP16 site scales and a separate result area (FP64 / FP32 results overwrite
+// their own input element: lane k reads b_s[k] before it writes y_s[k]).
+template <class SP>
+static size_t m5inv_lds_bytes(int Ls) {
+    size_t b = static_cast<size_t>(kM5invSites) * Ls * SP::kChunks * 16;
+    if (SP::kScaled) b += static_cast<size_t>(kM5invSites) * Ls * (sizeof(float) + 12 * sizeof(Cx<float>));
+    return b;
+}
+
 template <class SP>
 __global__ void __launch_bounds__(64)
 k_m5inv(const void *__restrict__ psi, const float *__restrict__ psi_scale, void *__restrict__ out,
         float *__restrict__ out_scale, long n4, int Ls, double diag, double mf, int dag) {
     using C = typename SP::C;
-    extern __shared__ unsigned char smem[];   // [kM5invSites][Ls][12] complex
+    constexpr int CH = SP::kChunks;
+    extern __shared__ m5chunk_t smem[];
     const int lane = threadIdx.x;
+    const long h0 = static_cast<long>(blockIdx.x) * kM5invSites;
+    const int nsite = static_cast<int>(n4 - h0 < kM5invSites ? n4 - h0 : kM5invSites);
+    // Stage the block's nsite * Ls consecutive records: coalesced 16-byte loads, eight in flight
+    // per lane, so the s recurrences below read LDS instead of waiting on one load per step.
+    m5chunk_t *xin = smem;
+    const int nch = nsite * Ls * CH;
+    const m5chunk_t *src = reinterpret_cast<const m5chunk_t *>(psi) + static_cast<size_t>(h0) * Ls * CH;
+    for (int c0 = 0; c0 < nch; c0 += 8 * 64) {
+        m5chunk_t w[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int c = c0 + j * 64 + lane;
+            if (c < nch) w[j] = src[c];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int c = c0 + j * 64 + lane;
+            if (c < nch) xin[c] = w[j];
+        }
+    }
+    [[maybe_unused]] float *scl = reinterpret_cast<float *>(xin + kM5invSites * Ls * CH);
+    if constexpr (SP::kScaled) {
+        for (int r = lane; r < nsite * Ls; r += 64) scl[r] = psi_scale[static_cast<size_t>(h0) * Ls + r];
+    }
+    __syncthreads();
+
     const int sl = lane >> 4, k16 = lane & 15;
-    const long h = static_cast<long>(blockIdx.x) * kM5invSites + sl;
-    const bool live = h < n4 && k16 < 12;
-    const long hh = h < n4 ? h : n4 - 1;
+    const bool live = sl < nsite && k16 < 12;
+    const int sli = sl < nsite ? sl : 0;   // idle lanes compute on a valid site, store nothing
     const int k = k16 < 12 ? k16 : 0;
     // non-adjoint: lower spins couple to s + 1, upper spins to s - 1; the adjoint swaps them
     const bool plus = ((k / 3) >= 2) != (dag != 0);
@@ -50,50 +88,58 @@ k_m5inv(const void *__restrict__ psi, const float *__restrict__ psi_scale, void 
     C dl = C(1);
     for (int i = 0; i < Ls; ++i) dl *= dinv;
     const C den = C(1) + m * dl;
-    Cx<C> *yb = reinterpret_cast<Cx<C> *>(smem) + static_cast<size_t>(sl) * Ls * 12;
-    const size_t base = static_cast<size_t>(hh) * Ls;
-    const bool wr = k16 < 12;
+    const m5chunk_t *rec0 = xin + static_cast<size_t>(sli) * Ls * CH;
+    auto b_at = [&](int s) -> Cx<C> {
+        return Elem<SP>::get(rec0 + s * CH, k, SP::kScaled ? scl[sli * Ls + s] : 1.0f);
+    };
+    // results: in place over the input element (FP64 / FP32), else the separate area
+    Cx<C> *yb = SP::kScaled ? reinterpret_cast<Cx<C> *>(scl + kM5invSites * Ls) + static_cast<size_t>(sli) * Ls * 12
+                            : reinterpret_cast<Cx<C> *>(xin) + static_cast<size_t>(sli) * Ls * 12;
+    const bool wr = live;
     auto put = [&](int s, Cx<C> v) {
         if (wr) yb[s * 12 + k] = v;
     };
+    // y_s solves the cyclic bidiagonal system of one chirality: first the corner value from the
+    // Horner sum over all s, then back substitution. Every b_s is read before y_s is written.
     if (plus) {
         Cx<C> S = {C(0), C(0)};
         for (int s = Ls - 1; s >= 0; --s) {
-            const Cx<C> b = global_elem<SP>(psi, psi_scale, base + s, k);
+            const Cx<C> b = b_at(s);
             S = {(S.r + b.r) * dinv, (S.i + b.i) * dinv};
         }
         const Cx<C> y0 = {S.r / den, S.i / den};
-        put(0, y0);
         if (Ls > 1) {
-            Cx<C> b = global_elem<SP>(psi, psi_scale, base + Ls - 1, k);
+            Cx<C> b = b_at(Ls - 1);
             Cx<C> y = {(b.r - m * y0.r) * dinv, (b.i - m * y0.i) * dinv};
             put(Ls - 1, y);
             for (int s = Ls - 2; s >= 1; --s) {
-                b = global_elem<SP>(psi, psi_scale, base + s, k);
+                b = b_at(s);
                 y = {(b.r + y.r) * dinv, (b.i + y.i) * dinv};
                 put(s, y);
             }
         }
+        put(0, y0);
     } else {
         Cx<C> S = {C(0), C(0)};
         for (int s = 0; s < Ls; ++s) {
-            const Cx<C> b = global_elem<SP>(psi, psi_scale, base + s, k);
+            const Cx<C> b = b_at(s);
             S = {(S.r + b.r) * dinv, (S.i + b.i) * dinv};
         }
         const Cx<C> yl = {S.r / den, S.i / den};
-        put(Ls - 1, yl);
         if (Ls > 1) {
-            Cx<C> b = global_elem<SP>(psi, psi_scale, base, k);
+            Cx<C> b = b_at(0);
             Cx<C> y = {(b.r - m * yl.r) * dinv, (b.i - m * yl.i) * dinv};
             put(0, y);
             for (int s = 1; s <= Ls - 2; ++s) {
-                b = global_elem<SP>(psi, psi_scale, base + s, k);
+                b = b_at(s);
                 y = {(b.r + y.r) * dinv, (b.i + y.i) * dinv};
                 put(s, y);
             }
         }
+        put(Ls - 1, yl);
     }
     __syncthreads();
+    const size_t base = static_cast<size_t>(h0 + sli) * Ls;
     for (int s = 0; s < Ls; ++s) {
         const Cx<C> v = yb[s * 12 + k];
         store_elem<SP>(out, out_scale, base + s, k, v, live);
@@ -105,15 +151,15 @@ hipError_t launch_m5inv(const void *psi, const float *psi_scale, void *out, floa
     if (n4 == 0) return hipSuccess;
     if (Ls < 1 || Ls > kM5invMaxLs) return hipErrorInvalidValue;
     const dim3 grid(static_cast<unsigned>((n4 + kM5invSites - 1) / kM5invSites)), block(64);
-    const size_t c = prec == GRID_F64 ? sizeof(Cx<double>) : sizeof(Cx<float>);
-    const size_t lds = kM5invSites * static_cast<size_t>(Ls) * 12 * c;
     if (prec == GRID_F64)
-        hipLaunchKernelGGL(k_m5inv<SpF64>, grid, block, lds, stream, psi, psi_scale, out, out_scale, n4, Ls, diag, mf, dag);
+        hipLaunchKernelGGL(k_m5inv<SpF64>, grid, block, m5inv_lds_bytes<SpF64>(Ls), stream, psi, psi_scale, out,
+                           out_scale, n4, Ls, diag, mf, dag);
     else if (prec == GRID_F32)
-        hipLaunchKernelGGL(k_m5inv<SpF32>, grid, block, lds, stream, psi, psi_scale, out, out_scale, n4, Ls, diag, mf, dag);
+        hipLaunchKernelGGL(k_m5inv<SpF32>, grid, block, m5inv_lds_bytes<SpF32>(Ls), stream, psi, psi_scale, out,
+                           out_scale, n4, Ls, diag, mf, dag);
     else
-        hipLaunchKernelGGL(k_m5inv<SpF16S>, grid, block, lds, stream, psi, psi_scale, out, out_scale, n4, Ls, diag, mf,
-                           dag);
+        hipLaunchKernelGGL(k_m5inv<SpF16S>, grid, block, m5inv_lds_bytes<SpF16S>(Ls), stream, psi, psi_scale, out,
+                           out_scale, n4, Ls, diag, mf, dag);
     return hipGetLastError();
 }
 
