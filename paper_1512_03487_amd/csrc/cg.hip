@@ -2,30 +2,24 @@
 // in mixed precision with reliable updates (sloppy FP32 / FP16-storage iterations, FP64 solution,
 // source and true residuals).
 //
-// Device side: streaming vector kernels fused as
-//   dot:       <p, A p> as |op p|^2 = <t, t>           -> per-block FP64 partial sums
-//   update_xr: alpha = rho / <p,q>; x += alpha p; r -= alpha q; |r|^2 partials
-//   update_p:  beta = |r_new|^2 / |r_old|^2; p = r + beta p
-// Every block of update_xr / update_p first re-sums the partials of the previous kernel in the
-// same fixed order, so alpha and beta never leave the device and are identical in all blocks;
-// the |r|^2 partials are double-buffered by iteration parity. No atomics: results are bitwise
-// reproducible run to run.
-//
-// Wilson, Shamir and Moebius domain-wall operators (full lattice) and the even-odd Schur operator
-// fuse the vector work into the operator's last kernel instead:
-//   t = op p with the |t|^2 partials (one block sum -> <p,Ap>),
-//   r -= alpha op^dagger t in the second application's epilogue with the |r|^2 partials (block
-//        sum -> rho), so A p is never stored or re-read,
-//   update_px: x += alpha p; p = r + beta p (alpha, beta from the device scalars),
-// moving 6 vectors of streaming traffic per iteration where the unfused sequence moves 10. (The
-// Moebius operator's last kernel is its s-local pass, which carries the same epilogues.)
+// Device side, one iteration: the vector work rides on the operator's last kernel (the Wilson,
+// Shamir and Moebius domain-wall operators and the even-odd Schur operator all take the fused
+// epilogues):
+//   t = op p, writing the per-block partials of |t|^2 (= <p, A p>);    one block sum -> <p,Ap>
+//   r -= alpha op^dagger t in the second application's epilogue (alpha = rho / <p,Ap> from the
+//        device scalars), writing the partials of |r|^2;              one block sum -> rho
+//   update_px: x += alpha p; p = r + beta p (beta = rho_new / rho_old).
+// A p is never stored: per iteration 6 vectors of streaming traffic beyond the two operator
+// applications' own, against 10 for separate dot, x/r-update and p-update kernels. The partials
+// are summed in a fixed order and rho is double-buffered by iteration parity; alpha and beta never
+// leave the device. No atomics: results are bitwise reproducible run to run.
 //
 // Host side: launches the iteration, reads |r|^2 back once every `check_every` iterations, and
 // performs a reliable update (x += x_hat, r = b - A x in FP64, r_hat = lo(r)) when the sloppy
 // residual fell below delta times its maximum since the last update, or below the target.
 // The solve stops only on an FP64 true residual <= tol |b|.
 //
-// With params.graph the check_every iterations between two host reads (their last p update
+// With params.graph the check_every iterations between two host reads (their last x/p update
 // excepted, which follows the check) are recorded once into a HIP graph per starting parity on a
 // stream of the driver's own, then replayed on the caller's stream: one launch per segment in
 // place of about six per iteration. The recorded kernels and arguments are those of the direct
@@ -87,49 +81,6 @@ k_dot_flat(const V *__restrict__ a, const V *__restrict__ b, long n, double *__r
         acc += dot2(a[i], b[i]);
     const double t = block_sum(acc, sm);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
-
-// alpha = sum(rr_prev) / sum(pq); x += alpha p; r -= alpha q; rr_new = |r|^2 partials.
-template <typename V>
-__global__ void __launch_bounds__(kThreads)
-k_update_xr_flat(V *__restrict__ x, const V *__restrict__ p, V *__restrict__ r, const V *__restrict__ q, long n,
-                 const double *__restrict__ rr_prev, const double *__restrict__ pq_part, int np, double *__restrict__ rr_new,
-                 double *__restrict__ scal) {
-    __shared__ double sm[4];
-    const double rho = sum_partials(rr_prev, np, sm);
-    const double pq = sum_partials(pq_part, np, sm);
-    const double alpha = rho / pq;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        scal[0] = alpha;
-        scal[1] = pq;
-        scal[2] = rho;
-    }
-    double acc = 0.0;
-    for (long i = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * kThreads) {
-        x[i] = axpy2(alpha, p[i], x[i]);
-        const V rn = axpy2(-alpha, q[i], r[i]);
-        r[i] = rn;
-        acc += dot2(rn, rn);
-    }
-    const double t = block_sum(acc, sm);
-    if (threadIdx.x == 0) rr_new[blockIdx.x] = t;
-}
-
-// beta = sum(rr_new) / sum(rr_prev); p = r + beta p.
-template <typename V>
-__global__ void __launch_bounds__(kThreads)
-k_update_p_flat(const V *__restrict__ r, V *__restrict__ p, long n, const double *__restrict__ rr_prev,
-                const double *__restrict__ rr_new, int np, double *__restrict__ scal) {
-    __shared__ double sm[4];
-    const double rho = sum_partials(rr_prev, np, sm);
-    const double rn = sum_partials(rr_new, np, sm);
-    const double beta = rn / rho;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        scal[3] = beta;
-        scal[4] = rn;
-    }
-    for (long i = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * kThreads)
-        p[i] = axpy2(beta, p[i], r[i]);
 }
 
 // Fused sequence: alpha = scal[so] / scal[sq], beta = scal[sn] / scal[so];
@@ -248,102 +199,6 @@ __device__ __forceinline__ long unit_first() {
     return (static_cast<long>(blockIdx.x) * (kThreads / 64) + (threadIdx.x >> 6)) * 21;
 }
 __device__ __forceinline__ long unit_stride() { return static_cast<long>(gridDim.x) * (kThreads / 64) * 21; }
-
-__global__ void __launch_bounds__(kThreads)
-k_dot_f16(const uint4 *__restrict__ a, const float *__restrict__ as, const uint4 *__restrict__ b, const float *__restrict__ bs,
-          long nsites, double *__restrict__ part) {
-    __shared__ double sm[4];
-    double acc = 0.0;
-    for (long u = static_cast<long>(blockIdx.x) * kThreads + threadIdx.x; u < nsites * 3; u += static_cast<long>(gridDim.x) * kThreads) {
-        float va[8], vb[8];
-        unit_decode(a[u], as[u / 3], va);
-        unit_decode(b[u], bs[u / 3], vb);
-        double d = 0.0;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) d += double(va[j]) * double(vb[j]);
-        acc += d;
-    }
-    const double t = block_sum(acc, sm);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
-
-// alpha = sum(rr_prev) / sum(pq); x_hat (FP32) += alpha p; r -= alpha q (FP16 re-encoded).
-__global__ void __launch_bounds__(kThreads)
-k_update_xr_f16(float4 *__restrict__ xh, const uint4 *__restrict__ p, const float *__restrict__ ps, uint4 *__restrict__ r,
-                float *__restrict__ rs, const uint4 *__restrict__ q, const float *__restrict__ qs, long nsites,
-                const double *__restrict__ rr_prev, const double *__restrict__ pq_part, int np, double *__restrict__ rr_new,
-                double *__restrict__ scal) {
-    __shared__ double sm[4];
-    const double rho = sum_partials(rr_prev, np, sm);
-    const double pq = sum_partials(pq_part, np, sm);
-    const double alpha = rho / pq;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        scal[0] = alpha;
-        scal[1] = pq;
-        scal[2] = rho;
-    }
-    const float al = static_cast<float>(alpha);
-    double acc = 0.0;
-    for (long sb = unit_first(); sb < nsites; sb += unit_stride()) {
-        const UnitPos u = unit_pos(sb, nsites);
-        float pv[8], rv[8], qv[8];
-        unit_decode(p[u.unit], ps[u.su], pv);
-        unit_decode(r[u.unit], rs[u.su], rv);
-        unit_decode(q[u.unit], qs[u.su], qv);
-        float4 x0 = xh[2 * u.unit], x1 = xh[2 * u.unit + 1];
-        x0 = make_float4(x0.x + al * pv[0], x0.y + al * pv[1], x0.z + al * pv[2], x0.w + al * pv[3]);
-        x1 = make_float4(x1.x + al * pv[4], x1.y + al * pv[5], x1.z + al * pv[6], x1.w + al * pv[7]);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) rv[j] -= al * qv[j];
-        float m;
-        const uint4 code = unit_encode(rv, m);
-        if (u.ok) {
-            xh[2 * u.unit] = x0;
-            xh[2 * u.unit + 1] = x1;
-            r[u.unit] = code;
-            if (u.sub == 0) rs[u.su] = m;
-            // the norm is taken of the stored (coded) residual
-            float dv[8];
-            unit_decode(code, m, dv);
-            double d = 0.0;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) d += double(dv[j]) * double(dv[j]);
-            acc += d;
-        }
-    }
-    const double t = block_sum(acc, sm);
-    if (threadIdx.x == 0) rr_new[blockIdx.x] = t;
-}
-
-// beta = sum(rr_new) / sum(rr_prev); p = r + beta p (FP16 re-encoded).
-__global__ void __launch_bounds__(kThreads)
-k_update_p_f16(const uint4 *__restrict__ r, const float *__restrict__ rs, uint4 *__restrict__ p, float *__restrict__ ps,
-               long nsites, const double *__restrict__ rr_prev, const double *__restrict__ rr_new, int np,
-               double *__restrict__ scal) {
-    __shared__ double sm[4];
-    const double rho = sum_partials(rr_prev, np, sm);
-    const double rn = sum_partials(rr_new, np, sm);
-    const double beta = rn / rho;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        scal[3] = beta;
-        scal[4] = rn;
-    }
-    const float be = static_cast<float>(beta);
-    for (long sb = unit_first(); sb < nsites; sb += unit_stride()) {
-        const UnitPos u = unit_pos(sb, nsites);
-        float pv[8], rv[8];
-        unit_decode(p[u.unit], ps[u.su], pv);
-        unit_decode(r[u.unit], rs[u.su], rv);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) pv[j] = rv[j] + be * pv[j];
-        float m;
-        const uint4 code = unit_encode(pv, m);
-        if (u.ok) {
-            p[u.unit] = code;
-            if (u.sub == 0) ps[u.su] = m;
-        }
-    }
-}
 
 // FP16-storage form of k_update_px_flat (x_hat in FP32, p re-encoded).
 __global__ void __launch_bounds__(kThreads)
@@ -473,21 +328,6 @@ struct Vec;
 
 template <>
 struct Vec<SpF64> {
-    static void dot(dim3 g, hipStream_t st, const void *a, const float *, const void *b, const float *, long n5, double *part) {
-        hipLaunchKernelGGL(k_dot_flat<double2>, g, dim3(kThreads), 0, st, static_cast<const double2 *>(a),
-                           static_cast<const double2 *>(b), n5 * 12, part);
-    }
-    static void update_xr(dim3 g, hipStream_t st, void *x, const void *p, const float *, void *r, float *, const void *q,
-                          const float *, long n5, const double *rrp, const double *pq, int np, double *rrn, double *scal) {
-        hipLaunchKernelGGL(k_update_xr_flat<double2>, g, dim3(kThreads), 0, st, static_cast<double2 *>(x),
-                           static_cast<const double2 *>(p), static_cast<double2 *>(r), static_cast<const double2 *>(q), n5 * 12,
-                           rrp, pq, np, rrn, scal);
-    }
-    static void update_p(dim3 g, hipStream_t st, const void *r, const float *, void *p, float *, long n5, const double *rrp,
-                         const double *rrn, int np, double *scal) {
-        hipLaunchKernelGGL(k_update_p_flat<double2>, g, dim3(kThreads), 0, st, static_cast<const double2 *>(r),
-                           static_cast<double2 *>(p), n5 * 12, rrp, rrn, np, scal);
-    }
     static void update_px(dim3 g, hipStream_t st, void *x, void *p, float *, const void *r, const float *, long n5,
                           const double *scal, int so, int sn, int sq, int mode) {
         hipLaunchKernelGGL(k_update_px_flat<double2>, g, dim3(kThreads), 0, st, static_cast<double2 *>(x),
@@ -497,21 +337,6 @@ struct Vec<SpF64> {
 
 template <>
 struct Vec<SpF32> {
-    static void dot(dim3 g, hipStream_t st, const void *a, const float *, const void *b, const float *, long n5, double *part) {
-        hipLaunchKernelGGL(k_dot_flat<float4>, g, dim3(kThreads), 0, st, static_cast<const float4 *>(a),
-                           static_cast<const float4 *>(b), n5 * 6, part);
-    }
-    static void update_xr(dim3 g, hipStream_t st, void *x, const void *p, const float *, void *r, float *, const void *q,
-                          const float *, long n5, const double *rrp, const double *pq, int np, double *rrn, double *scal) {
-        hipLaunchKernelGGL(k_update_xr_flat<float4>, g, dim3(kThreads), 0, st, static_cast<float4 *>(x),
-                           static_cast<const float4 *>(p), static_cast<float4 *>(r), static_cast<const float4 *>(q), n5 * 6, rrp,
-                           pq, np, rrn, scal);
-    }
-    static void update_p(dim3 g, hipStream_t st, const void *r, const float *, void *p, float *, long n5, const double *rrp,
-                         const double *rrn, int np, double *scal) {
-        hipLaunchKernelGGL(k_update_p_flat<float4>, g, dim3(kThreads), 0, st, static_cast<const float4 *>(r),
-                           static_cast<float4 *>(p), n5 * 6, rrp, rrn, np, scal);
-    }
     static void update_px(dim3 g, hipStream_t st, void *x, void *p, float *, const void *r, const float *, long n5,
                           const double *scal, int so, int sn, int sq, int mode) {
         hipLaunchKernelGGL(k_update_px_flat<float4>, g, dim3(kThreads), 0, st, static_cast<float4 *>(x),
@@ -527,21 +352,6 @@ struct Vec<SpF32> {
 
 template <>
 struct Vec<SpF16S> {
-    static void dot(dim3 g, hipStream_t st, const void *a, const float *as, const void *b, const float *bs, long n5,
-                    double *part) {
-        hipLaunchKernelGGL(k_dot_f16, g, dim3(kThreads), 0, st, static_cast<const uint4 *>(a), as,
-                           static_cast<const uint4 *>(b), bs, n5, part);
-    }
-    static void update_xr(dim3 g, hipStream_t st, void *x, const void *p, const float *ps, void *r, float *rs, const void *q,
-                          const float *qs, long n5, const double *rrp, const double *pq, int np, double *rrn, double *scal) {
-        hipLaunchKernelGGL(k_update_xr_f16, g, dim3(kThreads), 0, st, static_cast<float4 *>(x), static_cast<const uint4 *>(p),
-                           ps, static_cast<uint4 *>(r), rs, static_cast<const uint4 *>(q), qs, n5, rrp, pq, np, rrn, scal);
-    }
-    static void update_p(dim3 g, hipStream_t st, const void *r, const float *rs, void *p, float *ps, long n5,
-                         const double *rrp, const double *rrn, int np, double *scal) {
-        hipLaunchKernelGGL(k_update_p_f16, g, dim3(kThreads), 0, st, static_cast<const uint4 *>(r), rs,
-                           static_cast<uint4 *>(p), ps, n5, rrp, rrn, np, scal);
-    }
     static void update_px(dim3 g, hipStream_t st, void *x, void *p, float *ps, const void *r, const float *rs, long n5,
                           const double *scal, int so, int sn, int sq, int mode) {
         hipLaunchKernelGGL(k_update_px_f16, g, dim3(kThreads), 0, st, static_cast<float4 *>(x), static_cast<uint4 *>(p),
@@ -565,11 +375,11 @@ struct CgLayout {
     size_t r, q, t;                       // FP64 vectors
     size_t p;                             // FP64 mode: search direction
     size_t xh;                            // mixed: FP32 x_hat
-    size_t ph, rh, qh, th;                // mixed: sloppy vectors
-    size_t phs, rhs, qhs, ths;            // mixed F16S: scales
+    size_t ph, rh, th;                    // mixed: sloppy vectors
+    size_t phs, rhs, ths;                 // mixed F16S: scales
     size_t ulo;                           // mixed: sloppy links
     size_t u, uh, uhs;                    // operator temporaries (FP64, sloppy, sloppy scales)
-    size_t part;                          // partials: rr[2], pq, true, lo  (5 x kRedBlocks)
+    size_t part;                          // partials: rr[2], true  (3 x kRedBlocks)
     size_t opp;                           // fused-epilogue partials (one per operator block)
     size_t scal;                          // 16 doubles
     size_t total;
@@ -595,12 +405,10 @@ static CgLayout cg_layout(long nsites, long nlinks, int sloppy, int link_fmt, bo
         L.xh = take(n * 96);
         L.ph = take(n * sb);
         L.rh = take(n * sb);
-        L.qh = take(n * sb);
         L.th = take(n * sb);
         if (sloppy == GRID_F16S) {
             L.phs = take(n * 4);
             L.rhs = take(n * 4);
-            L.qhs = take(n * 4);
             L.ths = take(n * 4);
         }
         const size_t rows = link_fmt == GRID_L12 ? 2 : 3;
@@ -614,7 +422,7 @@ static CgLayout cg_layout(long nsites, long nlinks, int sloppy, int link_fmt, bo
             if (sloppy == GRID_F16S) L.uhs = take(n * 4);
         }
     }
-    L.part = take(5 * kRedBlocks * sizeof(double));
+    L.part = take(3 * kRedBlocks * sizeof(double));
     if (nparts > 0) L.opp = take(static_cast<size_t>(nparts) * sizeof(double));
     L.scal = take(16 * sizeof(double));
     L.total = off;
@@ -652,7 +460,7 @@ struct CgRun {
     char *ws;
     hipStream_t st;
     bool op_tmp;         // workspace holds the operator temporaries
-    long nparts;         // room for fused-epilogue partials (0: unfused sequence)
+    long nparts;         // room for the fused epilogues' partials
 };
 
 // Recorded iteration segments of one solve, by starting parity; released with the solve.
@@ -762,36 +570,35 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
                                         ? (static_cast<long>(n) + kThreads - 1) / kThreads
                                         : kRedBlocks);
     const dim3 grid(np), block(kThreads);
+    if (!c.op.apply_fused || c.nparts <= 0) return hipErrorInvalidValue;
     void *r = ws + L.r, *q = ws + L.q, *t = ws + L.t;
     double *part = reinterpret_cast<double *>(ws + L.part);
     double *rr[2] = {part, part + kRedBlocks};
-    double *pq = part + 2 * kRedBlocks, *ptrue = part + 3 * kRedBlocks, *plo = part + 4 * kRedBlocks;
+    double *ptrue = part + 2 * kRedBlocks;
     double *scal = reinterpret_cast<double *>(ws + L.scal);
     // sloppy vectors (FP64 mode: p in FP64 and r doubles as r_hat)
     void *ph = mixed ? ws + L.ph : ws + L.p;
     void *rh = mixed ? ws + L.rh : r;
-    void *qh = mixed ? ws + L.qh : q;
     void *th = mixed ? ws + L.th : t;
     float *phs = c.sloppy == GRID_F16S ? reinterpret_cast<float *>(ws + L.phs) : nullptr;
     float *rhs = c.sloppy == GRID_F16S ? reinterpret_cast<float *>(ws + L.rhs) : nullptr;
-    float *qhs = c.sloppy == GRID_F16S ? reinterpret_cast<float *>(ws + L.qhs) : nullptr;
     float *ths = c.sloppy == GRID_F16S ? reinterpret_cast<float *>(ws + L.ths) : nullptr;
     void *xh = mixed ? ws + L.xh : nullptr;
+    void *xs = mixed ? xh : c.x;   // the vector the iterations update
     const void *ulo = mixed ? ws + L.ulo : c.U;
     const int lo_fmt = mixed ? c.link_fmt : GRID_L18;
     hipError_t err;
-    // fused sequence: device scalars <p,Ap> and rho (by iteration parity), operator partials
-    const bool fused = c.op.apply_fused != nullptr && c.nparts > 0;
+    // device scalars <p,Ap> and rho (by iteration parity); the operator kernels' partials
     constexpr int kSlotPQ = 11, kSlotRho = 12;
-    double *opp = fused ? reinterpret_cast<double *>(ws + L.opp) : nullptr;
-    void *xs = mixed ? xh : c.x;   // the vector the iterations update
+    double *opp = reinterpret_cast<double *>(ws + L.opp);
     auto sum_to = [&](hipStream_t s, const double *pp, long cnt, int slot) -> hipError_t {
         hipLaunchKernelGGL(k_sum_wide, dim3(1), dim3(kWideThreads), 0, s, pp, static_cast<int>(cnt), scal, slot);
         return hipGetLastError();
     };
 
     // |b|
-    Vec<SpF64>::dot(grid, c.st, c.b, nullptr, c.b, nullptr, n, ptrue);
+    hipLaunchKernelGGL(k_dot_flat<double2>, grid, block, 0, c.st, static_cast<const double2 *>(c.b),
+                       static_cast<const double2 *>(c.b), static_cast<long>(n) * 12, ptrue);
     HIPCHK(hipGetLastError());
     const double bnorm = sqrt(read_scalar(c, ptrue, np, scal, 8, &err));
     HIPCHK(err);
@@ -835,7 +642,7 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
         HIPCHK(hipMemcpyAsync(ph, r, static_cast<size_t>(n) * 192, hipMemcpyDeviceToDevice, c.st));
     }
     HIPCHK(hipGetLastError());
-    if (fused) HIPCHK(sum_to(c.st, rr[1], np, kSlotRho + 1));
+    HIPCHK(sum_to(c.st, rr[1], np, kSlotRho + 1));
     double rtrue = sqrt(read_scalar(c, mixed ? ptrue : rr[1], np, scal, 9, &err));
     HIPCHK(err);
     double maxr = rtrue;
@@ -843,43 +650,27 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
     int it = 0;
     const int check = c.check_every < 1 ? 1 : c.check_every;
 
-    // one sloppy step on stream s (q_hat = A_lo p_hat, alpha, x_hat and r_hat), parity P
+    // one sloppy step on stream s, parity P: t = op p with |t|^2 = <p, A p>, then
+    // r -= alpha op^dagger t with |r|^2 (x follows in step_px)
     auto step_xr = [&](hipStream_t s, int P) -> hipError_t {
-        if (fused) {
-            // t = op p with |t|^2 = <p, A p>; r -= alpha op^dagger t with |r|^2 (x waits for step_p)
-            long nb = 0;
-            FuseDev f1;
-            f1.part = opp;
-            HIPCHK(c.op.apply_fused(c.op.ctx, ulo, c.sloppy, lo_fmt, ph, phs, th, ths, 0, kFuseNorm, f1, &nb, s));
-            HIPCHK(sum_to(s, opp, nb, kSlotPQ));
-            FuseDev f2;
-            f2.r = rh;
-            f2.r_scale = rhs;
-            f2.scal = scal;
-            f2.num = kSlotRho + (P ^ 1);
-            f2.den = kSlotPQ;
-            f2.part = opp;
-            HIPCHK(c.op.apply_fused(c.op.ctx, ulo, c.sloppy, lo_fmt, th, ths, rh, rhs, 1, kFuseAxpy, f2, &nb, s));
-            return sum_to(s, opp, nb, kSlotRho + P);
-        }
-        CgRun cs = c;
-        cs.st = s;
-        HIPCHK(apply_op(cs, ulo, c.sloppy, lo_fmt, ph, phs, th, ths, 0));
-        HIPCHK(apply_op(cs, ulo, c.sloppy, lo_fmt, th, ths, qh, qhs, 1));
-        // <p, A p> = <p, op^+ op p> = |op p|^2 = |t|^2: one vector read instead of two
-        Vec<SH>::dot(grid, s, th, ths, th, ths, n, pq);
-        HIPCHK(hipGetLastError());
-        Vec<SH>::update_xr(grid, s, mixed ? xh : c.x, ph, phs, rh, rhs, qh, qhs, n, rr[P ^ 1], pq, np, rr[P], scal);
-        return hipGetLastError();
+        long nb = 0;
+        FuseDev f1;
+        f1.part = opp;
+        HIPCHK(c.op.apply_fused(c.op.ctx, ulo, c.sloppy, lo_fmt, ph, phs, th, ths, 0, kFuseNorm, f1, &nb, s));
+        HIPCHK(sum_to(s, opp, nb, kSlotPQ));
+        FuseDev f2;
+        f2.r = rh;
+        f2.r_scale = rhs;
+        f2.scal = scal;
+        f2.num = kSlotRho + (P ^ 1);
+        f2.den = kSlotPQ;
+        f2.part = opp;
+        HIPCHK(c.op.apply_fused(c.op.ctx, ulo, c.sloppy, lo_fmt, th, ths, rh, rhs, 1, kFuseAxpy, f2, &nb, s));
+        return sum_to(s, opp, nb, kSlotRho + P);
     };
-    // fused: mode 3 = x += alpha p and p = r + beta p; mode 1 / 2 = either half
+    // mode 3: x += alpha p and p = r + beta p; mode 1 / 2: either half
     auto step_px = [&](hipStream_t s, int P, int mode) -> hipError_t {
         Vec<SH>::update_px(grid, s, xs, ph, phs, rh, rhs, n, scal, kSlotRho + (P ^ 1), kSlotRho + P, kSlotPQ, mode);
-        return hipGetLastError();
-    };
-    auto step_p = [&](hipStream_t s, int P) -> hipError_t {
-        if (fused) return step_px(s, P, 3);
-        Vec<SH>::update_p(grid, s, rh, rhs, ph, phs, n, rr[P ^ 1], rr[P], np, scal);
         return hipGetLastError();
     };
     // record the segment of `check` steps starting at parity P0
@@ -890,7 +681,7 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
         hipError_t e = hipSuccess;
         for (int i = 0; i < check && e == hipSuccess; ++i) {
             e = step_xr(seg.cs, (P0 + i) & 1);
-            if (e == hipSuccess && i + 1 < check) e = step_p(seg.cs, (P0 + i) & 1);
+            if (e == hipSuccess && i + 1 < check) e = step_px(seg.cs, (P0 + i) & 1, 3);
         }
         hipGraph_t gr = nullptr;
         const hipError_t e2 = hipStreamEndCapture(seg.cs, &gr);
@@ -911,21 +702,15 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
             HIPCHK(step_xr(c.st, P));
             ++it;
         }
-        bool x_done = false;   // fused: alpha p already added to x
+        bool x_done = false;   // alpha p already added to x
         if (it % check == 0 || it == c.maxiter) {
+            // |r|^2 and <p,Ap> are already summed on the device
             double sc[16];
-            double rn;
-            if (fused) {
-                // |r|^2 is already summed on the device
-                for (int k = 0; k < 16; ++k) sc[k] = NAN;
-                HIPCHK(hipMemcpyAsync(sc, scal, sizeof(sc), hipMemcpyDeviceToHost, c.st));
-                HIPCHK(hipStreamSynchronize(c.st));
-                rn = sqrt(sc[kSlotRho + P]);
-            } else {
-                rn = sqrt(read_scalar(c, rr[P], np, scal, 10, &err, sc));
-                HIPCHK(err);
-            }
-            const double pqh = sc[fused ? kSlotPQ : 1];
+            for (int k = 0; k < 16; ++k) sc[k] = NAN;
+            HIPCHK(hipMemcpyAsync(sc, scal, sizeof(sc), hipMemcpyDeviceToHost, c.st));
+            HIPCHK(hipStreamSynchronize(c.st));
+            const double rn = sqrt(sc[kSlotRho + P]);
+            const double pqh = sc[kSlotPQ];
             if (!isfinite(rn) || !(pqh > 0.0) || !isfinite(pqh)) {
                 *status = GRID_EBREAKDOWN;
                 break;
@@ -934,17 +719,15 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
             const bool small = rn <= c.tol * bnorm;
             if (small || (mixed && rn < c.delta * maxr)) {
                 // reliable update / residual replacement in FP64
-                if (fused) {
-                    HIPCHK(step_px(c.st, P, 1));
-                    x_done = true;
-                }
+                HIPCHK(step_px(c.st, P, 1));
+                x_done = true;
                 if (mixed) {
                     hipLaunchKernelGGL(k_accum_x, grid, block, 0, c.st, static_cast<double2 *>(c.x),
                                        static_cast<float4 *>(xh), static_cast<long>(n) * 6);
                     HIPCHK(hipGetLastError());
                 }
                 HIPCHK(true_residual(true, P));
-                if (fused) HIPCHK(sum_to(c.st, rr[P], np, kSlotRho + P));
+                HIPCHK(sum_to(c.st, rr[P], np, kSlotRho + P));
                 ++stats->reliable_updates;
                 rtrue = sqrt(read_scalar(c, mixed ? ptrue : rr[P], np, scal, 9, &err));
                 HIPCHK(err);
@@ -955,10 +738,7 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
                 maxr = rtrue;
             }
         }
-        if (fused && x_done)
-            HIPCHK(step_px(c.st, P, 2));
-        else
-            HIPCHK(step_p(c.st, P));
+        HIPCHK(step_px(c.st, P, x_done ? 2 : 3));
     }
     if (mixed && !converged) {
         hipLaunchKernelGGL(k_accum_x, grid, block, 0, c.st, static_cast<double2 *>(c.x), static_cast<float4 *>(xh),

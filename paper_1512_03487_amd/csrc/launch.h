@@ -105,22 +105,22 @@ struct CgOp {
     hipError_t (*apply)(const void *ctx, const void *U, int prec, int fmt, const void *in, const float *ins, void *out,
                         float *outs, int dag, hipStream_t st);
     const void *ctx;
-    // Optional: apply with a fused epilogue (kFuseNorm with dag 0, kFuseAxpy with dag 1), setting
-    // *nparts to the number of partial sums written.
+    // Apply with a fused epilogue (kFuseNorm with dag 0, kFuseAxpy with dag 1), setting *nparts
+    // to the number of partial sums written; the conjugate gradient needs it.
     hipError_t (*apply_fused)(const void *ctx, const void *U, int prec, int fmt, const void *in, const float *ins,
                               void *out, float *outs, int dag, int fuse, const FuseDev &fz, long *nparts,
                               hipStream_t st) = nullptr;
 };
 size_t cg_workspace_bytes(const GeomDev &g, int sloppy, int link_fmt);
-size_t cg_workspace_bytes_n(long nsites, long nlinks, int sloppy, int link_fmt, long nparts = 0);
+size_t cg_workspace_bytes_n(long nsites, long nlinks, int sloppy, int link_fmt, long nparts);
 hipError_t run_cg(const void *U, const void *b, void *x, const GeomDev &g, const grid_op &op, const grid_cg_params &p,
                   void *ws, hipStream_t st, grid_cg_stats *stats, int *status);
 // op_tmp: the workspace was sized with the operator temporaries (cg_workspace_bytes) or not
-// (cg_workspace_bytes_n); nparts: room for that many fused-epilogue partials (full-lattice
-// operators, cg_workspace_bytes), else 0 and op.apply_fused unused.
+// (cg_workspace_bytes_n); nparts: the room for fused-epilogue partials it was sized with
+// (fused_parts_max).
 hipError_t run_cg_op(const CgOp &op, const void *U, const void *b, void *x, long nsites, long nlinks,
                      const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status,
-                     bool op_tmp = false, long nparts = 0);
+                     bool op_tmp, long nparts);
 // ||a - b||^2 over n FP64 spinor sites (b may be NULL); part: kRedBlocks + 16 doubles of scratch.
 constexpr int kNormScratch = 1024 + 16;
 hipError_t norm2_diff(const void *a, const void *b, long n, double *part, hipStream_t st, double *result);
