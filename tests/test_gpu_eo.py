@@ -129,6 +129,21 @@ def test_m5inv(gpu, Ls, prec):
     assert rel(host(gm.m5inv(pk, 1.8, 0.05)), eo.m5inv(pr, 1.8, 0.05)) <= TOL[prec]
 
 
+@pytest.mark.parametrize("Ls", [5, 16])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+def test_m5inv_ragged_block(gpu, Ls, prec):
+    """7 4D sites: the last block of 4 sites holds 3 (its staged records and its stores stop there)."""
+    from tests.gpu_util import as_prec, host, rel
+    gm = _gm()
+    dims = (7, 1, 1, 1)
+    U = F.gauge_field(dims, seed=1)
+    psi = F.spinor_field(dims, seed=6, Ls=Ls)
+    _, pk, _, pr = as_prec(U, psi, prec)
+    for dag in (False, True):
+        got = host(gm.m5inv(pk, 1.8, 0.05, dag=dag))
+        assert rel(got, eo.m5inv(pr, 1.8, 0.05, dag)) <= TOL[prec], (Ls, dag)
+
+
 def _kw(kind):
     return dict(mass=0.1) if kind == "wilson" else dict(M5=1.8, mf=0.1)
 
