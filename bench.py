@@ -115,6 +115,30 @@ def time_dhop(sets, steps, warmup, kind="hop", **kw):
     return e0.elapsed_time(e1) * 1e-3 / steps, wall
 
 
+def copy_reference(nbytes, nsets=12, steps=100, warmup=10):
+    """A plain device copy moving `nbytes` per launch (half read, half written), its sources rotated
+    over `nsets` buffers like the headline's inputs: what a launch of this size reaches from HBM."""
+    import torch
+    dev = torch.device("cuda:0")
+    n = int(nbytes // 8)   # float32 elements per side
+    srcs = [torch.ones(n, dtype=torch.float32, device=dev) for _ in range(nsets)]
+    dst = torch.empty(n, dtype=torch.float32, device=dev)
+    for i in range(warmup):
+        dst.copy_(srcs[i % nsets])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps):
+        dst.copy_(srcs[i % nsets])
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / steps
+    moved = 8 * n
+    del srcs, dst
+    return {"bytes_per_launch": moved, "us_per_launch": round(t * 1e6, 2), "gbs": round(moved / t / 1e9, 1),
+            "roofline_frac": round(moved / t / 1e9 / HBM_PEAK_GBS, 4), "buffer_sets": nsets}
+
+
 def mobius_leg(dims, Ls, prec, steps, warmup, b5=1.5, c5=0.5):
     """Moebius operator (grid_mobius): s-local pass + hopping pass; GB/s on the same algorithmic
     bytes as the Shamir operator (read psi and the links once, write out once)."""
@@ -492,6 +516,7 @@ def main():
                                                "gflops": round(FLOPS_HOP * vol / t1 / 1e9, 1),
                                                "alg_gbs": round(bytes_launch / t1 / 1e9, 1)}
         del s1
+        legs["copy_same_bytes_as_hop_16^4_f64"] = copy_reference(bytes_launch)
         legs["hop_32^4_f32"] = leg((32, 32, 32, 32), "f32", "L18", "hop", None, 50, 5)
         legs["hop_32^4_f32_L12"] = leg((32, 32, 32, 32), "f32", "L12", "hop", None, 50, 5)
         legs["hop_32^4_f16s_L12"] = leg((32, 32, 32, 32), "f16s", "L12", "hop", None, 50, 5)
