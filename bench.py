@@ -139,6 +139,40 @@ def copy_reference(nbytes, nsets=12, steps=100, warmup=10):
             "roofline_frac": round(moved / t / 1e9 / HBM_PEAK_GBS, 4), "buffer_sets": nsets}
 
 
+def link_force_leg(dims=(32, 32, 32, 32), steps=20, warmup=3, nsets=2):
+    """The link force of the hopping term (grid_dhop_backward, FP32, su(3)-projected): per site it
+    reads chi and psi (2 x 96 B) and the 4 links (288 B) and writes the 4 force matrices (288 B)."""
+    import torch
+    import paper_1512_03487_amd as gm
+    from paper_1512_03487_amd import fields
+    dev = torch.device("cuda:0")
+    vol = dims[0] * dims[1] * dims[2] * dims[3]
+    U = torch.from_numpy(fields.gauge_field(dims, seed=1, kind="haar")).to(dev).to(torch.complex64)
+    g = torch.Generator(device=dev).manual_seed(3)
+    shape = (dims[3], dims[2], dims[1], dims[0], 4, 3)
+    sets = []
+    for _ in range(nsets):
+        mk = lambda: torch.complex(torch.randn(shape, generator=g, device=dev), torch.randn(shape, generator=g, device=dev))
+        sets.append((U.clone(), mk(), mk()))
+    for i in range(warmup):
+        Uk, psi, chi = sets[i % nsets]
+        gm.dhop_backward(Uk, psi, chi, want_psi=False, force=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps):
+        Uk, psi, chi = sets[i % nsets]
+        gm.dhop_backward(Uk, psi, chi, want_psi=False, force=True)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / steps
+    nbytes = (2 * 96 + 288 + 288) * vol
+    del sets, U
+    return {"lattice": list(dims), "prec": "f32", "us_per_launch": round(t * 1e6, 2),
+            "alg_bytes_per_launch": nbytes, "alg_gbs": round(nbytes / t / 1e9, 1),
+            "roofline_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4), "buffer_sets": nsets}
+
+
 def mobius_leg(dims, Ls, prec, steps, warmup, b5=1.5, c5=0.5):
     """Moebius operator (grid_mobius): s-local pass + hopping pass; GB/s on the same algorithmic
     bytes as the Shamir operator (read psi and the links once, write out once)."""
@@ -522,6 +556,7 @@ def main():
         legs["hop_32^4_f16s_L12"] = leg((32, 32, 32, 32), "f16s", "L12", "hop", None, 50, 5)
         legs["dwf_24^4x12_f32"] = leg((24, 24, 24, 24), "f32", "L18", "dwf", 12, 20, 3)
         legs["dwf_24^4x12_f16s_L12"] = leg((24, 24, 24, 24), "f16s", "L12", "dwf", 12, 20, 3)
+        legs["link_force_32^4_f32"] = link_force_leg()
         legs["mobius_16^4x16_f32"] = mobius_leg((16, 16, 16, 16), 16, "f32", 50, 5)
         legs["mobius_16^4x16_f64"] = mobius_leg((16, 16, 16, 16), 16, "f64", 20, 3)
         torch.cuda.empty_cache()

@@ -7,8 +7,8 @@
 // EF = -1 for H and +1 for H^dagger. Because (1 + e gamma) v = [h; e A^dagger h] with
 // h = v_up + e A v_dn, a spin trace of [(1 + e gamma) v] w^dagger equals the two-spin sum
 // h(v) h(w)^dagger of the projected half-spinors (with the same e), so each term is a sum of two
-// 3x3 outer products of half-spinors. One thread per (4D site, mu), mu fastest; the fifth
-// coordinate is summed inside the thread; no atomics, so results are bitwise reproducible.
+// 3x3 outer products of half-spinors. One thread per (4D site, mu), one mu per wavefront; the
+// fifth coordinate is summed inside the thread; no atomics, so results are bitwise reproducible.
 #include "device.h"
 #include "launch.h"
 
@@ -48,11 +48,14 @@ __global__ void __launch_bounds__(256)
 k_link_grad(const void *__restrict__ U, const void *__restrict__ chi, const void *__restrict__ psi, void *__restrict__ Gout,
             GeomDev g, double coef, int force_mode) {
     using C = typename SP::C;
+    // A block covers 64 consecutive sites; wavefront mu computes their direction-mu links, so
+    // the direction is uniform across a wavefront (no divergent switch) and the four wavefronts
+    // reading chi(x) and psi(x) share them through the CU's L1.
     const int lb = xcd_block(blockIdx.x, gridDim.x);
-    const int t = lb * 256 + threadIdx.x;
-    if (t >= g.vol * 4) return;
-    const int mu = t & 3;
-    const int x4 = t >> 2;
+    const int mu = threadIdx.x >> 6;
+    const int x4 = lb * 64 + (threadIdx.x & 63);
+    if (x4 >= g.vol) return;
+    const int t = x4 * 4 + mu;   // link index: site-major, direction fastest
     int nb[8];
     neighbours(g, x4, nb);
     Cx<C> G[3][3];
@@ -109,7 +112,7 @@ k_link_grad(const void *__restrict__ U, const void *__restrict__ chi, const void
 
 hipError_t launch_link_grad(const LinkGradArgs &a) {
     if (a.g.vol == 0) return hipSuccess;
-    const int blocks = (a.g.vol * 4 + 255) / 256;
+    const int blocks = (a.g.vol + 63) / 64;
     const dim3 grid(blocks), block(256);
     if (a.prec == GRID_F64) {
         if (a.dag)
