@@ -14,14 +14,22 @@
 
 namespace gridmi {
 
+// Records come through the wavefront's LDS slot (coalesced chunk loads, then each lane reads its
+// own record back); the four records of a step are all requested before the first is staged.
 template <int MU, int EF, class SP, typename C>
-__device__ __forceinline__ void grad_mu(const void *chi, const void *psi, int x4, int xp, int Ls, Cx<C> G[3][3]) {
+__device__ __forceinline__ void grad_mu(const void *chi, const void *psi, int x4, int xp, int Ls, chunk_t *lds,
+                                        Cx<C> G[3][3]) {
     Cx<C> p[4][3], hg[2][3], hp[2][3];
     for (int s = 0; s < Ls; ++s) {
+        Fetch<SP> f0, f1, f2, f3;
+        fetch<SP>(chi, nullptr, x4 * Ls + s, f0);
+        fetch<SP>(psi, nullptr, xp * Ls + s, f1);
+        fetch<SP>(psi, nullptr, x4 * Ls + s, f2);
+        fetch<SP>(chi, nullptr, xp * Ls + s, f3);
         // [(1 + EF gamma) g(x)] psi(x+mu)^dagger
-        SP::load(chi, nullptr, static_cast<size_t>(x4) * Ls + s, p);
+        stage<SP>(f0, lds, p);
         project<MU, EF>(p, hg);
-        SP::load(psi, nullptr, static_cast<size_t>(xp) * Ls + s, p);
+        stage<SP>(f1, lds, p);
         project<MU, EF>(p, hp);
 #pragma unroll
         for (int k = 0; k < 2; ++k)
@@ -30,9 +38,9 @@ __device__ __forceinline__ void grad_mu(const void *chi, const void *psi, int x4
 #pragma unroll
                 for (int b = 0; b < 3; ++b) G[a][b] = cmac(G[a][b], hg[k][a], cconj(hp[k][b]));
         // psi(x) [(1 - EF gamma) g(x+mu)]^dagger
-        SP::load(psi, nullptr, static_cast<size_t>(x4) * Ls + s, p);
+        stage<SP>(f2, lds, p);
         project<MU, -EF>(p, hp);
-        SP::load(chi, nullptr, static_cast<size_t>(xp) * Ls + s, p);
+        stage<SP>(f3, lds, p);
         project<MU, -EF>(p, hg);
 #pragma unroll
         for (int k = 0; k < 2; ++k)
@@ -48,14 +56,17 @@ __global__ void __launch_bounds__(256)
 k_link_grad(const void *__restrict__ U, const void *__restrict__ chi, const void *__restrict__ psi, void *__restrict__ Gout,
             GeomDev g, double coef, int force_mode) {
     using C = typename SP::C;
+    __shared__ chunk_t sm[4][64 * (SP::kChunks + 1)];
+    chunk_t *lds = sm[threadIdx.x >> 6];
     // A block covers 64 consecutive sites; wavefront mu computes their direction-mu links, so
     // the direction is uniform across a wavefront (no divergent switch) and the four wavefronts
     // reading chi(x) and psi(x) share them through the CU's L1.
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int mu = threadIdx.x >> 6;
-    const int x4 = lb * 64 + (threadIdx.x & 63);
-    if (x4 >= g.vol) return;
-    const int t = x4 * 4 + mu;   // link index: site-major, direction fastest
+    const int x4r = lb * 64 + (threadIdx.x & 63);
+    const bool live = x4r < g.vol;
+    const int x4 = live ? x4r : g.vol - 1;   // idle lanes take part in the wave's gathers
+    const int t = x4 * 4 + mu;               // link index: site-major, direction fastest
     int nb[8];
     neighbours(g, x4, nb);
     Cx<C> G[3][3];
@@ -63,10 +74,10 @@ k_link_grad(const void *__restrict__ U, const void *__restrict__ chi, const void
     for (int k = 0; k < 9; ++k) G[k / 3][k % 3] = {C(0), C(0)};
     constexpr int EF = DAG ? +1 : -1;
     switch (mu) {
-        case 0: grad_mu<0, EF, SP, C>(chi, psi, x4, nb[0], g.Ls, G); break;
-        case 1: grad_mu<1, EF, SP, C>(chi, psi, x4, nb[2], g.Ls, G); break;
-        case 2: grad_mu<2, EF, SP, C>(chi, psi, x4, nb[4], g.Ls, G); break;
-        default: grad_mu<3, EF, SP, C>(chi, psi, x4, nb[6], g.Ls, G); break;
+        case 0: grad_mu<0, EF, SP, C>(chi, psi, x4, nb[0], g.Ls, lds, G); break;
+        case 1: grad_mu<1, EF, SP, C>(chi, psi, x4, nb[2], g.Ls, lds, G); break;
+        case 2: grad_mu<2, EF, SP, C>(chi, psi, x4, nb[4], g.Ls, lds, G); break;
+        default: grad_mu<3, EF, SP, C>(chi, psi, x4, nb[6], g.Ls, lds, G); break;
     }
     const C c = static_cast<C>(coef);
 #pragma unroll
@@ -98,6 +109,7 @@ k_link_grad(const void *__restrict__ U, const void *__restrict__ chi, const void
                 G[a][b] = f;
             }
     }
+    if (!live) return;
     if constexpr (sizeof(C) == 8) {
         double2 *q = reinterpret_cast<double2 *>(Gout) + static_cast<size_t>(t) * 9;
 #pragma unroll

@@ -602,6 +602,79 @@ __device__ __forceinline__ void neighbours(const GeomDev &g, int x4, int nb[8]) 
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// Wavefront-level LDS staging
+// ------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 16-byte chunk as a native vector type.
+typedef unsigned int chunk_t __attribute__((ext_vector_type(4)));
+
+// Coalesced wavefront gather of spinor records through LDS, in two phases so that the global
+// loads of the next gather can be in flight while the current direction computes:
+//   fetch: lane l loads 16-byte chunk c = k*64 + l of the 64 records the wave needs (record
+//          c / chunks, the record index of that lane obtained by a cross-lane shuffle), so
+//          consecutive lanes read consecutive addresses;
+//   stage: the chunks go to padded LDS slots and each lane reads its own record back.
+// All 64 lanes must take part with a valid record index.
+
+template <class SP>
+struct Fetch {
+    chunk_t w[SP::kChunks];
+    float s;
+};
+
+template <class SP>
+__device__ __forceinline__ void fetch(const void *__restrict__ base, const float *__restrict__ scale, int rec,
+                                      Fetch<SP> &f) {
+    constexpr int CH = SP::kChunks;
+    const int lane = threadIdx.x & 63;
+    const chunk_t *src = reinterpret_cast<const chunk_t *>(base);
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const int c = k * 64 + lane;
+        const int r = c / CH, j = c - (c / CH) * CH;
+        const int n = __shfl(rec, r, 64);
+        f.w[k] = src[static_cast<size_t>(n) * CH + j];
+    }
+    f.s = SP::kScaled ? scale[rec] : 1.0f;
+}
+
+template <class SP>
+__device__ __forceinline__ void stage(const Fetch<SP> &f, chunk_t *lds, Cx<typename SP::C> p[4][3]) {
+    constexpr int CH = SP::kChunks;
+    constexpr int PITCH = CH + 1;   // padded record pitch (16-byte units) against bank conflicts
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const int c = k * 64 + lane;
+        const int r = c / CH, j = c - (c / CH) * CH;
+        lds[r * PITCH + j] = f.w[k];
+    }
+    wave_sync();
+    uint4 w[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const chunk_t v = lds[lane * PITCH + k];
+        w[k] = make_uint4(v.x, v.y, v.z, v.w);
+    }
+    wave_sync();
+    SP::unpack(w, f.s, p);
+}
+
+template <class SP>
+__device__ __forceinline__ void gather(const void *__restrict__ base, const float *__restrict__ scale, int rec, chunk_t *lds,
+                                       Cx<typename SP::C> p[4][3]) {
+    Fetch<SP> f;
+    fetch<SP>(base, scale, rec, f);
+    stage<SP>(f, lds, p);
+}
+
 // Hardware dispatches workgroup b to XCD b % 8. Renumber so that each XCD receives one
 // contiguous range of logical blocks: neighbouring lattice sites then share an L2.
 __device__ __forceinline__ int xcd_block(int b, int nblocks) {

@@ -39,15 +39,6 @@ constexpr int kSites = 32;           // 5D sites per block
 constexpr int kDirs = 8;             // wavefronts per block, one per hopping direction
 constexpr int kBlock = kDirs * 64;   // threads per block
 
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// 16-byte chunk as a native vector type.
-typedef unsigned int chunk_t __attribute__((ext_vector_type(4)));
-
 // Division by a launch-invariant divisor d >= 1 for 0 <= n < 2^31: q = (umulhi(n, m) + n) >> l with
 // l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1 (Granlund and Montgomery's division by
 // invariant integers; n + umulhi(n, m) < 2^32 because n < 2^31).
@@ -437,66 +428,6 @@ __device__ __forceinline__ void neighbours3(const GeomDev &g, int col, int nb[6]
     }
 }
 
-
-// Coalesced wavefront gather of spinor records through LDS, in two phases so that the global
-// loads of the next gather can be in flight while the current direction computes:
-//   fetch: lane l loads 16-byte chunk c = k*64 + l of the 64 records the wave needs (record
-//          c / chunks, the record index of that lane obtained by a cross-lane shuffle), so
-//          consecutive lanes read consecutive addresses;
-//   stage: the chunks go to padded LDS slots and each lane reads its own record back.
-// All 64 lanes must take part with a valid record index.
-
-template <class SP>
-struct Fetch {
-    chunk_t w[SP::kChunks];
-    float s;
-};
-
-template <class SP>
-__device__ __forceinline__ void fetch(const void *__restrict__ base, const float *__restrict__ scale, int rec,
-                                      Fetch<SP> &f) {
-    constexpr int CH = SP::kChunks;
-    const int lane = threadIdx.x & 63;
-    const chunk_t *src = reinterpret_cast<const chunk_t *>(base);
-#pragma unroll
-    for (int k = 0; k < CH; ++k) {
-        const int c = k * 64 + lane;
-        const int r = c / CH, j = c - (c / CH) * CH;
-        const int n = __shfl(rec, r, 64);
-        f.w[k] = src[static_cast<size_t>(n) * CH + j];
-    }
-    f.s = SP::kScaled ? scale[rec] : 1.0f;
-}
-
-template <class SP>
-__device__ __forceinline__ void stage(const Fetch<SP> &f, chunk_t *lds, Cx<typename SP::C> p[4][3]) {
-    constexpr int CH = SP::kChunks;
-    constexpr int PITCH = CH + 1;   // padded record pitch (16-byte units) against bank conflicts
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int k = 0; k < CH; ++k) {
-        const int c = k * 64 + lane;
-        const int r = c / CH, j = c - (c / CH) * CH;
-        lds[r * PITCH + j] = f.w[k];
-    }
-    wave_sync();
-    uint4 w[CH];
-#pragma unroll
-    for (int k = 0; k < CH; ++k) {
-        const chunk_t v = lds[lane * PITCH + k];
-        w[k] = make_uint4(v.x, v.y, v.z, v.w);
-    }
-    wave_sync();
-    SP::unpack(w, f.s, p);
-}
-
-template <class SP>
-__device__ __forceinline__ void gather(const void *__restrict__ base, const float *__restrict__ scale, int rec, chunk_t *lds,
-                                       Cx<typename SP::C> p[4][3]) {
-    Fetch<SP> f;
-    fetch<SP>(base, scale, rec, f);
-    stage<SP>(f, lds, p);
-}
 
 // Pin the accumulator in registers at this point of the program. The only use of the result is
 // the store of live lanes, so without this the compiler sinks all arithmetic below the last
