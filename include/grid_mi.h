@@ -348,6 +348,8 @@ typedef struct {
     double tol;         /* target |b - D x| / |b|                                               */
     int graph;          /* nonzero: the coarse solve of a cycle is recorded once per grid_mg_solve
                            into a HIP graph and replayed (same kernels, same results)             */
+    int setup_prec;     /* grid_mg_basis: precision of the setup CG's iterations, GRID_F64 (the
+                           value of a zeroed struct) or GRID_F32 / GRID_F16S (mixed, as grid_cg) */
 } grid_mg_params;
 
 /*

@@ -171,6 +171,7 @@ int check_mg(const GeomDev &g, const grid_op *op, const grid_mg_params *p) {
         return fail(GRID_EINVAL, "iteration counts must be >= 0");
     if (p->restart < 1 || p->restart > 64) return fail(GRID_EINVAL, "restart = %d outside 1..64", p->restart);
     if (!(p->tol > 0.0) || !(p->coarse_tol >= 0.0)) return fail(GRID_EINVAL, "need tol > 0 and coarse_tol >= 0");
+    TRY(check_prec(p->setup_prec));
     return GRID_OK;
 }
 

@@ -547,7 +547,7 @@ struct MgLayout {
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
-MgLayout mg_layout(const MgDims &m, int restart) {
+MgLayout mg_layout(const MgDims &m, int restart, int setup_prec) {
     MgLayout L;
     L.fv = al256(static_cast<size_t>(m.vol) * 192);
     L.cv = al256(static_cast<size_t>(m.vc) * m.N * 16);
@@ -575,7 +575,7 @@ MgLayout mg_layout(const MgDims &m, int restart) {
     g.Ls = 1;
     g.vol = m.vol;
     g.n5 = m.vol;
-    o += al256(cg_workspace_bytes(g, GRID_F64, GRID_L18));
+    o += al256(cg_workspace_bytes(g, setup_prec, GRID_L18));
     L.setup_end = o;
     L.total = L.solve_end > L.setup_end ? L.solve_end : L.setup_end;
     return L;
@@ -673,7 +673,7 @@ static bool mg_dims(const GeomDev &g, const grid_mg_params &p, MgDims *m) {
 size_t mg_workspace_bytes(const GeomDev &g, const grid_mg_params &p) {
     MgDims m;
     if (!mg_dims(g, p, &m)) return 0;
-    return mg_layout(m, p.restart).total;
+    return mg_layout(m, p.restart, p.setup_prec).total;
 }
 
 static CoarseGeo coarse_geo(const MgDims &m) {
@@ -722,7 +722,7 @@ hipError_t run_mg_basis(const void *U, void *vecs, const GeomDev &g, double mass
                         hipStream_t st) {
     MgDims m;
     mg_dims(g, p, &m);
-    const MgLayout L = mg_layout(m, p.restart);
+    const MgLayout L = mg_layout(m, p.restart, p.setup_prec);
     char *w = static_cast<char *>(ws);
     double2 *V = static_cast<double2 *>(vecs);
     const long nf = static_cast<long>(m.vol) * 12;
@@ -733,7 +733,7 @@ hipError_t run_mg_basis(const void *U, void *vecs, const GeomDev &g, double mass
         grid_cg_params cp = {};
         cp.tol = 1e-300;
         cp.maxiter = p.setup_iters;
-        cp.sloppy_prec = GRID_F64;
+        cp.sloppy_prec = p.setup_prec;   // the near-null vectors need no FP64 iterations
         cp.link_fmt = GRID_L18;
         cp.delta = 0.1;
         cp.check_every = p.setup_iters;
@@ -765,7 +765,7 @@ hipError_t run_mg_coarse_op(const void *U, const void *vecs, void *A, const Geom
                             const grid_mg_params &p, void *ws, hipStream_t st) {
     MgDims m;
     mg_dims(g, p, &m);
-    const MgLayout L = mg_layout(m, p.restart);
+    const MgLayout L = mg_layout(m, p.restart, p.setup_prec);
     double2 *H = reinterpret_cast<double2 *>(static_cast<char *>(ws) + L.H);
     const double2 *V = static_cast<const double2 *>(vecs);
     const long nf = static_cast<long>(m.vol) * 12;
@@ -879,7 +879,7 @@ hipError_t run_mg_solve(const void *U, const void *vecs, const void *A, const vo
     c.mass = mass;
     c.p = &p;
     c.ws = static_cast<char *>(ws);
-    c.L = mg_layout(c.m, p.restart);
+    c.L = mg_layout(c.m, p.restart, p.setup_prec);
     c.st = st;
     c.nf = static_cast<long>(g.vol) * 12;
     c.ncv = static_cast<long>(c.m.vc) * c.m.N;

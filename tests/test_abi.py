@@ -229,6 +229,7 @@ def mg_params(**kw):
     p.setup_rounds, p.setup_iters = 1, 4
     p.coarse_iters, p.coarse_tol, p.smooth_iters = 10, 0.1, 1
     p.restart, p.maxiter, p.tol = kw.get("restart", 4), 10, 1e-8
+    p.setup_prec = kw.get("setup_prec", _lib.GRID_F64)
     return p
 
 
@@ -237,8 +238,12 @@ def test_multigrid_validation(lib):
     ok = mg_params()
     assert lib.grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(ok)) > 0
     for bad in (mg_params(block=(3, 2, 2, 2)), mg_params(block=(0, 2, 2, 2)), mg_params(nvec=0), mg_params(nvec=33),
-                mg_params(restart=0), mg_params(restart=65), mg_params(block=(1, 1, 1, 1), nvec=7)):
+                mg_params(restart=0), mg_params(restart=65), mg_params(block=(1, 1, 1, 1), nvec=7),
+                mg_params(setup_prec=3), mg_params(setup_prec=-1)):
         assert lib.grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(bad)) == 0
+    # a mixed-precision setup needs the sloppy vectors and links besides
+    assert (lib.grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(mg_params(setup_prec=_lib.GRID_F32)))
+            >= lib.grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(ok)))
     op = _lib.GridOp(_lib.GRID_WILSON, 0, 0.1, 1.8, 0.01, 1.0, 0.0)
     dwf = _lib.GridOp(_lib.GRID_DWF, 0, 0.1, 1.8, 0.01, 1.0, 0.0)
     need = lib.grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(ok))
@@ -255,3 +260,15 @@ def test_multigrid_validation(lib):
     assert lib.grid_coarse_stencil(P(A), P(A + 2**30), P(A + 2**30), cd, 8, 0, None) == _lib.GRID_EINVAL
     cd0 = (ctypes.c_int * 4)(2, 0, 2, 2)
     assert lib.grid_coarse_stencil(P(A), P(A + 2**30), P(A + 2**31), cd0, 8, 0, None) == _lib.GRID_ESHAPE
+
+
+def test_parameter_builders():
+    """The Python parameter builders fill their ctypes structs without touching a GPU."""
+    from paper_1512_03487_amd import api
+    p = api.cg_params(tol=1e-9, sloppy="f16s", link_fmt="L12", graph=True)
+    assert (p.sloppy_prec, p.link_fmt, p.graph) == (_lib.GRID_F16S, _lib.GRID_L12, 1)
+    q = api.mg_params(block=(4, 4, 2, 2), nvec=8, setup_prec="f32")
+    assert (tuple(q.block), q.nvec, q.setup_prec) == ((4, 4, 2, 2), 8, _lib.GRID_F32)
+    assert api.mg_params().setup_prec == _lib.GRID_F64
+    m = api.md_params(5.5, integrator="force_gradient", n_inner=1)
+    assert m.integrator == _lib.GRID_FORCE_GRADIENT

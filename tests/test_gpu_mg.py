@@ -79,6 +79,31 @@ def test_near_null_setup(gpu):
     assert _rel(host(vd), ref) <= 1e-9
 
 
+@pytest.mark.parametrize("setup_prec", ["f32", "f16s"])
+def test_mixed_precision_setup(gpu, setup_prec):
+    """Setup CG in mixed precision: the near-null vectors stay close to the FP64 setup's (the
+    sloppy iterations perturb them at the sloppy precision's rounding level), and the basis still
+    gives a converged multigrid solve in about as many outer iterations."""
+    from tests.gpu_util import dev, host
+    gm = _gm()
+    dims, block, nvec, m = (8, 8, 8, 8), (4, 4, 4, 4), 8, 0.05
+    U = F.gauge_field(dims, seed=1, kind="weak")
+    b = F.spinor_field(dims, seed=3)
+    Ud = dev(U)
+    out, its = {}, {}
+    for prec in ("f64", setup_prec):
+        qd = dev(_vecs(dims, nvec))
+        gm.mg_basis(Ud, qd, m, block=block, setup_rounds=3, setup_iters=10, setup_prec=prec)
+        out[prec] = host(qd)
+        Ad = gm.mg_coarse_op(Ud, qd, m, block=block)
+        x, st = gm.mg_solve(Ud, qd, Ad, dev(b), m, block=block, restart=8, coarse_iters=50, coarse_tol=0.05)
+        res = float(np.linalg.norm(b - O.wilson(U, host(x), m)) / np.linalg.norm(b))
+        assert st["converged"] and res <= 1.05e-10, (prec, res)
+        its[prec] = st["iterations"]
+    assert _rel(out[setup_prec], out["f64"]) <= (1e-4 if setup_prec == "f32" else 5e-2), _rel(out[setup_prec], out["f64"])
+    assert abs(its[setup_prec] - its["f64"]) <= 2, its
+
+
 @pytest.mark.parametrize("dims,block,nvec,kind", [((8, 4, 2, 4), (2, 2, 2, 2), 3, "haar"),
                                                   ((4, 6, 4, 2), (1, 3, 2, 2), 4, "weak"),
                                                   ((4, 4, 4, 4), (4, 2, 1, 2), 2, "haar")])
