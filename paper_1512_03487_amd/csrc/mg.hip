@@ -426,6 +426,28 @@ k_zaxpy2(double2 *__restrict__ y, const double2 *__restrict__ x, double2 a, doub
     }
 }
 
+// The same two updates with the coefficient taken from device scalars sc (no read-back):
+// mode 0: y += -sc[0] x, y2 += -sc[0] x2 (Gram-Schmidt, sc[0] = <x, y>);
+// mode 1: alpha = sc[0] / Re sc[1]; y += alpha x, y2 += -alpha x2 (minimal residual,
+//         sc[0] = <t, s>, sc[1] = <t, t>).
+__global__ void __launch_bounds__(kMgThreads)
+k_zaxpy2_dev(double2 *__restrict__ y, const double2 *__restrict__ x, double2 *__restrict__ y2,
+             const double2 *__restrict__ x2, const double2 *__restrict__ sc, int mode, long n) {
+    double2 a, a2;
+    if (mode == 0) {
+        a = {-sc[0].x, -sc[0].y};
+        a2 = a;
+    } else {
+        a = {sc[0].x / sc[1].x, sc[0].y / sc[1].x};
+        a2 = {-a.x, -a.y};
+    }
+    for (long i = static_cast<long>(blockIdx.x) * kMgThreads + threadIdx.x; i < n;
+         i += static_cast<long>(gridDim.x) * kMgThreads) {
+        y[i] = add2(y[i], cmul2(a, x[i]));
+        y2[i] = add2(y2[i], cmul2(a2, x2[i]));
+    }
+}
+
 // out = a - b
 __global__ void __launch_bounds__(kMgThreads)
 k_zsub(double2 *__restrict__ out, const double2 *__restrict__ a, const double2 *__restrict__ b, long n) {
@@ -643,6 +665,28 @@ struct MgCtx {
         MGCHK(hipMemcpyAsync(res, scal(), 2 * sizeof(double2), hipMemcpyDeviceToHost, st));
         return hipStreamSynchronize(st);
     }
+    // <a, b> (and <a2, b2>) into the device scalars only, for a following axpy2_dev
+    hipError_t zdot_dev(const double2 *a, const double2 *b, long n) const {
+        const int nb = vec_blocks(n);
+        hipLaunchKernelGGL(k_zdot_part, dim3(nb), dim3(kMgThreads), 0, st, a, b, n, part());
+        MGCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_zsum, dim3(1), dim3(kMgThreads), 0, st, part(), nb, scal());
+        return hipGetLastError();
+    }
+    hipError_t zdot2_dev(const double2 *a1, const double2 *b1, const double2 *a2, const double2 *b2, long n) const {
+        const int nb = vec_blocks(n);
+        hipLaunchKernelGGL(k_zdot2_part, dim3(nb), dim3(kMgThreads), 0, st, a1, b1, a2, b2, n, part());
+        MGCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_zsum, dim3(1), dim3(kMgThreads), 0, st, part(), nb, scal());
+        MGCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_zsum, dim3(1), dim3(kMgThreads), 0, st, part() + kMgParts, nb, scal() + 1);
+        return hipGetLastError();
+    }
+    hipError_t axpy2_dev(double2 *y, const double2 *x, double2 *y2, const double2 *x2, int mode, long n) const {
+        hipLaunchKernelGGL(k_zaxpy2_dev, dim3(vec_blocks(n)), dim3(kMgThreads), 0, st, y, x, y2, x2,
+                           static_cast<const double2 *>(scal()), mode, n);
+        return hipGetLastError();
+    }
     hipError_t axpy2(double2 *y, const double2 *x, double2 a, double2 *y2, const double2 *x2, double2 a2, long n) const {
         hipLaunchKernelGGL(k_zaxpy2, dim3(vec_blocks(n)), dim3(kMgThreads), 0, st, y, x, a, y2, x2, a2, n);
         return hipGetLastError();
@@ -847,13 +891,11 @@ static hipError_t mg_cycle(const MgCtx &c, const void *U, const double2 *V, cons
         double2 *s = c.f(c.L.s), *t = c.f(c.L.t);
         MGCHK(c.D(U, z, t));
         MGCHK(c.sub(s, r, t, nf));
+        // alpha = <t, s> / |t|^2 stays on the device: z += alpha s, s -= alpha t
         for (int it = 0; it < c.p->smooth_iters; ++it) {
             MGCHK(c.D(U, s, t));
-            double2 d2[2];
-            MGCHK(c.zdot2(t, s, t, t, nf, d2));
-            const double2 ts = d2[0], tt = d2[1];
-            const double2 alpha = {ts.x / tt.x, ts.y / tt.x};
-            MGCHK(c.axpy2(z, s, alpha, s, t, {-alpha.x, -alpha.y}, nf));
+            MGCHK(c.zdot2_dev(t, s, t, t, nf));
+            MGCHK(c.axpy2_dev(z, s, s, t, 1, nf));
         }
     }
     return hipSuccess;
@@ -909,10 +951,10 @@ hipError_t run_mg_solve(const void *U, const void *vecs, const void *A, const vo
         double2 *zk = Z(k), *wk = W(k);
         MGCHK(mg_cycle(c, U, V, A, r, zk));
         MGCHK(c.D(U, zk, wk));
+        // modified Gram-Schmidt, beta_j = <w_j, w> on the device: w -= beta_j w_j, z -= beta_j z_j
         for (int j = 0; j < k; ++j) {
-            double2 beta;
-            MGCHK(c.zdot(W(j), wk, nf, &beta));
-            MGCHK(c.axpy2(wk, W(j), {-beta.x, -beta.y}, zk, Z(j), {-beta.x, -beta.y}, nf));
+            MGCHK(c.zdot_dev(W(j), wk, nf));
+            MGCHK(c.axpy2_dev(wk, W(j), zk, Z(j), 0, nf));
         }
         // |w|^2 and <w, r> in one pass; w, z scaled to |w| = 1, alpha = <w, r> / |w|
         double2 d2[2];
