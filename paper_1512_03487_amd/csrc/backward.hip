@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(256)
 k_link_grad(const void *__restrict__ U, const void *__restrict__ chi, const void *__restrict__ psi, void *__restrict__ Gout,
             GeomDev g, double coef, int force_mode) {
     using C = typename SP::C;
-    __shared__ chunk_t sm[4][64 * (SP::kChunks + 1)];
+    __shared__ chunk_t sm[4][64 * stage_pitch<SP>()];
     chunk_t *lds = sm[threadIdx.x >> 6];
     // A block covers 64 consecutive sites; wavefront mu computes their direction-mu links, so
     // the direction is uniform across a wavefront (no divergent switch) and the four wavefronts

@@ -623,6 +623,11 @@ typedef unsigned int chunk_t __attribute__((ext_vector_type(4)));
 //   stage: the chunks go to padded LDS slots and each lane reads its own record back.
 // All 64 lanes must take part with a valid record index.
 
+// Padded record pitch of the staging area (16-byte units; the pad spreads records over the LDS
+// banks): a wavefront's area is 64 * stage_pitch<SP>() chunks.
+template <class SP>
+__host__ __device__ constexpr int stage_pitch() { return SP::kChunks + 1; }
+
 template <class SP>
 struct Fetch {
     chunk_t w[SP::kChunks];
@@ -648,7 +653,7 @@ __device__ __forceinline__ void fetch(const void *__restrict__ base, const float
 template <class SP>
 __device__ __forceinline__ void stage(const Fetch<SP> &f, chunk_t *lds, Cx<typename SP::C> p[4][3]) {
     constexpr int CH = SP::kChunks;
-    constexpr int PITCH = CH + 1;   // padded record pitch (16-byte units) against bank conflicts
+    constexpr int PITCH = stage_pitch<SP>();
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int k = 0; k < CH; ++k) {

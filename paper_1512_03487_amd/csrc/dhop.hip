@@ -459,7 +459,7 @@ __global__ void __launch_bounds__(256)
 k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const float *__restrict__ psi_scale,
        void *out, float *out_scale, GeomDev g, int T, double diag, double mf, FuseDev fz) {
     using C = typename SP::C;
-    __shared__ chunk_t sm[kWaves][64 * (SP::kChunks + 1)];
+    __shared__ chunk_t sm[kWaves][64 * stage_pitch<SP>()];
     chunk_t *lds = sm[threadIdx.x >> 6];
 
     const int Ls = g.Ls;
@@ -608,7 +608,7 @@ k_dhop_walk_cb(const void *__restrict__ U, const void *__restrict__ psi, const f
                const void *__restrict__ yv, const float *__restrict__ y_scale, void *out, float *out_scale, GeomDev g,
                int T, int cbp, double diag, double mf, double beta, double cs, FuseDev fz) {
     using C = typename SP::C;
-    __shared__ chunk_t sm[kWaves][64 * (SP::kChunks + 1)];
+    __shared__ chunk_t sm[kWaves][64 * stage_pitch<SP>()];
     chunk_t *lds = sm[threadIdx.x >> 6];
 
     const int Ls = g.Ls, Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
