@@ -173,6 +173,44 @@ def link_force_leg(dims=(32, 32, 32, 32), steps=20, warmup=3, nsets=2):
             "roofline_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4), "buffer_sets": nsets}
 
 
+def cb_leg(dims, Ls, prec, fmt, steps=50, warmup=5, nsets=4):
+    """The even-odd hop with the domain-wall diagonal, out (parity 0) = M5 y - H psi / 4, on one
+    checkerboard: per output 5D site it reads psi (the other parity) and y once, writes out once,
+    and reads 8 links per 4D site (one parity's outputs touch every link)."""
+    import torch
+    import paper_1512_03487_amd as gm
+    from paper_1512_03487_amd import fields
+    dev = torch.device("cuda:0")
+    Lt, Lz, Ly, Lx = dims[3], dims[2], dims[1], dims[0]
+    U = torch.from_numpy(fields.gauge_field(dims, seed=1, kind="haar")).to(dev)
+    Uk = U.to(torch.complex64) if prec == "f32" else gm.convert_links(U, "f16s", fmt)
+    g = torch.Generator(device=dev).manual_seed(9)
+    shape = (Lt, Lz, Ly, Lx // 2, Ls, 4, 3)
+
+    def field():
+        v = torch.complex(torch.randn(shape, generator=g, device=dev), torch.randn(shape, generator=g, device=dev))
+        return v if prec == "f32" else gm.convert_spinor(v, "f16s")
+    sets = [(field(), field(), field()) for _ in range(nsets)]
+    run = lambda i: gm.dhop_cb(Uk, sets[i % nsets][0], 0, "dwf", y=sets[i % nsets][1], beta=-0.25, M5=1.8, mf=0.01,
+                               out=sets[i % nsets][2])
+    for i in range(warmup):
+        run(i)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps):
+        run(i)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / steps
+    n5 = Lx // 2 * Ly * Lz * Lt * Ls
+    nbytes = (3 * SPINOR_BYTES[prec] + 8 * LINK_BYTES[(prec, fmt)] / Ls) * n5
+    del sets
+    return {"lattice": list(dims), "Ls": Ls, "prec": prec, "links": fmt, "op": "dwf even-odd hop + diagonal",
+            "us_per_launch": round(t * 1e6, 2), "alg_gbs": round(nbytes / t / 1e9, 1),
+            "roofline_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4), "buffer_sets": nsets}
+
+
 def mobius_leg(dims, Ls, prec, steps, warmup, b5=1.5, c5=0.5):
     """Moebius operator (grid_mobius): s-local pass + hopping pass; GB/s on the same algorithmic
     bytes as the Shamir operator (read psi and the links once, write out once)."""
@@ -557,6 +595,8 @@ def main():
         legs["dwf_24^4x12_f32"] = leg((24, 24, 24, 24), "f32", "L18", "dwf", 12, 20, 3)
         legs["dwf_24^4x12_f16s_L12"] = leg((24, 24, 24, 24), "f16s", "L12", "dwf", 12, 20, 3)
         legs["link_force_32^4_f32"] = link_force_leg()
+        legs["dwf_eo_hop_16^4x16_f32"] = cb_leg((16, 16, 16, 16), 16, "f32", "L18")
+        legs["dwf_eo_hop_16^4x16_f16s_L12"] = cb_leg((16, 16, 16, 16), 16, "f16s", "L12")
         legs["mobius_16^4x16_f32"] = mobius_leg((16, 16, 16, 16), 16, "f32", 50, 5)
         legs["mobius_16^4x16_f64"] = mobius_leg((16, 16, 16, 16), 16, "f64", 20, 3)
         torch.cuda.empty_cache()
