@@ -150,3 +150,27 @@ def test_graph_segments_match_direct_launches(gpu, solver, kind, sloppy, check):
         assert s["true_residual"] == s0["true_residual"]
         assert bool((x == x0).all()), "graph replay differs from direct launches"
     assert s0["iterations"] > 2 * check
+
+
+@pytest.mark.parametrize("solver,sloppy", [("cg", "f64"), ("cg", "f16s"), ("eo", "f16s"), ("mobius", "f32")])
+def test_fused_reductions_reproducible(gpu, solver, sloppy):
+    """The operators' fused norms and residual updates sum their partials in a fixed order (the
+    last wavefront to arrive adds the block's sums in order): two identical solves give bitwise
+    identical solutions, iteration counts and residuals."""
+    import paper_1512_03487_amd as gm
+    from tests.gpu_util import dev
+    dims, Ls = (8, 4, 4, 6), 8
+    U, b = F.gauge_field(dims, seed=2, kind="haar"), F.spinor_field(dims, seed=4, Ls=Ls)
+    runs = []
+    for _ in range(2):
+        if solver == "eo":
+            x, st = gm.solve_eo(dev(U), dev(b), kind="dwf", M5=1.8, mf=0.05, tol=TOL, sloppy=sloppy)
+        elif solver == "mobius":
+            x, st = gm.cg(dev(U), dev(b), "mobius", M5=1.8, mf=0.05, b5=1.5, c5=0.5, tol=TOL, sloppy=sloppy)
+        else:
+            x, st = gm.cg(dev(U), dev(b), kind="dwf", M5=1.8, mf=0.05, tol=TOL, sloppy=sloppy)
+        runs.append((x.cpu().numpy(), st))
+    (x0, s0), (x1, s1) = runs
+    assert s0["converged"] and s0["iterations"] == s1["iterations"]
+    assert s0["true_residual"] == s1["true_residual"]
+    assert np.array_equal(x0, x1)
