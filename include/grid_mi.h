@@ -350,6 +350,8 @@ typedef struct {
                            into a HIP graph and replayed (same kernels, same results)             */
     int setup_prec;     /* grid_mg_basis: precision of the setup CG's iterations, GRID_F64 (the
                            value of a zeroed struct) or GRID_F32 / GRID_F16S (mixed, as grid_cg) */
+    int smooth_prec;    /* grid_mg_solve: the cycle's minimal-residual smoother in GRID_F64 (zeroed
+                           struct) or GRID_F32 (its D with FP32 links, FP64 inner products)      */
 } grid_mg_params;
 
 /*

@@ -61,7 +61,8 @@ class GridMgParams(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int * 4), ("nvec", ctypes.c_int), ("setup_rounds", ctypes.c_int),
                 ("setup_iters", ctypes.c_int), ("coarse_iters", ctypes.c_int), ("coarse_tol", ctypes.c_double),
                 ("smooth_iters", ctypes.c_int), ("restart", ctypes.c_int), ("maxiter", ctypes.c_int),
-                ("tol", ctypes.c_double), ("graph", ctypes.c_int), ("setup_prec", ctypes.c_int)]
+                ("tol", ctypes.c_double), ("graph", ctypes.c_int), ("setup_prec", ctypes.c_int),
+                ("smooth_prec", ctypes.c_int)]
 
 
 class GridError(RuntimeError):

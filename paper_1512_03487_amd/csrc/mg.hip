@@ -405,6 +405,52 @@ k_zdot2_part(const double2 *__restrict__ a1, const double2 *__restrict__ b1, con
     }
 }
 
+// FP32 forms for the FP32 smoother (inner products accumulated in FP64).
+__device__ __forceinline__ double2 up2(float2 v) { return {double(v.x), double(v.y)}; }
+__global__ void __launch_bounds__(kMgThreads)
+k_zdot2_part_f(const float2 *__restrict__ a1, const float2 *__restrict__ b1, const float2 *__restrict__ a2,
+               const float2 *__restrict__ b2, long n, double2 *__restrict__ part) {
+    __shared__ double2 sm[kMgThreads];
+    double2 c1 = {0.0, 0.0}, c2 = {0.0, 0.0};
+    for (long i = static_cast<long>(blockIdx.x) * kMgThreads + threadIdx.x; i < n;
+         i += static_cast<long>(gridDim.x) * kMgThreads) {
+        c1 = add2(c1, cmulc2(up2(a1[i]), up2(b1[i])));
+        c2 = add2(c2, cmulc2(up2(a2[i]), up2(b2[i])));
+    }
+    c1 = block_sum2(c1, sm);
+    c2 = block_sum2(c2, sm);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = c1;
+        part[kMgParts + blockIdx.x] = c2;
+    }
+}
+
+// minimal-residual step in FP32: alpha = sc[0] / Re sc[1]; y += alpha x, y2 -= alpha x2
+__global__ void __launch_bounds__(kMgThreads)
+k_mr_step_f(float2 *__restrict__ y, const float2 *__restrict__ x, float2 *__restrict__ y2, const float2 *__restrict__ x2,
+            const double2 *__restrict__ sc, long n) {
+    const float ar = static_cast<float>(sc[0].x / sc[1].x), ai = static_cast<float>(sc[0].y / sc[1].x);
+    for (long i = static_cast<long>(blockIdx.x) * kMgThreads + threadIdx.x; i < n;
+         i += static_cast<long>(gridDim.x) * kMgThreads) {
+        const float2 xv = x[i], x2v = x2[i];
+        float2 a = y[i], b = y2[i];
+        a.x += ar * xv.x - ai * xv.y;
+        a.y += ar * xv.y + ai * xv.x;
+        b.x -= ar * x2v.x - ai * x2v.y;
+        b.y -= ar * x2v.y + ai * x2v.x;
+        y[i] = a;
+        y2[i] = b;
+    }
+}
+
+// out = a - b (FP32)
+__global__ void __launch_bounds__(kMgThreads)
+k_zsub_f(float2 *__restrict__ out, const float2 *__restrict__ a, const float2 *__restrict__ b, long n) {
+    for (long i = static_cast<long>(blockIdx.x) * kMgThreads + threadIdx.x; i < n;
+         i += static_cast<long>(gridDim.x) * kMgThreads)
+        out[i] = {a[i].x - b[i].x, a[i].y - b[i].y};
+}
+
 // One block: thread t adds partials t, t + 256, ... then a tree sum (fixed order).
 __global__ void __launch_bounds__(kMgThreads)
 k_zsum(const double2 *__restrict__ part, int np, double2 *__restrict__ out) {
@@ -562,6 +608,7 @@ struct MgLayout {
     size_t r, s, t, Z, W;   // fine (Z, W: restart vectors each)
     size_t rc, ec, cr, cp, cq, cq1;
     size_t part, scal;      // 2 x kMgParts double2, 16 double2
+    size_t z32 = 0, s32 = 0, t32 = 0, r32 = 0, u32 = 0;   // FP32 smoother (smooth_prec GRID_F32)
     size_t solve_end;
     size_t H, xb, cg, setup_end;   // setup: 8 directional fields, CG solution, CG workspace
     size_t total;
@@ -569,7 +616,7 @@ struct MgLayout {
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
-MgLayout mg_layout(const MgDims &m, int restart, int setup_prec) {
+MgLayout mg_layout(const MgDims &m, int restart, int setup_prec, int smooth_prec) {
     MgLayout L;
     L.fv = al256(static_cast<size_t>(m.vol) * 192);
     L.cv = al256(static_cast<size_t>(m.vc) * m.N * 16);
@@ -587,6 +634,15 @@ MgLayout mg_layout(const MgDims &m, int restart, int setup_prec) {
     L.cq1 = o; o += L.cv;
     L.part = o; o += al256(2 * kMgParts * sizeof(double2));
     L.scal = o; o += al256(16 * sizeof(double2));
+    if (smooth_prec == GRID_F32) {
+        // FP32 smoother: z, s, t, r in FP32 and the FP32 links
+        const size_t hv = al256(static_cast<size_t>(m.vol) * 96);
+        L.z32 = o; o += hv;
+        L.s32 = o; o += hv;
+        L.t32 = o; o += hv;
+        L.r32 = o; o += hv;
+        L.u32 = o; o += al256(static_cast<size_t>(m.vol) * 4 * 72);
+    }
     L.solve_end = o;
     o = 0;
     L.H = o; o += 8 * L.fv;
@@ -622,8 +678,40 @@ struct MgCtx {
     hipStream_t rec = nullptr;
 
     double2 *f(size_t off) const { return reinterpret_cast<double2 *>(ws + off); }
+    float2 *h(size_t off) const { return reinterpret_cast<float2 *>(ws + off); }
     double2 *part() const { return f(L.part); }
     double2 *scal() const { return f(L.scal); }
+
+    // the FP32 smoother's D (FP32 links converted once per solve) and vector steps
+    hipError_t D32(const void *in, void *out) const {
+        DhopArgs a;
+        a.U = ws + L.u32;
+        a.psi = in;
+        a.psi_scale = nullptr;
+        a.out = out;
+        a.out_scale = nullptr;
+        a.g = g;
+        a.prec = GRID_F32;
+        a.link_fmt = GRID_L18;
+        a.kind = GRID_WILSON;
+        a.dag = 0;
+        a.diag = 4.0 + mass;
+        a.mf = 0.0;
+        a.stream = st;
+        return launch_dhop(a);
+    }
+    hipError_t mr_step_f(float2 *z, float2 *s, const float2 *t, long n) const {
+        const int nb = vec_blocks(n);
+        hipLaunchKernelGGL(k_zdot2_part_f, dim3(nb), dim3(kMgThreads), 0, st, t, s, t, t, n, part());
+        MGCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_zsum, dim3(1), dim3(kMgThreads), 0, st, part(), nb, scal());
+        MGCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_zsum, dim3(1), dim3(kMgThreads), 0, st, part() + kMgParts, nb, scal() + 1);
+        MGCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_mr_step_f, dim3(nb), dim3(kMgThreads), 0, st, z, s, s, t,
+                           static_cast<const double2 *>(scal()), n);
+        return hipGetLastError();
+    }
 
     hipError_t D(const void *U, const void *in, void *out) const {
         DhopArgs a;
@@ -717,7 +805,7 @@ static bool mg_dims(const GeomDev &g, const grid_mg_params &p, MgDims *m) {
 size_t mg_workspace_bytes(const GeomDev &g, const grid_mg_params &p) {
     MgDims m;
     if (!mg_dims(g, p, &m)) return 0;
-    return mg_layout(m, p.restart, p.setup_prec).total;
+    return mg_layout(m, p.restart, p.setup_prec, p.smooth_prec).total;
 }
 
 static CoarseGeo coarse_geo(const MgDims &m) {
@@ -766,7 +854,7 @@ hipError_t run_mg_basis(const void *U, void *vecs, const GeomDev &g, double mass
                         hipStream_t st) {
     MgDims m;
     mg_dims(g, p, &m);
-    const MgLayout L = mg_layout(m, p.restart, p.setup_prec);
+    const MgLayout L = mg_layout(m, p.restart, p.setup_prec, p.smooth_prec);
     char *w = static_cast<char *>(ws);
     double2 *V = static_cast<double2 *>(vecs);
     const long nf = static_cast<long>(m.vol) * 12;
@@ -809,7 +897,7 @@ hipError_t run_mg_coarse_op(const void *U, const void *vecs, void *A, const Geom
                             const grid_mg_params &p, void *ws, hipStream_t st) {
     MgDims m;
     mg_dims(g, p, &m);
-    const MgLayout L = mg_layout(m, p.restart, p.setup_prec);
+    const MgLayout L = mg_layout(m, p.restart, p.setup_prec, p.smooth_prec);
     double2 *H = reinterpret_cast<double2 *>(static_cast<char *>(ws) + L.H);
     const double2 *V = static_cast<const double2 *>(vecs);
     const long nf = static_cast<long>(m.vol) * 12;
@@ -886,7 +974,20 @@ static hipError_t mg_cycle(const MgCtx &c, const void *U, const double2 *V, cons
     hipLaunchKernelGGL(k_mg_prolong, dim3(static_cast<unsigned>((nf + kMgThreads - 1) / kMgThreads)), dim3(kMgThreads),
                        0, c.st, V, ec, z, m);
     MGCHK(hipGetLastError());
-    // MR smoothing on D z = r
+    // MR smoothing on D z = r, in FP32 (smooth_prec): z and r narrowed, z widened after
+    if (c.p->smooth_iters > 0 && c.p->smooth_prec == GRID_F32) {
+        float2 *z32 = c.h(c.L.z32), *s32 = c.h(c.L.s32), *t32 = c.h(c.L.t32), *r32 = c.h(c.L.r32);
+        MGCHK(launch_convert_spinor(z, GRID_F64, nullptr, z32, GRID_F32, nullptr, m.vol, c.st));
+        MGCHK(launch_convert_spinor(r, GRID_F64, nullptr, r32, GRID_F32, nullptr, m.vol, c.st));
+        MGCHK(c.D32(z32, t32));
+        hipLaunchKernelGGL(k_zsub_f, dim3(vec_blocks(nf)), dim3(kMgThreads), 0, c.st, s32, r32, t32, nf);
+        MGCHK(hipGetLastError());
+        for (int it = 0; it < c.p->smooth_iters; ++it) {
+            MGCHK(c.D32(s32, t32));
+            MGCHK(c.mr_step_f(z32, s32, t32, nf));
+        }
+        return launch_convert_spinor(z32, GRID_F32, nullptr, z, GRID_F64, nullptr, m.vol, c.st);
+    }
     if (c.p->smooth_iters > 0) {
         double2 *s = c.f(c.L.s), *t = c.f(c.L.t);
         MGCHK(c.D(U, z, t));
@@ -921,11 +1022,13 @@ hipError_t run_mg_solve(const void *U, const void *vecs, const void *A, const vo
     c.mass = mass;
     c.p = &p;
     c.ws = static_cast<char *>(ws);
-    c.L = mg_layout(c.m, p.restart, p.setup_prec);
+    c.L = mg_layout(c.m, p.restart, p.setup_prec, p.smooth_prec);
     c.st = st;
     c.nf = static_cast<long>(g.vol) * 12;
     c.ncv = static_cast<long>(c.m.vc) * c.m.N;
     const long nf = c.nf;
+    if (p.smooth_prec == GRID_F32)
+        MGCHK(launch_convert_links(U, c.ws + c.L.u32, GRID_F32, GRID_L18, 0, static_cast<long>(g.vol) * 4, st));
     const double2 *V = static_cast<const double2 *>(vecs);
     const double2 *bb = static_cast<const double2 *>(b);
     double2 *xx = static_cast<double2 *>(x);

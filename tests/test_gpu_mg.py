@@ -79,6 +79,28 @@ def test_near_null_setup(gpu):
     assert _rel(host(vd), ref) <= 1e-9
 
 
+def test_fp32_smoother(gpu):
+    """The cycle's minimal-residual smoother in FP32 (FP32 links, FP64 inner products): the flexible
+    GCR still reaches 1e-10 (checked by the oracle) in about as many outer iterations."""
+    from tests.gpu_util import dev, host
+    gm = _gm()
+    dims, block, nvec, m = (8, 8, 8, 8), (4, 4, 4, 4), 8, 0.05
+    U = F.gauge_field(dims, seed=1, kind="weak")
+    b = F.spinor_field(dims, seed=3)
+    Ud = dev(U)
+    qd = dev(_vecs(dims, nvec))
+    gm.mg_basis(Ud, qd, m, block=block, setup_rounds=3, setup_iters=10)
+    Ad = gm.mg_coarse_op(Ud, qd, m, block=block)
+    its = {}
+    for prec in ("f64", "f32"):
+        x, st = gm.mg_solve(Ud, qd, Ad, dev(b), m, block=block, restart=8, coarse_iters=50, coarse_tol=0.05,
+                            smooth_iters=4, smooth_prec=prec)
+        res = float(np.linalg.norm(b - O.wilson(U, host(x), m)) / np.linalg.norm(b))
+        assert st["converged"] and res <= 1.05e-10, (prec, res)
+        its[prec] = st["iterations"]
+    assert abs(its["f32"] - its["f64"]) <= 2, its
+
+
 @pytest.mark.parametrize("setup_prec", ["f32", "f16s"])
 def test_mixed_precision_setup(gpu, setup_prec):
     """Setup CG in mixed precision: the near-null vectors stay close to the FP64 setup's (the
