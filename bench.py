@@ -430,10 +430,10 @@ def mg_legs(mass=-0.1, nvec=12, block=(4, 4, 4, 4)):
     b = torch.from_numpy(fields.spinor_field(dims, seed=3)).to(dev)
     vec0 = torch.from_numpy(np.stack([fields.spinor_field(dims, seed=11 + k) for k in range(nvec)])).to(dev)
     kw = dict(block=block, restart=8, coarse_iters=8, coarse_tol=0.25, smooth_iters=4, tol=1e-10, setup_prec="f32",
-              smooth_prec="f32")
+              cycle_prec="f32")
     ws = torch.empty(gm.mg_workspace_bytes(U, nvec=nvec, **kw), dtype=torch.uint8, device=dev)
     res = {"lattice": list(dims), "mass": mass, "links": "weak field exp(0.3 i H)", "block": list(block), "nvec": nvec,
-           "tol": 1e-10, "setup_prec": "f32", "smooth_prec": "f32"}
+           "tol": 1e-10, "setup_prec": "f32", "cycle_prec": "f32"}
     vecs = vec0.clone()
     torch.cuda.synchronize()
     t0 = time.perf_counter()

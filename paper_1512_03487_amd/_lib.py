@@ -62,7 +62,7 @@ class GridMgParams(ctypes.Structure):
                 ("setup_iters", ctypes.c_int), ("coarse_iters", ctypes.c_int), ("coarse_tol", ctypes.c_double),
                 ("smooth_iters", ctypes.c_int), ("restart", ctypes.c_int), ("maxiter", ctypes.c_int),
                 ("tol", ctypes.c_double), ("graph", ctypes.c_int), ("setup_prec", ctypes.c_int),
-                ("smooth_prec", ctypes.c_int)]
+                ("cycle_prec", ctypes.c_int)]
 
 
 class GridError(RuntimeError):

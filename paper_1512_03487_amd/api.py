@@ -436,7 +436,7 @@ def version() -> int:
 
 def mg_params(block=(2, 2, 2, 2), nvec=6, setup_rounds=2, setup_iters=8, coarse_iters=40, coarse_tol=0.05,
               smooth_iters=2, restart=8, maxiter=500, tol=1e-10, graph=True, setup_prec="f64",
-              smooth_prec="f64") -> GridMgParams:
+              cycle_prec="f64") -> GridMgParams:
     p = GridMgParams()
     for mu in range(4):
         p.block[mu] = int(block[mu])
@@ -445,7 +445,7 @@ def mg_params(block=(2, 2, 2, 2), nvec=6, setup_rounds=2, setup_iters=8, coarse_
     p.restart, p.maxiter, p.tol = int(restart), int(maxiter), float(tol)
     p.graph = 1 if graph else 0
     p.setup_prec = _PREC[setup_prec]
-    p.smooth_prec = _PREC[smooth_prec]
+    p.cycle_prec = _PREC[cycle_prec]
     return p
 
 

@@ -172,8 +172,8 @@ int check_mg(const GeomDev &g, const grid_op *op, const grid_mg_params *p) {
     if (p->restart < 1 || p->restart > 64) return fail(GRID_EINVAL, "restart = %d outside 1..64", p->restart);
     if (!(p->tol > 0.0) || !(p->coarse_tol >= 0.0)) return fail(GRID_EINVAL, "need tol > 0 and coarse_tol >= 0");
     TRY(check_prec(p->setup_prec));
-    if (p->smooth_prec != GRID_F64 && p->smooth_prec != GRID_F32)
-        return fail(GRID_EDTYPE, "smooth_prec must be GRID_F64 or GRID_F32 (got %d)", p->smooth_prec);
+    if (p->cycle_prec != GRID_F64 && p->cycle_prec != GRID_F32)
+        return fail(GRID_EDTYPE, "cycle_prec must be GRID_F64 or GRID_F32 (got %d)", p->cycle_prec);
     return GRID_OK;
 }
 

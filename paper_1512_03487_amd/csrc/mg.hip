@@ -174,8 +174,13 @@ hipError_t coarse_stencil(const void *A, const void *v, void *out, const CoarseG
 // Restriction, prolongation and the blockwise Gram-Schmidt of the basis.
 // vecs: nvec fine fields [k][V][4][3] complex double.
 // ---------------------------------------------------------------------------------------------
+// The basis may be read from an FP32 copy (TB = float2, the cycle in FP32); arithmetic in FP64.
+__device__ __forceinline__ double2 ld2(const double2 &v) { return v; }
+__device__ __forceinline__ double2 ld2(const float2 &v) { return {double(v.x), double(v.y)}; }
+
+template <typename TB>
 __global__ void __launch_bounds__(kMgThreads)
-k_mg_restrict(const double2 *__restrict__ vecs, const double2 *__restrict__ psi, double2 *__restrict__ vc, MgDims m) {
+k_mg_restrict(const TB *__restrict__ vecs, const double2 *__restrict__ psi, double2 *__restrict__ vc, MgDims m) {
     __shared__ double2 part[kMgThreads];
     const int xc = blockIdx.x, N = m.N, t = threadIdx.x;
     const int G = kMgThreads / N;
@@ -183,12 +188,12 @@ k_mg_restrict(const double2 *__restrict__ vecs, const double2 *__restrict__ psi,
     double2 acc = {0.0, 0.0};
     if (g < G) {
         const int chi = n / m.nvec, k = n - chi * m.nvec;
-        const double2 *ph = vecs + static_cast<size_t>(k) * m.vol * 12;
+        const TB *ph = vecs + static_cast<size_t>(k) * m.vol * 12;
         for (int f = g; f < m.nb; f += G) {
             int x[4];
             const size_t o = static_cast<size_t>(fine_site(m, xc, f, x)) * 12 + chi * 6;
 #pragma unroll
-            for (int e = 0; e < 6; ++e) acc = add2(acc, cmulc2(ph[o + e], psi[o + e]));
+            for (int e = 0; e < 6; ++e) acc = add2(acc, cmulc2(ld2(ph[o + e]), psi[o + e]));
         }
     }
     part[t] = acc;
@@ -200,15 +205,16 @@ k_mg_restrict(const double2 *__restrict__ vecs, const double2 *__restrict__ psi,
     }
 }
 
+template <typename TB>
 __global__ void __launch_bounds__(kMgThreads)
-k_mg_prolong(const double2 *__restrict__ vecs, const double2 *__restrict__ vc, double2 *__restrict__ out, MgDims m) {
+k_mg_prolong(const TB *__restrict__ vecs, const double2 *__restrict__ vc, double2 *__restrict__ out, MgDims m) {
     const long id = static_cast<long>(blockIdx.x) * kMgThreads + threadIdx.x;
     if (id >= static_cast<long>(m.vol) * 12) return;
     const int x4 = static_cast<int>(id / 12), e = static_cast<int>(id - static_cast<long>(x4) * 12);
     const int chi = e / 6;
     const double2 *c = vc + static_cast<size_t>(coarse_of(m, x4)) * m.N + chi * m.nvec;
     double2 acc = {0.0, 0.0};
-    for (int k = 0; k < m.nvec; ++k) acc = add2(acc, cmul2(vecs[static_cast<size_t>(k) * m.vol * 12 + id], c[k]));
+    for (int k = 0; k < m.nvec; ++k) acc = add2(acc, cmul2(ld2(vecs[static_cast<size_t>(k) * m.vol * 12 + id]), c[k]));
     out[id] = acc;
 }
 
@@ -608,7 +614,7 @@ struct MgLayout {
     size_t r, s, t, Z, W;   // fine (Z, W: restart vectors each)
     size_t rc, ec, cr, cp, cq, cq1;
     size_t part, scal;      // 2 x kMgParts double2, 16 double2
-    size_t z32 = 0, s32 = 0, t32 = 0, r32 = 0, u32 = 0;   // FP32 smoother (smooth_prec GRID_F32)
+    size_t z32 = 0, s32 = 0, t32 = 0, r32 = 0, u32 = 0, v32 = 0;   // FP32 cycle (cycle_prec GRID_F32)
     size_t solve_end;
     size_t H, xb, cg, setup_end;   // setup: 8 directional fields, CG solution, CG workspace
     size_t total;
@@ -616,7 +622,7 @@ struct MgLayout {
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
-MgLayout mg_layout(const MgDims &m, int restart, int setup_prec, int smooth_prec) {
+MgLayout mg_layout(const MgDims &m, int restart, int setup_prec, int cycle_prec) {
     MgLayout L;
     L.fv = al256(static_cast<size_t>(m.vol) * 192);
     L.cv = al256(static_cast<size_t>(m.vc) * m.N * 16);
@@ -634,7 +640,7 @@ MgLayout mg_layout(const MgDims &m, int restart, int setup_prec, int smooth_prec
     L.cq1 = o; o += L.cv;
     L.part = o; o += al256(2 * kMgParts * sizeof(double2));
     L.scal = o; o += al256(16 * sizeof(double2));
-    if (smooth_prec == GRID_F32) {
+    if (cycle_prec == GRID_F32) {
         // FP32 smoother: z, s, t, r in FP32 and the FP32 links
         const size_t hv = al256(static_cast<size_t>(m.vol) * 96);
         L.z32 = o; o += hv;
@@ -642,6 +648,7 @@ MgLayout mg_layout(const MgDims &m, int restart, int setup_prec, int smooth_prec
         L.t32 = o; o += hv;
         L.r32 = o; o += hv;
         L.u32 = o; o += al256(static_cast<size_t>(m.vol) * 4 * 72);
+        L.v32 = o; o += al256(static_cast<size_t>(m.nvec) * m.vol * 96);   // the basis for R and P
     }
     L.solve_end = o;
     o = 0;
@@ -805,7 +812,7 @@ static bool mg_dims(const GeomDev &g, const grid_mg_params &p, MgDims *m) {
 size_t mg_workspace_bytes(const GeomDev &g, const grid_mg_params &p) {
     MgDims m;
     if (!mg_dims(g, p, &m)) return 0;
-    return mg_layout(m, p.restart, p.setup_prec, p.smooth_prec).total;
+    return mg_layout(m, p.restart, p.setup_prec, p.cycle_prec).total;
 }
 
 static CoarseGeo coarse_geo(const MgDims &m) {
@@ -834,7 +841,7 @@ hipError_t launch_mg_restrict(const void *vecs, const void *psi, void *vc, const
                               hipStream_t st) {
     MgDims m;
     mg_dims(g, p, &m);
-    hipLaunchKernelGGL(k_mg_restrict, dim3(m.vc), dim3(kMgThreads), 0, st, static_cast<const double2 *>(vecs),
+    hipLaunchKernelGGL(k_mg_restrict<double2>, dim3(m.vc), dim3(kMgThreads), 0, st, static_cast<const double2 *>(vecs),
                        static_cast<const double2 *>(psi), static_cast<double2 *>(vc), m);
     return hipGetLastError();
 }
@@ -844,7 +851,7 @@ hipError_t launch_mg_prolong(const void *vecs, const void *vc, void *psi, const 
     MgDims m;
     mg_dims(g, p, &m);
     const long n = static_cast<long>(m.vol) * 12;
-    hipLaunchKernelGGL(k_mg_prolong, dim3(static_cast<unsigned>((n + kMgThreads - 1) / kMgThreads)), dim3(kMgThreads), 0,
+    hipLaunchKernelGGL(k_mg_prolong<double2>, dim3(static_cast<unsigned>((n + kMgThreads - 1) / kMgThreads)), dim3(kMgThreads), 0,
                        st, static_cast<const double2 *>(vecs), static_cast<const double2 *>(vc),
                        static_cast<double2 *>(psi), m);
     return hipGetLastError();
@@ -854,7 +861,7 @@ hipError_t run_mg_basis(const void *U, void *vecs, const GeomDev &g, double mass
                         hipStream_t st) {
     MgDims m;
     mg_dims(g, p, &m);
-    const MgLayout L = mg_layout(m, p.restart, p.setup_prec, p.smooth_prec);
+    const MgLayout L = mg_layout(m, p.restart, p.setup_prec, p.cycle_prec);
     char *w = static_cast<char *>(ws);
     double2 *V = static_cast<double2 *>(vecs);
     const long nf = static_cast<long>(m.vol) * 12;
@@ -897,7 +904,7 @@ hipError_t run_mg_coarse_op(const void *U, const void *vecs, void *A, const Geom
                             const grid_mg_params &p, void *ws, hipStream_t st) {
     MgDims m;
     mg_dims(g, p, &m);
-    const MgLayout L = mg_layout(m, p.restart, p.setup_prec, p.smooth_prec);
+    const MgLayout L = mg_layout(m, p.restart, p.setup_prec, p.cycle_prec);
     double2 *H = reinterpret_cast<double2 *>(static_cast<char *>(ws) + L.H);
     const double2 *V = static_cast<const double2 *>(vecs);
     const long nf = static_cast<long>(m.vol) * 12;
@@ -926,7 +933,11 @@ static hipError_t mg_cycle(const MgCtx &c, const void *U, const double2 *V, cons
     const long n = c.ncv;
     const int nb = vec_blocks(n);
     // r_c = R r
-    hipLaunchKernelGGL(k_mg_restrict, dim3(m.vc), dim3(kMgThreads), 0, c.st, V, r, rc, m);
+    const float2 *V32 = c.p->cycle_prec == GRID_F32 ? c.h(c.L.v32) : nullptr;
+    if (V32)
+        hipLaunchKernelGGL(k_mg_restrict<float2>, dim3(m.vc), dim3(kMgThreads), 0, c.st, V32, r, rc, m);
+    else
+        hipLaunchKernelGGL(k_mg_restrict<double2>, dim3(m.vc), dim3(kMgThreads), 0, c.st, V, r, rc, m);
     MGCHK(hipGetLastError());
     // coarse CGNR from e_c = 0: cr = A^+ r_c = G5 A G5 r_c; cp = cr; then the iterations, every
     // scalar on the device (the same kernels and arguments in every cycle of the solve)
@@ -971,11 +982,15 @@ static hipError_t mg_cycle(const MgCtx &c, const void *U, const double2 *V, cons
     }
     // z = P e_c
     const long nf = c.nf;
-    hipLaunchKernelGGL(k_mg_prolong, dim3(static_cast<unsigned>((nf + kMgThreads - 1) / kMgThreads)), dim3(kMgThreads),
-                       0, c.st, V, ec, z, m);
+    if (V32)
+        hipLaunchKernelGGL(k_mg_prolong<float2>, dim3(static_cast<unsigned>((nf + kMgThreads - 1) / kMgThreads)),
+                           dim3(kMgThreads), 0, c.st, V32, ec, z, m);
+    else
+        hipLaunchKernelGGL(k_mg_prolong<double2>, dim3(static_cast<unsigned>((nf + kMgThreads - 1) / kMgThreads)),
+                           dim3(kMgThreads), 0, c.st, V, ec, z, m);
     MGCHK(hipGetLastError());
-    // MR smoothing on D z = r, in FP32 (smooth_prec): z and r narrowed, z widened after
-    if (c.p->smooth_iters > 0 && c.p->smooth_prec == GRID_F32) {
+    // MR smoothing on D z = r, in FP32 (cycle_prec): z and r narrowed, z widened after
+    if (c.p->smooth_iters > 0 && c.p->cycle_prec == GRID_F32) {
         float2 *z32 = c.h(c.L.z32), *s32 = c.h(c.L.s32), *t32 = c.h(c.L.t32), *r32 = c.h(c.L.r32);
         MGCHK(launch_convert_spinor(z, GRID_F64, nullptr, z32, GRID_F32, nullptr, m.vol, c.st));
         MGCHK(launch_convert_spinor(r, GRID_F64, nullptr, r32, GRID_F32, nullptr, m.vol, c.st));
@@ -1022,13 +1037,16 @@ hipError_t run_mg_solve(const void *U, const void *vecs, const void *A, const vo
     c.mass = mass;
     c.p = &p;
     c.ws = static_cast<char *>(ws);
-    c.L = mg_layout(c.m, p.restart, p.setup_prec, p.smooth_prec);
+    c.L = mg_layout(c.m, p.restart, p.setup_prec, p.cycle_prec);
     c.st = st;
     c.nf = static_cast<long>(g.vol) * 12;
     c.ncv = static_cast<long>(c.m.vc) * c.m.N;
     const long nf = c.nf;
-    if (p.smooth_prec == GRID_F32)
+    if (p.cycle_prec == GRID_F32) {
         MGCHK(launch_convert_links(U, c.ws + c.L.u32, GRID_F32, GRID_L18, 0, static_cast<long>(g.vol) * 4, st));
+        MGCHK(launch_convert_spinor(vecs, GRID_F64, nullptr, c.ws + c.L.v32, GRID_F32, nullptr,
+                                    static_cast<long>(c.m.nvec) * g.vol, st));
+    }
     const double2 *V = static_cast<const double2 *>(vecs);
     const double2 *bb = static_cast<const double2 *>(b);
     double2 *xx = static_cast<double2 *>(x);

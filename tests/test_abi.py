@@ -230,7 +230,7 @@ def mg_params(**kw):
     p.coarse_iters, p.coarse_tol, p.smooth_iters = 10, 0.1, 1
     p.restart, p.maxiter, p.tol = kw.get("restart", 4), 10, 1e-8
     p.setup_prec = kw.get("setup_prec", _lib.GRID_F64)
-    p.smooth_prec = kw.get("smooth_prec", _lib.GRID_F64)
+    p.cycle_prec = kw.get("cycle_prec", _lib.GRID_F64)
     return p
 
 
@@ -240,8 +240,8 @@ def test_multigrid_validation(lib):
     assert lib.grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(ok)) > 0
     for bad in (mg_params(block=(3, 2, 2, 2)), mg_params(block=(0, 2, 2, 2)), mg_params(nvec=0), mg_params(nvec=33),
                 mg_params(restart=0), mg_params(restart=65), mg_params(block=(1, 1, 1, 1), nvec=7),
-                mg_params(setup_prec=3), mg_params(setup_prec=-1), mg_params(smooth_prec=_lib.GRID_F16S),
-                mg_params(smooth_prec=7)):
+                mg_params(setup_prec=3), mg_params(setup_prec=-1), mg_params(cycle_prec=_lib.GRID_F16S),
+                mg_params(cycle_prec=7)):
         assert lib.grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(bad)) == 0
     # a mixed-precision setup needs the sloppy vectors and links besides
     assert (lib.grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(mg_params(setup_prec=_lib.GRID_F32)))
@@ -271,7 +271,7 @@ def test_parameter_builders():
     assert (p.sloppy_prec, p.link_fmt, p.graph) == (_lib.GRID_F16S, _lib.GRID_L12, 1)
     q = api.mg_params(block=(4, 4, 2, 2), nvec=8, setup_prec="f32")
     assert (tuple(q.block), q.nvec, q.setup_prec) == ((4, 4, 2, 2), 8, _lib.GRID_F32)
-    assert api.mg_params().setup_prec == _lib.GRID_F64 and api.mg_params().smooth_prec == _lib.GRID_F64
-    assert api.mg_params(smooth_prec="f32").smooth_prec == _lib.GRID_F32
+    assert api.mg_params().setup_prec == _lib.GRID_F64 and api.mg_params().cycle_prec == _lib.GRID_F64
+    assert api.mg_params(cycle_prec="f32").cycle_prec == _lib.GRID_F32
     m = api.md_params(5.5, integrator="force_gradient", n_inner=1)
     assert m.integrator == _lib.GRID_FORCE_GRADIENT

@@ -79,9 +79,10 @@ def test_near_null_setup(gpu):
     assert _rel(host(vd), ref) <= 1e-9
 
 
-def test_fp32_smoother(gpu):
-    """The cycle's minimal-residual smoother in FP32 (FP32 links, FP64 inner products): the flexible
-    GCR still reaches 1e-10 (checked by the oracle) in about as many outer iterations."""
+def test_fp32_cycle(gpu):
+    """The cycle in FP32 (minimal-residual smoother with FP32 links and FP64 inner products; R and P
+    reading an FP32 copy of the basis): the flexible GCR still reaches 1e-10 (checked by the
+    oracle) in about as many outer iterations."""
     from tests.gpu_util import dev, host
     gm = _gm()
     dims, block, nvec, m = (8, 8, 8, 8), (4, 4, 4, 4), 8, 0.05
@@ -94,7 +95,7 @@ def test_fp32_smoother(gpu):
     its = {}
     for prec in ("f64", "f32"):
         x, st = gm.mg_solve(Ud, qd, Ad, dev(b), m, block=block, restart=8, coarse_iters=50, coarse_tol=0.05,
-                            smooth_iters=4, smooth_prec=prec)
+                            smooth_iters=4, cycle_prec=prec)
         res = float(np.linalg.norm(b - O.wilson(U, host(x), m)) / np.linalg.norm(b))
         assert st["converged"] and res <= 1.05e-10, (prec, res)
         its[prec] = st["iterations"]
