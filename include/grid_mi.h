@@ -351,9 +351,9 @@ typedef struct {
     int setup_prec;     /* grid_mg_basis: precision of the setup CG's iterations, GRID_F64 (the
                            value of a zeroed struct) or GRID_F32 / GRID_F16S (mixed, as grid_cg) */
     int cycle_prec;     /* grid_mg_solve: GRID_F64 (zeroed struct) or GRID_F32: the cycle's minimal-
-                           residual smoother in FP32 (FP32 links, FP64 inner products) and R, P
-                           reading an FP32 copy of the basis (FP64 arithmetic); the coarse operator
-                           and the GCR stay FP64                                                  */
+                           residual smoother in FP32 (FP32 links, FP64 inner products), and R, P
+                           and the coarse solve reading FP32 copies of the basis and of A (FP64
+                           arithmetic and coarse vectors); the GCR stays FP64                     */
 } grid_mg_params;
 
 /*

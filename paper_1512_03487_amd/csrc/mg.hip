@@ -114,7 +114,12 @@ __device__ double2 block_sum2(double2 v, double2 *sm) {
 // added in a fixed order. g5: apply G5 to the input and the output (A_c^+ = G5 A_c G5).
 // dag: the true adjoint, (A^+ v)(xc) = sum_d A_d(xc - e_d)^+ v(xc - e_d).
 // ctl (nullable): skip the launch when ctl[1 + par] <= ctl[0] (the coarse solver has converged).
+// TA: the element type of A (double2, or float2 for the FP32 copy the FP32 cycle reads; the
+// products and sums are FP64 either way).
 // ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ double2 ld2(const double2 &v) { return v; }
+__device__ __forceinline__ double2 ld2(const float2 &v) { return {double(v.x), double(v.y)}; }
+
 struct CoarseGeo {
     int Lc[4];
     int vc;
@@ -122,8 +127,9 @@ struct CoarseGeo {
     int nvec;   // G5 split (N / 2)
 };
 
+template <typename TA>
 __global__ void __launch_bounds__(kMgThreads)
-k_coarse_stencil(const double2 *__restrict__ A, const double2 *__restrict__ v, double2 *__restrict__ out, CoarseGeo cg,
+k_coarse_stencil(const TA *__restrict__ A, const double2 *__restrict__ v, double2 *__restrict__ out, CoarseGeo cg,
                  int dag, int g5, const double *__restrict__ ctl, int par) {
     if (ctl && ctl[1 + par] <= ctl[0]) return;
     __shared__ double2 vnb[9 * 64];
@@ -144,11 +150,11 @@ k_coarse_stencil(const double2 *__restrict__ A, const double2 *__restrict__ v, d
         for (int p = g; p < 9 * N; p += G) {
             const int d = p / N, j = p - d * N;
             if (!dag) {
-                const double2 a = A[((static_cast<size_t>(xc) * 9 + d) * N + j) * N + i];
+                const double2 a = ld2(A[((static_cast<size_t>(xc) * 9 + d) * N + j) * N + i]);
                 acc = add2(acc, cmul2(a, vnb[p]));
             } else {
                 const int y = coarse_nb(cg.Lc, xc, opposite(d));
-                const double2 a = A[((static_cast<size_t>(y) * 9 + d) * N + i) * N + j];
+                const double2 a = ld2(A[((static_cast<size_t>(y) * 9 + d) * N + i) * N + j]);
                 acc = add2(acc, cmulc2(a, vnb[p]));
             }
         }
@@ -164,10 +170,22 @@ k_coarse_stencil(const double2 *__restrict__ A, const double2 *__restrict__ v, d
 }
 
 hipError_t coarse_stencil(const void *A, const void *v, void *out, const CoarseGeo &cg, int dag, int g5,
-                          const double *ctl, int par, hipStream_t st) {
-    hipLaunchKernelGGL(k_coarse_stencil, dim3(cg.vc), dim3(kMgThreads), 0, st, static_cast<const double2 *>(A),
-                       static_cast<const double2 *>(v), static_cast<double2 *>(out), cg, dag, g5, ctl, par);
+                          const double *ctl, int par, hipStream_t st, bool a32 = false) {
+    if (a32)
+        hipLaunchKernelGGL(k_coarse_stencil<float2>, dim3(cg.vc), dim3(kMgThreads), 0, st,
+                           static_cast<const float2 *>(A), static_cast<const double2 *>(v),
+                           static_cast<double2 *>(out), cg, dag, g5, ctl, par);
+    else
+        hipLaunchKernelGGL(k_coarse_stencil<double2>, dim3(cg.vc), dim3(kMgThreads), 0, st,
+                           static_cast<const double2 *>(A), static_cast<const double2 *>(v),
+                           static_cast<double2 *>(out), cg, dag, g5, ctl, par);
     return hipGetLastError();
+}
+
+// out[i] = (float2)in[i], i < n (the FP32 copy of the coarse operator).
+__global__ void __launch_bounds__(256) k_narrow2(const double2 *__restrict__ in, float2 *__restrict__ out, long n) {
+    const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = {static_cast<float>(in[i].x), static_cast<float>(in[i].y)};
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -175,8 +193,6 @@ hipError_t coarse_stencil(const void *A, const void *v, void *out, const CoarseG
 // vecs: nvec fine fields [k][V][4][3] complex double.
 // ---------------------------------------------------------------------------------------------
 // The basis may be read from an FP32 copy (TB = float2, the cycle in FP32); arithmetic in FP64.
-__device__ __forceinline__ double2 ld2(const double2 &v) { return v; }
-__device__ __forceinline__ double2 ld2(const float2 &v) { return {double(v.x), double(v.y)}; }
 
 template <typename TB>
 __global__ void __launch_bounds__(kMgThreads)
@@ -614,7 +630,7 @@ struct MgLayout {
     size_t r, s, t, Z, W;   // fine (Z, W: restart vectors each)
     size_t rc, ec, cr, cp, cq, cq1;
     size_t part, scal;      // 2 x kMgParts double2, 16 double2
-    size_t z32 = 0, s32 = 0, t32 = 0, r32 = 0, u32 = 0, v32 = 0;   // FP32 cycle (cycle_prec GRID_F32)
+    size_t z32 = 0, s32 = 0, t32 = 0, r32 = 0, u32 = 0, v32 = 0, a32 = 0;   // FP32 cycle (cycle_prec GRID_F32)
     size_t solve_end;
     size_t H, xb, cg, setup_end;   // setup: 8 directional fields, CG solution, CG workspace
     size_t total;
@@ -649,6 +665,7 @@ MgLayout mg_layout(const MgDims &m, int restart, int setup_prec, int cycle_prec)
         L.r32 = o; o += hv;
         L.u32 = o; o += al256(static_cast<size_t>(m.vol) * 4 * 72);
         L.v32 = o; o += al256(static_cast<size_t>(m.nvec) * m.vol * 96);   // the basis for R and P
+        L.a32 = o; o += al256(static_cast<size_t>(m.vc) * 9 * m.N * m.N * sizeof(float2));   // coarse A
     }
     L.solve_end = o;
     o = 0;
@@ -934,6 +951,8 @@ static hipError_t mg_cycle(const MgCtx &c, const void *U, const double2 *V, cons
     const int nb = vec_blocks(n);
     // r_c = R r
     const float2 *V32 = c.p->cycle_prec == GRID_F32 ? c.h(c.L.v32) : nullptr;
+    const bool a32 = V32 != nullptr;
+    const void *Ac = a32 ? static_cast<const void *>(c.h(c.L.a32)) : A;
     if (V32)
         hipLaunchKernelGGL(k_mg_restrict<float2>, dim3(m.vc), dim3(kMgThreads), 0, c.st, V32, r, rc, m);
     else
@@ -942,7 +961,7 @@ static hipError_t mg_cycle(const MgCtx &c, const void *U, const double2 *V, cons
     // coarse CGNR from e_c = 0: cr = A^+ r_c = G5 A G5 r_c; cp = cr; then the iterations, every
     // scalar on the device (the same kernels and arguments in every cycle of the solve)
     auto coarse_solve = [&](hipStream_t s) -> hipError_t {
-        MGCHK(coarse_stencil(A, rc, cr, cg, 0, 1, nullptr, 0, s));
+        MGCHK(coarse_stencil(Ac, rc, cr, cg, 0, 1, nullptr, 0, s, a32));
         hipLaunchKernelGGL(k_ccg_start, dim3(nb), dim3(kMgThreads), 0, s, cp, cr, ec, n);
         MGCHK(hipGetLastError());
         hipLaunchKernelGGL(k_cdot_re, dim3(nb), dim3(kMgThreads), 0, s, cr, cr, n, rr, static_cast<const double *>(nullptr),
@@ -952,8 +971,8 @@ static hipError_t mg_cycle(const MgCtx &c, const void *U, const double2 *V, cons
         MGCHK(hipGetLastError());
         for (int i = 0; i < c.p->coarse_iters; ++i) {
             const int P = i & 1;
-            MGCHK(coarse_stencil(A, cp, cq1, cg, 0, 0, ctl, P, s));
-            MGCHK(coarse_stencil(A, cq1, cq, cg, 0, 1, ctl, P, s));
+            MGCHK(coarse_stencil(Ac, cp, cq1, cg, 0, 0, ctl, P, s, a32));
+            MGCHK(coarse_stencil(Ac, cq1, cq, cg, 0, 1, ctl, P, s, a32));
             hipLaunchKernelGGL(k_cdot_re, dim3(nb), dim3(kMgThreads), 0, s, cp, cq, n, pq, ctl, P);
             MGCHK(hipGetLastError());
             hipLaunchKernelGGL(k_ccg_update, dim3(nb), dim3(kMgThreads), 0, s, ec, cr, cp, cq, n, pq, rr, nb, ctl, P);
@@ -1046,6 +1065,10 @@ hipError_t run_mg_solve(const void *U, const void *vecs, const void *A, const vo
         MGCHK(launch_convert_links(U, c.ws + c.L.u32, GRID_F32, GRID_L18, 0, static_cast<long>(g.vol) * 4, st));
         MGCHK(launch_convert_spinor(vecs, GRID_F64, nullptr, c.ws + c.L.v32, GRID_F32, nullptr,
                                     static_cast<long>(c.m.nvec) * g.vol, st));
+        const long na = static_cast<long>(c.m.vc) * 9 * c.m.N * c.m.N;
+        hipLaunchKernelGGL(k_narrow2, dim3(static_cast<unsigned>((na + 255) / 256)), dim3(256), 0, st,
+                           static_cast<const double2 *>(A), c.h(c.L.a32), na);
+        MGCHK(hipGetLastError());
     }
     const double2 *V = static_cast<const double2 *>(vecs);
     const double2 *bb = static_cast<const double2 *>(b);
