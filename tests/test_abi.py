@@ -246,7 +246,14 @@ def test_multigrid_validation(lib):
     # a mixed-precision setup needs the sloppy vectors and links besides
     assert (lib.grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(mg_params(setup_prec=_lib.GRID_F32)))
             >= lib.grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(ok)))
-    op = _lib.GridOp(_lib.GRID_WILSON, 0, 0.1, 1.8, 0.01, 1.0, 0.0)
+    # an FP32 cycle also holds FP32 z, s, t, r, the links, the basis and the coarse operator (the
+    # workspace is the larger of the solve's and the setup's; 16 restart vectors make it the solve's)
+    vol, nvec, vc = 4**4, 4, 2**4
+    fp32_cycle = 4 * vol * 96 + vol * 4 * 72 + nvec * vol * 96 + vc * 9 * (2 * nvec) ** 2 * 8
+    w64 = lib.grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(mg_params(restart=16)))
+    w32 = lib.grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(mg_params(restart=16, cycle_prec=_lib.GRID_F32)))
+    assert w32 >= w64 + fp32_cycle
+    op =_lib.GridOp(_lib.GRID_WILSON, 0, 0.1, 1.8, 0.01, 1.0, 0.0)
     dwf = _lib.GridOp(_lib.GRID_DWF, 0, 0.1, 1.8, 0.01, 1.0, 0.0)
     need = lib.grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(ok))
     st = _lib.GridCgStats()
