@@ -457,7 +457,8 @@ __device__ __forceinline__ void hop_term(Cx<C> acc[4][3], const Cx<C> p[4][3], c
 template <class SP, class LK, bool DAG, int KIND, int FUSE>
 __global__ void __launch_bounds__(256)
 k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const float *__restrict__ psi_scale,
-       void *out, float *out_scale, GeomDev g, int T, double diag, double mf, FuseDev fz) {
+       const void *__restrict__ yv, const float *__restrict__ y_scale, void *out, float *out_scale, GeomDev g, int T,
+       double diag, double mf, double cs, FuseDev fz) {
     using C = typename SP::C;
     __shared__ chunk_t sm[kWaves][64 * stage_pitch<SP>()];
     chunk_t *lds = sm[threadIdx.x >> 6];
@@ -491,8 +492,8 @@ k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const floa
         project<3, -EF>(p, hb);
     }
     // Records gathered per step, in order: psi(x, t+1), the six spatial neighbours at t, and the
-    // centre psi(x, t) for the Wilson / domain-wall epilogue. The next record's loads are issued
-    // before the current direction computes.
+    // centre y(x, t) for the Wilson / domain-wall epilogue (y = psi but for the Moebius operator's
+    // hopping pass). The next record's loads are issued before the current direction computes.
     constexpr int NREC = (KIND == GRID_HOP) ? 7 : 8;
     [[maybe_unused]] double n2 = 0.0;   // fused epilogue: this thread's |out|^2
 #pragma unroll 1
@@ -519,7 +520,12 @@ k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const floa
             const int mu = (i == 0) ? 3 : (i - 1) / 2;
             const bool bwd = (i >= 1 && i <= 6 && ((i - 1) & 1));
             if (i <= 6) LK::load(U, (loff + (bwd ? nb[i - 1] : col)) * 4 + mu, u);
-            if (i + 1 < NREC) fetch<SP>(psi, psi_scale, rec[i + 1], f);
+            if (i + 1 < NREC) {
+                if (i + 1 == 7)
+                    fetch<SP>(yv, y_scale, rec[7], f);
+                else
+                    fetch<SP>(psi, psi_scale, rec[i + 1], f);
+            }
             if (i == 0) {
                 hop_term<3, EF, false>(acc, p, u);
                 su3_adj_mul(u, hb, chi_b);       // backward t-hop of the next slice, same link
@@ -548,23 +554,24 @@ k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const floa
             }
         }
         if (KIND == GRID_DWF) {
-            // M:   - P_- psi~_{s+1} - P_+ psi~_{s-1};  M^dagger: - P_+ psi~_{s+1} - P_- psi~_{s-1}
-            // walls: psi~_{Ls} = -mf psi_0, psi~_{-1} = -mf psi_{Ls-1}
+            // M:   - P_- y~_{s+1} - P_+ y~_{s-1};  M^dagger: - P_+ y~_{s+1} - P_- y~_{s-1}, times cs
+            // walls: y~_{Ls} = -mf y_0, y~_{-1} = -mf y_{Ls-1}
             const int sp = (s == Ls - 1) ? 0 : s + 1;
             const int sm1 = (s == 0) ? Ls - 1 : s - 1;
-            const C fp = (s == Ls - 1) ? static_cast<C>(-mf) : C(1);
-            const C fm = (s == 0) ? static_cast<C>(-mf) : C(1);
+            const C c5 = static_cast<C>(cs);
+            const C fp = (s == Ls - 1) ? c5 * static_cast<C>(-mf) : c5;
+            const C fm = (s == 0) ? c5 * static_cast<C>(-mf) : c5;
             const int hup = DAG ? 0 : 1;   // chiral half taken from s + 1 (0: spins 0,1; 1: spins 2,3)
             const int hdn = 1 - hup;
             const size_t site4 = static_cast<size_t>(off) + static_cast<size_t>(col) * Ls;
             Cx<C> qh[2][3];
-            SP::load_half(psi, psi_scale, site4 + sp, hup, qh);
+            SP::load_half(yv, y_scale, site4 + sp, hup, qh);
 #pragma unroll
             for (int j = 0; j < 6; ++j) {
                 Cx<C> &o = acc[2 * hup + j / 3][j % 3];
                 o = {o.r - fp * qh[j / 3][j % 3].r, o.i - fp * qh[j / 3][j % 3].i};
             }
-            SP::load_half(psi, psi_scale, site4 + sm1, hdn, qh);
+            SP::load_half(yv, y_scale, site4 + sm1, hdn, qh);
 #pragma unroll
             for (int j = 0; j < 6; ++j) {
                 Cx<C> &o = acc[2 * hdn + j / 3][j % 3];
@@ -777,9 +784,12 @@ static hipError_t launch_walk(const DhopArgs &a) {
     const long nbc = (static_cast<long>(a.g.L[0]) * a.g.L[1] * a.g.L[2] * a.g.Ls + 255) / 256;
     const dim3 grid(static_cast<unsigned>(nbc * (a.g.L[3] / T))), block(256);
     hipStream_t st = a.stream;
+    const void *y = a.custom ? a.y : a.psi;
+    const float *ys = a.custom ? a.y_scale : a.psi_scale;
+    const double cs = a.custom ? a.cs : 1.0;
 #define GRIDMI_LAUNCH(DAG, KIND, FUSE)                                                                    \
-    hipLaunchKernelGGL((k_dhop_walk<SP, LK, DAG, KIND, FUSE>), grid, block, 0, st, a.U, a.psi, a.psi_scale, a.out, \
-                       a.out_scale, a.g, T, a.diag, a.mf, a.fz)
+    hipLaunchKernelGGL((k_dhop_walk<SP, LK, DAG, KIND, FUSE>), grid, block, 0, st, a.U, a.psi, a.psi_scale, y, ys,  \
+                       a.out, a.out_scale, a.g, T, a.diag, a.mf, cs, a.fz)
     if (a.fuse != kFuseNone) {
         switch (a.kind * 4 + a.fuse * 2 + (a.dag ? 1 : 0)) {
             case GRID_WILSON * 4 + kFuseNorm * 2 + 0: GRIDMI_LAUNCH(false, GRID_WILSON, kFuseNorm); break;
@@ -848,9 +858,13 @@ static hipError_t launch_walk_cb(const DhopArgs &a) {
 }
 
 // Schedules: column walk for FP16 storage and 5D FP32 fields (full lattice, or checkerboard
-// fields in the even-odd form), direction-parallel otherwise (measured faster there).
+// fields in the even-odd form), direction-parallel otherwise (measured faster there). The
+// full-lattice walk also takes the custom form with a separate y and beta = -1/2 (the Moebius
+// operator's hopping pass).
 static bool walk_prec(const DhopArgs &a) { return a.prec == GRID_F16S || (a.prec == GRID_F32 && a.g.Ls > 1); }
-static bool use_walk(const DhopArgs &a) { return !a.custom && walk_prec(a); }
+static bool use_walk(const DhopArgs &a) {
+    return walk_prec(a) && (!a.custom || (a.cb < 0 && a.kind != GRID_HOP && a.beta == -0.5));
+}
 static bool use_walk_cb(const DhopArgs &a) { return a.custom && a.cb >= 0 && walk_prec(a); }
 
 template <class SP, class LK>

@@ -38,9 +38,10 @@ struct DhopArgs {
     double diag;   // 4 + mass (Wilson) or 5 - M5 (domain wall)
     double mf;
     hipStream_t stream;
-    // Even-odd form (direction-parallel schedule only): out (checkerboard cb) = beta * H psi
-    // (psi on checkerboard 1 - cb) + the diagonal part of `kind` applied to y (checkerboard cb).
-    // With custom == false: full lattice, y = psi, beta = 1 (HOP) or -1/2 (WILSON, DWF).
+    // Custom form: out = beta * H psi + the diagonal part of `kind` applied to y, its
+    // fifth-dimension hopping scaled by cs; on checkerboard fields (the even-odd form) out is on
+    // checkerboard cb and psi on 1 - cb, with cb = -1 on the full lattice (the Moebius operator).
+    // With custom == false: full lattice, y = psi, beta = 1 (HOP) or -1/2 (WILSON, DWF), cs = 1.
     bool custom = false;
     int cb = -1;               // output checkerboard 0 / 1, or -1 for full-lattice fields
     const void *y = nullptr;
