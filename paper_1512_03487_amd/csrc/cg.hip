@@ -21,7 +21,7 @@
 //
 // With params.graph the check_every iterations between two host reads (their last x/p update
 // excepted, which follows the check) are recorded once into a HIP graph per starting parity on a
-// stream of the driver's own, then replayed on the caller's stream: one launch per segment in
+// stream the solver creates, then replayed on the caller's stream: one launch per segment in
 // place of about six per iteration. The recorded kernels and arguments are those of the direct
 // path (all workspace pointers are fixed for the solve), so results are bitwise identical.
 #include <chrono>

@@ -131,7 +131,7 @@ def test_config2_dwf_16_4_ls16(gpu, sloppy):
 def test_graph_segments_match_direct_launches(gpu, solver, kind, sloppy, check):
     """Recorded iteration segments (grid_cg_params.graph) replay the direct path's kernels with the
     same arguments: the solution, iteration count, reliable updates and residual are identical.
-    Each solve replays a segment tens of times with the driver's own checks, reliable updates and
+    Each solve replays a segment tens of times with the solver's host checks, reliable updates and
     synchronisations in between; an odd check_every exercises both starting parities."""
     import paper_1512_03487_amd as gm
     from tests.gpu_util import dev
