@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -523,8 +524,60 @@ def cpu_baseline(seconds_target=15.0):
         if el >= seconds_target:
             break
     vol = 16 ** 4
-    return {"value": round(FLOPS_HOP * vol * n / el / 1e9, 3), "unit": "GFLOP/s", "cores": orc.threads(),
-            "kind": "oracle", "sample": f"{n} applications of H on the 16^4 FP64 workload ({el:.1f} s)"}
+    res = {"value": round(FLOPS_HOP * vol * n / el / 1e9, 3), "unit": "GFLOP/s", "cores": orc.threads(),
+           "kind": "oracle", "sample": f"{n} applications of H on the 16^4 FP64 workload ({el:.1f} s)",
+           "cpu_model": _cpu_model()}
+    res["single_thread"] = _oracle_single_thread()
+    # the domain-wall normal operator M^dagger M on 16^4 x 16 (M5 = 1.8, mf = 0.01), per application
+    psi5 = fields.spinor_field(dims, seed=3, Ls=16)
+    op = orc.Op.dwf(16, 1.8, 0.01)
+    orc.normal(op, U, psi5)
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        orc.normal(op, U, psi5)
+    res["dwf_mdag_m_16^4x16_seconds"] = round((time.perf_counter() - t0) / reps, 4)
+    return res
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_single_thread(seconds_target=3.0):
+    """The oracle's H on 16^4 with one OpenMP thread, in a CPU-only child process (the thread count
+    is fixed when the oracle library loads). The inputs are plain random arrays: the time of H does
+    not depend on the values."""
+    code = (
+        "import sys, time, numpy as np\n"
+        f"sys.path.insert(0, {ROOT!r})\n"
+        "from oracle import oracle as orc\n"
+        "r = np.random.default_rng(7)\n"
+        "d = (16, 16, 16, 16)\n"
+        "U = r.standard_normal(d + (4, 3, 3)) + 1j * r.standard_normal(d + (4, 3, 3))\n"
+        "psi = r.standard_normal(d + (4, 3)) + 1j * r.standard_normal(d + (4, 3))\n"
+        "orc.hop(U, psi)\n"
+        "n, t0 = 0, time.perf_counter()\n"
+        "while True:\n"
+        "    orc.hop(U, psi); n += 1; el = time.perf_counter() - t0\n"
+        f"    if el >= {seconds_target}: break\n"
+        "print(orc.threads(), n, el)\n")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120,
+                             check=True).stdout.split()
+        th, n, el = int(out[-3]), int(out[-2]), float(out[-1])
+    except (subprocess.SubprocessError, ValueError, IndexError) as e:
+        return {"error": str(e)[:200]}
+    return {"value": round(FLOPS_HOP * 16 ** 4 * n / el / 1e9, 3), "unit": "GFLOP/s", "cores": th,
+            "sample": f"{n} applications of H on 16^4 ({el:.1f} s)"}
 
 
 def main():
