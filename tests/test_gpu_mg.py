@@ -80,9 +80,9 @@ def test_near_null_setup(gpu):
 
 
 def test_fp32_cycle(gpu):
-    """The cycle in FP32 (minimal-residual smoother with FP32 links and FP64 inner products; R and P
-    reading an FP32 copy of the basis): the flexible GCR still reaches 1e-10 (checked by the
-    oracle) in about as many outer iterations."""
+    """The cycle in FP32 (minimal-residual smoother with FP32 links and FP64 inner products; R, P
+    and the coarse solve reading FP32 copies of the basis and of A): the flexible GCR still reaches
+    1e-10 (checked by the oracle) in about as many outer iterations."""
     from tests.gpu_util import dev, host
     gm = _gm()
     dims, block, nvec, m = (8, 8, 8, 8), (4, 4, 4, 4), 8, 0.05
@@ -164,7 +164,10 @@ def test_gcr_iterates_match_the_oracle(gpu):
 
 
 @pytest.mark.parametrize("dims,block,nvec,restart", [((4, 4, 4, 4), (2, 2, 2, 2), 6, 8), ((8, 4, 4, 4), (2, 2, 2, 2), 4, 4)])
-def test_mg_solve(gpu, dims, block, nvec, restart):
+@pytest.mark.parametrize("cycle_prec", ["f64", "f32"])
+def test_mg_solve(gpu, dims, block, nvec, restart, cycle_prec):
+    """Solves D x = b to 1e-10 (checked by the oracle) in as many outer iterations as the oracle's
+    flexible GCR (within one; within two with the FP32 cycle, a slightly different preconditioner)."""
     from tests.gpu_util import dev, host
     gm = _gm()
     m = 0.2
@@ -172,13 +175,14 @@ def test_mg_solve(gpu, dims, block, nvec, restart):
     b = F.spinor_field(dims, seed=3)
     Ud, qd = dev(U), dev(q)
     Ad = gm.mg_coarse_op(Ud, qd, m, block=block)
-    x, st = gm.mg_solve(Ud, qd, Ad, dev(b), m, block=block, restart=restart, coarse_iters=40, tol=1e-10)
+    x, st = gm.mg_solve(Ud, qd, Ad, dev(b), m, block=block, restart=restart, coarse_iters=40, tol=1e-10,
+                        cycle_prec=cycle_prec)
     assert st["converged"]
     res = float(np.linalg.norm(b - O.wilson(U, host(x), m)) / np.linalg.norm(b))
     assert res <= 1.05e-10 and abs(res - st["true_residual"]) <= 1e-3 * res
     _, ito, _ = mg.fgcr(U, q, A, b, m, block, tol=1e-10, restart=restart, coarse_iters=40, coarse_tol=0.05,
                         smooth_iters=2)
-    assert abs(st["iterations"] - ito) <= 1, (st["iterations"], ito)
+    assert abs(st["iterations"] - ito) <= (1 if cycle_prec == "f64" else 2), (st["iterations"], ito)
 
 
 def test_mg_full_pipeline_on_device(gpu):
