@@ -318,6 +318,26 @@ int grid_hmc_energy(const void *U, const void *P, const void *phi, const grid_ge
                     grid_md_stats *stats, void *stream);
 
 /*
+ * Two-flavour pseudofermion action (the fermion part of the HMC action, Section 4) with its
+ * gradients, for callers that differentiate it (an autograd function, a force evaluation):
+ *   X  = (Op^+ Op)^-1 phi by grid_cg with `params` (Op = D for GRID_WILSON, the Shamir M for
+ *        GRID_DWF); X holds the initial guess on entry and the solution on exit;
+ *   *S = Re <phi, X> = phi^+ (Op^+ Op)^-1 phi, an FP64 sum in a fixed order (S nullable);
+ *   dS_dU   (nullable) = grad_scale * dS/dU, dS/dU = -2 G(g = Op X, psi = X) with G the link
+ *           gradient of grid_dhop_backward (c = -1/2), i.e. the sum there with coefficient 1;
+ *           force_mode 1 writes its su(3) projection TA(dS/dU U^+) instead;
+ *   dS_dphi (nullable) = grad_scale * 2 X.
+ * U, phi, X, dS_dphi FP64 ([V][4][3][3] / spinor layout); workspace >=
+ * grid_pseudofermion_workspace_bytes(), 256-byte aligned; outputs must not overlap each other or
+ * the inputs. Synchronous. Returns GRID_OK, GRID_ENOCONV (S and the gradients are still written,
+ * from the unconverged X), GRID_EBREAKDOWN or an argument / HIP error.
+ */
+size_t grid_pseudofermion_workspace_bytes(const grid_geom *geom, const grid_cg_params *params);
+int grid_pseudofermion_action(const void *U, const void *phi, void *X, const grid_geom *geom, const grid_op *op,
+                              const grid_cg_params *params, double grad_scale, double *S, void *dS_dU, int force_mode,
+                              void *dS_dphi, void *workspace, size_t ws_bytes, grid_cg_stats *stats, void *stream);
+
+/*
  * Generic coarse stencil and two-level multigrid for the Wilson operator D (Section 2.4's stencil
  * example is the coarse-grid operator of an adaptive multigrid inverter; Section 4 lists
  * multigrid-preconditioned GCR). FP64 throughout.

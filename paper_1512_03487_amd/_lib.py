@@ -22,6 +22,7 @@ GRID_LEAPFROG, GRID_OMELYAN, GRID_FORCE_GRADIENT = 0, 1, 2
 EXPORTS = ("grid_dhop", "grid_mobius", "grid_dwf_mdag_m", "grid_cg_workspace_bytes", "grid_cg", "grid_dhop_backward",
            "grid_dhop_cb", "grid_m5inv", "grid_solve_eo_workspace_bytes", "grid_solve_eo",
            "grid_md_workspace_bytes", "grid_gauge_force", "grid_link_exp", "grid_md_leapfrog", "grid_hmc_energy",
+           "grid_pseudofermion_workspace_bytes", "grid_pseudofermion_action",
            "grid_convert_spinor", "grid_convert_links", "grid_coarse_stencil", "grid_mg_workspace_bytes",
            "grid_mg_basis", "grid_mg_coarse_op", "grid_mg_restrict", "grid_mg_prolong", "grid_mg_solve",
            "grid_last_error", "grid_version")
@@ -118,6 +119,12 @@ def load():
     lib.grid_hmc_energy.argtypes = [P, P, P, ctypes.POINTER(GridGeom), ctypes.POINTER(GridMdParams), P,
                                     ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(GridMdStats), P]
     lib.grid_hmc_energy.restype = I
+    lib.grid_pseudofermion_workspace_bytes.argtypes = [ctypes.POINTER(GridGeom), ctypes.POINTER(GridCgParams)]
+    lib.grid_pseudofermion_workspace_bytes.restype = ctypes.c_size_t
+    lib.grid_pseudofermion_action.argtypes = [P, P, P, ctypes.POINTER(GridGeom), ctypes.POINTER(GridOp),
+                                              ctypes.POINTER(GridCgParams), D, ctypes.POINTER(ctypes.c_double), P, I,
+                                              P, P, ctypes.c_size_t, ctypes.POINTER(GridCgStats), P]
+    lib.grid_pseudofermion_action.restype = I
     lib.grid_convert_spinor.argtypes = [P, I, P, P, I, P, ctypes.c_long, P]
     lib.grid_convert_spinor.restype = I
     lib.grid_convert_links.argtypes = [P, P, I, I, I, ctypes.c_long, P]

@@ -103,6 +103,42 @@ def link_format(U, prec: int) -> int:
     raise ValueError(f"link shape {tuple(U.shape)} is not (..., 4, 3, 3) or (..., 4, 2, 3)")
 
 
+def _check_like(t, ref, name, ref_name="psi"):
+    """Raise unless t is a field of ref's kind, shape, dtype and device (checked before any launch)."""
+    if isinstance(ref, F16Spinor):
+        if not isinstance(t, F16Spinor):
+            raise TypeError(f"{name} must be an F16Spinor like {ref_name}")
+        pairs = ((t.codes, ref.codes, ".codes"), (t.scale, ref.scale, ".scale"))
+    else:
+        if isinstance(t, F16Spinor) or not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor like {ref_name}")
+        pairs = ((t, ref, ""),)
+    for a, b, sfx in pairs:
+        _need_cuda(a, name + sfx)
+        if a.dtype != b.dtype:
+            raise TypeError(f"{name}{sfx} has dtype {a.dtype}, {ref_name}{sfx} has {b.dtype}")
+        if tuple(a.shape) != tuple(b.shape):
+            raise ValueError(f"{name}{sfx} has shape {tuple(a.shape)}, {ref_name}{sfx} has {tuple(b.shape)}")
+        if a.device != b.device:
+            raise ValueError(f"{name}{sfx} is on {a.device}, {ref_name}{sfx} on {b.device}")
+
+
+def _check_links(U, psi, name="U"):
+    """The links' site shape and device must be psi's (full-lattice fields)."""
+    sites = tuple(psi.shape[:4])
+    if tuple(U.shape[:4]) != sites:
+        raise ValueError(f"{name} has site shape {tuple(U.shape[:4])}, the spinor has {sites}")
+    dev = psi.device
+    if U.device != dev:
+        raise ValueError(f"{name} is on {U.device}, the spinor on {dev}")
+
+
+def _check_workspace(ws, ref):
+    _need_cuda(ws, "workspace")
+    if ws.device != ref.device:
+        raise ValueError(f"workspace is on {ws.device}, the fields on {ref.device}")
+
+
 def _data_scale(psi):
     if isinstance(psi, F16Spinor):
         return psi.codes, psi.scale
@@ -129,8 +165,11 @@ def dhop(U, psi, kind="hop", dag=False, mass=0.0, M5=1.8, mf=0.01, out=None):
     prec = spinor_prec(psi)
     fmt = link_format(U, prec)
     g = geom_of(psi)
+    _check_links(U, psi)
     if out is None:
         out = _empty_like(psi)
+    else:
+        _check_like(out, psi, "out")
     pd, ps = _data_scale(psi)
     od, os_ = _data_scale(out)
     op = make_op(kind, dag, mass, M5, mf)
@@ -152,6 +191,10 @@ def mobius(U, psi, M5, mf, b5, c5, dag=False, out=None, tmp=None):
     prec = spinor_prec(psi)
     fmt = link_format(U, prec)
     g = geom_of(psi)
+    _check_links(U, psi)
+    for t, n in ((out, "out"), (tmp, "tmp")):
+        if t is not None:
+            _check_like(t, psi, n)
     out = _empty_like(psi) if out is None else out
     tmp = _empty_like(psi) if tmp is None else tmp
     pd, ps = _data_scale(psi)
@@ -168,6 +211,10 @@ def dwf_mdag_m(U, psi, M5, mf, out=None, tmp=None):
     prec = spinor_prec(psi)
     fmt = link_format(U, prec)
     g = geom_of(psi)
+    _check_links(U, psi)
+    for t, n in ((out, "out"), (tmp, "tmp")):
+        if t is not None:
+            _check_like(t, psi, n)
     out = _empty_like(psi) if out is None else out
     tmp = _empty_like(psi) if tmp is None else tmp
     pd, ps = _data_scale(psi)
@@ -205,10 +252,15 @@ def cg(U, b, kind="dwf", mass=0.0, M5=1.8, mf=0.01, x0=None, workspace=None, rai
     if spinor_prec(b) != GRID_F64 or link_format(U, GRID_F64) != GRID_L18:
         raise TypeError("cg takes complex128 b and complex128 18-real links")
     g = geom_of(b)
+    _check_links(U, b)
+    if x0 is not None:
+        _check_like(x0, b, "x0", "b")
     p = cg_params(**params)
     need = int(load().grid_cg_workspace_bytes(ctypes.byref(g), ctypes.byref(p)))
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=b.device)
+    else:
+        _check_workspace(workspace, b)
     x = torch.zeros_like(b) if x0 is None else x0.clone()
     op = make_op(kind, False, mass, M5, mf, b5, c5)
     st = GridCgStats()
@@ -219,6 +271,43 @@ def cg(U, b, kind="dwf", mass=0.0, M5=1.8, mf=0.01, x0=None, workspace=None, rai
     if rc != 0 and raise_on_fail:
         check(rc)
     return x, stats
+
+
+def pseudofermion_action(U, phi, kind="wilson", mass=0.1, M5=1.8, mf=0.01, x0=None, grad_scale=1.0, want_S=True,
+                         want_U=False, force=False, want_phi=False, workspace=None, raise_on_fail=True, **params):
+    """Two-flavour pseudofermion action S = Re phi^dagger (Op^dagger Op)^-1 phi (Op = D or M, FP64).
+
+    Returns (S, X, dS_dU, dS_dphi, stats): S a float (None unless want_S), X the solution, and the
+    gradients scaled by grad_scale (None unless asked for); force=True gives the su(3) projection
+    of dS/dU. Every value is computed by the library (grid_pseudofermion_action). Synchronous.
+    """
+    if spinor_prec(phi) != GRID_F64 or link_format(U, GRID_F64) != GRID_L18:
+        raise TypeError("pseudofermion_action takes complex128 phi and complex128 18-real links")
+    g = geom_of(phi)
+    _check_links(U, phi)
+    if x0 is not None:
+        _check_like(x0, phi, "x0", "phi")
+    p = cg_params(**params)
+    need = int(load().grid_pseudofermion_workspace_bytes(ctypes.byref(g), ctypes.byref(p)))
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=phi.device)
+    else:
+        _check_workspace(workspace, phi)
+    X = torch.zeros_like(phi) if x0 is None else x0.clone()
+    gU = torch.empty(tuple(phi.shape[:4]) + (4, 3, 3), dtype=torch.complex128, device=phi.device) if want_U else None
+    gphi = torch.empty_like(phi) if want_phi else None
+    op = make_op(kind, False, mass, M5, mf)
+    S = ctypes.c_double(0.0)
+    st = GridCgStats()
+    rc = load().grid_pseudofermion_action(_ptr(U), _ptr(phi), _ptr(X), ctypes.byref(g), ctypes.byref(op),
+                                          ctypes.byref(p), float(grad_scale), ctypes.byref(S) if want_S else None,
+                                          _ptr(gU), int(bool(force)), _ptr(gphi), _ptr(workspace),
+                                          ctypes.c_size_t(workspace.numel()), ctypes.byref(st), _stream(phi.device))
+    stats = {"iterations": st.iterations, "reliable_updates": st.reliable_updates, "converged": bool(st.converged),
+             "true_residual": st.true_residual, "seconds": st.seconds, "status": rc}
+    if rc != 0 and raise_on_fail:
+        check(rc)
+    return (S.value if want_S else None), X, gU, gphi, stats
 
 
 def _geom_cb(U, psi) -> GridGeom:
@@ -238,8 +327,14 @@ def dhop_cb(U, psi, out_parity, kind="hop", y=None, beta=1.0, dag=False, mass=0.
     prec = spinor_prec(psi)
     fmt = link_format(U, prec)
     g = _geom_cb(U, psi)
+    if U.device != psi.device:
+        raise ValueError(f"U is on {U.device}, psi on {psi.device}")
     if out is None:
         out = _empty_like(psi)
+    else:
+        _check_like(out, psi, "out")
+    if y is not None:
+        _check_like(y, psi, "y")
     pd, ps = _data_scale(psi)
     yd, ys = _data_scale(y) if y is not None else (None, None)
     od, os_ = _data_scale(out)
@@ -256,6 +351,8 @@ def m5inv(psi, M5, mf, dag=False, out=None):
     if len(shape) != 7:
         raise ValueError("m5inv takes a 5D field (..., Ls, 4, 3)")
     n4 = int(shape[0]) * int(shape[1]) * int(shape[2]) * int(shape[3])
+    if out is not None:
+        _check_like(out, psi, "out")
     out = _empty_like(psi) if out is None else out
     pd, ps = _data_scale(psi)
     od, os_ = _data_scale(out)
@@ -278,12 +375,17 @@ def solve_eo(U, b, kind="dwf", mass=0.0, M5=1.8, mf=0.01, x0=None, workspace=Non
     if spinor_prec(b) != GRID_F64 or link_format(U, GRID_F64) != GRID_L18:
         raise TypeError("solve_eo takes complex128 b and complex128 18-real links")
     g = geom_of(b)
+    _check_links(U, b)
+    if x0 is not None:
+        _check_like(x0, b, "x0", "b")
     p = cg_params(**params)
     need = int(load().grid_solve_eo_workspace_bytes(ctypes.byref(g), ctypes.byref(p)))
     if need == 0:
         raise ValueError("invalid geometry or parameters for solve_eo (every extent must be even)")
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=b.device)
+    else:
+        _check_workspace(workspace, b)
     x = torch.zeros_like(b) if x0 is None else x0.clone()
     op = make_op(kind, False, mass, M5, mf)
     st = GridCgStats()
@@ -309,6 +411,8 @@ def _geom_links(U, Ls=1) -> GridGeom:
 def gauge_force(U, beta, out=None):
     """su(3) force of the Wilson plaquette action on every link."""
     g = _geom_links(U)
+    if out is not None:
+        _check_like(out, U, "out", "U")
     F = torch.empty_like(U) if out is None else out
     check(load().grid_gauge_force(_ptr(U), _ptr(F), ctypes.byref(g), float(beta), _stream(U.device)))
     return F
@@ -317,8 +421,7 @@ def gauge_force(U, beta, out=None):
 def link_exp(U, P, eps):
     """U <- exp(eps P) U in place (returns U)."""
     _geom_links(U)
-    if P.shape != U.shape or P.dtype != U.dtype:
-        raise ValueError("P must match U")
+    _check_like(P, U, "P", "U")
     check(load().grid_link_exp(_ptr(U), _ptr(P), float(eps), U.numel() // 9, _stream(U.device)))
     return U
 
@@ -334,13 +437,18 @@ def md_params(beta, eps=0.1, n_steps=10, kind="dwf", mass=0.0, M5=1.8, mf=0.01, 
     return p
 
 
-def _md_setup(U, phi, workspace, p):
+def _md_setup(U, phi, workspace, p, P=None):
     Ls = 1
     if phi is not None:
         if spinor_prec(phi) != GRID_F64:
             raise TypeError("phi must be complex128")
         Ls = geom_of(phi).Ls
+        _check_links(U, phi)
     g = _geom_links(U, Ls)
+    if P is not None:
+        _check_like(P, U, "P", "U")
+    if workspace is not None:
+        _check_workspace(workspace, U)
     need = int(load().grid_md_workspace_bytes(ctypes.byref(g), ctypes.byref(p)))
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=U.device)
@@ -351,7 +459,7 @@ def md_leapfrog(U, P, beta, eps, n_steps, phi=None, workspace=None, **kw):
     """Molecular dynamics of (U, P) in place (integrator="leapfrog" | "omelyan" | "force_gradient" in
     kw); phi adds the pseudofermion force. Returns stats."""
     p = md_params(beta, eps, n_steps, **kw)
-    g, workspace = _md_setup(U, phi, workspace, p)
+    g, workspace = _md_setup(U, phi, workspace, p, P)
     st = GridMdStats()
     check(load().grid_md_leapfrog(_ptr(U), _ptr(P), _ptr(phi), ctypes.byref(g), ctypes.byref(p), _ptr(workspace),
                                   ctypes.c_size_t(workspace.numel()), ctypes.byref(st), _stream(U.device)))
@@ -362,7 +470,7 @@ def md_leapfrog(U, P, beta, eps, n_steps, phi=None, workspace=None, **kw):
 def hmc_energy(U, P, beta, phi=None, workspace=None, **kw):
     """{"K", "S_G", "S_F", "H"} in FP64."""
     p = md_params(beta, **kw)
-    g, workspace = _md_setup(U, phi, workspace, p)
+    g, workspace = _md_setup(U, phi, workspace, p, P)
     st = GridMdStats()
     e = (ctypes.c_double * 4)()
     check(load().grid_hmc_energy(_ptr(U), _ptr(P), _ptr(phi), ctypes.byref(g), ctypes.byref(p), _ptr(workspace),
@@ -379,6 +487,8 @@ def dhop_backward(U, psi, grad_out, kind="hop", dag=False, mass=0.0, M5=1.8, mf=
     if link_format(U, prec) != GRID_L18:
         raise TypeError("dhop_backward takes 18-real links")
     g = geom_of(psi)
+    _check_links(U, psi)
+    _check_like(grad_out, psi, "grad_out")
     gp = torch.empty_like(psi) if want_psi else None
     gu = torch.empty(tuple(psi.shape[:4]) + (4, 3, 3), dtype=psi.dtype, device=psi.device) if want_U else None
     op = make_op(kind, dag, mass, M5, mf)
@@ -450,13 +560,16 @@ def mg_params(block=(2, 2, 2, 2), nvec=6, setup_rounds=2, setup_iters=8, coarse_
 
 
 def _coarse_shape(psi_or_U, block, N):
-    lt, lz, ly, lx = psi_or_U.shape[:4]
+    shape = psi_or_U.shape if hasattr(psi_or_U, "shape") else psi_or_U
+    lt, lz, ly, lx = shape[:4]
     bx, by, bz, bt = block
     return (lt // bt, lz // bz, ly // by, lx // bx, N)
 
 
 def _mg_ws(U, p, workspace):
     g = geom_of_links(U)
+    if workspace is not None:
+        _check_workspace(workspace, U)
     need = int(load().grid_mg_workspace_bytes(ctypes.byref(g), ctypes.byref(p)))
     if need == 0:
         check(load().grid_mg_restrict(None, None, None, ctypes.byref(g), ctypes.byref(p), None))
@@ -465,7 +578,24 @@ def _mg_ws(U, p, workspace):
     return g, workspace
 
 
+def _check_vecs(vecs, U):
+    """Basis vectors (nvec, Lt, Lz, Ly, Lx, 4, 3) complex128 on U's lattice and device."""
+    _need_cuda(vecs, "vecs")
+    if vecs.dtype != torch.complex128 or vecs.dim() != 7 or tuple(vecs.shape[5:]) != (4, 3):
+        raise ValueError("vecs must be complex128 (nvec, Lt, Lz, Ly, Lx, 4, 3)")
+    if tuple(vecs.shape[1:5]) != tuple(U.shape[:4]) or vecs.device != U.device:
+        raise ValueError(f"vecs {tuple(vecs.shape)} on {vecs.device} do not match U {tuple(U.shape)} on {U.device}")
+
+
+def _check_coarse_op(A, U, block, N):
+    _need_cuda(A, "A")
+    want = _coarse_shape(U, block, N)[:4] + (9, N, N)
+    if A.dtype != torch.complex128 or tuple(A.shape) != want or A.device != U.device:
+        raise ValueError(f"A must be complex128 {want} on {U.device}")
+
+
 def geom_of_links(U) -> GridGeom:
+    _need_cuda(U, "U")
     if U.dtype != torch.complex128 or tuple(U.shape[4:]) != (4, 3, 3):
         raise TypeError("multigrid takes complex128 links (Lt, Lz, Ly, Lx, 4, 3, 3)")
     g = GridGeom()
@@ -493,7 +623,7 @@ def mg_basis(U, vecs, mass, workspace=None, **params):
     """In place: near-null improvement of the caller's vecs (nvec, Lt, Lz, Ly, Lx, 4, 3) and blockwise
     Gram-Schmidt. Returns vecs."""
     p = mg_params(nvec=int(vecs.shape[0]), **params)
-    _need_cuda(vecs, "vecs")
+    _check_vecs(vecs, U)
     g, workspace = _mg_ws(U, p, workspace)
     op = make_op("wilson", False, mass)
     check(load().grid_mg_basis(_ptr(U), _ptr(vecs), ctypes.byref(g), ctypes.byref(op), ctypes.byref(p), _ptr(workspace),
@@ -505,8 +635,11 @@ def mg_coarse_op(U, vecs, mass, workspace=None, out=None, **params):
     """Galerkin coarse operator R D P as a (Lct, Lcz, Lcy, Lcx, 9, N, N) complex128 tensor."""
     nvec = int(vecs.shape[0])
     p = mg_params(nvec=nvec, **params)
+    _check_vecs(vecs, U)
     g, workspace = _mg_ws(U, p, workspace)
     cs = _coarse_shape(U, p.block, 2 * nvec)
+    if out is not None:
+        _check_coarse_op(out, U, p.block, 2 * nvec)
     A = torch.empty(cs[:4] + (9, 2 * nvec, 2 * nvec), dtype=torch.complex128, device=U.device) if out is None else out
     op = make_op("wilson", False, mass)
     check(load().grid_mg_coarse_op(_ptr(U), _ptr(vecs), _ptr(A), ctypes.byref(g), ctypes.byref(op), ctypes.byref(p),
@@ -517,7 +650,10 @@ def mg_coarse_op(U, vecs, mass, workspace=None, out=None, **params):
 def mg_restrict(vecs, psi, block):
     nvec = int(vecs.shape[0])
     p = mg_params(block=block, nvec=nvec)
+    if spinor_prec(psi) != GRID_F64:
+        raise TypeError("mg_restrict takes a complex128 psi")
     g = geom_of(psi)
+    _check_vecs(vecs, psi)
     vc = torch.empty(_coarse_shape(psi, block, 2 * nvec), dtype=torch.complex128, device=psi.device)
     check(load().grid_mg_restrict(_ptr(vecs), _ptr(psi), _ptr(vc), ctypes.byref(g), ctypes.byref(p),
                                   _stream(psi.device)))
@@ -527,6 +663,11 @@ def mg_restrict(vecs, psi, block):
 def mg_prolong(vecs, vc, block):
     nvec = int(vecs.shape[0])
     p = mg_params(block=block, nvec=nvec)
+    _need_cuda(vecs, "vecs")
+    _need_cuda(vc, "vc")
+    want = _coarse_shape(vecs.shape[1:], block, 2 * nvec)
+    if vc.dtype != torch.complex128 or tuple(vc.shape) != want or vc.device != vecs.device:
+        raise ValueError(f"vc must be complex128 {want} on {vecs.device}")
     psi = torch.empty(tuple(vecs.shape[1:]), dtype=torch.complex128, device=vecs.device)
     g = geom_of(psi)
     check(load().grid_mg_prolong(_ptr(vecs), _ptr(vc), _ptr(psi), ctypes.byref(g), ctypes.byref(p),
@@ -538,6 +679,13 @@ def mg_solve(U, vecs, A, b, mass, x0=None, workspace=None, raise_on_fail=True, *
     """D x = b by multigrid-preconditioned flexible GCR. Returns (x, stats)."""
     nvec = int(vecs.shape[0])
     p = mg_params(nvec=nvec, **params)
+    _check_vecs(vecs, U)
+    _check_coarse_op(A, U, p.block, 2 * nvec)
+    if spinor_prec(b) != GRID_F64:
+        raise TypeError("mg_solve takes a complex128 b")
+    _check_links(U, b)
+    if x0 is not None:
+        _check_like(x0, b, "x0", "b")
     g, workspace = _mg_ws(U, p, workspace)
     x = torch.zeros_like(b) if x0 is None else x0.clone()
     op = make_op("wilson", False, mass)

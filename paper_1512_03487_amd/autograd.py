@@ -33,27 +33,24 @@ class DhopFn(torch.autograd.Function):
 class PseudofermionActionFn(torch.autograd.Function):
     """S = Re phi^dagger (Op^dagger Op)^-1 phi (Op = D or M, FP64), differentiable in U and phi.
 
-    The solve is recomputed in backward instead of being stored: with X = (Op^dagger Op)^-1 phi
-    and Y = Op X, dS/dU = -2 G(grad_out = Y, psi = X) and dS/dphi = 2 X.
+    The library computes S (a fixed-order FP64 reduction) and, in backward, dS/dU = -2 G(Op X, X)
+    and dS/dphi = 2 X scaled by the upstream gradient (grid_pseudofermion_action); the solve X is
+    recomputed there instead of being stored.
     """
 
     @staticmethod
     def forward(ctx, U, phi, kind="wilson", mass=0.1, M5=1.8, mf=0.01, tol=1e-12, sloppy="f64"):
         ctx.save_for_backward(U, phi)
-        ctx.cfg = dict(kind=kind, mass=mass, M5=M5, mf=mf)
-        ctx.solve = dict(tol=tol, sloppy=sloppy)
-        X, _ = api.cg(U, phi, **ctx.cfg, **ctx.solve)
-        return torch.vdot(phi.reshape(-1), X.reshape(-1)).real
+        ctx.cfg = dict(kind=kind, mass=mass, M5=M5, mf=mf, tol=tol, sloppy=sloppy)
+        S, _, _, _, _ = api.pseudofermion_action(U, phi, **ctx.cfg)
+        return torch.tensor(S, dtype=torch.float64, device=phi.device)
 
     @staticmethod
     def backward(ctx, gS):
         U, phi = ctx.saved_tensors
-        X, _ = api.cg(U, phi, **ctx.cfg, **ctx.solve)
-        gU = gphi = None
-        if ctx.needs_input_grad[0]:
-            Y = api.dhop(U, X, **ctx.cfg)
-            _, G = api.dhop_backward(U, X, Y, want_psi=False, want_U=True, **ctx.cfg)
-            gU = (-2.0 * gS) * G
-        if ctx.needs_input_grad[1]:
-            gphi = (2.0 * gS) * X
+        want_U, want_phi = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        if not (want_U or want_phi):
+            return None, None, None, None, None, None, None, None
+        _, _, gU, gphi, _ = api.pseudofermion_action(U, phi, grad_scale=float(gS), want_S=False, want_U=want_U,
+                                                     want_phi=want_phi, **ctx.cfg)
         return gU, gphi, None, None, None, None, None, None

@@ -183,6 +183,61 @@ int check_ws(const void *ws, size_t bytes, size_t need) {
     return GRID_OK;
 }
 
+// Normal operator M^dagger M: argument checks (tmp == NULL skips those of tmp) and the two launches.
+int check_mdag_m(const GeomDev &g, const void *U, const void *psi, const float *psi_scale, const void *out,
+                 const float *out_scale, const void *tmp, const float *tmp_scale, int prec, int link_fmt) {
+    TRY(check_prec(prec));
+    TRY(check_fmt(link_fmt));
+    TRY(check_ptr(U, "U", 16));
+    TRY(check_spinor(psi, psi_scale, prec, "psi", "psi_scale"));
+    TRY(check_spinor(out, out_scale, prec, "out", "out_scale"));
+    const size_t sb = spinor_site_bytes(prec) * static_cast<size_t>(g.n5);
+    const size_t ub = link_bytes(prec, link_fmt) * static_cast<size_t>(g.vol) * 4;
+    const size_t cb = prec == GRID_F16S ? sizeof(float) * static_cast<size_t>(g.n5) : 0;
+    if (overlap(out, sb, psi, sb) || overlap(out, sb, U, ub)) return fail(GRID_EINVAL, "out overlaps psi or U");
+    if (cb && (overlap(out_scale, cb, psi_scale, cb) || overlap(out_scale, cb, out, sb) ||
+               overlap(out_scale, cb, psi, sb)))
+        return fail(GRID_EINVAL, "out_scale overlaps an input or out");
+    if (tmp) {
+        TRY(check_spinor(tmp, tmp_scale, prec, "tmp", "tmp_scale"));
+        if (overlap(tmp, sb, psi, sb) || overlap(tmp, sb, out, sb) || overlap(tmp, sb, U, ub))
+            return fail(GRID_EINVAL, "tmp overlaps psi, out or U");
+        if (cb && (overlap(tmp_scale, cb, psi_scale, cb) || overlap(tmp_scale, cb, out_scale, cb) ||
+                   overlap(tmp_scale, cb, tmp, sb)))
+            return fail(GRID_EINVAL, "tmp_scale overlaps another field");
+    } else if (tmp_scale) {
+        return fail(GRID_EINVAL, "tmp_scale without tmp");
+    }
+    return GRID_OK;
+}
+
+hipError_t launch_mdag_m(const GeomDev &g, const void *U, const void *psi, const float *psi_scale, void *out,
+                         float *out_scale, void *tmp, float *tmp_scale, double M5, double mf, int prec, int link_fmt,
+                         hipStream_t st) {
+    DhopArgs a;
+    a.U = U;
+    a.psi = psi;
+    a.psi_scale = psi_scale;
+    a.out = tmp;
+    a.out_scale = tmp_scale;
+    a.g = g;
+    a.prec = prec;
+    a.link_fmt = link_fmt;
+    a.kind = GRID_DWF;
+    a.dag = 0;
+    a.diag = 5.0 - M5;
+    a.mf = mf;
+    a.stream = st;
+    hipError_t e = launch_dhop(a);
+    if (e != hipSuccess) return e;
+    a.psi = tmp;
+    a.psi_scale = tmp_scale;
+    a.out = out;
+    a.out_scale = out_scale;
+    a.dag = 1;
+    return launch_dhop(a);
+}
+
 }  // namespace
 
 extern "C" {
@@ -277,15 +332,11 @@ int grid_dwf_mdag_m(const void *U, const void *psi, const float *psi_scale, void
                     void *stream) {
     GeomDev g;
     TRY(check_geom(geom, &g));
-    TRY(check_prec(prec));
-    TRY(check_fmt(link_fmt));
-    TRY(check_spinor(tmp, tmp_scale, prec, "tmp", "tmp_scale"));
-    const size_t sb = spinor_site_bytes(prec) * static_cast<size_t>(g.n5);
-    if (overlap(tmp, sb, psi, sb) || overlap(tmp, sb, out, sb)) return fail(GRID_EINVAL, "tmp overlaps psi or out");
-    grid_op m = {GRID_DWF, 0, 0.0, M5, mf, 1.0, 0.0};
-    TRY(grid_dhop(U, psi, psi_scale, tmp, tmp_scale, geom, &m, prec, link_fmt, stream));
-    m.dag = 1;
-    return grid_dhop(U, tmp, tmp_scale, out, out_scale, geom, &m, prec, link_fmt, stream);
+    TRY(check_mdag_m(g, U, psi, psi_scale, out, out_scale, tmp, tmp_scale, prec, link_fmt));
+    hipError_t e = launch_mdag_m(g, U, psi, psi_scale, out, out_scale, tmp, tmp_scale, M5, mf, prec, link_fmt,
+                                 static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "grid_dwf_mdag_m launch");
+    return ok();
 }
 
 int grid_dhop_backward(const void *U, const void *psi, const void *grad_out, void *grad_psi, void *grad_U,
@@ -527,6 +578,50 @@ int grid_md_leapfrog(void *U, void *P, const void *phi, const grid_geom *geom, c
     TRY(check_md_buffers(g, params, U, P, phi, workspace, ws_bytes));
     hipError_t e = run_md_leapfrog(U, P, phi, g, *params, workspace, static_cast<hipStream_t>(stream), stats);
     if (e != hipSuccess) return hip_fail(e, "grid_md_leapfrog");
+    return ok();
+}
+
+size_t grid_pseudofermion_workspace_bytes(const grid_geom *geom, const grid_cg_params *params) {
+    GeomDev g;
+    if (!params || check_geom(geom, &g) != GRID_OK) return 0;
+    if (check_prec(params->sloppy_prec) != GRID_OK || check_fmt(params->link_fmt) != GRID_OK) return 0;
+    return pf_workspace_bytes(g, *params);
+}
+
+int grid_pseudofermion_action(const void *U, const void *phi, void *X, const grid_geom *geom, const grid_op *op,
+                              const grid_cg_params *params, double grad_scale, double *S, void *dS_dU, int force_mode,
+                              void *dS_dphi, void *workspace, size_t ws_bytes, grid_cg_stats *stats, void *stream) {
+    GeomDev g;
+    TRY(check_geom(geom, &g));
+    TRY(check_solver_args(g, op, params, stats));
+    if (op->kind != GRID_WILSON && op->kind != GRID_DWF)
+        return fail(GRID_EINVAL, "the pseudofermion action takes GRID_WILSON or GRID_DWF (got kind %d)", op->kind);
+    if (force_mode != 0 && force_mode != 1) return fail(GRID_EINVAL, "force_mode must be 0 or 1 (got %d)", force_mode);
+    if (!isfinite(grad_scale)) return fail(GRID_EINVAL, "grad_scale must be finite");
+    TRY(check_ptr(U, "U", 16));
+    TRY(check_ptr(phi, "phi", 16));
+    TRY(check_ptr(X, "X", 16));
+    if (dS_dU) TRY(check_ptr(dS_dU, "dS_dU", 16));
+    if (dS_dphi) TRY(check_ptr(dS_dphi, "dS_dphi", 16));
+    TRY(check_ptr(workspace, "workspace", 256));
+    const size_t need = pf_workspace_bytes(g, *params);
+    if (ws_bytes < need) return fail(GRID_ESPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    const size_t sb = static_cast<size_t>(g.n5) * 192, ub = static_cast<size_t>(g.vol) * 4 * 144;
+    const void *bufs[6] = {U, phi, X, dS_dU, dS_dphi, workspace};
+    const size_t sizes[6] = {ub, sb, sb, ub, sb, need};
+    for (int i = 2; i < 6; ++i)        // outputs against every other buffer (inputs may share memory)
+        for (int j = 0; j < 6; ++j)
+            if (j != i && overlap(bufs[i], sizes[i], bufs[j], sizes[j]))
+                return fail(GRID_EINVAL, "X, dS_dU, dS_dphi and workspace must not overlap each other or U, phi");
+    int status = GRID_OK;
+    memset(stats, 0, sizeof(*stats));
+    hipError_t e = run_pseudofermion(U, phi, X, g, *op, *params, grad_scale, S, dS_dU, force_mode, dS_dphi, workspace,
+                                     static_cast<hipStream_t>(stream), stats, &status);
+    if (e != hipSuccess) return hip_fail(e, "grid_pseudofermion_action");
+    if (status == GRID_ENOCONV)
+        return fail(GRID_ENOCONV, "the solve stopped after %d iterations at true residual %.3e", stats->iterations,
+                    stats->true_residual);
+    if (status == GRID_EBREAKDOWN) return fail(GRID_EBREAKDOWN, "CG breakdown after %d iterations", stats->iterations);
     return ok();
 }
 

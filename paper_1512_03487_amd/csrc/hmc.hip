@@ -454,6 +454,83 @@ hipError_t run_md_leapfrog(void *U, void *P, const void *phi, const GeomDev &g, 
     return hipSuccess;
 }
 
+// ----------------------------------------------------------------------------------------------
+// Two-flavour pseudofermion action on its own (the fermion part of the HMC action, Section 4):
+// X = (Op^dagger Op)^-1 phi, S = Re <phi, X> by the fixed-order FP64 reduction, and the gradients
+// scaled by the caller's upstream factor: dS/dU = -2 G_{c=-1/2}(chi = Op X, psi = X) = G_{c=1}
+// (raw, or TA(dS/dU U^dagger)) and dS/dphi = 2 X.
+// ----------------------------------------------------------------------------------------------
+
+// y = a x over n doubles.
+__global__ void __launch_bounds__(256) k_dscal(double *__restrict__ y, const double *__restrict__ x, double a, long n) {
+    for (long i = static_cast<long>(blockIdx.x) * 256 + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * 256)
+        y[i] = a * x[i];
+}
+
+struct PfLayout {
+    size_t Y, part, cg, total;
+};
+
+static PfLayout pf_layout(const GeomDev &g, const grid_cg_params &p) {
+    PfLayout L;
+    size_t off = 0;
+    L.Y = off;
+    off = al256(off + static_cast<size_t>(g.n5) * 192);
+    L.part = off;
+    off = al256(off + (kHmcParts + 16) * sizeof(double));
+    L.cg = off;
+    L.total = off + cg_workspace_bytes(g, p.sloppy_prec, p.link_fmt);
+    return L;
+}
+
+size_t pf_workspace_bytes(const GeomDev &g, const grid_cg_params &p) { return pf_layout(g, p).total; }
+
+hipError_t run_pseudofermion(const void *U, const void *phi, void *X, const GeomDev &g, const grid_op &op,
+                             const grid_cg_params &p, double grad_scale, double *S, void *dS_dU, int force_mode,
+                             void *dS_dphi, void *ws, hipStream_t st, grid_cg_stats *stats, int *status) {
+    const PfLayout L = pf_layout(g, p);
+    char *w = static_cast<char *>(ws);
+    HMCCHK(run_cg(U, phi, X, g, op, p, w + L.cg, st, stats, status));
+    if (S) HMCCHK(dot_re(phi, X, g.n5, reinterpret_cast<double *>(w + L.part), st, S));
+    if (dS_dU) {
+        DhopArgs a;
+        a.U = U;
+        a.psi = X;
+        a.psi_scale = nullptr;
+        a.out = w + L.Y;
+        a.out_scale = nullptr;
+        a.g = g;
+        a.prec = GRID_F64;
+        a.link_fmt = GRID_L18;
+        a.kind = op.kind;
+        a.dag = 0;
+        a.diag = op.kind == GRID_WILSON ? 4.0 + op.mass : 5.0 - op.M5;
+        a.mf = op.mf;
+        a.stream = st;
+        HMCCHK(launch_dhop(a));
+        LinkGradArgs la;
+        la.U = U;
+        la.chi = w + L.Y;
+        la.psi = X;
+        la.G = dS_dU;
+        la.g = g;
+        la.prec = GRID_F64;
+        la.dag = 0;
+        la.force_mode = force_mode;
+        la.coef = grad_scale;   // -2 G_{c=-1/2} = G_{c=1}, times the upstream factor
+        la.stream = st;
+        HMCCHK(launch_link_grad(la));
+    }
+    if (dS_dphi && g.n5 > 0) {
+        const long n = static_cast<long>(g.n5) * 24;
+        const long blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+        hipLaunchKernelGGL(k_dscal, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, static_cast<double *>(dS_dphi),
+                           static_cast<const double *>(X), 2.0 * grad_scale, n);
+        HMCCHK(hipGetLastError());
+    }
+    return hipSuccess;
+}
+
 // energies[0..3] = K, S_G, S_F, H.
 hipError_t run_hmc_energy(const void *U, const void *P, const void *phi, const GeomDev &g, const grid_md_params &p,
                           void *ws, hipStream_t st, double energies[4], grid_md_stats *stats) {

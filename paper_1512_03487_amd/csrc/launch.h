@@ -138,6 +138,13 @@ hipError_t run_md_leapfrog(void *U, void *P, const void *phi, const GeomDev &g, 
 hipError_t run_hmc_energy(const void *U, const void *P, const void *phi, const GeomDev &g, const grid_md_params &p,
                           void *ws, hipStream_t st, double energies[4], grid_md_stats *stats);
 
+// Two-flavour pseudofermion action and gradients (hmc.hip); arguments validated. X: initial guess
+// on entry, the solution on exit; S, dS_dU, dS_dphi nullable.
+size_t pf_workspace_bytes(const GeomDev &g, const grid_cg_params &p);
+hipError_t run_pseudofermion(const void *U, const void *phi, void *X, const GeomDev &g, const grid_op &op,
+                             const grid_cg_params &p, double grad_scale, double *S, void *dS_dU, int force_mode,
+                             void *dS_dphi, void *ws, hipStream_t st, grid_cg_stats *stats, int *status);
+
 // Coarse stencil and two-level multigrid for the Wilson operator (mg.hip); arguments validated.
 hipError_t launch_coarse_stencil(const void *A, const void *v, void *out, const int Lc[4], int N, int dag,
                                  hipStream_t st);

@@ -282,3 +282,34 @@ def test_parameter_builders():
     assert api.mg_params(cycle_prec="f32").cycle_prec == _lib.GRID_F32
     m = api.md_params(5.5, integrator="force_gradient", n_inner=1)
     assert m.integrator == _lib.GRID_FORCE_GRADIENT
+
+
+def test_pseudofermion_action_validation(lib):
+    g = geom((4, 4, 4, 4), Ls=4)
+    n, nl = 4 ** 4 * 4, 4 ** 4 * 4
+    p64 = _lib.GridCgParams(1e-10, 100, _lib.GRID_F64, _lib.GRID_L18, 0.1, 10)
+    w = lib.grid_pseudofermion_workspace_bytes(ctypes.byref(g), ctypes.byref(p64))
+    # the CG's workspace plus one FP64 field for Op X
+    assert w >= lib.grid_cg_workspace_bytes(ctypes.byref(g), ctypes.byref(p64)) + n * 192
+    assert lib.grid_pseudofermion_workspace_bytes(ctypes.byref(g), ctypes.byref(_lib.GridCgParams(1e-10, 100, 9, 0, 0.1,
+                                                                                                  10))) == 0
+    st = _lib.GridCgStats()
+    S = ctypes.c_double()
+    U, phi, X, dU, dphi, ws = A, A + 2**28, A + 2**29, A + 3 * 2**28, A + 2**30, A + 2**31
+
+    def call(oo=op(kind=_lib.GRID_DWF), x=X, du=dU, dp=dphi, wsp=ws, nb=w, fm=0, scale=1.0, gg=g):
+        return lib.grid_pseudofermion_action(P(U), P(phi), P(x), ctypes.byref(gg), ctypes.byref(oo),
+                                             ctypes.byref(p64), ctypes.c_double(scale), ctypes.byref(S), P(du), fm,
+                                             P(dp), P(wsp), ctypes.c_size_t(nb), ctypes.byref(st), None)
+    assert call(oo=op(kind=_lib.GRID_MOBIUS)) == _lib.GRID_EINVAL
+    assert call(oo=op(kind=_lib.GRID_HOP)) == _lib.GRID_EINVAL
+    assert call(oo=op(kind=_lib.GRID_WILSON)) == _lib.GRID_ESHAPE            # Wilson needs Ls 1
+    assert call(fm=2) == _lib.GRID_EINVAL
+    assert call(scale=float("inf")) == _lib.GRID_EINVAL
+    assert call(x=0) == _lib.GRID_EINVAL
+    assert call(nb=w - 1) == _lib.GRID_ESPACE
+    assert call(wsp=ws + 64) == _lib.GRID_EALIGN
+    assert call(x=phi + 64) == _lib.GRID_EINVAL and "overlap" in _lib.last_error()   # X overlaps phi
+    assert call(dp=X) == _lib.GRID_EINVAL                                    # dS/dphi overlaps X
+    assert call(du=U + 16 * nl) == _lib.GRID_EINVAL                          # dS/dU overlaps U
+    assert call(dp=dphi + 8) == _lib.GRID_EALIGN

@@ -112,3 +112,65 @@ def test_pseudofermion_force_8_4(gpu):
     assert rel(phid.grad.cpu().numpy(), 2 * X_ref) <= 1e-9
     F_gpu = O.force(Ud.grad.cpu().numpy(), U)
     assert rel(F_gpu, O.force(dS_ref, U)) <= 1e-9
+
+
+def test_autograd_dhopfn_fp32_12_4(gpu):
+    """12^4 weak field, FP32 DhopFn (Wilson D, m = 0.1): grad_psi and grad_U against the oracle
+    gradient evaluated on the FP32-rounded inputs."""
+    import torch
+    import paper_1512_03487_amd as gm
+    from tests.gpu_util import rel
+    (U, psi, chi), (Ur, pr, cr) = _inputs((12, 12, 12, 12), "f32")
+    U = U.clone().requires_grad_(True)
+    psi = psi.clone().requires_grad_(True)
+    out = gm.DhopFn.apply(U, psi, "wilson", False, 0.1)
+    loss = torch.vdot(chi.reshape(-1), out.reshape(-1)).real
+    loss.backward()
+    assert rel(psi.grad.cpu().numpy(), O.wilson(Ur, cr, 0.1, dag=True)) <= TOL["f32"]
+    assert rel(U.grad.cpu().numpy(), O.link_grad(cr, pr, c=-0.5)) <= TOL["f32"]
+
+
+def _pf_case(kind):
+    if kind == "wilson":
+        dims, Ls, op, kw = (8, 8, 8, 8), None, O.Op.wilson(0.1), dict(mass=0.1)
+    else:
+        dims, Ls, op, kw = (4, 4, 4, 4), 8, O.Op.dwf(8, 1.8, 0.01), dict(M5=1.8, mf=0.01)
+    U = F.gauge_field(dims, seed=1, kind="haar")
+    phi = F.spinor_field(dims, seed=5, Ls=Ls)
+    return U, phi, op, kw
+
+
+@pytest.mark.parametrize("kind", ["wilson", "dwf"])
+def test_pseudofermion_action_abi(gpu, kind):
+    """grid_pseudofermion_action: S, the scaled dS/dU (raw and su(3)-projected) and dS/dphi against
+    the oracle (Wilson 8^4, m = 0.1; domain wall 4^4 x 8, M5 = 1.8, mf = 0.01; Haar links)."""
+    import paper_1512_03487_amd as gm
+    from tests.gpu_util import dev, rel
+    U, phi, op, kw = _pf_case(kind)
+    S_ref, dS_ref, X_ref = O.pseudofermion(op, U, phi, tol=1e-13)
+    Ud, phid = dev(U), dev(phi)
+    S, X, gU, gphi, st = gm.pseudofermion_action(Ud, phid, kind, tol=1e-13, grad_scale=0.75, want_U=True,
+                                                 want_phi=True, **kw)
+    assert st["converged"]
+    assert abs(S - S_ref) <= 1e-11 * abs(S_ref)
+    assert rel(X.cpu().numpy(), X_ref) <= 1e-9
+    assert rel(gU.cpu().numpy(), 0.75 * dS_ref) <= 1e-9
+    assert rel(gphi.cpu().numpy(), 1.5 * X_ref) <= 1e-9
+    S2, _, Fk, _, _ = gm.pseudofermion_action(Ud, phid, kind, tol=1e-13, want_U=True, force=True, **kw)
+    assert S2 == S                                           # same solve from zero, same fixed-order sum
+    assert rel(Fk.cpu().numpy(), O.force(dS_ref, U)) <= 1e-9
+
+
+def test_pseudofermion_autograd_dwf(gpu):
+    """PseudofermionActionFn on the domain-wall operator at 4^4 x 8: S and both gradients."""
+    import paper_1512_03487_amd as gm
+    from tests.gpu_util import dev, rel
+    U, phi, op, kw = _pf_case("dwf")
+    S_ref, dS_ref, X_ref = O.pseudofermion(op, U, phi, tol=1e-13)
+    Ud = dev(U).requires_grad_(True)
+    phid = dev(phi).requires_grad_(True)
+    S = gm.PseudofermionActionFn.apply(Ud, phid, "dwf", 0.0, 1.8, 0.01, 1e-13)
+    (3.0 * S).backward()
+    assert abs(float(S) - S_ref) <= 1e-11 * abs(S_ref)
+    assert rel(Ud.grad.cpu().numpy(), 3.0 * dS_ref) <= 1e-9
+    assert rel(phid.grad.cpu().numpy(), 6.0 * X_ref) <= 1e-9
