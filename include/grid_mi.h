@@ -139,6 +139,19 @@ int grid_dwf_mdag_m(const void *U, const void *psi, const float *psi_scale, void
                     int link_fmt, void *stream);
 
 /*
+ * grid_dwf_mdag_m_noalloc -- grid_dwf_mdag_m for callers that cannot allocate device memory (code
+ * under HIP stream capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels, with M psi held in a static scratch array of the library (64 MiB per device, held from
+ * module load until the process ends) instead of a caller's tmp. Fields whose M psi needs more
+ * (V Ls x 192 / 96 / 52 bytes for FP64 / FP32 / FP16 storage, rounded up) are rejected with
+ * GRID_ESPACE. Calls no allocating routine. The scratch is shared by every call on a device: calls
+ * that overlap in time on one device (other streams, other threads) race and must be ordered by
+ * the caller. `stream` must belong to the current device. Same argument rules as grid_dwf_mdag_m.
+ */
+int grid_dwf_mdag_m_noalloc(const void *U, const void *psi, const float *psi_scale, void *out, float *out_scale,
+                            const grid_geom *geom, double M5, double mf, int prec, int link_fmt, void *stream);
+
+/*
  * grid_mobius -- out = M_mob psi (M_mob^+ psi when op->dag) for op->kind = GRID_MOBIUS: one
  * s-local pass (chi = B psi; for the adjoint B^+ after the hop) and one hopping pass. tmp (and
  * tmp_scale for GRID_F16S) holds the intermediate field and must have psi's size. Same argument

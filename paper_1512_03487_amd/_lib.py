@@ -19,7 +19,7 @@ GRID_HOP, GRID_WILSON, GRID_DWF, GRID_MOBIUS = 0, 1, 2, 3
 GRID_LEAPFROG, GRID_OMELYAN, GRID_FORCE_GRADIENT = 0, 1, 2
 
 #: every symbol include/grid_mi.h declares
-EXPORTS = ("grid_dhop", "grid_mobius", "grid_dwf_mdag_m", "grid_cg_workspace_bytes", "grid_cg", "grid_dhop_backward",
+EXPORTS = ("grid_dhop", "grid_mobius", "grid_dwf_mdag_m", "grid_dwf_mdag_m_noalloc", "grid_cg_workspace_bytes", "grid_cg", "grid_dhop_backward",
            "grid_dhop_cb", "grid_m5inv", "grid_solve_eo_workspace_bytes", "grid_solve_eo",
            "grid_md_workspace_bytes", "grid_gauge_force", "grid_link_exp", "grid_md_leapfrog", "grid_hmc_energy",
            "grid_pseudofermion_workspace_bytes", "grid_pseudofermion_action",
@@ -91,6 +91,8 @@ def load():
     lib.grid_mobius.restype = I
     lib.grid_dwf_mdag_m.argtypes = [P, P, P, P, P, P, P, ctypes.POINTER(GridGeom), D, D, I, I, P]
     lib.grid_dwf_mdag_m.restype = I
+    lib.grid_dwf_mdag_m_noalloc.argtypes = [P, P, P, P, P, ctypes.POINTER(GridGeom), D, D, I, I, P]
+    lib.grid_dwf_mdag_m_noalloc.restype = I
     lib.grid_cg_workspace_bytes.argtypes = [ctypes.POINTER(GridGeom), ctypes.POINTER(GridCgParams)]
     lib.grid_cg_workspace_bytes.restype = ctypes.c_size_t
     lib.grid_cg.argtypes = [P, P, P, ctypes.POINTER(GridGeom), ctypes.POINTER(GridOp), ctypes.POINTER(GridCgParams),

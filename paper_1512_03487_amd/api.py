@@ -225,6 +225,21 @@ def dwf_mdag_m(U, psi, M5, mf, out=None, tmp=None):
     return out
 
 
+def dwf_mdag_m_noalloc(U, psi, M5, mf, out):
+    """M^dagger M psi into the caller's out with no device allocation by the library (M psi goes to
+    its static 64 MiB scratch; larger fields are rejected). Calls overlapping on one device race."""
+    prec = spinor_prec(psi)
+    fmt = link_format(U, prec)
+    g = geom_of(psi)
+    _check_links(U, psi)
+    _check_like(out, psi, "out")
+    pd, ps = _data_scale(psi)
+    od, os_ = _data_scale(out)
+    check(load().grid_dwf_mdag_m_noalloc(_ptr(U), _ptr(pd), _ptr(ps), _ptr(od), _ptr(os_), ctypes.byref(g),
+                                         float(M5), float(mf), prec, fmt, _stream(pd.device)))
+    return out
+
+
 def cg_params(tol=1e-10, maxiter=20000, sloppy="f64", link_fmt="L18", delta=0.1, check_every=10,
               graph=False) -> GridCgParams:
     p = GridCgParams()

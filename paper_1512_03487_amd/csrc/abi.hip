@@ -7,6 +7,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "launch.h"
 
 using namespace gridmi;
@@ -238,6 +240,35 @@ hipError_t launch_mdag_m(const GeomDev &g, const void *U, const void *psi, const
     return launch_dhop(a);
 }
 
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Static scratch of the entry points that allocate nothing (callers that cannot call hipMalloc:
+// code under stream capture, tight serving loops). Each device holds its own copy from module load
+// until the process ends; its address on a device is looked up once, with that device current, and
+// kept. In host code `scratch` names a host-side stand-in, never passed to a kernel or copy.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(char **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(GRID_EINVAL, "device %d beyond the %d the library serves", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(GRID_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = static_cast<char *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return GRID_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -336,6 +367,24 @@ int grid_dwf_mdag_m(const void *U, const void *psi, const float *psi_scale, void
     hipError_t e = launch_mdag_m(g, U, psi, psi_scale, out, out_scale, tmp, tmp_scale, M5, mf, prec, link_fmt,
                                  static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "grid_dwf_mdag_m launch");
+    return ok();
+}
+
+int grid_dwf_mdag_m_noalloc(const void *U, const void *psi, const float *psi_scale, void *out, float *out_scale,
+                            const grid_geom *geom, double M5, double mf, int prec, int link_fmt, void *stream) {
+    GeomDev g;
+    TRY(check_geom(geom, &g));
+    TRY(check_mdag_m(g, U, psi, psi_scale, out, out_scale, nullptr, nullptr, prec, link_fmt));
+    const size_t tb = align256(spinor_site_bytes(prec) * static_cast<size_t>(g.n5));
+    const size_t need = tb + (prec == GRID_F16S ? sizeof(float) * static_cast<size_t>(g.n5) : 0);
+    if (need > kScratchBytes)
+        return fail(GRID_ESPACE, "M psi needs %zu bytes of scratch, above the library's static %zu bytes", need,
+                    kScratchBytes);
+    char *sp = nullptr;
+    TRY(scratch_of_current_device(&sp));
+    hipError_t e = launch_mdag_m(g, U, psi, psi_scale, out, out_scale, sp, prec == GRID_F16S ? reinterpret_cast<float *>(sp + tb) : nullptr,
+                                 M5, mf, prec, link_fmt, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "grid_dwf_mdag_m_noalloc launch");
     return ok();
 }
 

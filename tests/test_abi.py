@@ -313,3 +313,19 @@ def test_pseudofermion_action_validation(lib):
     assert call(dp=X) == _lib.GRID_EINVAL                                    # dS/dphi overlaps X
     assert call(du=U + 16 * nl) == _lib.GRID_EINVAL                          # dS/dU overlaps U
     assert call(dp=dphi + 8) == _lib.GRID_EALIGN
+
+
+def test_noalloc_normal_operator_validation(lib):
+    """The allocation-free normal operator rejects fields whose M psi exceeds its static scratch,
+    and bad arguments, on the host (nothing here reaches a HIP call)."""
+    o, big = op(), geom((16, 16, 16, 16), Ls=8)         # 524288 sites: 96 MiB of M psi in FP64
+    call = lambda g, prec=0, psi=A + 0x10000000, ps=None, out=A + 0x40000000, os_=None: lib.grid_dwf_mdag_m_noalloc(
+        P(A), P(psi), P(ps), P(out), P(os_), ctypes.byref(g), ctypes.c_double(1.8), ctypes.c_double(0.01), prec, 0,
+        None)
+    assert call(big) == _lib.GRID_ESPACE and "scratch" in _lib.last_error()
+    # FP16 storage at 16^4 x 16 fits (48 MiB of codes, 4 MiB of scales); 16^4 x 32 does not
+    assert call(geom((16, 16, 16, 16), Ls=32), prec=_lib.GRID_F16S, ps=A + 0x80000000,
+                os_=A + 0x90000000) == _lib.GRID_ESPACE
+    assert call(geom((4, 4, 4, 4), Ls=4), out=A + 0x10000000 + 64) == _lib.GRID_EINVAL    # out overlaps psi
+    assert call(geom((4, 4, 4, 4), Ls=4), prec=_lib.GRID_F16S) == _lib.GRID_EINVAL        # scales missing
+    assert call(geom((4, 4, 4, 1), Ls=4)) == _lib.GRID_ESHAPE
