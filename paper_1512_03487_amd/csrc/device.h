@@ -575,6 +575,31 @@ __device__ __forceinline__ void su3_adj_mul(const Cx<C> u[3][3], const Cx<C> h[2
         }
 }
 
+// Pin the accumulator in registers at this point of the program. The only use of the result is
+// the store of live lanes, so without this the compiler sinks all arithmetic below the last
+// gather (which every lane must execute) and keeps every gathered record live at once.
+template <typename C>
+__device__ __forceinline__ void pin(Cx<C> a[4][3]) {
+#pragma unroll
+    for (int j = 0; j < 12; ++j) __asm__ volatile("" : "+v"(a[j / 3][j % 3].r), "+v"(a[j / 3][j % 3].i));
+}
+
+// acc += (1 + E gamma_MU) V psi with V = U (ADJ false) or U^dagger (ADJ true)
+template <int MU, int E, bool ADJ, typename C>
+__device__ __forceinline__ void hop_term(Cx<C> acc[4][3], const Cx<C> p[4][3], const Cx<C> u[3][3]) {
+    Cx<C> h[2][3], chi[2][3];
+    project<MU, E>(p, h);
+    if (ADJ)
+        su3_adj_mul(u, h, chi);
+    else
+        su3_mul(u, h, chi);
+    reconstruct_add<MU, E>(acc, chi);
+    pin(acc);
+    // One direction at a time: hoisting later directions' loads above this point would raise
+    // per-wave parallelism at a larger cost in occupancy.
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 // ------------------------------------------------------------------------------------------
 // Geometry
 // ------------------------------------------------------------------------------------------

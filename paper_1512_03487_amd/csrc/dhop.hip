@@ -429,31 +429,6 @@ __device__ __forceinline__ void neighbours3(const GeomDev &g, int col, int nb[6]
 }
 
 
-// Pin the accumulator in registers at this point of the program. The only use of the result is
-// the store of live lanes, so without this the compiler sinks all arithmetic below the last
-// gather (which every lane must execute) and keeps every gathered record live at once.
-template <typename C>
-__device__ __forceinline__ void pin(Cx<C> a[4][3]) {
-#pragma unroll
-    for (int j = 0; j < 12; ++j) __asm__ volatile("" : "+v"(a[j / 3][j % 3].r), "+v"(a[j / 3][j % 3].i));
-}
-
-// acc += (1 + E gamma_MU) V psi with V = U (ADJ false) or U^dagger (ADJ true)
-template <int MU, int E, bool ADJ, typename C>
-__device__ __forceinline__ void hop_term(Cx<C> acc[4][3], const Cx<C> p[4][3], const Cx<C> u[3][3]) {
-    Cx<C> h[2][3], chi[2][3];
-    project<MU, E>(p, h);
-    if (ADJ)
-        su3_adj_mul(u, h, chi);
-    else
-        su3_mul(u, h, chi);
-    reconstruct_add<MU, E>(acc, chi);
-    pin(acc);
-    // One direction at a time: hoisting later directions' loads above this point would raise
-    // per-wave parallelism at a larger cost in occupancy.
-    __builtin_amdgcn_sched_barrier(0);
-}
-
 template <class SP, class LK, bool DAG, int KIND, int FUSE>
 __global__ void __launch_bounds__(256)
 k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const float *__restrict__ psi_scale,
@@ -869,12 +844,14 @@ static bool use_walk_cb(const DhopArgs &a) { return a.custom && a.cb >= 0 && wal
 
 template <class SP, class LK>
 static hipError_t launch_sched(const DhopArgs &a) {
+    if (tile_applies(a)) return launch_tile(a);
     if (use_walk(a)) return launch_walk<SP, LK>(a);
     if (use_walk_cb(a)) return launch_walk_cb<SP, LK>(a);
     return launch_dir<SP, LK>(a);
 }
 
 long dhop_blocks(const DhopArgs &a) {
+    if (tile_applies(a)) return tile_blocks(a);
     if (use_walk(a)) {
         const long nbc = (static_cast<long>(a.g.L[0]) * a.g.L[1] * a.g.L[2] * a.g.Ls + 255) / 256;
         return nbc * (a.g.L[3] / choose_steps(a.g));

@@ -55,6 +55,11 @@ struct DhopArgs {
 };
 
 hipError_t launch_dhop(const DhopArgs &a);
+// Tiled time-walk schedule (tile.hip): full-lattice 4D FP32 / FP16-storage fields whose x, y, z
+// extents the tile divides.
+bool tile_applies(const DhopArgs &a);
+long tile_blocks(const DhopArgs &a);
+hipError_t launch_tile(const DhopArgs &a);
 // Number of blocks (= partial sums written by a fused epilogue) launch_dhop uses for `a`.
 long dhop_blocks(const DhopArgs &a);
 // Upper bound of dhop_blocks over all schedules for a field of n5 sites and time extent Lt.

@@ -61,6 +61,22 @@ def test_cg_ragged_blocks(gpu, kind, sloppy):
         assert sto == 0 and abs(st["iterations"] - ito) <= max(3, ito // 20), (st["iterations"], ito)
 
 
+@pytest.mark.parametrize("dims", [(8, 8, 4, 6), (16, 8, 8, 4)])
+@pytest.mark.parametrize("sloppy,fmt", [("f32", "L18"), ("f32", "L12"), ("f16s", "L12")])
+def test_wilson_cg_tiled_lattices(gpu, dims, sloppy, fmt):
+    """Mixed-precision Wilson solves on lattices the tiled time walk covers (x, y multiples of 8, z
+    of 4): its fused epilogues carry the norms and r -= alpha A p; one tile per slice in the first
+    (every face wraps onto the tile itself)."""
+    import paper_1512_03487_amd as gm
+    from tests.gpu_util import dev
+    U = F.gauge_field(dims, seed=7, kind="haar")
+    b = F.spinor_field(dims, seed=8)
+    x, st = gm.cg(dev(U), dev(b), kind="wilson", mass=0.1, tol=TOL, sloppy=sloppy, link_fmt=fmt, check_every=4)
+    res = O.true_residual(O.Op.wilson(0.1), U, b, x.cpu().numpy())
+    print(f"wilson {dims} {sloppy} {fmt}: {st['iterations']} it, {st['reliable_updates']} RU, residual {res:.2e}")
+    assert st["converged"] and res <= RES_SLACK * TOL
+
+
 @pytest.mark.parametrize("sloppy,fmt", [("f64", "L18"), ("f32", "L18"), ("f32", "L12"), ("f16s", "L18"),
                                         ("f16s", "L12")])
 def test_dwf_cg_modes(gpu, sloppy, fmt):
