@@ -355,10 +355,9 @@ k_dhop_tile(const void *__restrict__ U, const void *__restrict__ psi, const floa
     }
 }
 
-// Tile 8 x 8 x 4 (256 threads), walks of the longest divisor of Lt that keeps >= 1024 blocks
+// 4D: tile 8 x 8 x 4 (256 threads), walks of the longest divisor of Lt that keeps >= 1024 blocks
 // (>= 1 otherwise).
 constexpr int kTX = 8, kTY = 8, kTZ = 4;
-
 static TileDev tile_dev(const GeomDev &g) {
     TileDev td;
     td.ntx = g.L[0] / kTX;
@@ -371,16 +370,18 @@ static TileDev tile_dev(const GeomDev &g) {
     return td;
 }
 
-// FP32 18-real links stay on the direction-parallel schedule: there the eight direction wavefronts
-// of a block read a site's four links at about the same time, whereas the walk reads them one
-// direction after another and a link's cache lines are fetched again (measured 157 against
-// 166 us at 32^4); 12-real FP32 links (131 against 144 us) and FP16 storage (86 against 93 us
-// for the column walk) are faster here.
-bool tile_applies(const DhopArgs &a) {
+// FP32 18-real links stay on the direction-parallel schedule for 4D fields: there the eight
+// direction wavefronts of a block read a site's four links at about the same time, whereas the
+// walk reads them one direction after another and a link's cache lines are fetched again
+// (measured 157 against 166 us at 32^4); 12-real FP32 links (131 against 144 us) and FP16 storage
+// (86 against 93 us for the column walk) are faster here.
+static bool tile4_applies(const DhopArgs &a) {
     const bool prec_ok = a.prec == GRID_F16S || (a.prec == GRID_F32 && a.link_fmt == GRID_L12);
     return !a.custom && a.g.Ls == 1 && prec_ok && a.g.L[0] % kTX == 0 && a.g.L[1] % kTY == 0 &&
            a.g.L[2] % kTZ == 0 && a.kind != GRID_DWF;
 }
+
+bool tile_applies(const DhopArgs &a) { return tile4_applies(a); }
 
 long tile_blocks(const DhopArgs &a) {
     const TileDev td = tile_dev(a.g);
@@ -416,7 +417,6 @@ static hipError_t launch_tile_t(const DhopArgs &a) {
 
 hipError_t launch_tile(const DhopArgs &a) {
     switch (a.prec * 2 + a.link_fmt) {
-        case GRID_F32 * 2 + GRID_L18: return launch_tile_t<SpF32, LkF32<3>>(a);
         case GRID_F32 * 2 + GRID_L12: return launch_tile_t<SpF32, LkF32<2>>(a);
         case GRID_F16S * 2 + GRID_L18: return launch_tile_t<SpF16S, LkF16<3>>(a);
         case GRID_F16S * 2 + GRID_L12: return launch_tile_t<SpF16S, LkF16<2>>(a);
