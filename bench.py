@@ -1,16 +1,17 @@
-"""Benchmark: Wilson hopping operator GFLOP/s and HBM GB/s on one MI355X, plus the domain-wall CG
-time to a true residual of 1e-10 in FP64 and in mixed precision.
+"""Benchmark: Wilson hopping operator GFLOP/s and HBM GB/s on one MI355X at the throughput size
+(32^4, FP32), the domain-wall operator at 24^4 x 12, and the domain-wall CG time to a true
+residual of 1e-10 in FP64 and in mixed precision.
 
-One "step" is one application of the hopping operator H on a 16^4 lattice in FP64 with weak-field
-links exp(0.3 i H) and a Gaussian spinor (1320 flop per site). The timed loop rotates over
-several independent (U, psi, out) buffer sets whose inputs alone exceed twice the 256 MB
-last-level cache, so every application streams its inputs from HBM. Further legs (FP32, 32^4, domain wall
-24^4 x 12 in FP32 and FP16 storage, the CG on 16^4 x 16, the even-odd preconditioned solve of
-M x = b on the same lattice against CG on M^dagger M, and the throughput of graph-recorded sloppy CG
-iterations at 32^4 and 24^4 x 12) are reported alongside.
+One "step" is one application of the hopping operator H on a 32^4 lattice with FP32 spinors and
+18-real FP32 links (Haar links, Gaussian spinor; 1320 flop per site). The timed loop rotates over
+two independent (U, psi, out) buffer sets of 403 MB of inputs each, three times the 256 MB
+last-level cache, so every application streams its inputs from HBM. Further legs (the
+domain-wall operator on 24^4 x 12 in FP32 and FP16 storage with their own roofline records,
+16^4 FP64, the CG on 16^4 x 16, the even-odd preconditioned solve, recorded-graph CG iterations,
+multigrid and HMC kernels) are reported alongside.
 
-Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--no-cg] [--no-cpu]
-Prints one JSON line.
+Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--no-cg] [--no-cpu] [--oracle-cg]
+Prints one JSON line (progress lines go to stderr).
 """
 from __future__ import annotations
 
@@ -32,8 +33,20 @@ FLOPS_HOP = 1320
 SPINOR_BYTES = {"f64": 192, "f32": 96, "f16s": 52}
 LINK_BYTES = {("f64", "L18"): 144, ("f64", "L12"): 96, ("f32", "L18"): 72, ("f32", "L12"): 48,
               ("f16s", "L18"): 36, ("f16s", "L12"): 24}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dhop_f64_16x16x16x16.txt")
+# HBM traffic summaries (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated) of the timed kernels
+TRAFFIC_FILES = {
+    "hop_32^4_f32": os.path.join(ROOT, "profiles", "traffic_dhop_f32_32x32x32x32.txt"),
+    "dwf_24^4x12_f32": os.path.join(ROOT, "profiles", "traffic_dwf_f32_24x24x24x24_ls12.txt"),
+    "dwf_24^4x12_f16s_L12": os.path.join(ROOT, "profiles", "traffic_dwf_f16s_24x24x24x24_ls12.txt"),
+}
+ORACLE_CG_FILE = os.path.join(ROOT, "profiles", "oracle_cg_dwf_16x16x16x16_ls16.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1512_03487_amd", "csrc", f) for f in ("dhop.hip", "device.h")]
+HEAD_DIMS = (32, 32, 32, 32)
+HEAD_KERNEL = "k_dhop_dir<SpF32, LkF32<3>, hop>"
+
+
+def progress(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def alg_bytes_per_site(prec: str, fmt: str, Ls: int) -> float:
@@ -48,12 +61,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(name="hop_32^4_f32"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it matches the source."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILES[name]
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
@@ -249,7 +263,7 @@ def leg(dims, prec, fmt, kind, Ls, steps, warmup, min_bytes=600e6):
             "alg_gbs": round(gbs, 1), "roofline_frac": round(gbs / HBM_PEAK_GBS, 4), "buffer_sets": nsets}
 
 
-def cg_legs():
+def cg_legs(keep_solutions=False):
     import torch
     import paper_1512_03487_amd as gm
     from paper_1512_03487_amd import fields
@@ -258,6 +272,7 @@ def cg_legs():
     U = torch.from_numpy(fields.gauge_field(dims, seed=1, kind="haar")).to(dev)
     b = torch.from_numpy(fields.spinor_field(dims, seed=3, Ls=Ls)).to(dev)
     out = {"lattice": list(dims), "Ls": Ls, "M5": 1.8, "mf": 0.01, "tol": 1e-10}
+    sols = {}
     for name, sloppy, fmt in (("fp64", "f64", "L18"), ("mixed_f32", "f32", "L18"), ("mixed_f16s", "f16s", "L12")):
         ws = torch.empty(gm.cg_workspace_bytes(b, sloppy=sloppy, link_fmt=fmt), dtype=torch.uint8, device=dev)
         gm.cg(U, b, kind="dwf", M5=1.8, mf=0.01, tol=1e-10, sloppy=sloppy, link_fmt=fmt, workspace=ws,
@@ -269,21 +284,36 @@ def cg_legs():
         out[name] = {"seconds": round(time.perf_counter() - t0, 4), "iterations": st["iterations"],
                      "reliable_updates": st["reliable_updates"], "true_residual": st["true_residual"],
                      "converged": st["converged"]}
+        if name == "fp64":
+            x64 = x
+        else:
+            # the solution is unique only up to the tolerance: its distance to the FP64 solve's
+            out[name]["rel_error_vs_fp64_solution"] = float(torch.linalg.vector_norm(x - x64) /
+                                                            torch.linalg.vector_norm(x64))
+        sols[name] = x.cpu().numpy() if keep_solutions else None
         del ws, x
-    ws = torch.empty(gm.cg_workspace_bytes(b, sloppy="f32"), dtype=torch.uint8, device=dev)
-    gm.cg(U, b, kind="mobius", M5=1.8, mf=0.01, b5=1.5, c5=0.5, tol=1e-10, sloppy="f32", workspace=ws, maxiter=20,
-          raise_on_fail=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    x, st = gm.cg(U, b, kind="mobius", M5=1.8, mf=0.01, b5=1.5, c5=0.5, tol=1e-10, sloppy="f32", workspace=ws)
-    torch.cuda.synchronize()
-    out["mobius_b1.5_c0.5_mixed_f32"] = {"seconds": round(time.perf_counter() - t0, 4), "iterations": st["iterations"],
-                                         "reliable_updates": st["reliable_updates"],
-                                         "true_residual": st["true_residual"], "converged": st["converged"]}
-    del ws, x
+    mob = dict(kind="mobius", M5=1.8, mf=0.01, b5=1.5, c5=0.5, tol=1e-10)
+    xm64 = None
+    for name, sloppy in (("mobius_b1.5_c0.5_fp64", "f64"), ("mobius_b1.5_c0.5_mixed_f32", "f32")):
+        ws = torch.empty(gm.cg_workspace_bytes(b, sloppy=sloppy), dtype=torch.uint8, device=dev)
+        gm.cg(U, b, sloppy=sloppy, workspace=ws, maxiter=20, raise_on_fail=False, **mob)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st = gm.cg(U, b, sloppy=sloppy, workspace=ws, **mob)
+        torch.cuda.synchronize()
+        out[name] = {"seconds": round(time.perf_counter() - t0, 4), "iterations": st["iterations"],
+                     "reliable_updates": st["reliable_updates"], "true_residual": st["true_residual"],
+                     "converged": st["converged"]}
+        if xm64 is None:
+            xm64 = x
+        else:
+            out[name]["rel_error_vs_fp64_solution"] = float(torch.linalg.vector_norm(x - xm64) /
+                                                            torch.linalg.vector_norm(xm64))
+        del ws, x
+    del xm64
     out["speedup_mixed_f32"] = round(out["fp64"]["seconds"] / out["mixed_f32"]["seconds"], 2)
     out["speedup_mixed_f16s"] = round(out["fp64"]["seconds"] / out["mixed_f16s"]["seconds"], 2)
-    return out
+    return (out, sols) if keep_solutions else out
 
 
 def eo_legs():
@@ -329,6 +359,11 @@ def eo_legs():
                      "even_odd": {"seconds": round(t_eo, 4), "iterations": ste["iterations"],
                                   "full_residual": ste["true_residual"]},
                      "speedup_even_odd": round(t_full / t_eo, 2)}
+        if name == "fp64":
+            x_eo64 = x
+        else:
+            out[name]["even_odd"]["rel_error_vs_fp64_solution"] = float(
+                torch.linalg.vector_norm(x - x_eo64) / torch.linalg.vector_norm(x_eo64))
         del ws, x
     return out
 
@@ -508,13 +543,15 @@ def hmc_legs():
     return out
 
 
-def cpu_baseline(seconds_target=15.0):
-    """The FP64 oracle's H on the same 16^4 workload, timed on the host cores."""
+def cpu_baseline(U_host, psi_host, seconds_target=15.0):
+    """The FP64 oracle's H on the headline workload (the same Haar links and Gaussian spinor, FP32-
+    rounded, in FP64), timed on the host cores for about seconds_target; plus the oracle on one
+    thread, its domain-wall normal operator per application, and its full FP64 CG at 16^4 x 16
+    as measured by `bench.py --oracle-cg` (the committed record, see oracle_cg_leg)."""
+    import numpy as np
     from oracle import oracle as orc
-    from paper_1512_03487_amd import fields
-    dims = (16, 16, 16, 16)
-    U = fields.gauge_field(dims, seed=1, kind="weak")
-    psi = fields.spinor_field(dims, seed=2)
+    U = np.asarray(U_host).astype(np.complex64).astype(np.complex128)
+    psi = np.asarray(psi_host).astype(np.complex64).astype(np.complex128)
     orc.hop(U, psi)    # load / warm
     n, t0 = 0, time.perf_counter()
     while True:
@@ -523,21 +560,59 @@ def cpu_baseline(seconds_target=15.0):
         el = time.perf_counter() - t0
         if el >= seconds_target:
             break
-    vol = 16 ** 4
+    vol = int(np.prod(HEAD_DIMS))
     res = {"value": round(FLOPS_HOP * vol * n / el / 1e9, 3), "unit": "GFLOP/s", "cores": orc.threads(),
-           "kind": "oracle", "sample": f"{n} applications of H on the 16^4 FP64 workload ({el:.1f} s)",
+           "kind": "oracle",
+           "sample": f"{n} applications of H on the 32^4 workload (FP32-rounded inputs, FP64 oracle, {el:.1f} s)",
            "cpu_model": _cpu_model()}
+    del U, psi
     res["single_thread"] = _oracle_single_thread()
-    # the domain-wall normal operator M^dagger M on 16^4 x 16 (M5 = 1.8, mf = 0.01), per application
+    from paper_1512_03487_amd import fields
+    dims = (16, 16, 16, 16)
+    U16 = fields.gauge_field(dims, seed=1, kind="haar")
     psi5 = fields.spinor_field(dims, seed=3, Ls=16)
     op = orc.Op.dwf(16, 1.8, 0.01)
-    orc.normal(op, U, psi5)
+    orc.normal(op, U16, psi5)
     t0 = time.perf_counter()
     reps = 3
     for _ in range(reps):
-        orc.normal(op, U, psi5)
+        orc.normal(op, U16, psi5)
     res["dwf_mdag_m_16^4x16_seconds"] = round((time.perf_counter() - t0) / reps, 4)
+    if os.path.exists(ORACLE_CG_FILE):
+        rec = {}
+        for line in open(ORACLE_CG_FILE):
+            if line.startswith("{"):
+                rec = json.loads(line)
+        if rec:
+            res["oracle_cg_16^4x16"] = dict(rec, source=os.path.relpath(ORACLE_CG_FILE, ROOT))
     return res
+
+
+def oracle_cg_leg():
+    """The FP64 oracle CG (Hestenes-Stiefel on M^dagger M, stopping on the true residual) on the
+    16^4 x 16 domain-wall workload of the CG legs, timed to a true residual of 1e-10 on the host
+    cores (minutes), and each GPU solution's distance to the oracle's solution."""
+    import numpy as np
+    from oracle import oracle as orc
+    from paper_1512_03487_amd import fields
+    _, sols = cg_legs(keep_solutions=True)
+    dims, Ls = (16, 16, 16, 16), 16
+    U = fields.gauge_field(dims, seed=1, kind="haar")
+    b = fields.spinor_field(dims, seed=3, Ls=Ls)
+    op = orc.Op.dwf(Ls, 1.8, 0.01)
+    progress("oracle CG on 16^4 x 16 (minutes; the oracle reports every 25 iterations)")
+    os.environ["ORACLE_CG_PROGRESS"] = "25"
+    t0 = time.perf_counter()
+    x, status, its, relres = orc.cg(op, U, b, tol=1e-10)
+    el = time.perf_counter() - t0
+    xn = float(np.linalg.norm(x))
+    out = {"seconds": round(el, 2), "iterations": its, "status": status, "true_residual": relres,
+           "cores": orc.threads(), "cpu_model": _cpu_model(), "lattice": list(dims), "Ls": Ls, "M5": 1.8,
+           "mf": 0.01, "tol": 1e-10}
+    for name, xs in sols.items():
+        out[f"gpu_{name}_rel_error_vs_oracle"] = float(np.linalg.norm(xs - x) / xn)
+        out[f"gpu_{name}_true_residual_by_oracle"] = orc.true_residual(op, U, b, xs)
+    return out
 
 
 def _cpu_model():
@@ -595,7 +670,15 @@ def main():
     ap.add_argument("--only-mg", action="store_true", help="profiling aid: run only the multigrid legs")
     ap.add_argument("--only-cg-iterations", action="store_true",
                     help="profiling aid: run only the recorded-graph CG iteration legs and print them")
+    ap.add_argument("--only-dwf", action="store_true",
+                    help="profiling aid: run only the 24^4 x 12 domain-wall operator legs and print them")
+    ap.add_argument("--oracle-cg", action="store_true",
+                    help="run the FP64 oracle CG on 16^4 x 16 to 1e-10 (minutes) and print its record")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (multi-GPU sharding is not built)",
+              file=sys.stderr)
+        sys.exit(2)
     if args.only_solvers:
         print(json.dumps({"cg_dwf_16^4x16": cg_legs(), "solve_dwf_16^4x16_even_odd": eo_legs()}), flush=True)
         return
@@ -605,19 +688,21 @@ def main():
     if args.only_cg_iterations:
         print(json.dumps({"cg_iterations_graph": cg_iteration_legs()}), flush=True)
         return
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (multi-GPU sharding is not built)",
-              file=sys.stderr)
-        sys.exit(2)
+    if args.only_dwf:
+        print(json.dumps(dwf_config5(args.calibrate_copy)), flush=True)
+        return
+    if args.oracle_cg:
+        print(json.dumps(oracle_cg_leg()), flush=True)
+        return
 
     import torch
-    dims = (16, 16, 16, 16)
-    vol = 16 ** 4
-    # 12 x 50.3 MB of inputs (links + psi) = 604 MB, over twice the 256 MB MALL, so every
-    # application streams its inputs from HBM (the outputs are written non-temporally and do not
-    # occupy the MALL, so the inputs alone must exceed it)
-    nsets = 12
-    sets, _ = make_sets(dims, "f64", nsets)
+    dims = HEAD_DIMS
+    vol = dims[0] * dims[1] * dims[2] * dims[3]
+    # 2 x 403 MB of inputs (FP32 links + psi) = 806 MB, three times the 256 MB MALL, so every
+    # application streams its inputs from HBM
+    nsets = 2
+    sets, (U_host, psi_host) = make_sets(dims, "f32", nsets, kind="haar")
+    progress("headline: H on 32^4 FP32")
     t, wall = time_dhop(sets, args.steps, args.warmup)
     del sets
     if args.calibrate_copy:
@@ -628,40 +713,54 @@ def main():
         torch.cuda.synchronize()
         del a, b
     torch.cuda.empty_cache()
-    bytes_launch = alg_bytes_per_site("f64", "L18", 1) * vol
+    bytes_launch = alg_bytes_per_site("f32", "L18", 1) * vol
     achieved = bytes_launch / t / 1e9
     gflops = FLOPS_HOP * vol / t / 1e9
-
+    dwf5 = None
     legs = {}
     if not args.no_legs:
-        legs["hop_16^4_f32"] = leg((16, 16, 16, 16), "f32", "L18", "hop", None, 100, 10)
-        legs["hop_16^4_f64_cache_resident"] = None
-        s1, _ = make_sets(dims, "f64", 1)
-        t1, _ = time_dhop(s1, 100, 10)
-        legs["hop_16^4_f64_cache_resident"] = {"us_per_launch": round(t1 * 1e6, 2),
-                                               "gflops": round(FLOPS_HOP * vol / t1 / 1e9, 1),
-                                               "alg_gbs": round(bytes_launch / t1 / 1e9, 1)}
-        del s1
-        legs["copy_same_bytes_as_hop_16^4_f64"] = copy_reference(bytes_launch)
-        legs["hop_32^4_f32"] = leg((32, 32, 32, 32), "f32", "L18", "hop", None, 50, 5)
+        progress("domain-wall operator 24^4 x 12")
+        dwf5 = dwf_config5(False)
+        progress("operator legs")
         legs["hop_32^4_f32_L12"] = leg((32, 32, 32, 32), "f32", "L12", "hop", None, 50, 5)
         legs["hop_32^4_f16s_L12"] = leg((32, 32, 32, 32), "f16s", "L12", "hop", None, 50, 5)
-        legs["dwf_24^4x12_f32"] = leg((24, 24, 24, 24), "f32", "L18", "dwf", 12, 20, 3)
-        legs["dwf_24^4x12_f16s_L12"] = leg((24, 24, 24, 24), "f16s", "L12", "dwf", 12, 20, 3)
+        s16, _ = make_sets((16, 16, 16, 16), "f64", 12)
+        t16, _ = time_dhop(s16, 100, 10)
+        del s16
+        b16 = alg_bytes_per_site("f64", "L18", 1) * 16 ** 4
+        legs["hop_16^4_f64"] = {"us_per_launch": round(t16 * 1e6, 2), "gflops": round(FLOPS_HOP * 16 ** 4 / t16 / 1e9, 1),
+                                "alg_gbs": round(b16 / t16 / 1e9, 1),
+                                "roofline_frac": round(b16 / t16 / 1e9 / HBM_PEAK_GBS, 4), "buffer_sets": 12,
+                                "links": "weak field"}
+        legs["hop_16^4_f32"] = leg((16, 16, 16, 16), "f32", "L18", "hop", None, 100, 10)
+        legs["copy_same_bytes_as_hop_32^4_f32"] = copy_reference(bytes_launch, nsets=2, steps=50, warmup=5)
         legs["link_force_32^4_f32"] = link_force_leg()
         legs["dwf_eo_hop_16^4x16_f32"] = cb_leg((16, 16, 16, 16), 16, "f32", "L18")
         legs["dwf_eo_hop_16^4x16_f16s_L12"] = cb_leg((16, 16, 16, 16), 16, "f16s", "L12")
         legs["mobius_16^4x16_f32"] = mobius_leg((16, 16, 16, 16), 16, "f32", 50, 5)
         legs["mobius_16^4x16_f64"] = mobius_leg((16, 16, 16, 16), 16, "f64", 20, 3)
         torch.cuda.empty_cache()
-    cg = None if args.no_cg else cg_legs()
-    eo = None if args.no_cg else eo_legs()
-    cgi = None if args.no_cg else cg_iteration_legs()
-    mgl = None if args.no_cg else mg_legs()
-    md = None if args.no_legs else hmc_legs()
-    cpu = None if args.no_cpu else cpu_baseline()
+    cg = eo = cgi = mgl = None
+    if not args.no_cg:
+        progress("CG on 16^4 x 16")
+        cg = cg_legs()
+        progress("even-odd solves")
+        eo = eo_legs()
+        progress("recorded CG iterations")
+        cgi = cg_iteration_legs()
+        progress("multigrid")
+        mgl = mg_legs()
+    md = None
+    if not args.no_legs:
+        progress("HMC kernels")
+        md = hmc_legs()
+    cpu = None
+    if not args.no_cpu:
+        progress("oracle on the host cores")
+        cpu = cpu_baseline(U_host, psi_host)
+    del U_host, psi_host
 
-    traffic = measured_traffic()
+    traffic = measured_traffic("hop_32^4_f32")
     rec = {
         "metric": METRIC,
         "value": round(gflops, 1),
@@ -673,18 +772,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "Wilson hopping operator H, 16^4 periodic lattice, FP64, weak-field links "
-                               "exp(0.3 i H), Gaussian spinor, repeated applications",
+        "config": {"workload": "Wilson hopping operator H, 32^4 periodic lattice, FP32 spinors and 18-real FP32 "
+                               "links, Haar-random SU(3) links, Gaussian spinor, repeated applications",
                    "lattice": list(dims), "links": "L18", "buffer_sets": nsets, "flop_per_site": FLOPS_HOP},
         "hbm_gbs_algorithmic": round(achieved, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "alg_bytes_per_launch": int(bytes_launch),
-                     "hbm_bytes_per_launch": traffic, "kernel": "k_dhop_dir<SpF64, LkF64<3>, hop>"},
+                     "hbm_bytes_per_launch": traffic, "kernel": HEAD_KERNEL},
         "cpu_baseline": cpu,
+        "dwf_24^4x12": dwf5,
         "legs": legs,
         "cg_dwf_16^4x16": cg,
         "solve_dwf_16^4x16_even_odd": eo,
@@ -694,6 +794,33 @@ def main():
         "wall_s_timed": round(wall, 4),
     }
     print(json.dumps(rec), flush=True)
+
+
+def dwf_config5(calibrate_copy=False):
+    """The domain-wall operator M on 24^4 x 12 (M5 = 1.8, mf = 0.01, Haar links, Gaussian spinor),
+    the throughput size of the domain-wall workload, in FP32 (18-real links) and FP16 storage
+    (12-real FP16 links): time per application over buffer sets rotating through > 600 MB of
+    inputs, GFLOP/s at 1320 per 5D site, and the HBM roofline record of its kernel (algorithmic
+    bytes: psi and out once per 5D site, the links once per 4D site)."""
+    import torch
+    out = {"workload": "domain-wall operator M, 24^4 x Ls = 12, M5 = 1.8, mf = 0.01, Haar links, Gaussian spinor"}
+    for name, prec, fmt, kern in (("f32", "f32", "L18", "k_dhop_walk<SpF32, LkF32<3>, false, GRID_DWF, 0>"),
+                                  ("f16s_L12", "f16s", "L12", "k_dhop_walk<SpF16S, LkF16<2>, false, GRID_DWF, 0>")):
+        r = leg((24, 24, 24, 24), prec, fmt, "dwf", 12, 20, 3)
+        traffic = measured_traffic(f"dwf_24^4x12_{name}")
+        r["roofline"] = {"bound": "hbm", "achieved": r["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": r["roofline_frac"], "traffic": traffic,
+                         "alg_bytes_per_launch": int(alg_bytes_per_site(prec, fmt, 12) * 24 ** 4 * 12),
+                         "kernel": kern}
+        out[name] = r
+        torch.cuda.empty_cache()
+    if calibrate_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+    return out
 
 
 if __name__ == "__main__":

@@ -36,6 +36,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #include <omp.h>
@@ -324,7 +325,14 @@ int oracle_cg(const cplx *U, const cplx *b, cplx *x, const int *dims, const orac
     double rho = norm2(r, n);
     if (bnorm == 0.0 || sqrt(rho) <= tol * bnorm) { status = 0; relres = bnorm > 0 ? sqrt(rho) / bnorm : 0; }
 
+    /* progress on stderr every ORACLE_CG_PROGRESS iterations (long solves); no effect on the result */
+    const char *pe = getenv("ORACLE_CG_PROGRESS");
+    const int every = pe ? atoi(pe) : 0;
     for (it = 1; status == 1 && it <= maxiter; ++it) {
+        if (every > 0 && it % every == 0) {
+            fprintf(stderr, "oracle cg: iteration %d, |r|/|b| = %.3e\n", it, sqrt(rho) / bnorm);
+            fflush(stderr);
+        }
         oracle_normal(U, p, q, t, dims, op);
         const double pq = redot(p, q, n);
         if (!(pq > 0.0) || !isfinite(pq)) { status = 2; break; }

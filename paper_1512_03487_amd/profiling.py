@@ -5,8 +5,11 @@ calibrated here against a plain device copy of known size run in the same comman
 the bytes it must read and write divided by what the counters report).
 
 Usage:
-  python -m paper_1512_03487_amd.profiling traffic FETCH_DIR WRITE_DIR KERNEL_SUBSTR OUT.txt [--cmd "..."]
-  python -m paper_1512_03487_amd.profiling stats KT_DIR OUT.txt [--cmd "..."]
+  python -m paper_1512_03487_amd.profiling traffic FETCH_DIR WRITE_DIR KERNEL_SUBSTR OUT.txt [--grid N] [--cmd "..."]
+  python -m paper_1512_03487_amd.profiling stats KT_DIR OUT.txt [--focus SUBSTR ...] [--cmd "..."]
+
+--grid N keeps only dispatches of N work-items (one launch shape of a kernel that several
+workloads share). The stats summary lists each kernel per launch shape as well.
 """
 from __future__ import annotations
 
@@ -18,6 +21,7 @@ import sys
 
 COPY_BYTES = 256 << 20
 COPY_KERNEL = "copyBuffer"
+TOP = 40   # rows per table of the stats summary
 
 
 def _rows(d):
@@ -27,17 +31,18 @@ def _rows(d):
     return out
 
 
-def _per_kernel(rows, counter, substr):
-    return [float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == counter and substr in r["Kernel_Name"]]
+def _per_kernel(rows, counter, substr, grid=None):
+    return [float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == counter and substr in r["Kernel_Name"]
+            and (grid is None or int(r["Grid_Size"]) == grid)]
 
 
-def _calibration_copies(rows, counter):
-    """Counter values of the largest copy dispatches (the 256 MiB calibration copy)."""
-    vals = [float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == counter and COPY_KERNEL in r["Kernel_Name"]]
-    if not vals:
-        return []
-    vmax = max(vals)
-    return [v for v in vals if v >= 0.95 * vmax]
+def _calibration_copies(rows, counter, n=3):
+    """Counter values of the calibration copy: the command's last n copy dispatches (bench.py
+    --calibrate-copy runs a 256 MiB device copy three times after everything else; the fields'
+    own copies come earlier and have other sizes)."""
+    rows = [r for r in rows if r["Counter_Name"] == counter and COPY_KERNEL in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return [float(r["Counter_Value"]) for r in rows[-n:]]
 
 
 def kernel_source_hash(root):
@@ -48,9 +53,9 @@ def kernel_source_hash(root):
     return h.hexdigest()[:16]
 
 
-def traffic(fetch_dir, write_dir, kernel, out, cmd=""):
+def traffic(fetch_dir, write_dir, kernel, out, cmd="", grid=None):
     fr, wr = _rows(fetch_dir), _rows(write_dir)
-    fk, wk = _per_kernel(fr, "FETCH_SIZE", kernel), _per_kernel(wr, "WRITE_SIZE", kernel)
+    fk, wk = _per_kernel(fr, "FETCH_SIZE", kernel, grid), _per_kernel(wr, "WRITE_SIZE", kernel, grid)
     fc, wc = _calibration_copies(fr, "FETCH_SIZE"), _calibration_copies(wr, "WRITE_SIZE")
     if not fk or not wk or not fc or not wc:
         raise SystemExit("missing kernel or copy dispatches in the counter output")
@@ -60,7 +65,8 @@ def traffic(fetch_dir, write_dir, kernel, out, cmd=""):
     w_b = sum(wk) / len(wk) * 1024 * w_factor
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     with open(out, "w") as fh:
-        fh.write(f"# HBM traffic per dispatch of kernels matching '{kernel}' (rocprofv3 --pmc)\n")
+        fh.write(f"# HBM traffic per dispatch of kernels matching '{kernel}'"
+                 + (f" launched with {grid} work-items" if grid else "") + " (rocprofv3 --pmc)\n")
         if cmd:
             fh.write(f"# command: {cmd}\n")
         fh.write(f"dispatches_fetch: {len(fk)}\ndispatches_write: {len(wk)}\n")
@@ -75,7 +81,7 @@ def traffic(fetch_dir, write_dir, kernel, out, cmd=""):
     print(open(out).read())
 
 
-def stats(kt_dir, out, cmd=""):
+def stats(kt_dir, out, cmd="", focus=()):
     files = glob.glob(os.path.join(kt_dir, "**", "*kernel_stats.csv"), recursive=True)
     if not files:
         raise SystemExit("no kernel_stats.csv under " + kt_dir)
@@ -84,13 +90,30 @@ def stats(kt_dir, out, cmd=""):
         fh.write("# rocprofv3 --kernel-trace --stats summary\n")
         if cmd:
             fh.write(f"# command: {cmd}\n")
+        fh.write(f"Top {min(len(rows), TOP)} of {len(rows)} kernels by total time:\n\n")
         fh.write("| kernel | calls | avg us | min us | max us | total % |\n|---|---|---|---|---|---|\n")
-        for r in rows:
+        for r in rows[:TOP]:
             name = r["Name"]
             if len(name) > 110:
                 name = name[:110] + "..."
             fh.write(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
                      f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} |\n")
+        traces = glob.glob(os.path.join(kt_dir, "**", "*kernel_trace.csv"), recursive=True)
+        if traces:
+            groups = {}
+            for r in csv.DictReader(open(traces[0])):
+                key = (r["Kernel_Name"], int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]))
+                groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+            ranked = sorted(groups.items(), key=lambda kv: -sum(kv[1]))
+            picked = [kv for kv in ranked if any(f in kv[0][0] for f in focus)]
+            picked += [kv for kv in ranked[:TOP] if kv not in picked]
+            fh.write(f"\nPer launch shape (work-items per dispatch): the kernels matching {list(focus)}, then the top "
+                     f"{min(len(groups), TOP)} of {len(groups)} by total time:\n\n")
+            fh.write("| kernel | work-items | calls | avg us | min us | max us |\n|---|---|---|---|---|---|\n")
+            for (name, n), v in picked:
+                if len(name) > 110:
+                    name = name[:110] + "..."
+                fh.write(f"| `{name}` | {n} | {len(v)} | {sum(v) / len(v):.2f} | {min(v):.2f} | {max(v):.2f} |\n")
     print(open(out).read())
 
 
@@ -101,9 +124,19 @@ if __name__ == "__main__":
         i = args.index("--cmd")
         cmd = args[i + 1]
         args = args[:i] + args[i + 2:]
+    grid = None
+    if "--grid" in args:
+        i = args.index("--grid")
+        grid = int(args[i + 1])
+        args = args[:i] + args[i + 2:]
+    focus = []
+    while "--focus" in args:
+        i = args.index("--focus")
+        focus.append(args[i + 1])
+        args = args[:i] + args[i + 2:]
     if args and args[0] == "traffic":
-        traffic(*args[1:5], cmd=cmd)
+        traffic(*args[1:5], cmd=cmd, grid=grid)
     elif args and args[0] == "stats":
-        stats(*args[1:3], cmd=cmd)
+        stats(*args[1:3], cmd=cmd, focus=tuple(focus))
     else:
         print(__doc__)
