@@ -316,10 +316,11 @@ def cg_legs(keep_solutions=False):
     return (out, sols) if keep_solutions else out
 
 
-def eo_legs():
-    """M x = b on the 16^4 x 16 domain-wall workload: CG on M^dagger M (source M^dagger b) against
-    even-odd preconditioned CG, each in FP64 and mixed precision, to a normal-equation residual of
-    1e-10; the full residual |b - M x| / |b| is reported for both."""
+def eo_legs(kind="dwf"):
+    """M x = b on the 16^4 x 16 domain-wall workload (kind "dwf": the Shamir M; "mobius": the
+    Moebius M with b5 = 1.5, c5 = 0.5): CG on M^dagger M (source M^dagger b) against even-odd
+    preconditioned CG, each in FP64 and mixed precision, to a normal-equation residual of 1e-10;
+    the full residual |b - M x| / |b| is reported for both."""
     import torch
     import paper_1512_03487_amd as gm
     from paper_1512_03487_amd import fields
@@ -328,36 +329,39 @@ def eo_legs():
     U = torch.from_numpy(fields.gauge_field(dims, seed=1, kind="haar")).to(dev)
     b = torch.from_numpy(fields.spinor_field(dims, seed=3, Ls=Ls)).to(dev)
     bn = float(torch.linalg.vector_norm(b))
-    kw = dict(M5=1.8, mf=0.01)
-    out = {"lattice": list(dims), "Ls": Ls, "M5": 1.8, "mf": 0.01, "tol": 1e-10, "system": "M x = b"}
+    kw = dict(M5=1.8, mf=0.01) if kind == "dwf" else dict(M5=1.8, mf=0.01, b5=1.5, c5=0.5)
+    out = {"lattice": list(dims), "Ls": Ls, **kw, "tol": 1e-10, "system": "M x = b"}
+
+    def op(x, dag=False):
+        return gm.dwf(U, x, dag=dag, **kw) if kind == "dwf" else gm.mobius(U, x, dag=dag, **kw)
 
     def full_res(x):
-        return float(torch.linalg.vector_norm(gm.dwf(U, x, **kw) - b)) / bn
+        return float(torch.linalg.vector_norm(op(x) - b)) / bn
 
     for name, sloppy, fmt in (("fp64", "f64", "L18"), ("mixed_f32", "f32", "L18"), ("mixed_f16s", "f16s", "L12")):
         ws = torch.empty(gm.cg_workspace_bytes(b, sloppy=sloppy, link_fmt=fmt), dtype=torch.uint8, device=dev)
-        gm.cg(U, b, kind="dwf", tol=1e-10, sloppy=sloppy, link_fmt=fmt, workspace=ws, maxiter=20, raise_on_fail=False,
+        gm.cg(U, b, kind=kind, tol=1e-10, sloppy=sloppy, link_fmt=fmt, workspace=ws, maxiter=20, raise_on_fail=False,
               **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        c = gm.dwf(U, b, dag=True, **kw)
-        x, st = gm.cg(U, c, kind="dwf", tol=1e-10, sloppy=sloppy, link_fmt=fmt, workspace=ws, **kw)
+        c = op(b, dag=True)
+        x, st = gm.cg(U, c, kind=kind, tol=1e-10, sloppy=sloppy, link_fmt=fmt, workspace=ws, **kw)
         torch.cuda.synchronize()
         t_full = time.perf_counter() - t0
         r_full = full_res(x)
         del ws, x, c
         ws = torch.empty(gm.solve_eo_workspace_bytes(b, sloppy=sloppy, link_fmt=fmt), dtype=torch.uint8, device=dev)
-        gm.solve_eo(U, b, kind="dwf", tol=1e-10, sloppy=sloppy, link_fmt=fmt, workspace=ws, maxiter=20,
+        gm.solve_eo(U, b, kind=kind, tol=1e-10, sloppy=sloppy, link_fmt=fmt, workspace=ws, maxiter=20,
                     raise_on_fail=False, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, ste = gm.solve_eo(U, b, kind="dwf", tol=1e-10, sloppy=sloppy, link_fmt=fmt, workspace=ws, **kw)
+        x, ste = gm.solve_eo(U, b, kind=kind, tol=1e-10, sloppy=sloppy, link_fmt=fmt, workspace=ws, **kw)
         torch.cuda.synchronize()
         t_eo = time.perf_counter() - t0
         out[name] = {"cgnr": {"seconds": round(t_full, 4), "iterations": st["iterations"],
                               "full_residual": r_full},
                      "even_odd": {"seconds": round(t_eo, 4), "iterations": ste["iterations"],
-                                  "full_residual": ste["true_residual"]},
+                                  "full_residual": ste["true_residual"], "full_residual_recomputed": full_res(x)},
                      "speedup_even_odd": round(t_full / t_eo, 2)}
         if name == "fp64":
             x_eo64 = x
@@ -680,7 +684,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.only_solvers:
-        print(json.dumps({"cg_dwf_16^4x16": cg_legs(), "solve_dwf_16^4x16_even_odd": eo_legs()}), flush=True)
+        print(json.dumps({"cg_dwf_16^4x16": cg_legs(), "solve_dwf_16^4x16_even_odd": eo_legs(),
+                          "solve_mobius_16^4x16_even_odd": eo_legs("mobius")}), flush=True)
         return
     if args.only_mg:
         print(json.dumps({"multigrid": mg_legs()}), flush=True)
@@ -740,12 +745,14 @@ def main():
         legs["mobius_16^4x16_f32"] = mobius_leg((16, 16, 16, 16), 16, "f32", 50, 5)
         legs["mobius_16^4x16_f64"] = mobius_leg((16, 16, 16, 16), 16, "f64", 20, 3)
         torch.cuda.empty_cache()
-    cg = eo = cgi = mgl = None
+    cg = eo = eo_mob = cgi = mgl = None
     if not args.no_cg:
         progress("CG on 16^4 x 16")
         cg = cg_legs()
         progress("even-odd solves")
         eo = eo_legs()
+        progress("even-odd Moebius solves")
+        eo_mob = eo_legs("mobius")
         progress("recorded CG iterations")
         cgi = cg_iteration_legs()
         progress("multigrid")
@@ -788,6 +795,7 @@ def main():
         "legs": legs,
         "cg_dwf_16^4x16": cg,
         "solve_dwf_16^4x16_even_odd": eo,
+        "solve_mobius_16^4x16_even_odd": eo_mob,
         "cg_iterations_graph": cgi,
         "multigrid": mgl,
         "hmc_16^4": md,

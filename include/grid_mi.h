@@ -254,7 +254,10 @@ size_t grid_solve_eo_workspace_bytes(const grid_geom *geom, const grid_cg_params
  *   Mhat = M_ee - M_eo M_oo^-1 M_oe,  bhat = b_e - M_eo M_oo^-1 b_o,
  *   x_o  = M_oo^-1 (b_o - M_oe x_e),
  * M_eo = M_oe = -H/2 between checkerboards and M_ee = M_oo = 4 + mass (Wilson) or the
- * fifth-dimension part M5 (domain wall). Precision options as grid_cg (params). x on entry is
+ * fifth-dimension part M5 (domain wall). Moebius (GRID_MOBIUS, M = D_W B + 1 - S with
+ * B = b5 + c5 S): M_eo = -H_eo B / 2, M_oe = -H_oe B / 2 and M_ee = M_oo = alpha - beta S,
+ * alpha = 1 + (4 - M5) b5, beta = 1 - (4 - M5) c5; needs Ls <= 64 and |alpha / beta| > 1 (or
+ * beta = 0, alpha != 0), GRID_EINVAL otherwise. Precision options as grid_cg (params). x on entry is
  * the initial guess (its even sites are used). The CG stops when the FP64 true residual of the
  * preconditioned normal equations is <= tol relative to |Mhat^+ bhat|; stats->true_residual is
  * then |b - Op x| / |b| of the full system, recomputed in FP64, and stats->converged reports the

@@ -135,3 +135,70 @@ def odd_solution(U, b, x_e, kind: str, mass: float = 0.0, M5: float = 1.8, mf: f
 
 def merge(x_e, x_o) -> np.ndarray:
     return embed(x_e, 0) + embed(x_o, 1)
+
+
+# ---------------------------------------------------------------------------------------------
+# Moebius domain wall (M = D_W (b5 + c5 S) + 1 - S, see oracle.mobius). Its blocks are read off
+# the pinned full-lattice operator: a field living on parity q, mapped by M (or M^dagger) and
+# restricted to parity p, is M_pq applied to it. The 4D-diagonal block M_ee = M_oo has no hopping
+# term (it acts on the fifth coordinate and the chirality only, the same at every 4D site), so its
+# inverse is a dense solve of the 4 Ls x 4 Ls matrix it has on one 4D site and colour, written
+# out column by column from the operator itself.
+# ---------------------------------------------------------------------------------------------
+
+def mobius_block(U, psi_q, q: int, p: int, M5: float, mf: float, b5: float, c5: float,
+                 dag: bool = False) -> np.ndarray:
+    """M_pq psi_q (the blocks of M^dagger when dag) for checkerboard fields."""
+    from . import mobius as _mob
+    return pick(_mob.mobius(U, embed(psi_q, q), M5, mf, b5, c5, dag), p)
+
+
+def mobius_diag_matrix(Ls: int, M5: float, mf: float, b5: float, c5: float, dag: bool = False) -> np.ndarray:
+    """The (Ls, 4) x (Ls, 4) matrix of M_ee on one 4D site and colour: the Moebius operator of the
+    module ``oracle.mobius`` with its hopping term dropped, applied to unit vectors."""
+    from . import mobius as _mob
+    n = Ls * 4
+    A = np.zeros((n, n), dtype=np.complex128)
+    for j in range(n):
+        e = np.zeros((Ls, 4, 3), dtype=np.complex128)
+        e[j // 4, j % 4, 0] = 1.0
+        # M_ee psi = (4 - M5) B psi + psi - S psi (B^dagger D^dagger ... for the adjoint): the
+        # Moebius operator with the hopping term dropped
+        if not dag:
+            v = (4.0 - M5) * (b5 * e + c5 * _mob.shift5(e, mf)) + e - _mob.shift5(e, mf)
+        else:
+            f = (4.0 - M5) * e
+            v = b5 * f + c5 * _mob.shift5(f, mf, True) + e - _mob.shift5(e, mf, True)
+        A[:, j] = v[:, :, 0].ravel()
+    return A
+
+
+def mobius_diag_inv(psi, M5: float, mf: float, b5: float, c5: float, dag: bool = False) -> np.ndarray:
+    """M_ee^-1 psi (the adjoint's inverse when dag) by a dense solve per 4D site and colour."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    Ls = psi.shape[-3]
+    A = mobius_diag_matrix(Ls, M5, mf, b5, c5, dag)
+    lead = psi.shape[:-3]
+    rhs = np.moveaxis(psi, -1, 0).reshape(3, -1, Ls * 4)          # colour, sites, (s, spin)
+    sol = np.linalg.solve(A, rhs.reshape(-1, Ls * 4).T).T.reshape(3, *lead, Ls, 4)
+    return np.ascontiguousarray(np.moveaxis(sol, 0, -1))
+
+
+def schur_mobius(U, psi_e, M5: float, mf: float, b5: float, c5: float, dag: bool = False) -> np.ndarray:
+    """Mhat psi_e = M_ee psi_e - M_eo M_oo^-1 M_oe psi_e (Mhat^dagger, from the blocks of M^dagger,
+    when dag)."""
+    kw = dict(M5=M5, mf=mf, b5=b5, c5=c5, dag=dag)
+    t = mobius_block(U, psi_e, 0, 1, **kw)
+    t = mobius_diag_inv(t, M5, mf, b5, c5, dag)
+    return mobius_block(U, psi_e, 0, 0, **kw) - mobius_block(U, t, 1, 0, **kw)
+
+
+def source_mobius(U, b, M5: float, mf: float, b5: float, c5: float) -> np.ndarray:
+    """bhat = b_e - M_eo M_oo^-1 b_o."""
+    bo = mobius_diag_inv(pick(b, 1), M5, mf, b5, c5)
+    return pick(b, 0) - mobius_block(U, bo, 1, 0, M5, mf, b5, c5)
+
+
+def odd_solution_mobius(U, b, x_e, M5: float, mf: float, b5: float, c5: float) -> np.ndarray:
+    """x_o = M_oo^-1 (b_o - M_oe x_e)."""
+    return mobius_diag_inv(pick(b, 1) - mobius_block(U, x_e, 0, 1, M5, mf, b5, c5), M5, mf, b5, c5)

@@ -382,8 +382,10 @@ def solve_eo_workspace_bytes(b, **params) -> int:
     return int(load().grid_solve_eo_workspace_bytes(ctypes.byref(g), ctypes.byref(p)))
 
 
-def solve_eo(U, b, kind="dwf", mass=0.0, M5=1.8, mf=0.01, x0=None, workspace=None, raise_on_fail=True, **params):
-    """Solve Op x = b (Op = D or M) with even-odd preconditioned CG; FP64 full-lattice U, b, x.
+def solve_eo(U, b, kind="dwf", mass=0.0, M5=1.8, mf=0.01, x0=None, workspace=None, raise_on_fail=True, b5=1.0, c5=0.0,
+             **params):
+    """Solve Op x = b (Op = D, the Shamir M or the Moebius M with b5, c5) with even-odd
+    preconditioned CG; FP64 full-lattice U, b, x.
 
     Returns (x, stats); stats["true_residual"] is |b - Op x| / |b|. Synchronous.
     """
@@ -402,7 +404,7 @@ def solve_eo(U, b, kind="dwf", mass=0.0, M5=1.8, mf=0.01, x0=None, workspace=Non
     else:
         _check_workspace(workspace, b)
     x = torch.zeros_like(b) if x0 is None else x0.clone()
-    op = make_op(kind, False, mass, M5, mf)
+    op = make_op(kind, False, mass, M5, mf, b5, c5)
     st = GridCgStats()
     rc = load().grid_solve_eo(_ptr(U), _ptr(b), _ptr(x), ctypes.byref(g), ctypes.byref(op), ctypes.byref(p),
                               _ptr(workspace), ctypes.c_size_t(workspace.numel()), ctypes.byref(st), _stream(b.device))

@@ -557,10 +557,17 @@ int grid_solve_eo(const void *U, const void *b, void *x, const grid_geom *geom, 
     TRY(check_geom(geom, &g));
     TRY(check_even(g));
     TRY(check_solver_args(g, op, params, stats));
-    if (op->kind == GRID_MOBIUS) return fail(GRID_EINVAL, "grid_solve_eo takes GRID_WILSON or GRID_DWF");
     if (op->kind == GRID_DWF) {
         if (g.Ls > 64) return fail(GRID_ESHAPE, "grid_solve_eo needs Ls <= 64 for the domain-wall M5 inverse");
         if (!(fabs(5.0 - op->M5) > 1.0)) return fail(GRID_EINVAL, "grid_solve_eo needs |5 - M5| > 1");
+    } else if (op->kind == GRID_MOBIUS) {
+        if (g.Ls > 64) return fail(GRID_ESHAPE, "grid_solve_eo needs Ls <= 64 for the Moebius M_ee inverse");
+        const double alpha = 1.0 + (4.0 - op->M5) * op->b5, beta = 1.0 - (4.0 - op->M5) * op->c5;
+        if (beta != 0.0 ? !(fabs(alpha / beta) > 1.0) : !(alpha != 0.0))
+            return fail(GRID_EINVAL,
+                        "grid_solve_eo needs |alpha / beta| > 1 (alpha = 1 + (4 - M5) b5 = %g, beta = 1 - (4 - M5) c5 = "
+                        "%g), or beta = 0 and alpha != 0",
+                        alpha, beta);
     } else if (!(fabs(4.0 + op->mass) > 0.0)) {
         return fail(GRID_EINVAL, "grid_solve_eo needs 4 + mass != 0");
     }
@@ -576,9 +583,7 @@ int grid_solve_eo(const void *U, const void *b, void *x, const grid_geom *geom, 
         return fail(GRID_EINVAL, "x, b, U and workspace must not overlap");
     int status = GRID_OK;
     memset(stats, 0, sizeof(*stats));
-    const double diag = op->kind == GRID_WILSON ? 4.0 + op->mass : 5.0 - op->M5;
-    hipError_t e = run_solve_eo(U, b, x, g, op->kind, diag, op->mf, *params, workspace, static_cast<hipStream_t>(stream),
-                                stats, &status);
+    hipError_t e = run_solve_eo(U, b, x, g, *op, *params, workspace, static_cast<hipStream_t>(stream), stats, &status);
     if (e != hipSuccess) return hip_fail(e, "grid_solve_eo");
     if (status == GRID_ENOCONV)
         return fail(GRID_ENOCONV, "CG stopped after %d iterations (full residual %.3e)", stats->iterations,

@@ -20,6 +20,15 @@
 //   y_0 = [sum_k b_k d^-(k+1)] / (1 + m_f d^-Ls),  y_{Ls-1} = (b_{Ls-1} - m_f y_0) / d,
 //   y_s = (b_s + y_{s+1}) / d  for s = Ls-2 .. 1,
 // and mirrored in s for the other chirality (the recurrences are stable for |d| > 1).
+//
+// Moebius (M = D_W B + 1 - S, B = b5 + c5 S): the hopping term enters as M_eo = -H_eo B / 2,
+// M_oe = -H_oe B / 2, and M_ee = M_oo = (4 - M5) B + 1 - S = alpha - beta S with
+// alpha = 1 + (4 - M5) b5, beta = 1 - (4 - M5) c5: per chirality the same cyclic bidiagonal
+// system, so M_oo^-1 = (1 / beta) (alpha / beta - S)^-1 (d = alpha / beta), the factor 1 / beta
+// folded into the s-local pass that follows (M_oo = alpha when beta = 0). Then
+//   Mhat = M_ee - H_eo B M_oo^-1 H_oe B / 4,   Mhat^dagger = M_ee^dagger - B^dagger H_eo^dagger
+//   (M_oo^dagger)^-1 B^dagger H_oe^dagger / 4,
+//   bhat = b_e + H_eo B M_oo^-1 b_o / 2,   x_o = M_oo^-1 (b_o + H_oe B x_e / 2).
 #include <chrono>
 #include <string.h>
 
@@ -206,7 +215,7 @@ static hipError_t cb_copy(const void *src, void *dst, const GeomDev &g, int pari
 static hipError_t hop_cb(const void *U, int prec, int fmt, const GeomDev &g, int kind, int dag, double dg, double mf,
                          int cb, const void *psi, const float *psis, const void *y, const float *ys, double beta, void *out,
                          float *outs, hipStream_t st, int fuse = kFuseNone, const FuseDev *fz = nullptr,
-                         long *nparts = nullptr) {
+                         long *nparts = nullptr, double cs = 1.0) {
     DhopArgs a;
     a.U = U;
     a.psi = psi;
@@ -226,6 +235,7 @@ static hipError_t hop_cb(const void *U, int prec, int fmt, const GeomDev &g, int
     a.y = y;
     a.y_scale = ys;
     a.beta = beta;
+    a.cs = cs;
     if (fuse != kFuseNone) {
         a.fuse = fuse;
         a.fz = *fz;
@@ -240,14 +250,59 @@ struct EoOp {
     GeomDev g;
     int kind;
     double diag, mf;
+    double b5 = 1.0, c5 = 0.0, alpha = 0.0, beta = 0.0;   // Moebius: M_ee = alpha - beta S
     void *t1[2], *t2[2];
     float *t1s, *t2s;   // sloppy FP16 scales
 };
+
+// Moebius: out = (alpha / beta - S)^-1 in (S^dagger when dag), returning the factor f (1 / beta)
+// that makes f out = M_oo^-1 in; with beta = 0, out = in and f = 1 / alpha.
+static hipError_t mob_ee_inv(const EoOp &o, int prec, const void *in, const float *ins, void *out, float *outs, int dag,
+                             hipStream_t st, double *f) {
+    const long n4 = o.g.vol / 2;
+    if (o.beta == 0.0) {
+        *f = 1.0 / o.alpha;
+        return launch_s5axpy(prec, in, ins, nullptr, nullptr, out, outs, n4 * o.g.Ls, o.g.Ls, 1.0, 0.0, 0.0, 0.0, o.mf, dag,
+                             st);
+    }
+    *f = 1.0 / o.beta;
+    return launch_m5inv(in, ins, out, outs, n4, o.g.Ls, o.alpha / o.beta, o.mf, dag, prec, st);
+}
+
+// Moebius Schur operator (see the header): five kernels, the last carrying the fused epilogue.
+static hipError_t eo_apply_mobius(const EoOp &o, const void *U, int prec, int fmt, const void *in, const float *ins,
+                                  void *out, float *outs, int dag, int fuse, const FuseDev *fz, long *nparts,
+                                  hipStream_t st) {
+    const int ix = prec == GRID_F64 ? 0 : 1;
+    void *t1 = o.t1[ix], *t2 = o.t2[ix];
+    float *t1s = prec == GRID_F16S ? o.t1s : nullptr, *t2s = prec == GRID_F16S ? o.t2s : nullptr;
+    const long n5 = static_cast<long>(o.g.vol / 2) * o.g.Ls;
+    const int Ls = o.g.Ls;
+    double f = 1.0;
+    if (!dag) {
+        EOCHK(launch_s5axpy(prec, in, ins, nullptr, nullptr, t1, t1s, n5, Ls, o.b5, o.c5, 0.0, 0.0, o.mf, 0, st));
+        EOCHK(hop_cb(U, prec, fmt, o.g, GRID_HOP, 0, 0.0, o.mf, 1, t1, t1s, nullptr, nullptr, 1.0, t2, t2s, st));
+        EOCHK(mob_ee_inv(o, prec, t2, t2s, t1, t1s, 0, st, &f));
+        EOCHK(launch_s5axpy(prec, t1, t1s, nullptr, nullptr, t2, t2s, n5, Ls, f * o.b5, f * o.c5, 0.0, 0.0, o.mf, 0, st));
+        // out = alpha in - beta S in - H_eo t2 / 4
+        return hop_cb(U, prec, fmt, o.g, GRID_DWF, 0, o.alpha, o.mf, 0, t2, t2s, in, ins, -0.25, out, outs, st, fuse, fz,
+                      nparts, o.beta);
+    }
+    EOCHK(hop_cb(U, prec, fmt, o.g, GRID_HOP, 1, 0.0, o.mf, 1, in, ins, nullptr, nullptr, 1.0, t1, t1s, st));
+    EOCHK(launch_s5axpy(prec, t1, t1s, nullptr, nullptr, t2, t2s, n5, Ls, o.b5, o.c5, 0.0, 0.0, o.mf, 1, st));
+    EOCHK(mob_ee_inv(o, prec, t2, t2s, t1, t1s, 1, st, &f));
+    EOCHK(hop_cb(U, prec, fmt, o.g, GRID_HOP, 1, 0.0, o.mf, 0, t1, t1s, nullptr, nullptr, 1.0, t2, t2s, st));
+    // out = alpha in - beta S^dagger in - (b5 t2 + c5 S^dagger t2) f / 4
+    if (fuse != kFuseNone) *nparts = s5_blocks(n5);
+    return launch_s5axpy(prec, in, ins, t2, t2s, out, outs, n5, Ls, o.alpha, -o.beta, -0.25 * f * o.b5,
+                         -0.25 * f * o.c5, o.mf, 1, st, fuse, fz ? *fz : FuseDev());
+}
 
 static hipError_t eo_apply_fz(const void *ctx, const void *U, int prec, int fmt, const void *in, const float *ins,
                               void *out, float *outs, int dag, int fuse, const FuseDev *fz, long *nparts,
                               hipStream_t st) {
     const EoOp &o = *static_cast<const EoOp *>(ctx);
+    if (o.kind == GRID_MOBIUS) return eo_apply_mobius(o, U, prec, fmt, in, ins, out, outs, dag, fuse, fz, nparts, st);
     const int ix = prec == GRID_F64 ? 0 : 1;
     float *t1s = prec == GRID_F16S ? o.t1s : nullptr, *t2s = prec == GRID_F16S ? o.t2s : nullptr;
     // t1 = H_oe in
@@ -298,8 +353,9 @@ static EoLayout eo_layout(const GeomDev &g, int sloppy, int link_fmt) {
     L.bo = L.be + n * 192;
     L.bhat = take(n * 192);
     L.rhs = take(n * 192);
-    L.xe = take(n * 192);
-    L.xo = take(n * 192);
+    // xe and xo adjacent: a full FP64 field (the Moebius residual's intermediate) once x is assembled
+    L.xe = take(2 * n * 192);
+    L.xo = L.xe + n * 192;
     L.t1 = take(n * 192);
     L.t2 = take(n * 192);
     if (sloppy != GRID_F64) {
@@ -320,8 +376,11 @@ static EoLayout eo_layout(const GeomDev &g, int sloppy, int link_fmt) {
 
 size_t solve_eo_workspace_bytes(const GeomDev &g, int sloppy, int link_fmt) { return eo_layout(g, sloppy, link_fmt).total; }
 
-hipError_t run_solve_eo(const void *U, const void *b, void *x, const GeomDev &g, int kind, double diag, double mf,
+hipError_t run_solve_eo(const void *U, const void *b, void *x, const GeomDev &g, const grid_op &opd,
                         const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status) {
+    const int kind = opd.kind;
+    const double mf = opd.mf;
+    const double diag = kind == GRID_WILSON ? 4.0 + opd.mass : 5.0 - opd.M5;
     const auto t0 = std::chrono::steady_clock::now();
     const EoLayout L = eo_layout(g, p.sloppy_prec, p.link_fmt);
     char *w = static_cast<char *>(ws);
@@ -351,13 +410,27 @@ hipError_t run_solve_eo(const void *U, const void *b, void *x, const GeomDev &g,
     o.t2[1] = p.sloppy_prec != GRID_F64 ? w + L.t2h : nullptr;
     o.t1s = p.sloppy_prec == GRID_F16S ? reinterpret_cast<float *>(w + L.t1hs) : nullptr;
     o.t2s = p.sloppy_prec == GRID_F16S ? reinterpret_cast<float *>(w + L.t2hs) : nullptr;
+    if (kind == GRID_MOBIUS) {
+        o.b5 = opd.b5;
+        o.c5 = opd.c5;
+        o.alpha = 1.0 + (4.0 - opd.M5) * opd.b5;
+        o.beta = 1.0 - (4.0 - opd.M5) * opd.c5;
+    }
+    const long n5h = n;
 
     EOCHK(cb_copy(b, be, g, 0, 1, st));
     EOCHK(cb_copy(b, bo, g, 1, 1, st));
-    // bhat = b_e + H_eo M_oo^-1 b_o / 2
+    // bhat = b_e + H_eo M_oo^-1 b_o / 2  (Moebius: H_eo B M_oo^-1 b_o / 2)
     const void *src = bo;
     double beta = 0.5 / diag;
-    if (kind == GRID_DWF) {
+    if (kind == GRID_MOBIUS) {
+        double f = 1.0;
+        EOCHK(mob_ee_inv(o, GRID_F64, bo, nullptr, o.t1[0], nullptr, 0, st, &f));
+        EOCHK(launch_s5axpy(GRID_F64, o.t1[0], nullptr, nullptr, nullptr, o.t2[0], nullptr, n5h, g.Ls, f * o.b5,
+                            f * o.c5, 0.0, 0.0, mf, 0, st));
+        src = o.t2[0];
+        beta = 0.5;
+    } else if (kind == GRID_DWF) {
         EOCHK(launch_m5inv(bo, nullptr, o.t1[0], nullptr, g.vol / 2, g.Ls, diag, mf, 0, GRID_F64, st));
         src = o.t1[0];
         beta = 0.5;
@@ -374,8 +447,17 @@ hipError_t run_solve_eo(const void *U, const void *b, void *x, const GeomDev &g,
     memset(&cs, 0, sizeof(cs));
     EOCHK(run_cg_op(op, U, rhs, xe, n, static_cast<long>(g.vol) * 4, p, w + L.cg, st, &cs, status, false,
                     fused_parts_max(static_cast<long>(n), g.L[3])));
-    // x_o = M_oo^-1 (b_o + H_oe x_e / 2)
-    if (kind == GRID_DWF) {
+    // x_o = M_oo^-1 (b_o + H_oe x_e / 2)  (Moebius: M_oo^-1 (b_o + H_oe B x_e / 2))
+    if (kind == GRID_MOBIUS) {
+        double f = 1.0;
+        EOCHK(launch_s5axpy(GRID_F64, xe, nullptr, nullptr, nullptr, o.t2[0], nullptr, n5h, g.Ls, o.b5, o.c5, 0.0, 0.0,
+                            mf, 0, st));
+        EOCHK(hop_cb(U, GRID_F64, GRID_L18, g, GRID_WILSON, 0, 1.0, mf, 1, o.t2[0], nullptr, bo, nullptr, 0.5, o.t1[0],
+                     nullptr, st));
+        EOCHK(mob_ee_inv(o, GRID_F64, o.t1[0], nullptr, o.t2[0], nullptr, 0, st, &f));
+        EOCHK(launch_s5axpy(GRID_F64, o.t2[0], nullptr, nullptr, nullptr, xo, nullptr, n5h, g.Ls, f, 0.0, 0.0, 0.0, mf, 0,
+                            st));
+    } else if (kind == GRID_DWF) {
         EOCHK(hop_cb(U, GRID_F64, GRID_L18, g, GRID_WILSON, 0, 1.0, mf, 1, xe, nullptr, bo, nullptr, 0.5, o.t1[0], nullptr,
                      st));
         EOCHK(launch_m5inv(o.t1[0], nullptr, xo, nullptr, g.vol / 2, g.Ls, diag, mf, 0, GRID_F64, st));
@@ -400,7 +482,10 @@ hipError_t run_solve_eo(const void *U, const void *b, void *x, const GeomDev &g,
     a.diag = diag;
     a.mf = mf;
     a.stream = st;
-    EOCHK(launch_dhop(a));
+    if (kind == GRID_MOBIUS)
+        EOCHK(launch_mobius(a, opd.M5, opd.b5, opd.c5, xe, nullptr));   // xe | xo: a full-field temporary
+    else
+        EOCHK(launch_dhop(a));
     double rr = 0.0;
     EOCHK(norm2_diff(b, be, g.n5, norm, st, &rr));
     stats->iterations = cs.iterations;

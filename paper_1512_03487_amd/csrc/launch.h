@@ -73,6 +73,13 @@ hipError_t launch_mobius(const DhopArgs &a, double M5, double b5, double c5, voi
                          long *nparts = nullptr);
 // Upper bound of the partial sums any fused epilogue writes for n5 sites (hopping or s-local kernel).
 long fused_parts_max(long n5, int Lt);
+// The s-local pass (mobius.hip): out = a1 u + a2 S u + a3 v + a4 S v (S^dagger when dag) on n5 5D
+// sites of Ls records (full or checkerboard fields); v may be NULL. fuse: kFuseNone or kFuseAxpy
+// (out = r - alpha (...), partials of |out|^2 in s5_blocks(n5) blocks).
+hipError_t launch_s5axpy(int prec, const void *u, const float *us, const void *v, const float *vs, void *out,
+                         float *outs, long n5, int Ls, double a1, double a2, double a3, double a4, double mf, int dag,
+                         hipStream_t st, int fuse = kFuseNone, const FuseDev &fz = FuseDev());
+long s5_blocks(long n5);
 
 // Fifth-dimension operator inverse of the domain-wall operator (eo.hip): out = M5^-1 psi or
 // (M5^dagger)^-1 psi on n4 4D sites of Ls records each (full or checkerboard fields).
@@ -81,7 +88,8 @@ hipError_t launch_m5inv(const void *psi, const float *psi_scale, void *out, floa
 
 // Even-odd solve of M x = b (eo.hip).
 size_t solve_eo_workspace_bytes(const GeomDev &g, int sloppy, int link_fmt);
-hipError_t run_solve_eo(const void *U, const void *b, void *x, const GeomDev &g, int kind, double diag, double mf,
+// op: GRID_WILSON (mass), GRID_DWF (M5, mf) or GRID_MOBIUS (M5, mf, b5, c5).
+hipError_t run_solve_eo(const void *U, const void *b, void *x, const GeomDev &g, const grid_op &op,
                         const grid_cg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats, int *status);
 
 // Link gradient / force of the hopping term (backward.hip).

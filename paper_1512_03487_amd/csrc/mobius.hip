@@ -59,7 +59,7 @@ k_s5axpy(const void *__restrict__ u, const float *__restrict__ us, const void *_
     store_elem<SP>(out, outs, qq, k, r, live);
 }
 
-static long s5_blocks(long n5) { return (n5 + kS5Sites - 1) / kS5Sites; }
+long s5_blocks(long n5) { return (n5 + kS5Sites - 1) / kS5Sites; }
 
 template <int FUSE>
 static void s5axpy_prec(int prec, dim3 grid, hipStream_t st, const void *u, const float *us, const void *v,
@@ -77,9 +77,9 @@ static void s5axpy_prec(int prec, dim3 grid, hipStream_t st, const void *u, cons
                            a4, mf, dag, fz);
 }
 
-static hipError_t launch_s5axpy(int prec, const void *u, const float *us, const void *v, const float *vs, void *out,
-                                float *outs, long n5, int Ls, double a1, double a2, double a3, double a4, double mf,
-                                int dag, hipStream_t st, int fuse = kFuseNone, const FuseDev &fz = FuseDev()) {
+hipError_t launch_s5axpy(int prec, const void *u, const float *us, const void *v, const float *vs, void *out,
+                         float *outs, long n5, int Ls, double a1, double a2, double a3, double a4, double mf, int dag,
+                         hipStream_t st, int fuse, const FuseDev &fz) {
     if (n5 == 0) return hipSuccess;
     const dim3 grid(static_cast<unsigned>(s5_blocks(n5)));
     if (fuse == kFuseAxpy)

@@ -163,13 +163,18 @@ def test_mobius_validation(lib):
     assert call(tmp=A + 0x10000000 + 64) == _lib.GRID_EINVAL                # tmp overlaps psi
     assert call(prec=_lib.GRID_F16S) == _lib.GRID_EINVAL                     # scales missing
     assert dhop(lib, o=mob, g=g) == _lib.GRID_EINVAL and "grid_mobius" in _lib.last_error()
-    # the CG takes the Moebius kind; the even-odd solver does not
+    # the even-odd solver takes the Moebius kind when M_ee = alpha - beta S has a stable inverse:
+    # alpha = 1 + (4 - M5) b5, beta = 1 - (4 - M5) c5 with |alpha / beta| > 1, or beta = 0 != alpha
     p64 = _lib.GridCgParams(1e-10, 100, _lib.GRID_F64, _lib.GRID_L18, 0.1, 10)
     st = _lib.GridCgStats()
     w = lib.grid_solve_eo_workspace_bytes(ctypes.byref(g), ctypes.byref(p64))
-    assert lib.grid_solve_eo(P(A), P(A + 0x10000000), P(A + 0x20000000), ctypes.byref(g), ctypes.byref(mob),
-                             ctypes.byref(p64), P(A + 0x40000000), ctypes.c_size_t(w), ctypes.byref(st),
-                             None) == _lib.GRID_EINVAL
+    eo = lambda oo, gg=g: lib.grid_solve_eo(P(A), P(A + 0x10000000), P(A + 0x20000000), ctypes.byref(gg),
+                                            ctypes.byref(oo), ctypes.byref(p64), P(A + 0x40000000), ctypes.c_size_t(w),
+                                            ctypes.byref(st), None)
+    assert eo(op(kind=_lib.GRID_MOBIUS, b5=0.0, c5=0.0)) == _lib.GRID_EINVAL            # alpha = beta = 1
+    assert "alpha" in _lib.last_error()
+    assert eo(op(kind=_lib.GRID_MOBIUS, M5=2.0, b5=-0.5, c5=0.5)) == _lib.GRID_EINVAL    # beta = 0 = alpha
+    assert eo(op(kind=_lib.GRID_MOBIUS, b5=1.5, c5=0.5), gg=geom((4, 4, 4, 4), Ls=65)) == _lib.GRID_ESHAPE
 
 
 def test_md_validation(lib):

@@ -179,6 +179,56 @@ def test_solve_eo(gpu, kind, dims, Ls, sloppy, fmt):
     assert r_full <= 1e-9
 
 
+MOB_CASES = {"mobius": dict(M5=1.8, mf=0.1, b5=1.5, c5=0.5),      # alpha = 4.3, beta = -0.1
+             "beta0": dict(M5=2.0, mf=0.1, b5=1.5, c5=0.5),       # beta = 0: M_ee = alpha = 4
+             "shamir": dict(M5=1.8, mf=0.1, b5=1.0, c5=0.0)}      # the domain-wall M
+
+
+@pytest.mark.parametrize("case", sorted(MOB_CASES))
+@pytest.mark.parametrize("dims,Ls", [((4, 4, 4, 4), 8), ((2, 2, 4, 6), 4)])
+@pytest.mark.parametrize("sloppy,fmt", [("f64", "L18"), ("f32", "L18"), ("f16s", "L12")])
+def test_solve_eo_mobius(gpu, case, dims, Ls, sloppy, fmt):
+    """Even-odd CG for the Moebius operator, checked with the oracle's Moebius blocks: the CG
+    criterion on the Schur system, the odd-site reconstruction and the full residual."""
+    from oracle import mobius as OM
+    from tests.gpu_util import dev, host, rel
+    gm = _gm()
+    kw = MOB_CASES[case]
+    U = F.gauge_field(dims, seed=1, kind="haar")
+    b = F.spinor_field(dims, seed=3, Ls=Ls)
+    tol = 1e-12
+    print(f"[gpu] solve_eo mobius {case} {dims} Ls={Ls} {sloppy}", flush=True)
+    x, st = gm.solve_eo(dev(U), dev(b), "mobius", tol=tol, sloppy=sloppy, link_fmt=fmt, **kw)
+    xh = host(x)
+    assert st["converged"] and st["status"] == 0
+    bh = eo.source_mobius(U, b, **kw)
+    xe = eo.pick(xh, 0)
+    rhs = eo.schur_mobius(U, bh, dag=True, **kw)
+    rn = np.linalg.norm(rhs - eo.schur_mobius(U, eo.schur_mobius(U, xe, **kw), dag=True, **kw)) / np.linalg.norm(rhs)
+    assert rn <= 1.05 * tol, rn
+    assert rel(eo.pick(xh, 1), eo.odd_solution_mobius(U, b, xe, **kw)) <= 1e-12
+    r_full = rel(OM.mobius(U, xh, **kw), b)
+    assert abs(r_full - st["true_residual"]) <= 1e-3 * r_full + 1e-15
+    assert r_full <= 1e-9
+
+
+def test_solve_eo_mobius_matches_shamir_and_cg(gpu):
+    """b5 = 1, c5 = 0 is the Shamir operator: the Moebius even-odd solution equals the domain-wall
+    one, and the Moebius even-odd solve takes fewer iterations than CG on M^+ M."""
+    from tests.gpu_util import dev, host, rel
+    gm = _gm()
+    dims, Ls = (4, 4, 4, 4), 8
+    U, b = dev(F.gauge_field(dims, seed=1, kind="haar")), dev(F.spinor_field(dims, seed=3, Ls=Ls))
+    xm, _ = gm.solve_eo(U, b, "mobius", M5=1.8, mf=0.1, b5=1.0, c5=0.0, tol=1e-12)
+    xd, _ = gm.solve_eo(U, b, "dwf", M5=1.8, mf=0.1, tol=1e-12)
+    assert rel(host(xm), host(xd)) <= 1e-10
+    kw = dict(M5=1.8, mf=0.1, b5=1.5, c5=0.5)
+    _, st_eo = gm.solve_eo(U, b, "mobius", tol=1e-10, **kw)
+    mdb = gm.mobius(U, b, dag=True, **kw)
+    _, st_full = gm.cg(U, mdb, "mobius", tol=1e-10, **kw)
+    assert st_eo["iterations"] < 0.8 * st_full["iterations"], (st_eo["iterations"], st_full["iterations"])
+
+
 def test_solve_eo_needs_fewer_iterations(gpu):
     """The even-odd system converges in fewer iterations than CG on M^+ M for the same M x = b."""
     from tests.gpu_util import dev, host, rel

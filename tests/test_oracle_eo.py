@@ -122,3 +122,56 @@ def test_schur_complement_solve_equals_full_solve(kind):
     x = eo.merge(x_e, eo.odd_solution(U, b, x_e, kind, **kw))
     assert rel(x, x_full) < 1e-12
     assert rel(O.apply(op, U, x), b) < 1e-12
+
+
+MOB = dict(M5=1.8, mf=0.1, b5=1.5, c5=0.5)
+
+
+def test_mobius_diagonal_block_is_the_operator_without_hopping():
+    """M_ee read off the full Moebius operator equals the matrix of its s-local part, the dense
+    inverse inverts it, and the Shamir limit gives the domain-wall M5 (whose projectors and walls
+    the C oracle fixes)."""
+    dims, Ls = (2, 2, 2, 4), 4
+    U = F.gauge_field(dims, seed=1)
+    psi = eo.pick(_rand5(dims, Ls, 3), 0)
+    blk = eo.mobius_block(U, psi, 0, 0, **MOB)
+    A = eo.mobius_diag_matrix(Ls, MOB["M5"], MOB["mf"], MOB["b5"], MOB["c5"])
+    direct = np.einsum("ij,...jc->...ic", A, psi.reshape(psi.shape[:4] + (Ls * 4, 3))).reshape(psi.shape)
+    assert rel(blk, direct) < 1e-14
+    assert rel(eo.mobius_diag_inv(blk, MOB["M5"], MOB["mf"], MOB["b5"], MOB["c5"]), psi) < 1e-13
+    shamir = eo.mobius_block(U, psi, 0, 0, M5=1.8, mf=0.1, b5=1.0, c5=0.0)
+    assert rel(shamir, eo.m5(psi, 1.8, 0.1)) < 1e-14
+    for dag in (False, True):
+        assert rel(eo.mobius_diag_inv(eo.mobius_block(U, psi, 0, 0, dag=dag, **MOB), MOB["M5"], MOB["mf"], MOB["b5"],
+                                      MOB["c5"], dag), psi) < 1e-13
+
+
+def test_mobius_schur_shamir_limit_and_adjoint():
+    dims, Ls = (2, 2, 2, 4), 4
+    U = F.gauge_field(dims, seed=1)
+    x = eo.pick(_rand5(dims, Ls, 6), 0)
+    y = eo.pick(_rand5(dims, Ls, 7), 0)
+    # b5 = 1, c5 = 0 is the Shamir operator: the same Schur complement as the domain-wall one
+    for dag in (False, True):
+        a = eo.schur_mobius(U, x, 1.8, 0.1, 1.0, 0.0, dag)
+        assert rel(a, eo.schur(U, x, "dwf", M5=1.8, mf=0.1, dag=dag)) < 1e-13
+    a = np.vdot(y, eo.schur_mobius(U, x, **MOB))
+    b = np.vdot(eo.schur_mobius(U, y, dag=True, **MOB), x)
+    assert abs(a - b) < 1e-13 * abs(a)
+
+
+def test_mobius_schur_complement_solve_equals_full_solve():
+    """Moebius 2^4 x 4: x_e = Mhat^-1 bhat and x_o = M_oo^-1 (b_o - M_oe x_e) solve M x = b, with
+    M the dense matrix of the full-lattice Moebius oracle."""
+    from oracle import mobius as mob
+    dims, Ls = (2, 2, 2, 2), 4
+    U = F.gauge_field(dims, seed=1)
+    b = _rand5(dims, Ls, 3)
+    M = _dense(lambda v: mob.mobius(U, v, **MOB), b.shape)
+    x_full = np.linalg.solve(M, b.ravel()).reshape(b.shape)
+    bh = eo.source_mobius(U, b, **MOB)
+    Mh = _dense(lambda v: eo.schur_mobius(U, v, **MOB), bh.shape)
+    x_e = np.linalg.solve(Mh, bh.ravel()).reshape(bh.shape)
+    x = eo.merge(x_e, eo.odd_solution_mobius(U, b, x_e, **MOB))
+    assert rel(x, x_full) < 1e-12
+    assert rel(mob.mobius(U, x, **MOB), b) < 1e-12
