@@ -226,27 +226,30 @@ def cb_leg(dims, Ls, prec, fmt, steps=50, warmup=5, nsets=4):
             "roofline_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4), "buffer_sets": nsets}
 
 
-def mobius_leg(dims, Ls, prec, steps, warmup, b5=1.5, c5=0.5):
-    """Moebius operator (grid_mobius): s-local pass + hopping pass; GB/s on the same algorithmic
-    bytes as the Shamir operator (read psi and the links once, write out once)."""
+def mobius_leg(dims, Ls, prec, steps, warmup, b5=1.5, c5=0.5, fmt="L18"):
+    """Moebius operator M and M^dagger (grid_mobius); GB/s on the same algorithmic bytes as the
+    Shamir operator (read psi and the links once, write out once)."""
     import torch
     import paper_1512_03487_amd as gm
-    (U, p, o), = make_sets(dims, prec, 1, kind="haar", Ls=Ls)[0]
-    tmp = torch.empty_like(p)
-    for _ in range(warmup):
-        gm.mobius(U, p, 1.8, 0.01, b5, c5, out=o, tmp=tmp)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        gm.mobius(U, p, 1.8, 0.01, b5, c5, out=o, tmp=tmp)
-    e1.record()
-    torch.cuda.synchronize()
-    t = e0.elapsed_time(e1) * 1e-3 / steps
+    (U, p, o), = make_sets(dims, prec, 1, kind="haar", Ls=Ls, fmt=fmt)[0]
+    tmp = gm.F16Spinor(torch.empty_like(p.codes), torch.empty_like(p.scale)) if prec == "f16s" else torch.empty_like(p)
     n5 = dims[0] * dims[1] * dims[2] * dims[3] * Ls
-    gbs = alg_bytes_per_site(prec, "L18", Ls) * n5 / t / 1e9
-    return {"lattice": list(dims), "Ls": Ls, "prec": prec, "b5": b5, "c5": c5, "us_per_launch": round(t * 1e6, 2),
-            "alg_gbs": round(gbs, 1), "roofline_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out = {"lattice": list(dims), "Ls": Ls, "prec": prec, "links": fmt, "b5": b5, "c5": c5}
+    for dag in (False, True):
+        for _ in range(warmup):
+            gm.mobius(U, p, 1.8, 0.01, b5, c5, dag=dag, out=o, tmp=tmp)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            gm.mobius(U, p, 1.8, 0.01, b5, c5, dag=dag, out=o, tmp=tmp)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3 / steps
+        gbs = alg_bytes_per_site(prec, fmt, Ls) * n5 / t / 1e9
+        out["Mdag" if dag else "M"] = {"us_per_launch": round(t * 1e6, 2), "alg_gbs": round(gbs, 1),
+                                       "roofline_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def leg(dims, prec, fmt, kind, Ls, steps, warmup, min_bytes=600e6):
@@ -743,6 +746,7 @@ def main():
         legs["dwf_eo_hop_16^4x16_f32"] = cb_leg((16, 16, 16, 16), 16, "f32", "L18")
         legs["dwf_eo_hop_16^4x16_f16s_L12"] = cb_leg((16, 16, 16, 16), 16, "f16s", "L12")
         legs["mobius_16^4x16_f32"] = mobius_leg((16, 16, 16, 16), 16, "f32", 50, 5)
+        legs["mobius_16^4x16_f16s_L12"] = mobius_leg((16, 16, 16, 16), 16, "f16s", 50, 5, fmt="L12")
         legs["mobius_16^4x16_f64"] = mobius_leg((16, 16, 16, 16), 16, "f64", 20, 3)
         torch.cuda.empty_cache()
     cg = eo = eo_mob = cgi = mgl = None

@@ -705,6 +705,96 @@ __device__ __forceinline__ void gather(const void *__restrict__ base, const floa
     stage<SP>(f, lds, p);
 }
 
+// Fifth-dimension columns inside a wavefront (the Moebius operator's fused passes): when Ls
+// divides 64 and the wavefront's first lane holds s = 0, lanes lbase .. lbase + Ls - 1 hold
+// s = 0 .. Ls - 1 of one 4D site, and the lanes of s + 1 and s - 1 (cyclic in the column) are
+// lp and lm.
+//
+// stage() for the Moebius hopping pass: the lane's record becomes chi_s = b5 psi_s + c5 (S psi)_s,
+// (S psi)_s = P_- psi~_{s+1} + P_+ psi~_{s-1} (P_+ the upper spins 0, 1), with cp and cm the
+// factors c5 times the wall factor of s + 1 and of s - 1 (-mf across a wall, else 1).
+template <class SP>
+__device__ __forceinline__ void stage_b5(const Fetch<SP> &f, chunk_t *lds, Cx<typename SP::C> p[4][3], int lp, int lm,
+                                         typename SP::C b5, typename SP::C cp, typename SP::C cm) {
+    using C = typename SP::C;
+    constexpr int CH = SP::kChunks;
+    constexpr int PITCH = stage_pitch<SP>();
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const int c = k * 64 + lane;
+        const int r = c / CH, j = c - (c / CH) * CH;
+        lds[r * PITCH + j] = f.w[k];
+    }
+    wave_sync();
+    uint4 w[CH], wp[CH], wm[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const chunk_t v = lds[lane * PITCH + k], vp = lds[lp * PITCH + k], vm = lds[lm * PITCH + k];
+        w[k] = make_uint4(v.x, v.y, v.z, v.w);
+        wp[k] = make_uint4(vp.x, vp.y, vp.z, vp.w);
+        wm[k] = make_uint4(vm.x, vm.y, vm.z, vm.w);
+    }
+    wave_sync();
+    float sp = f.s, sm = f.s;
+    if constexpr (SP::kScaled) {
+        sp = __shfl(f.s, lp, 64);
+        sm = __shfl(f.s, lm, 64);
+    }
+    Cx<C> q[4][3];
+    SP::unpack(w, f.s, p);
+    SP::unpack(wm, sm, q);   // upper spins from s - 1
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        Cx<C> &o = p[j / 3][j % 3];
+        o = {b5 * o.r + cm * q[j / 3][j % 3].r, b5 * o.i + cm * q[j / 3][j % 3].i};
+    }
+    SP::unpack(wp, sp, q);   // lower spins from s + 1
+#pragma unroll
+    for (int j = 6; j < 12; ++j) {
+        Cx<C> &o = p[j / 3][j % 3];
+        o = {b5 * o.r + cp * q[j / 3][j % 3].r, b5 * o.i + cp * q[j / 3][j % 3].i};
+    }
+}
+
+template <class SP>
+__device__ __forceinline__ void gather_b5(const void *__restrict__ base, const float *__restrict__ scale, int rec,
+                                          chunk_t *lds, Cx<typename SP::C> p[4][3], int lp, int lm, typename SP::C b5,
+                                          typename SP::C cp, typename SP::C cm) {
+    Fetch<SP> f;
+    fetch<SP>(base, scale, rec, f);
+    stage_b5<SP>(f, lds, p, lp, lm, b5, cp, cm);
+}
+
+// Half-spinor exchange inside fifth-dimension columns: h = spins 2 hf, 2 hf + 1 of lane src's v,
+// through the wavefront's staging area (every lane takes part).
+template <class SP>
+__device__ __forceinline__ void column_half(chunk_t *lds, const Cx<typename SP::C> v[4][3], int hf, int src,
+                                            Cx<typename SP::C> h[2][3]) {
+    using C = typename SP::C;
+    constexpr int NC = static_cast<int>(12 * sizeof(C) / 16);   // 16-byte chunks of six complex numbers
+    constexpr int PITCH = stage_pitch<SP>();
+    static_assert(NC <= PITCH, "a half spinor fits the lane's staging slot");
+    const int lane = threadIdx.x & 63;
+    C buf[12];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        buf[2 * j] = v[2 * hf + j / 3][j % 3].r;
+        buf[2 * j + 1] = v[2 * hf + j / 3][j % 3].i;
+    }
+    chunk_t cb[NC];
+    __builtin_memcpy(cb, buf, sizeof(cb));
+#pragma unroll
+    for (int k = 0; k < NC; ++k) lds[lane * PITCH + k] = cb[k];
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < NC; ++k) cb[k] = lds[src * PITCH + k];
+    wave_sync();
+    __builtin_memcpy(buf, cb, sizeof(cb));
+#pragma unroll
+    for (int j = 0; j < 6; ++j) h[j / 3][j % 3] = {buf[2 * j], buf[2 * j + 1]};
+}
+
 // Hardware dispatches workgroup b to XCD b % 8. Renumber so that each XCD receives one
 // contiguous range of logical blocks: neighbouring lattice sites then share an L2.
 __device__ __forceinline__ int xcd_block(int b, int nblocks) {

@@ -433,8 +433,14 @@ template <class SP, class LK, bool DAG, int KIND, int FUSE>
 __global__ void __launch_bounds__(256)
 k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const float *__restrict__ psi_scale,
        const void *__restrict__ yv, const float *__restrict__ y_scale, void *out, float *out_scale, GeomDev g, int T,
-       double diag, double mf, double cs, FuseDev fz) {
+       double diag, double mf, double cs, double b5, double c5, FuseDev fz) {
     using C = typename SP::C;
+    // Moebius (KIND GRID_MOBIUS, y = psi, Ls dividing 64): M psi gathers chi = B psi, B = b5 + c5 S,
+    // for the hopping records (stage_b5) and ends like the domain-wall operator with diag =
+    // 1 + (4 - M5) b5 and cs = 1 - (4 - M5) c5; M^dagger psi forms w = (4 - M5) psi - H^dagger psi / 2
+    // (diag = 4 - M5) and then b5 w + psi + S^dagger (c5 w - psi) across the column's lanes.
+    constexpr bool MOBF = KIND == GRID_MOBIUS && !DAG;
+    constexpr bool MOBA = KIND == GRID_MOBIUS && DAG;
     __shared__ chunk_t sm[kWaves][64 * stage_pitch<SP>()];
     chunk_t *lds = sm[threadIdx.x >> 6];
 
@@ -454,16 +460,34 @@ k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const floa
     const int t0 = seg * T;
     // H: (1 - gamma) forward, (1 + gamma) backward; H^dagger the opposite.
     constexpr int EF = DAG ? +1 : -1;
+    // Moebius: the column's lanes of s + 1 and s - 1 and the wall factors
+    int lp = 0, lm = 0;
+    C mb5 = C(0), mc5 = C(0), wp = C(1), wm = C(1);
+    if constexpr (KIND == GRID_MOBIUS) {
+        const int lane = threadIdx.x & 63, sl = lane % Ls, lbase = lane - sl;
+        lp = lbase + (sl == Ls - 1 ? 0 : sl + 1);
+        lm = lbase + (sl == 0 ? Ls - 1 : sl - 1);
+        mb5 = static_cast<C>(b5);
+        mc5 = static_cast<C>(c5);
+        wp = sl == Ls - 1 ? static_cast<C>(-mf) : C(1);
+        wm = sl == 0 ? static_cast<C>(-mf) : C(1);
+    }
 
     Cx<C> chi_b[2][3], hb[2][3], p[4][3], u[3][3];
     {
         // backward t-hop of slice t0: U_t(x, t0 - 1)^dagger h(psi(x, t0 - 1))
         const int tm = (t0 == 0) ? Lt - 1 : t0 - 1;
-        gather<SP>(psi, psi_scale, tm * nq + qq, lds, p);
+        if constexpr (MOBF)
+            gather_b5<SP>(psi, psi_scale, tm * nq + qq, lds, p, lp, lm, mb5, mc5 * wp, mc5 * wm);
+        else
+            gather<SP>(psi, psi_scale, tm * nq + qq, lds, p);
         project<3, -EF>(p, hb);
         LK::load(U, (static_cast<size_t>(tm) * V3 + col) * 4 + 3, u);
         su3_adj_mul(u, hb, chi_b);
-        gather<SP>(psi, psi_scale, t0 * nq + qq, lds, p);
+        if constexpr (MOBF)
+            gather_b5<SP>(psi, psi_scale, t0 * nq + qq, lds, p, lp, lm, mb5, mc5 * wp, mc5 * wm);
+        else
+            gather<SP>(psi, psi_scale, t0 * nq + qq, lds, p);
         project<3, -EF>(p, hb);
     }
     // Records gathered per step, in order: psi(x, t+1), the six spatial neighbours at t, and the
@@ -490,7 +514,10 @@ k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const floa
         reconstruct_add<3, -EF>(acc, chi_b);
 #pragma unroll
         for (int i = 0; i < NREC; ++i) {
-            stage<SP>(f, lds, p);
+            if (MOBF && i < 7)
+                stage_b5<SP>(f, lds, p, lp, lm, mb5, mc5 * wp, mc5 * wm);
+            else
+                stage<SP>(f, lds, p);
             // link of this direction first, then the next record: loads complete in issue order
             const int mu = (i == 0) ? 3 : (i - 1) / 2;
             const bool bwd = (i >= 1 && i <= 6 && ((i - 1) & 1));
@@ -528,7 +555,30 @@ k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const floa
                 }
             }
         }
-        if (KIND == GRID_DWF) {
+        if constexpr (MOBA) {
+            // M^dagger psi = b5 w + psi + S^dagger v with v = c5 w - psi, w = acc and psi = p (the
+            // centre record); (S^dagger v)_s = P_+ v~_{s+1} + P_- v~_{s-1}
+            Cx<C> v[4][3], h[2][3];
+#pragma unroll
+            for (int j = 0; j < 12; ++j) {
+                const Cx<C> a = acc[j / 3][j % 3], c = p[j / 3][j % 3];
+                v[j / 3][j % 3] = {mc5 * a.r - c.r, mc5 * a.i - c.i};
+                acc[j / 3][j % 3] = {mb5 * a.r + c.r, mb5 * a.i + c.i};
+            }
+            column_half<SP>(lds, v, 0, lp, h);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                Cx<C> &o = acc[j / 3][j % 3];
+                o = {o.r + wp * h[j / 3][j % 3].r, o.i + wp * h[j / 3][j % 3].i};
+            }
+            column_half<SP>(lds, v, 1, lm, h);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                Cx<C> &o = acc[2 + j / 3][j % 3];
+                o = {o.r + wm * h[j / 3][j % 3].r, o.i + wm * h[j / 3][j % 3].i};
+            }
+        }
+        if (KIND == GRID_DWF || MOBF) {
             // M:   - P_- y~_{s+1} - P_+ y~_{s-1};  M^dagger: - P_+ y~_{s+1} - P_- y~_{s-1}, times cs
             // walls: y~_{Ls} = -mf y_0, y~_{-1} = -mf y_{Ls-1}
             const int sp = (s == Ls - 1) ? 0 : s + 1;
@@ -753,6 +803,13 @@ static int choose_steps(const GeomDev &g) {
     return best;
 }
 
+// The fused Moebius operator runs on the full-lattice column walk (FP32 and FP16-storage 5D fields)
+// when whole fifth-dimension columns fit a wavefront.
+bool walk_mobius_applies(const DhopArgs &a) {
+    return a.kind == GRID_MOBIUS && !a.custom && a.g.Ls >= 2 && 64 % a.g.Ls == 0 &&
+           (a.prec == GRID_F32 || a.prec == GRID_F16S);
+}
+
 template <class SP, class LK>
 static hipError_t launch_walk(const DhopArgs &a) {
     const int T = choose_steps(a.g);
@@ -761,16 +818,19 @@ static hipError_t launch_walk(const DhopArgs &a) {
     hipStream_t st = a.stream;
     const void *y = a.custom ? a.y : a.psi;
     const float *ys = a.custom ? a.y_scale : a.psi_scale;
-    const double cs = a.custom ? a.cs : 1.0;
+    const double cs = (a.custom || a.kind == GRID_MOBIUS) ? a.cs : 1.0;
 #define GRIDMI_LAUNCH(DAG, KIND, FUSE)                                                                    \
     hipLaunchKernelGGL((k_dhop_walk<SP, LK, DAG, KIND, FUSE>), grid, block, 0, st, a.U, a.psi, a.psi_scale, y, ys,  \
-                       a.out, a.out_scale, a.g, T, a.diag, a.mf, cs, a.fz)
+                       a.out, a.out_scale, a.g, T, a.diag, a.mf, cs, a.b5, a.c5, a.fz)
+    if (a.kind == GRID_MOBIUS && !walk_mobius_applies(a)) return hipErrorInvalidValue;
     if (a.fuse != kFuseNone) {
         switch (a.kind * 4 + a.fuse * 2 + (a.dag ? 1 : 0)) {
             case GRID_WILSON * 4 + kFuseNorm * 2 + 0: GRIDMI_LAUNCH(false, GRID_WILSON, kFuseNorm); break;
             case GRID_DWF * 4 + kFuseNorm * 2 + 0: GRIDMI_LAUNCH(false, GRID_DWF, kFuseNorm); break;
+            case GRID_MOBIUS * 4 + kFuseNorm * 2 + 0: GRIDMI_LAUNCH(false, GRID_MOBIUS, kFuseNorm); break;
             case GRID_WILSON * 4 + kFuseAxpy * 2 + 1: GRIDMI_LAUNCH(true, GRID_WILSON, kFuseAxpy); break;
             case GRID_DWF * 4 + kFuseAxpy * 2 + 1: GRIDMI_LAUNCH(true, GRID_DWF, kFuseAxpy); break;
+            case GRID_MOBIUS * 4 + kFuseAxpy * 2 + 1: GRIDMI_LAUNCH(true, GRID_MOBIUS, kFuseAxpy); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -782,6 +842,8 @@ static hipError_t launch_walk(const DhopArgs &a) {
         case GRID_WILSON * 2 + 1: GRIDMI_LAUNCH(true, GRID_WILSON, kFuseNone); break;
         case GRID_DWF * 2 + 0: GRIDMI_LAUNCH(false, GRID_DWF, kFuseNone); break;
         case GRID_DWF * 2 + 1: GRIDMI_LAUNCH(true, GRID_DWF, kFuseNone); break;
+        case GRID_MOBIUS * 2 + 0: GRIDMI_LAUNCH(false, GRID_MOBIUS, kFuseNone); break;
+        case GRID_MOBIUS * 2 + 1: GRIDMI_LAUNCH(true, GRID_MOBIUS, kFuseNone); break;
         default: return hipErrorInvalidValue;
     }
 #undef GRIDMI_LAUNCH
@@ -844,6 +906,7 @@ static bool use_walk_cb(const DhopArgs &a) { return a.custom && a.cb >= 0 && wal
 
 template <class SP, class LK>
 static hipError_t launch_sched(const DhopArgs &a) {
+    if (a.kind == GRID_MOBIUS && !walk_mobius_applies(a)) return hipErrorInvalidValue;
     if (tile_applies(a)) return launch_tile(a);
     if (use_walk(a)) return launch_walk<SP, LK>(a);
     if (use_walk_cb(a)) return launch_walk_cb<SP, LK>(a);

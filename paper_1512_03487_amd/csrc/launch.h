@@ -48,6 +48,9 @@ struct DhopArgs {
     const float *y_scale = nullptr;
     double beta = 0.0;
     double cs = 1.0;           // DWF epilogue: coefficient of the fifth-dimension hopping of y
+    // kind GRID_MOBIUS (full lattice, walk_mobius_applies): the whole operator in one kernel, with
+    // diag = 1 + (4 - M5) b5 and cs = 1 - (4 - M5) c5 (M), or diag = 4 - M5 (M^dagger)
+    double b5 = 1.0, c5 = 0.0;
     // Fused epilogue (kind WILSON or DWF; full lattice or the custom even-odd form): kFuseNorm
     // with dag = 0, kFuseAxpy with dag = 1.
     int fuse = kFuseNone;
@@ -55,6 +58,7 @@ struct DhopArgs {
 };
 
 hipError_t launch_dhop(const DhopArgs &a);
+bool walk_mobius_applies(const DhopArgs &a);
 // Tiled time-walk schedule (tile.hip): full-lattice 4D FP32 / FP16-storage fields whose x, y, z
 // extents the tile divides.
 bool tile_applies(const DhopArgs &a);

@@ -7,6 +7,9 @@
 // 4D-diagonal rest, (4 - M5) chi + psi - S psi = (1 + b5 (4 - M5)) psi - (1 - c5 (4 - M5)) S psi;
 // M^dagger psi is one hopping pass phi = D_W^dagger psi followed by the s-local
 // b5 phi + c5 S^dagger phi + psi - S^dagger psi. b5 = 1, c5 = 0 is the Shamir operator.
+// FP32 and FP16-storage fields whose Ls divides 64 take one column-walk kernel instead (the
+// s-local parts formed across the lanes of a fifth-dimension column, see k_dhop_walk), which
+// saves the intermediate field's write and read.
 #include "device.h"
 #include "launch.h"
 
@@ -103,6 +106,18 @@ hipError_t launch_mobius(const DhopArgs &a, double M5, double b5, double c5, voi
     // a fused epilogue (a.fuse: norm with dag = 0, r update with dag = 1) goes to the last kernel
     if (a.fuse != kFuseNone && (!nparts || a.fuse != (a.dag ? kFuseAxpy : kFuseNorm))) return hipErrorInvalidValue;
     DhopArgs h = a;
+    h.kind = GRID_MOBIUS;
+    h.custom = false;
+    h.b5 = b5;
+    h.c5 = c5;
+    h.diag = a.dag ? d4 : 1.0 + b5 * d4;
+    h.cs = 1.0 - c5 * d4;
+    if (walk_mobius_applies(h)) {
+        // one column-walk kernel: B folded into the records it gathers (M) or applied across the
+        // column's lanes after the hop (M^dagger); tmp is not used
+        if (h.fuse != kFuseNone) *nparts = dhop_blocks(h);
+        return launch_dhop(h);
+    }
     h.custom = true;
     h.cb = -1;
     h.beta = -0.5;

@@ -378,7 +378,7 @@ static TileDev tile_dev(const GeomDev &g) {
 static bool tile4_applies(const DhopArgs &a) {
     const bool prec_ok = a.prec == GRID_F16S || (a.prec == GRID_F32 && a.link_fmt == GRID_L12);
     return !a.custom && a.g.Ls == 1 && prec_ok && a.g.L[0] % kTX == 0 && a.g.L[1] % kTY == 0 &&
-           a.g.L[2] % kTZ == 0 && a.kind != GRID_DWF;
+           a.g.L[2] % kTZ == 0 && (a.kind == GRID_HOP || a.kind == GRID_WILSON);
 }
 
 bool tile_applies(const DhopArgs &a) { return tile4_applies(a); }
