@@ -414,13 +414,19 @@ def cg_iteration_legs():
                     assert st["iterations"] == n and st["reliable_updates"] == 0
                     return time.perf_counter() - t0
                 run(20)
-                t_it = (run(120) - run(20)) / 100
+                t20 = run(20)
+                t_it = (run(120) - t20) / 100
                 per["graph" if graph else "direct"] = t_it
+                per["t20_graph" if graph else "t20_direct"] = t20
             t_it = per["graph"]
             nbytes = (2 * alg_bytes_per_site(sloppy, fmt, Ls or 1) + CG_VEC_BYTES[sloppy]) * n5
             res[f"{sloppy}_{fmt}"] = {
                 "ms_per_iteration": round(t_it * 1e3, 4),
                 "ms_per_iteration_direct_launches": round(per["direct"] * 1e3, 4),
+                # recording and instantiating the two segment graphs of a solve (created per solve):
+                # the 20-iteration solve's extra time over direct launches, less the replays' gain
+                "graph_recording_ms_per_solve": round(
+                    (per["t20_graph"] - per["t20_direct"] - 20 * (per["graph"] - per["direct"])) * 1e3, 3),
                 "alg_bytes_per_iteration": int(nbytes),
                 "alg_gbs": round(nbytes / t_it / 1e9, 1), "roofline_frac": round(nbytes / t_it / 1e9 / HBM_PEAK_GBS, 4),
                 "op_gflops": round(2 * OP_FLOPS[kind] * n5 / t_it / 1e9, 1)}

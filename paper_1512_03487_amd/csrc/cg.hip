@@ -463,9 +463,28 @@ struct CgRun {
     long nparts;         // room for the fused epilogues' partials
 };
 
-// Recorded iteration segments of one solve, by starting parity; released with the solve.
-// The caller's stream is drained before the executables are destroyed (the normal exits have
-// already synchronised it; an error exit may leave replays in flight).
+// Capture stream of the calling host thread on the current device: created on first use and kept
+// for the life of the process, so a solve creates no stream, and a capture in one host thread
+// never meets another thread's.
+hipError_t capture_stream(hipStream_t *s) {
+    constexpr int kMaxDevices = 64;
+    thread_local hipStream_t streams[kMaxDevices] = {};
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    if (!streams[dev]) {
+        const hipError_t e2 = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+        if (e2 != hipSuccess) return e2;
+    }
+    *s = streams[dev];
+    return hipSuccess;
+}
+
+// Recorded iteration segments of one solve, by starting parity; released with the solve (the
+// recorded kernels name this solve's fields and workspace). The caller's stream is drained before
+// the executables are destroyed (the normal exits have already synchronised it; an error exit may
+// leave replays in flight).
 struct SegmentGraphs {
     hipStream_t user;
     hipStream_t cs = nullptr;
@@ -477,7 +496,6 @@ struct SegmentGraphs {
         if (ex[0] || ex[1]) (void)hipStreamSynchronize(user);
         for (hipGraphExec_t e : ex)
             if (e) (void)hipGraphExecDestroy(e);
-        if (cs) (void)hipStreamDestroy(cs);
     }
 };
 
@@ -676,7 +694,7 @@ static hipError_t cg_T(const CgRun &c, grid_cg_stats *stats, int *status) {
     // record the segment of `check` steps starting at parity P0
     SegmentGraphs seg(c.st);
     auto record = [&](int P0) -> hipError_t {
-        if (!seg.cs) HIPCHK(hipStreamCreateWithFlags(&seg.cs, hipStreamNonBlocking));
+        if (!seg.cs) HIPCHK(capture_stream(&seg.cs));
         HIPCHK(hipStreamBeginCapture(seg.cs, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
         for (int i = 0; i < check && e == hipSuccess; ++i) {

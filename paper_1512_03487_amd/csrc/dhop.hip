@@ -505,7 +505,7 @@ k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const floa
         rec[0] = tn * nq + qq;
 #pragma unroll
         for (int d = 0; d < 6; ++d) rec[1 + d] = off + nb[d] * Ls + s;
-        if (KIND != GRID_HOP) rec[7] = off + qq;
+        if constexpr (NREC == 8) rec[7] = off + qq;
         Fetch<SP> f;
         fetch<SP>(psi, psi_scale, rec[0], f);
         Cx<C> acc[4][3];
@@ -634,12 +634,21 @@ k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const floa
 // (full 4D index) / 2. A thread owns (xh, y, z, s) and walks T slices; its physical x shifts with
 // t (x = 2 xh + ((cb + y + z + t) & 1)), so the backward t-hop cannot be carried from the previous
 // step and both t-neighbours are gathered: 8 neighbour records (+ y) and 8 links per step.
+//
+// Moebius Schur operator (kinds kMobHop, kMobDiag; Ls dividing 64, so a wavefront holds whole
+// fifth-dimension columns): without dag the gathered records become B psi = b5 psi + c5 S psi
+// (stage_b5) and out = beta H B psi (kMobHop) or diag y - cs S y + beta H B psi (kMobDiag); with
+// dag, h = beta H^dagger psi and out = B^dagger h = b5 h + S^dagger (c5 h) (kMobHop) or
+// diag y + b5 h + S^dagger (c5 h - cs y) (kMobDiag), S^dagger taken across the column's lanes.
 template <class SP, class LK, bool DAG, int KIND, int FUSE>
 __global__ void __launch_bounds__(256)
 k_dhop_walk_cb(const void *__restrict__ U, const void *__restrict__ psi, const float *__restrict__ psi_scale,
                const void *__restrict__ yv, const float *__restrict__ y_scale, void *out, float *out_scale, GeomDev g,
-               int T, int cbp, double diag, double mf, double beta, double cs, FuseDev fz) {
+               int T, int cbp, double diag, double mf, double beta, double cs, double b5, double c5, FuseDev fz) {
     using C = typename SP::C;
+    constexpr bool MOB = KIND == kMobHop || KIND == kMobDiag;
+    constexpr bool MOBF = MOB && !DAG;
+    constexpr bool MOBA = MOB && DAG;
     __shared__ chunk_t sm[kWaves][64 * stage_pitch<SP>()];
     chunk_t *lds = sm[threadIdx.x >> 6];
 
@@ -662,8 +671,20 @@ k_dhop_walk_cb(const void *__restrict__ U, const void *__restrict__ psi, const f
     const int V3 = Lx * Ly * Lz;
     const int t0 = seg * T;
     constexpr int EF = DAG ? +1 : -1;
-    constexpr int NREC = (KIND == GRID_HOP) ? 8 : 9;
+    constexpr int NREC = (KIND == GRID_HOP || KIND == kMobHop) ? 8 : 9;
     [[maybe_unused]] double n2 = 0.0;   // fused epilogue: this thread's |out|^2
+    // Moebius: the column's lanes of s + 1 and s - 1 and the wall factors
+    int lp = 0, lm = 0;
+    C mb5 = C(0), mc5 = C(0), wp = C(1), wm = C(1);
+    if constexpr (MOB) {
+        const int lane = threadIdx.x & 63, sl = lane % Ls, lbase = lane - sl;
+        lp = lbase + (sl == Ls - 1 ? 0 : sl + 1);
+        lm = lbase + (sl == 0 ? Ls - 1 : sl - 1);
+        mb5 = static_cast<C>(b5);
+        mc5 = static_cast<C>(c5);
+        wp = sl == Ls - 1 ? static_cast<C>(-mf) : C(1);
+        wm = sl == 0 ? static_cast<C>(-mf) : C(1);
+    }
 
     Cx<C> p[4][3], u[3][3];
 #pragma unroll 1
@@ -684,7 +705,7 @@ k_dhop_walk_cb(const void *__restrict__ U, const void *__restrict__ psi, const f
         rec[5] = (offh + (z * Ly + ym) * Lxh + xh) * Ls + s;
         rec[6] = (offh + (zp * Ly + y) * Lxh + xh) * Ls + s;
         rec[7] = (offh + (zm * Ly + y) * Lxh + xh) * Ls + s;
-        if (KIND != GRID_HOP) rec[8] = oq;
+        if constexpr (NREC == 9) rec[8] = oq;
         // links, full-lattice index: U_mu(x) forward, U_mu(x - mu) backward
         const size_t f4 = (static_cast<size_t>(t) * Lz + z) * Ly * Lx + static_cast<size_t>(y) * Lx + x;
         const size_t row4 = f4 - x;
@@ -704,7 +725,10 @@ k_dhop_walk_cb(const void *__restrict__ U, const void *__restrict__ psi, const f
         for (int j = 0; j < 12; ++j) acc[j / 3][j % 3] = {C(0), C(0)};
 #pragma unroll
         for (int i = 0; i < NREC; ++i) {
-            stage<SP>(f, lds, p);
+            if (MOBF && i < 8)
+                stage_b5<SP>(f, lds, p, lp, lm, mb5, mc5 * wp, mc5 * wm);
+            else
+                stage<SP>(f, lds, p);
             // link of this direction first, then the next record: loads complete in issue order
             if (i < 8) LK::load(U, lk[i], u);
             if (i + 1 < 8)
@@ -719,7 +743,7 @@ k_dhop_walk_cb(const void *__restrict__ U, const void *__restrict__ psi, const f
             else if (i == 5) hop_term<1, -EF, true>(acc, p, u);
             else if (i == 6) hop_term<2, EF, false>(acc, p, u);
             else if (i == 7) hop_term<2, -EF, true>(acc, p, u);
-            else {
+            else if (!MOB) {
                 // the diagonal part of `kind` on y, H scaled by beta
                 const C dg = static_cast<C>(diag), bt = static_cast<C>(beta);
 #pragma unroll
@@ -729,12 +753,47 @@ k_dhop_walk_cb(const void *__restrict__ U, const void *__restrict__ psi, const f
                 }
             }
         }
-        if (KIND == GRID_HOP) {
+        if (KIND == GRID_HOP || KIND == kMobHop || MOBA) {
             const C bt = static_cast<C>(beta);
 #pragma unroll
             for (int j = 0; j < 12; ++j) acc[j / 3][j % 3] = {bt * acc[j / 3][j % 3].r, bt * acc[j / 3][j % 3].i};
         }
-        if (KIND == GRID_DWF) {
+        if (MOBF && KIND == kMobDiag) {
+            // diag y + beta H B psi (y = p, the last record staged)
+            const C dg = static_cast<C>(diag), bt = static_cast<C>(beta);
+#pragma unroll
+            for (int j = 0; j < 12; ++j) {
+                const Cx<C> a = acc[j / 3][j % 3], v = p[j / 3][j % 3];
+                acc[j / 3][j % 3] = {dg * v.r + bt * a.r, dg * v.i + bt * a.i};
+            }
+        }
+        if constexpr (MOBA) {
+            // out = diag y + b5 h + S^dagger v, v = c5 h - cs y (y = 0 for kMobHop), h = acc;
+            // (S^dagger v)_s = P_+ v~_{s+1} + P_- v~_{s-1}
+            const C dg = static_cast<C>(diag), csc = static_cast<C>(cs);
+            Cx<C> v[4][3], hh[2][3];
+#pragma unroll
+            for (int j = 0; j < 12; ++j) {
+                const Cx<C> h = acc[j / 3][j % 3];
+                Cx<C> yy = {C(0), C(0)};
+                if (KIND == kMobDiag) yy = p[j / 3][j % 3];
+                v[j / 3][j % 3] = {mc5 * h.r - csc * yy.r, mc5 * h.i - csc * yy.i};
+                acc[j / 3][j % 3] = {mb5 * h.r + dg * yy.r, mb5 * h.i + dg * yy.i};
+            }
+            column_half<SP>(lds, v, 0, lp, hh);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                Cx<C> &o = acc[j / 3][j % 3];
+                o = {o.r + wp * hh[j / 3][j % 3].r, o.i + wp * hh[j / 3][j % 3].i};
+            }
+            column_half<SP>(lds, v, 1, lm, hh);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                Cx<C> &o = acc[2 + j / 3][j % 3];
+                o = {o.r + wm * hh[j / 3][j % 3].r, o.i + wm * hh[j / 3][j % 3].i};
+            }
+        }
+        if (KIND == GRID_DWF || (MOBF && KIND == kMobDiag)) {
             // - cs (P_- y~_{s+1} + P_+ y~_{s-1}) (M; P_+ and P_- exchanged for M^dagger), walls -mf
             const int sp = (s == Ls - 1) ? 0 : s + 1;
             const int sm1 = (s == 0) ? Ls - 1 : s - 1;
@@ -870,13 +929,17 @@ static hipError_t launch_walk_cb(const DhopArgs &a) {
     hipStream_t st = a.stream;
 #define GRIDMI_LAUNCH(DAG, KIND, FUSE)                                                                    \
     hipLaunchKernelGGL((k_dhop_walk_cb<SP, LK, DAG, KIND, FUSE>), grid, block, 0, st, a.U, a.psi, a.psi_scale, \
-                       a.y, a.y_scale, a.out, a.out_scale, a.g, T, a.cb, a.diag, a.mf, a.beta, a.cs, a.fz)
+                       a.y, a.y_scale, a.out, a.out_scale, a.g, T, a.cb, a.diag, a.mf, a.beta, a.cs, a.b5, a.c5, a.fz)
+    const bool mob = a.kind == kMobHop || a.kind == kMobDiag;
+    if (mob && !(a.g.Ls >= 2 && 64 % a.g.Ls == 0)) return hipErrorInvalidValue;
     if (a.fuse != kFuseNone) {
         switch (a.kind * 4 + a.fuse * 2 + (a.dag ? 1 : 0)) {
             case GRID_WILSON * 4 + kFuseNorm * 2 + 0: GRIDMI_LAUNCH(false, GRID_WILSON, kFuseNorm); break;
             case GRID_DWF * 4 + kFuseNorm * 2 + 0: GRIDMI_LAUNCH(false, GRID_DWF, kFuseNorm); break;
+            case kMobDiag * 4 + kFuseNorm * 2 + 0: GRIDMI_LAUNCH(false, kMobDiag, kFuseNorm); break;
             case GRID_WILSON * 4 + kFuseAxpy * 2 + 1: GRIDMI_LAUNCH(true, GRID_WILSON, kFuseAxpy); break;
             case GRID_DWF * 4 + kFuseAxpy * 2 + 1: GRIDMI_LAUNCH(true, GRID_DWF, kFuseAxpy); break;
+            case kMobDiag * 4 + kFuseAxpy * 2 + 1: GRIDMI_LAUNCH(true, kMobDiag, kFuseAxpy); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -888,6 +951,10 @@ static hipError_t launch_walk_cb(const DhopArgs &a) {
         case GRID_WILSON * 2 + 1: GRIDMI_LAUNCH(true, GRID_WILSON, kFuseNone); break;
         case GRID_DWF * 2 + 0: GRIDMI_LAUNCH(false, GRID_DWF, kFuseNone); break;
         case GRID_DWF * 2 + 1: GRIDMI_LAUNCH(true, GRID_DWF, kFuseNone); break;
+        case kMobHop * 2 + 0: GRIDMI_LAUNCH(false, kMobHop, kFuseNone); break;
+        case kMobHop * 2 + 1: GRIDMI_LAUNCH(true, kMobHop, kFuseNone); break;
+        case kMobDiag * 2 + 0: GRIDMI_LAUNCH(false, kMobDiag, kFuseNone); break;
+        case kMobDiag * 2 + 1: GRIDMI_LAUNCH(true, kMobDiag, kFuseNone); break;
         default: return hipErrorInvalidValue;
     }
 #undef GRIDMI_LAUNCH
@@ -907,6 +974,7 @@ static bool use_walk_cb(const DhopArgs &a) { return a.custom && a.cb >= 0 && wal
 template <class SP, class LK>
 static hipError_t launch_sched(const DhopArgs &a) {
     if (a.kind == GRID_MOBIUS && !walk_mobius_applies(a)) return hipErrorInvalidValue;
+    if ((a.kind == kMobHop || a.kind == kMobDiag) && !use_walk_cb(a)) return hipErrorInvalidValue;
     if (tile_applies(a)) return launch_tile(a);
     if (use_walk(a)) return launch_walk<SP, LK>(a);
     if (use_walk_cb(a)) return launch_walk_cb<SP, LK>(a);

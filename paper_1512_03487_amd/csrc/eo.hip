@@ -215,7 +215,7 @@ static hipError_t cb_copy(const void *src, void *dst, const GeomDev &g, int pari
 static hipError_t hop_cb(const void *U, int prec, int fmt, const GeomDev &g, int kind, int dag, double dg, double mf,
                          int cb, const void *psi, const float *psis, const void *y, const float *ys, double beta, void *out,
                          float *outs, hipStream_t st, int fuse = kFuseNone, const FuseDev *fz = nullptr,
-                         long *nparts = nullptr, double cs = 1.0) {
+                         long *nparts = nullptr, double cs = 1.0, double b5 = 1.0, double c5 = 0.0) {
     DhopArgs a;
     a.U = U;
     a.psi = psi;
@@ -236,6 +236,8 @@ static hipError_t hop_cb(const void *U, int prec, int fmt, const GeomDev &g, int
     a.y_scale = ys;
     a.beta = beta;
     a.cs = cs;
+    a.b5 = b5;
+    a.c5 = c5;
     if (fuse != kFuseNone) {
         a.fuse = fuse;
         a.fz = *fz;
@@ -269,7 +271,9 @@ static hipError_t mob_ee_inv(const EoOp &o, int prec, const void *in, const floa
     return launch_m5inv(in, ins, out, outs, n4, o.g.Ls, o.alpha / o.beta, o.mf, dag, prec, st);
 }
 
-// Moebius Schur operator (see the header): five kernels, the last carrying the fused epilogue.
+// Moebius Schur operator (see the header): three kernels on the checkerboard column walk when it
+// takes the Moebius kinds, else five (with separate s-local passes); the last carries the fused
+// epilogue.
 static hipError_t eo_apply_mobius(const EoOp &o, const void *U, int prec, int fmt, const void *in, const float *ins,
                                   void *out, float *outs, int dag, int fuse, const FuseDev *fz, long *nparts,
                                   hipStream_t st) {
@@ -279,6 +283,15 @@ static hipError_t eo_apply_mobius(const EoOp &o, const void *U, int prec, int fm
     const long n5 = static_cast<long>(o.g.vol / 2) * o.g.Ls;
     const int Ls = o.g.Ls;
     double f = 1.0;
+    if (mob_cb_applies(prec, Ls)) {
+        // three kernels: B folded into the checkerboard walks (gathered records, or across the
+        // column after the hop for the adjoint)
+        EOCHK(hop_cb(U, prec, fmt, o.g, kMobHop, dag, 0.0, o.mf, 1, in, ins, nullptr, nullptr, 1.0, t1, t1s, st,
+                     kFuseNone, nullptr, nullptr, 1.0, o.b5, o.c5));
+        EOCHK(mob_ee_inv(o, prec, t1, t1s, t2, t2s, dag, st, &f));
+        return hop_cb(U, prec, fmt, o.g, kMobDiag, dag, o.alpha, o.mf, 0, t2, t2s, in, ins, -0.25 * f, out, outs, st,
+                      fuse, fz, nparts, o.beta, o.b5, o.c5);
+    }
     if (!dag) {
         EOCHK(launch_s5axpy(prec, in, ins, nullptr, nullptr, t1, t1s, n5, Ls, o.b5, o.c5, 0.0, 0.0, o.mf, 0, st));
         EOCHK(hop_cb(U, prec, fmt, o.g, GRID_HOP, 0, 0.0, o.mf, 1, t1, t1s, nullptr, nullptr, 1.0, t2, t2s, st));

@@ -24,6 +24,15 @@ struct FuseDev {
     double *part = nullptr;
 };
 
+// Internal operator kinds of the checkerboard column walk (the even-odd Moebius Schur operator,
+// B = b5 + c5 S; see k_dhop_walk_cb): kMobHop out = beta H B psi (dag: B^dagger beta H^dagger psi),
+// kMobDiag adds diag y - cs S y (dag: diag y - cs S^dagger y). Full-lattice FP32 / FP16-storage
+// checkerboard fields whose Ls divides 64 (mob_cb_applies).
+enum { kMobHop = 8, kMobDiag = 9 };
+inline bool mob_cb_applies(int prec, int Ls) {
+    return (prec == GRID_F32 || prec == GRID_F16S) && Ls >= 2 && 64 % Ls == 0;
+}
+
 struct DhopArgs {
     const void *U;
     const void *psi;
@@ -58,6 +67,9 @@ struct DhopArgs {
 };
 
 hipError_t launch_dhop(const DhopArgs &a);
+// The calling host thread's stream for recording HIP graphs on the current device (kept for the
+// life of the process; cg.hip).
+hipError_t capture_stream(hipStream_t *s);
 bool walk_mobius_applies(const DhopArgs &a);
 // Tiled time-walk schedule (tile.hip): full-lattice 4D FP32 / FP16-storage fields whose x, y, z
 // extents the tile divides.

@@ -987,7 +987,7 @@ static hipError_t mg_cycle(const MgCtx &c, const void *U, const double2 *V, cons
     } else {
         if (!c.coarse_exec) {
             MgCtx &mc = const_cast<MgCtx &>(c);
-            if (!mc.rec) MGCHK(hipStreamCreateWithFlags(&mc.rec, hipStreamNonBlocking));
+            if (!mc.rec) MGCHK(capture_stream(&mc.rec));
             MGCHK(hipStreamBeginCapture(mc.rec, hipStreamCaptureModeThreadLocal));
             hipError_t e = coarse_solve(mc.rec);
             hipGraph_t gr = nullptr;
@@ -1048,7 +1048,6 @@ hipError_t run_mg_solve(const void *U, const void *vecs, const void *A, const vo
                 (void)hipStreamSynchronize(c.st);
                 (void)hipGraphExecDestroy(c.coarse_exec);
             }
-            if (c.rec) (void)hipStreamDestroy(c.rec);
         }
     } release{c};
     mg_dims(g, p, &c.m);

@@ -185,11 +185,12 @@ MOB_CASES = {"mobius": dict(M5=1.8, mf=0.1, b5=1.5, c5=0.5),      # alpha = 4.3,
 
 
 @pytest.mark.parametrize("case", sorted(MOB_CASES))
-@pytest.mark.parametrize("dims,Ls", [((4, 4, 4, 4), 8), ((2, 2, 4, 6), 4)])
+@pytest.mark.parametrize("dims,Ls", [((4, 4, 4, 4), 8), ((2, 2, 4, 6), 4), ((2, 4, 2, 4), 6)])
 @pytest.mark.parametrize("sloppy,fmt", [("f64", "L18"), ("f32", "L18"), ("f16s", "L12")])
 def test_solve_eo_mobius(gpu, case, dims, Ls, sloppy, fmt):
     """Even-odd CG for the Moebius operator, checked with the oracle's Moebius blocks: the CG
-    criterion on the Schur system, the odd-site reconstruction and the full residual."""
+    criterion on the Schur system, the odd-site reconstruction and the full residual. Ls = 4, 8
+    take the three-kernel Schur operator in FP32 / FP16 storage, Ls = 6 the five-kernel one."""
     from oracle import mobius as OM
     from tests.gpu_util import dev, host, rel
     gm = _gm()
