@@ -38,6 +38,7 @@ TRAFFIC_FILES = {
     "hop_32^4_f32": os.path.join(ROOT, "profiles", "traffic_dhop_f32_32x32x32x32.txt"),
     "dwf_24^4x12_f32": os.path.join(ROOT, "profiles", "traffic_dwf_f32_24x24x24x24_ls12.txt"),
     "dwf_24^4x12_f16s_L12": os.path.join(ROOT, "profiles", "traffic_dwf_f16s_24x24x24x24_ls12.txt"),
+    "dwf_24^4x12_f32_L12": os.path.join(ROOT, "profiles", "traffic_dwf_f32_L12_24x24x24x24_ls12.txt"),
 }
 ORACLE_CG_FILE = os.path.join(ROOT, "profiles", "oracle_cg_dwf_16x16x16x16_ls16.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1512_03487_amd", "csrc", f) for f in ("dhop.hip", "device.h")]
@@ -823,9 +824,11 @@ def dwf_config5(calibrate_copy=False):
     import torch
     out = {"workload": "domain-wall operator M, 24^4 x Ls = 12, M5 = 1.8, mf = 0.01, Haar links, Gaussian spinor"}
     for name, prec, fmt, kern in (("f32", "f32", "L18", "k_dhop_walk<SpF32, LkF32<3>, false, GRID_DWF, 0>"),
-                                  ("f16s_L12", "f16s", "L12", "k_dhop_walk<SpF16S, LkF16<2>, false, GRID_DWF, 0>")):
+                                  ("f16s_L12", "f16s", "L12", "k_dhop_walk<SpF16S, LkF16<2>, false, GRID_DWF, 0>"),
+                                  ("f32_L12", "f32", "L12", "k_dhop_walk<SpF32, LkF32<2>, false, GRID_DWF, 0>")):
         r = leg((24, 24, 24, 24), prec, fmt, "dwf", 12, 20, 3)
-        traffic = measured_traffic(f"dwf_24^4x12_{name}")
+        key = f"dwf_24^4x12_{name}"
+        traffic = measured_traffic(key) if key in TRAFFIC_FILES else None
         r["roofline"] = {"bound": "hbm", "achieved": r["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": r["roofline_frac"], "traffic": traffic,
                          "alg_bytes_per_launch": int(alg_bytes_per_site(prec, fmt, 12) * 24 ** 4 * 12),
