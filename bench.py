@@ -823,9 +823,9 @@ def dwf_config5(calibrate_copy=False):
     bytes: psi and out once per 5D site, the links once per 4D site)."""
     import torch
     out = {"workload": "domain-wall operator M, 24^4 x Ls = 12, M5 = 1.8, mf = 0.01, Haar links, Gaussian spinor"}
-    for name, prec, fmt, kern in (("f32", "f32", "L18", "k_dhop_walk<SpF32, LkF32<3>, false, GRID_DWF, 0>"),
-                                  ("f16s_L12", "f16s", "L12", "k_dhop_walk<SpF16S, LkF16<2>, false, GRID_DWF, 0>"),
-                                  ("f32_L12", "f32", "L12", "k_dhop_walk<SpF32, LkF32<2>, false, GRID_DWF, 0>")):
+    for name, prec, fmt, kern in (("f32", "f32", "L18", "k_dhop_walk2<SpF32, LkF32<3>, false, GRID_DWF, 0>"),
+                                  ("f16s_L12", "f16s", "L12", "k_dhop_walk2<SpF16S, LkF16<2>, false, GRID_DWF, 0>"),
+                                  ("f32_L12", "f32", "L12", "k_dhop_walk2<SpF32, LkF32<2>, false, GRID_DWF, 0>")):
         r = leg((24, 24, 24, 24), prec, fmt, "dwf", 12, 20, 3)
         key = f"dwf_24^4x12_{name}"
         traffic = measured_traffic(key) if key in TRAFFIC_FILES else None

@@ -629,6 +629,162 @@ k_dhop_walk(const void *__restrict__ U, const void *__restrict__ psi, const floa
     }
 }
 
+// Same-step column walk (5D full-lattice fields, y = psi): step k finishes out(t) with its forward
+// t-hop and builds most of out(t+1) from the records of slice t+1 that the same step brings in
+// (the thread's own record, then the six spatial neighbours), so every use of a record of slice
+// t+1 -- forward neighbour and centre in its own column, spatial neighbour in the adjacent columns,
+// some of which belong to other blocks of the XCD -- falls within one step of the walk. In the
+// column walk above the neighbouring columns read a record one step after its own column loaded
+// it, and with a 5D time slice several times the size of an XCD's L2 the other resident blocks'
+// traffic has often evicted it by then. The partial sum of out(t+1) is carried in registers in
+// units of beta (its diagonal and fifth-dimension parts divided by beta) and one scale finishes it.
+template <class SP, class LK, bool DAG, int KIND, int FUSE>
+__global__ void __launch_bounds__(256)
+k_dhop_walk2(const void *__restrict__ U, const void *__restrict__ psi, const float *__restrict__ psi_scale,
+             void *out, float *out_scale, GeomDev g, int T, double diag, double mf, FuseDev fz) {
+    using C = typename SP::C;
+    static_assert(KIND == GRID_HOP || KIND == GRID_WILSON || KIND == GRID_DWF, "plain operators only");
+    __shared__ chunk_t sm[kWaves][64 * stage_pitch<SP>()];
+    chunk_t *lds = sm[threadIdx.x >> 6];
+
+    const int Ls = g.Ls;
+    const int V3 = g.L[0] * g.L[1] * g.L[2];
+    const int nq = V3 * Ls;                 // 5D sites per time slice
+    const int nbc = (nq + 255) / 256;       // column blocks per slice
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int seg = lb / nbc, cb = lb - seg * nbc;
+    const int q = cb * 256 + threadIdx.x;
+    const bool live = q < nq;
+    const int qq = live ? q : 0;            // idle lanes still take part in the wave's gathers
+    const int col = qq / Ls, s = qq - (qq / Ls) * Ls;
+    int nb[6];
+    neighbours3(g, col, nb);
+    const int Lt = g.L[3];
+    const int t0 = seg * T;
+    // H: (1 - gamma) forward, (1 + gamma) backward; H^dagger the opposite.
+    constexpr int EF = DAG ? +1 : -1;
+    // out = beta (H psi + (diag psi - S psi) / beta), beta = 1 for H and -1/2 for D and M
+    const C bt = KIND == GRID_HOP ? C(1) : C(-0.5);
+    const C dgb = static_cast<C>(diag) / bt;
+    // fifth-dimension hop of M (M^dagger: P_+ and P_- exchanged), walls -mf, divided by beta
+    const C fpb = ((s == Ls - 1) ? static_cast<C>(-mf) : C(1)) / bt;
+    const C fmb = ((s == 0) ? static_cast<C>(-mf) : C(1)) / bt;
+    const int sp = (s == Ls - 1) ? 0 : s + 1, sm1 = (s == 0) ? Ls - 1 : s - 1;
+
+    Cx<C> A[4][3], hb[2][3], p[4][3], u[3][3];
+    // the diagonal and fifth-dimension parts of out(tt) from the centre record p = psi(x, tt)
+    auto diag_part = [&](int tt) {
+        if constexpr (KIND != GRID_HOP) {
+#pragma unroll
+            for (int j = 0; j < 12; ++j) {
+                Cx<C> &o = A[j / 3][j % 3];
+                o = {o.r + dgb * p[j / 3][j % 3].r, o.i + dgb * p[j / 3][j % 3].i};
+            }
+        }
+        if constexpr (KIND == GRID_DWF) {
+            const int hup = DAG ? 0 : 1;   // chiral half taken from s + 1 (0: spins 0,1; 1: spins 2,3)
+            const size_t site4 = static_cast<size_t>(tt) * nq + static_cast<size_t>(col) * Ls;
+            Cx<C> qh[2][3];
+            SP::load_half(psi, psi_scale, site4 + sp, hup, qh);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                Cx<C> &o = A[2 * hup + j / 3][j % 3];
+                o = {o.r - fpb * qh[j / 3][j % 3].r, o.i - fpb * qh[j / 3][j % 3].i};
+            }
+            SP::load_half(psi, psi_scale, site4 + sm1, 1 - hup, qh);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                Cx<C> &o = A[2 * (1 - hup) + j / 3][j % 3];
+                o = {o.r - fmb * qh[j / 3][j % 3].r, o.i - fmb * qh[j / 3][j % 3].i};
+            }
+        }
+    };
+    // the six spatial hops of slice tt into A (records fetched one ahead of the one in use)
+    auto spatial = [&](int tt) {
+        const int off = tt * nq;
+        const size_t loff = static_cast<size_t>(tt) * V3;
+        Fetch<SP> f;
+        fetch<SP>(psi, psi_scale, off + nb[0] * Ls + s, f);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            stage<SP>(f, lds, p);
+            const int mu = d / 2;
+            const bool bwd = d & 1;
+            LK::load(U, (loff + (bwd ? nb[d] : col)) * 4 + mu, u);
+            if (d + 1 < 6) fetch<SP>(psi, psi_scale, off + nb[d + 1] * Ls + s, f);
+            if (d == 0) hop_term<0, EF, false>(A, p, u);
+            else if (d == 1) hop_term<0, -EF, true>(A, p, u);
+            else if (d == 2) hop_term<1, EF, false>(A, p, u);
+            else if (d == 3) hop_term<1, -EF, true>(A, p, u);
+            else if (d == 4) hop_term<2, EF, false>(A, p, u);
+            else hop_term<2, -EF, true>(A, p, u);
+        }
+    };
+
+    {
+        // out(t0) without its forward t-hop: backward t-hop from psi(x, t0 - 1), centre, spatial
+        const int tm = (t0 == 0) ? Lt - 1 : t0 - 1;
+        gather<SP>(psi, psi_scale, tm * nq + qq, lds, p);
+        project<3, -EF>(p, hb);
+        LK::load(U, (static_cast<size_t>(tm) * V3 + col) * 4 + 3, u);
+        Cx<C> chi[2][3];
+        su3_adj_mul(u, hb, chi);
+#pragma unroll
+        for (int j = 0; j < 12; ++j) A[j / 3][j % 3] = {C(0), C(0)};
+        reconstruct_add<3, -EF>(A, chi);
+        gather<SP>(psi, psi_scale, t0 * nq + qq, lds, p);
+        project<3, -EF>(p, hb);
+        diag_part(t0);
+        spatial(t0);
+    }
+    [[maybe_unused]] double n2 = 0.0;   // fused epilogue: this thread's |out|^2
+#pragma unroll 1
+    for (int k = 0; k < T; ++k) {
+        const int t = t0 + k;
+        const int tn = (t == Lt - 1) ? 0 : t + 1;
+        // psi(x, t + 1): the forward t-hop that finishes out(t)
+        gather<SP>(psi, psi_scale, tn * nq + qq, lds, p);
+        LK::load(U, (static_cast<size_t>(t) * V3 + col) * 4 + 3, u);
+        hop_term<3, EF, false>(A, p, u);
+#pragma unroll
+        for (int j = 0; j < 12; ++j) A[j / 3][j % 3] = {bt * A[j / 3][j % 3].r, bt * A[j / 3][j % 3].i};
+        const int off = t * nq;
+        if constexpr (FUSE == kFuseAxpy) {
+            // r - alpha op psi; r may alias out: the wavefront gathers its own records before storing
+            Cx<C> rv[4][3];
+            gather<SP>(fz.r, fz.r_scale, off + qq, lds, rv);
+            const C al = static_cast<C>(fz.scal[fz.num] / fz.scal[fz.den]);
+#pragma unroll
+            for (int j = 0; j < 12; ++j) {
+                const Cx<C> a = A[j / 3][j % 3], b = rv[j / 3][j % 3];
+                A[j / 3][j % 3] = {b.r - al * a.r, b.i - al * a.i};
+            }
+        }
+        if constexpr (FUSE == kFuseNone) {
+            if (live) SP::store(out, out_scale, static_cast<size_t>(off) + q, A);
+        } else {
+            if (live) n2 += SP::store_n2(out, out_scale, static_cast<size_t>(off) + q, A);
+        }
+        if (k + 1 == T) break;
+        // out(t + 1): backward t-hop U_t(x, t)^dagger h(psi(x, t)), centre, spatial hops
+        Cx<C> chi[2][3];
+        su3_adj_mul(u, hb, chi);
+#pragma unroll
+        for (int j = 0; j < 12; ++j) A[j / 3][j % 3] = {C(0), C(0)};
+        reconstruct_add<3, -EF>(A, chi);
+        project<3, -EF>(p, hb);
+        diag_part(tn);
+        spatial(tn);
+    }
+    if constexpr (FUSE != kFuseNone) {
+        n2 = wave_sum64(n2);
+        __shared__ double fred[4];
+        if ((threadIdx.x & 63) == 0) fred[threadIdx.x >> 6] = n2;
+        __syncthreads();
+        if (threadIdx.x == 0) fz.part[blockIdx.x] = (fred[0] + fred[1]) + (fred[2] + fred[3]);
+    }
+}
+
 // Column walk on checkerboard fields (the even-odd form): out (parity cb) = Diag(y) + beta H psi,
 // psi of parity 1 - cb, y and out of parity cb. A checkerboard field holds one site per x-pair, at
 // (full 4D index) / 2. A thread owns (xh, y, z, s) and walks T slices; its physical x shifts with
@@ -869,8 +1025,46 @@ bool walk_mobius_applies(const DhopArgs &a) {
            (a.prec == GRID_F32 || a.prec == GRID_F16S);
 }
 
+// The same-step walk takes the plain operators on 5D fields (y = psi).
+static bool use_walk2(const DhopArgs &a) {
+    return !a.custom && a.g.Ls > 1 && (a.kind == GRID_HOP || a.kind == GRID_WILSON || a.kind == GRID_DWF);
+}
+
+template <class SP, class LK>
+static hipError_t launch_walk2(const DhopArgs &a) {
+    const int T = choose_steps(a.g);
+    const long nbc = (static_cast<long>(a.g.L[0]) * a.g.L[1] * a.g.L[2] * a.g.Ls + 255) / 256;
+    const dim3 grid(static_cast<unsigned>(nbc * (a.g.L[3] / T))), block(256);
+    hipStream_t st = a.stream;
+#define GRIDMI_LAUNCH(DAG, KIND, FUSE)                                                                       \
+    hipLaunchKernelGGL((k_dhop_walk2<SP, LK, DAG, KIND, FUSE>), grid, block, 0, st, a.U, a.psi, a.psi_scale, a.out, \
+                       a.out_scale, a.g, T, a.diag, a.mf, a.fz)
+    if (a.fuse != kFuseNone) {
+        switch (a.kind * 4 + a.fuse * 2 + (a.dag ? 1 : 0)) {
+            case GRID_WILSON * 4 + kFuseNorm * 2 + 0: GRIDMI_LAUNCH(false, GRID_WILSON, kFuseNorm); break;
+            case GRID_DWF * 4 + kFuseNorm * 2 + 0: GRIDMI_LAUNCH(false, GRID_DWF, kFuseNorm); break;
+            case GRID_WILSON * 4 + kFuseAxpy * 2 + 1: GRIDMI_LAUNCH(true, GRID_WILSON, kFuseAxpy); break;
+            case GRID_DWF * 4 + kFuseAxpy * 2 + 1: GRIDMI_LAUNCH(true, GRID_DWF, kFuseAxpy); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    switch (a.kind * 2 + (a.dag ? 1 : 0)) {
+        case GRID_HOP * 2 + 0: GRIDMI_LAUNCH(false, GRID_HOP, kFuseNone); break;
+        case GRID_HOP * 2 + 1: GRIDMI_LAUNCH(true, GRID_HOP, kFuseNone); break;
+        case GRID_WILSON * 2 + 0: GRIDMI_LAUNCH(false, GRID_WILSON, kFuseNone); break;
+        case GRID_WILSON * 2 + 1: GRIDMI_LAUNCH(true, GRID_WILSON, kFuseNone); break;
+        case GRID_DWF * 2 + 0: GRIDMI_LAUNCH(false, GRID_DWF, kFuseNone); break;
+        case GRID_DWF * 2 + 1: GRIDMI_LAUNCH(true, GRID_DWF, kFuseNone); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef GRIDMI_LAUNCH
+    return hipGetLastError();
+}
+
 template <class SP, class LK>
 static hipError_t launch_walk(const DhopArgs &a) {
+    if (use_walk2(a)) return launch_walk2<SP, LK>(a);
     const int T = choose_steps(a.g);
     const long nbc = (static_cast<long>(a.g.L[0]) * a.g.L[1] * a.g.L[2] * a.g.Ls + 255) / 256;
     const dim3 grid(static_cast<unsigned>(nbc * (a.g.L[3] / T))), block(256);
