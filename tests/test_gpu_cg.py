@@ -141,6 +141,23 @@ def test_config2_dwf_16_4_ls16(gpu, sloppy):
     assert st["converged"] and res <= RES_SLACK * TOL
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("sloppy,fmt", [("f32", "L18"), ("f16s", "L12")])
+def test_dwf_cg_24_4_ls12(gpu, sloppy, fmt):
+    """24^4 x 12 (the throughput size: sloppy iterations on three-slice walks with the fused
+    epilogues), M5 = 1.8, mf = 0.01, Haar links, to a true residual of 1e-8 recomputed by the
+    oracle."""
+    import paper_1512_03487_amd as gm
+    from tests.gpu_util import cached, dev
+    dims, Ls, tol = (24, 24, 24, 24), 12, 1e-8
+    U, b = cached("gauge", dims, 1, kind="haar"), cached("spinor", dims, 3, Ls=Ls)
+    x, st = gm.cg(dev(U), dev(b), kind="dwf", M5=1.8, mf=0.01, tol=tol, sloppy=sloppy, link_fmt=fmt)
+    res = O.true_residual(O.Op.dwf(Ls, 1.8, 0.01), U, b, x.cpu().numpy())
+    print(f"dwf 24^4x12 {sloppy}: {st['iterations']} it, {st['reliable_updates']} RU, oracle residual {res:.3e}",
+          flush=True)
+    assert st["converged"] and res <= RES_SLACK * tol
+
+
 @pytest.mark.parametrize("solver,kind,sloppy,check", [
     ("cg", "dwf", "f64", 10), ("cg", "dwf", "f32", 3), ("cg", "dwf", "f16s", 4), ("cg", "wilson", "f32", 7),
     ("cg", "mobius", "f32", 5), ("eo", "dwf", "f32", 3), ("eo", "wilson", "f16s", 6)])
