@@ -795,6 +795,69 @@ __device__ __forceinline__ void column_half(chunk_t *lds, const Cx<typename SP::
     for (int j = 0; j < 6; ++j) h[j / 3][j % 3] = {buf[2 * j], buf[2 * j + 1]};
 }
 
+// v = (d - S)^-1 v across a fifth-dimension column (S^dagger when dag), lanes lbase .. lbase +
+// Ls - 1 holding s = 0 .. Ls - 1, r = 1 / d. S moves the lower spins from s + 1 and the upper from
+// s - 1 (S^dagger the other way), with the factor -mf across the wall, so per chirality
+//   x_s = sum_{j=0}^{Ls-1} c_j v_{s+-j},  c_j = r^(j+1) / (1 + mf r^Ls), times -mf once s +- j wraps,
+// which is the cyclic bidiagonal system solved in closed form (stable for |d| > 1). Each half
+// spinor goes through the wavefront's staging area in turn; every lane takes part.
+template <class SP>
+__device__ __forceinline__ void column_m5inv(chunk_t *lds, Cx<typename SP::C> v[4][3], int sl, int lbase, int Ls,
+                                             typename SP::C r, typename SP::C mf, bool dag) {
+    using C = typename SP::C;
+    constexpr int NC = static_cast<int>(12 * sizeof(C) / 16);   // 16-byte chunks of six complex numbers
+    constexpr int PITCH = stage_pitch<SP>();
+    static_assert(NC <= PITCH, "a half spinor fits the lane's staging slot");
+    const int lane = threadIdx.x & 63;
+    C rl = C(1);
+    for (int i = 0; i < Ls; ++i) rl *= r;
+    const C c0 = r / (C(1) + mf * rl);
+    Cx<C> x[4][3];
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+        C buf[12];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            buf[2 * j] = v[2 * hf + j / 3][j % 3].r;
+            buf[2 * j + 1] = v[2 * hf + j / 3][j % 3].i;
+        }
+        chunk_t cb[NC];
+        __builtin_memcpy(cb, buf, sizeof(cb));
+#pragma unroll
+        for (int k = 0; k < NC; ++k) lds[lane * PITCH + k] = cb[k];
+        wave_sync();
+        const bool fwd = (hf == 1) != dag;   // this half couples to s + 1 (else to s - 1)
+        Cx<C> acc[2][3];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) acc[j / 3][j % 3] = {C(0), C(0)};
+        C c = c0;
+        int sj = sl;
+        for (int j = 0; j < Ls; ++j) {
+            if (j > 0) {
+                sj += fwd ? 1 : -1;
+                if (sj == Ls || sj == -1) {   // across the wall (at most once)
+                    sj = fwd ? 0 : Ls - 1;
+                    c *= -mf;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NC; ++k) cb[k] = lds[(lbase + sj) * PITCH + k];
+            __builtin_memcpy(buf, cb, sizeof(cb));
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                Cx<C> &o = acc[q / 3][q % 3];
+                o = {o.r + c * buf[2 * q], o.i + c * buf[2 * q + 1]};
+            }
+            c *= r;
+        }
+        wave_sync();
+#pragma unroll
+        for (int j = 0; j < 6; ++j) x[2 * hf + j / 3][j % 3] = acc[j / 3][j % 3];
+    }
+#pragma unroll
+    for (int j = 0; j < 12; ++j) v[j / 3][j % 3] = x[j / 3][j % 3];
+}
+
 // Hardware dispatches workgroup b to XCD b % 8. Renumber so that each XCD receives one
 // contiguous range of logical blocks: neighbouring lattice sites then share an L2.
 __device__ __forceinline__ int xcd_block(int b, int nblocks) {

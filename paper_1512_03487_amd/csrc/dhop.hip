@@ -802,7 +802,7 @@ k_dhop_walk_cb(const void *__restrict__ U, const void *__restrict__ psi, const f
                const void *__restrict__ yv, const float *__restrict__ y_scale, void *out, float *out_scale, GeomDev g,
                int T, int cbp, double diag, double mf, double beta, double cs, double b5, double c5, FuseDev fz) {
     using C = typename SP::C;
-    constexpr bool MOB = KIND == kMobHop || KIND == kMobDiag;
+    constexpr bool MOB = KIND == kMobHop || KIND == kMobDiag || KIND == kMobHopInv;
     constexpr bool MOBF = MOB && !DAG;
     constexpr bool MOBA = MOB && DAG;
     __shared__ chunk_t sm[kWaves][64 * stage_pitch<SP>()];
@@ -827,7 +827,7 @@ k_dhop_walk_cb(const void *__restrict__ U, const void *__restrict__ psi, const f
     const int V3 = Lx * Ly * Lz;
     const int t0 = seg * T;
     constexpr int EF = DAG ? +1 : -1;
-    constexpr int NREC = (KIND == GRID_HOP || KIND == kMobHop) ? 8 : 9;
+    constexpr int NREC = (KIND == GRID_HOP || KIND == kMobHop || KIND == kHopInv || KIND == kMobHopInv) ? 8 : 9;
     [[maybe_unused]] double n2 = 0.0;   // fused epilogue: this thread's |out|^2
     // Moebius: the column's lanes of s + 1 and s - 1 and the wall factors
     int lp = 0, lm = 0;
@@ -909,10 +909,14 @@ k_dhop_walk_cb(const void *__restrict__ U, const void *__restrict__ psi, const f
                 }
             }
         }
-        if (KIND == GRID_HOP || KIND == kMobHop || MOBA) {
+        if (KIND == GRID_HOP || KIND == kMobHop || KIND == kHopInv || KIND == kMobHopInv || MOBA) {
             const C bt = static_cast<C>(beta);
 #pragma unroll
             for (int j = 0; j < 12; ++j) acc[j / 3][j % 3] = {bt * acc[j / 3][j % 3].r, bt * acc[j / 3][j % 3].i};
+        }
+        if constexpr (KIND == kHopInv) {
+            const int lane = threadIdx.x & 63, sl = lane % Ls;
+            column_m5inv<SP>(lds, acc, sl, lane - sl, Ls, static_cast<C>(1.0 / diag), static_cast<C>(mf), DAG);
         }
         if (MOBF && KIND == kMobDiag) {
             // diag y + beta H B psi (y = p, the last record staged)
@@ -948,6 +952,10 @@ k_dhop_walk_cb(const void *__restrict__ U, const void *__restrict__ psi, const f
                 Cx<C> &o = acc[2 + j / 3][j % 3];
                 o = {o.r + wm * hh[j / 3][j % 3].r, o.i + wm * hh[j / 3][j % 3].i};
             }
+        }
+        if constexpr (KIND == kMobHopInv) {
+            const int lane = threadIdx.x & 63, sl = lane % Ls;
+            column_m5inv<SP>(lds, acc, sl, lane - sl, Ls, static_cast<C>(1.0 / diag), static_cast<C>(mf), DAG);
         }
         if (KIND == GRID_DWF || (MOBF && KIND == kMobDiag)) {
             // - cs (P_- y~_{s+1} + P_+ y~_{s-1}) (M; P_+ and P_- exchanged for M^dagger), walls -mf
@@ -1124,7 +1132,7 @@ static hipError_t launch_walk_cb(const DhopArgs &a) {
 #define GRIDMI_LAUNCH(DAG, KIND, FUSE)                                                                    \
     hipLaunchKernelGGL((k_dhop_walk_cb<SP, LK, DAG, KIND, FUSE>), grid, block, 0, st, a.U, a.psi, a.psi_scale, \
                        a.y, a.y_scale, a.out, a.out_scale, a.g, T, a.cb, a.diag, a.mf, a.beta, a.cs, a.b5, a.c5, a.fz)
-    const bool mob = a.kind == kMobHop || a.kind == kMobDiag;
+    const bool mob = a.kind == kMobHop || a.kind == kMobDiag || a.kind == kHopInv || a.kind == kMobHopInv;
     if (mob && !(a.g.Ls >= 2 && 64 % a.g.Ls == 0)) return hipErrorInvalidValue;
     if (a.fuse != kFuseNone) {
         switch (a.kind * 4 + a.fuse * 2 + (a.dag ? 1 : 0)) {
@@ -1149,6 +1157,10 @@ static hipError_t launch_walk_cb(const DhopArgs &a) {
         case kMobHop * 2 + 1: GRIDMI_LAUNCH(true, kMobHop, kFuseNone); break;
         case kMobDiag * 2 + 0: GRIDMI_LAUNCH(false, kMobDiag, kFuseNone); break;
         case kMobDiag * 2 + 1: GRIDMI_LAUNCH(true, kMobDiag, kFuseNone); break;
+        case kHopInv * 2 + 0: GRIDMI_LAUNCH(false, kHopInv, kFuseNone); break;
+        case kHopInv * 2 + 1: GRIDMI_LAUNCH(true, kHopInv, kFuseNone); break;
+        case kMobHopInv * 2 + 0: GRIDMI_LAUNCH(false, kMobHopInv, kFuseNone); break;
+        case kMobHopInv * 2 + 1: GRIDMI_LAUNCH(true, kMobHopInv, kFuseNone); break;
         default: return hipErrorInvalidValue;
     }
 #undef GRIDMI_LAUNCH
@@ -1168,7 +1180,8 @@ static bool use_walk_cb(const DhopArgs &a) { return a.custom && a.cb >= 0 && wal
 template <class SP, class LK>
 static hipError_t launch_sched(const DhopArgs &a) {
     if (a.kind == GRID_MOBIUS && !walk_mobius_applies(a)) return hipErrorInvalidValue;
-    if ((a.kind == kMobHop || a.kind == kMobDiag) && !use_walk_cb(a)) return hipErrorInvalidValue;
+    if ((a.kind == kMobHop || a.kind == kMobDiag || a.kind == kHopInv || a.kind == kMobHopInv) && !use_walk_cb(a))
+        return hipErrorInvalidValue;
     if (tile_applies(a)) return launch_tile(a);
     if (use_walk(a)) return launch_walk<SP, LK>(a);
     if (use_walk_cb(a)) return launch_walk_cb<SP, LK>(a);

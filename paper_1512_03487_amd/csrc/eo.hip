@@ -271,9 +271,9 @@ static hipError_t mob_ee_inv(const EoOp &o, int prec, const void *in, const floa
     return launch_m5inv(in, ins, out, outs, n4, o.g.Ls, o.alpha / o.beta, o.mf, dag, prec, st);
 }
 
-// Moebius Schur operator (see the header): three kernels on the checkerboard column walk when it
-// takes the Moebius kinds, else five (with separate s-local passes); the last carries the fused
-// epilogue.
+// Moebius Schur operator (see the header): two kernels on the checkerboard column walk when it
+// takes the Moebius kinds, else five (with separate s-local passes and the M_ee inverse); the last
+// carries the fused epilogue.
 static hipError_t eo_apply_mobius(const EoOp &o, const void *U, int prec, int fmt, const void *in, const float *ins,
                                   void *out, float *outs, int dag, int fuse, const FuseDev *fz, long *nparts,
                                   hipStream_t st) {
@@ -284,11 +284,13 @@ static hipError_t eo_apply_mobius(const EoOp &o, const void *U, int prec, int fm
     const int Ls = o.g.Ls;
     double f = 1.0;
     if (mob_cb_applies(prec, Ls)) {
-        // three kernels: B folded into the checkerboard walks (gathered records, or across the
-        // column after the hop for the adjoint)
-        EOCHK(hop_cb(U, prec, fmt, o.g, kMobHop, dag, 0.0, o.mf, 1, in, ins, nullptr, nullptr, 1.0, t1, t1s, st,
-                     kFuseNone, nullptr, nullptr, 1.0, o.b5, o.c5));
-        EOCHK(mob_ee_inv(o, prec, t1, t1s, t2, t2s, dag, st, &f));
+        // two kernels: B folded into the checkerboard walks (gathered records, or across the column
+        // after the hop for the adjoint), the first also applying (alpha / beta - S)^-1 across the
+        // column (M_oo = alpha when beta = 0: no inverse, f = 1 / alpha)
+        const bool inv = o.beta != 0.0;
+        f = inv ? 1.0 / o.beta : 1.0 / o.alpha;
+        EOCHK(hop_cb(U, prec, fmt, o.g, inv ? kMobHopInv : kMobHop, dag, inv ? o.alpha / o.beta : 0.0, o.mf, 1, in,
+                     ins, nullptr, nullptr, 1.0, t2, t2s, st, kFuseNone, nullptr, nullptr, 1.0, o.b5, o.c5));
         return hop_cb(U, prec, fmt, o.g, kMobDiag, dag, o.alpha, o.mf, 0, t2, t2s, in, ins, -0.25 * f, out, outs, st,
                       fuse, fz, nparts, o.beta, o.b5, o.c5);
     }
@@ -318,6 +320,13 @@ static hipError_t eo_apply_fz(const void *ctx, const void *U, int prec, int fmt,
     if (o.kind == GRID_MOBIUS) return eo_apply_mobius(o, U, prec, fmt, in, ins, out, outs, dag, fuse, fz, nparts, st);
     const int ix = prec == GRID_F64 ? 0 : 1;
     float *t1s = prec == GRID_F16S ? o.t1s : nullptr, *t2s = prec == GRID_F16S ? o.t2s : nullptr;
+    if (o.kind == GRID_DWF && mob_cb_applies(prec, o.g.Ls)) {
+        // M5^-1 H_oe in by one checkerboard walk (the inverse formed across the column's lanes)
+        EOCHK(hop_cb(U, prec, fmt, o.g, kHopInv, dag, o.diag, o.mf, 1, in, ins, nullptr, nullptr, 1.0, o.t2[ix], t2s,
+                     st));
+        return hop_cb(U, prec, fmt, o.g, GRID_DWF, dag, o.diag, o.mf, 0, o.t2[ix], t2s, in, ins, -0.25, out, outs, st,
+                      fuse, fz, nparts);
+    }
     // t1 = H_oe in
     EOCHK(hop_cb(U, prec, fmt, o.g, GRID_HOP, dag, 0.0, o.mf, 1, in, ins, nullptr, nullptr, 1.0, o.t1[ix], t1s, st));
     const void *src = o.t1[ix];

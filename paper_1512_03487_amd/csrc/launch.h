@@ -29,6 +29,12 @@ struct FuseDev {
 // kMobDiag adds diag y - cs S y (dag: diag y - cs S^dagger y). Full-lattice FP32 / FP16-storage
 // checkerboard fields whose Ls divides 64 (mob_cb_applies).
 enum { kMobHop = 8, kMobDiag = 9 };
+// kHopInv: out = (diag - S)^-1 (beta H psi) ((diag - S^dagger)^-1 with dag), the even-odd domain-wall
+// M5^-1 H_oe in one checkerboard walk (S as in M5, walls -mf); same field conditions.
+enum { kHopInv = 10 };
+// kMobHopInv: kMobHop followed by (diag - S)^-1 across the column (diag = alpha / beta), the
+// Moebius M_oo^-1 up to its factor 1 / beta.
+enum { kMobHopInv = 11 };
 inline bool mob_cb_applies(int prec, int Ls) {
     return (prec == GRID_F32 || prec == GRID_F16S) && Ls >= 2 && 64 % Ls == 0;
 }

@@ -153,7 +153,7 @@ def _oracle_op(kind, Ls):
 
 
 @pytest.mark.parametrize("kind,dims,Ls", [("wilson", (4, 4, 4, 4), 1), ("wilson", (2, 4, 6, 8), 1),
-                                          ("dwf", (4, 4, 4, 4), 8), ("dwf", (2, 2, 4, 6), 4)])
+                                          ("dwf", (4, 4, 4, 4), 8), ("dwf", (2, 2, 4, 6), 4), ("dwf", (2, 4, 2, 4), 6)])
 @pytest.mark.parametrize("sloppy,fmt", [("f64", "L18"), ("f32", "L18"), ("f16s", "L12")])
 def test_solve_eo(gpu, kind, dims, Ls, sloppy, fmt):
     from tests.gpu_util import dev, host, rel
