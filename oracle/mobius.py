@@ -47,3 +47,40 @@ def mobius(U, psi, M5: float, mf: float, b5: float, c5: float, dag: bool = False
 def normal(U, psi, M5: float, mf: float, b5: float, c5: float) -> np.ndarray:
     """M^dagger M psi."""
     return mobius(U, mobius(U, psi, M5, mf, b5, c5), M5, mf, b5, c5, True)
+
+
+def cg(U, b, M5: float, mf: float, b5: float, c5: float, tol: float = 1e-13, maxiter: int = 20000):
+    """Textbook CG (Hestenes-Stiefel) on M^dagger M x = b from x = 0, stopping when the true
+    relative residual |b - M^dagger M x| / |b| is <= tol. Returns (x, iterations)."""
+    b = np.asarray(b, dtype=np.complex128)
+    A = lambda v: normal(U, v, M5, mf, b5, c5)
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rr = np.vdot(r, r).real
+    bn = np.sqrt(np.vdot(b, b).real)
+    for it in range(1, maxiter + 1):
+        Ap = A(p)
+        alpha = rr / np.vdot(p, Ap).real
+        x += alpha * p
+        r -= alpha * Ap
+        rr_new = np.vdot(r, r).real
+        if np.sqrt(rr_new) <= tol * bn and np.linalg.norm(b - A(x)) <= tol * bn:
+            return x, it
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    raise RuntimeError("Moebius oracle CG did not converge")
+
+
+def pseudofermion(U, phi, M5: float, mf: float, b5: float, c5: float, tol: float = 1e-13):
+    """S = Re phi^dagger (M^dagger M)^-1 phi and dS/dU for the Moebius M, the solve recomputed.
+
+    M depends on the links only through its hopping part -H B / 2 (B = b5 + c5 S acts on the fifth
+    coordinate), so with X = (M^dagger M)^-1 phi and Y = M X, dS = -2 Re <Y, dM X> gives
+    dS/dU = -2 G(chi = Y, psi = B X), G the link gradient at c = -1/2. Returns (S, dS/dU, X).
+    """
+    X, _ = cg(U, phi, M5, mf, b5, c5, tol=tol)
+    Y = mobius(U, X, M5, mf, b5, c5)
+    S = float(np.vdot(np.asarray(phi, dtype=np.complex128), X).real)
+    BX = b5 * X + c5 * shift5(X, mf)
+    return S, -2.0 * _o.link_grad(Y, BX, c=-0.5), X

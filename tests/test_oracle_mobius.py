@@ -92,3 +92,46 @@ def test_adjoint_inner_product():
     # the Shamir limit keeps R5 gamma5 hermiticity
     lhs = MB.mobius(U, psi, 1.8, 0.02, 1.0, 0.0, True)
     assert rel(lhs, G5(MB.mobius(U, G5(psi), 1.8, 0.02, 1.0, 0.0))) < 1e-14
+
+
+def _dense_mobius(U, shape, **kw):
+    n = int(np.prod(shape))
+    M = np.empty((n, n), dtype=np.complex128)
+    for j in range(n):
+        e = np.zeros(n, dtype=np.complex128)
+        e[j] = 1.0
+        M[:, j] = MB.mobius(U, e.reshape(shape), **kw).ravel()
+    return M
+
+
+def test_pseudofermion_shamir_limit():
+    """b5 = 1, c5 = 0: the Moebius pseudofermion action and force are the domain-wall ones of the C
+    oracle."""
+    dims, Ls = (2, 2, 2, 2), 4
+    U = F.gauge_field(dims, seed=1, kind="haar")
+    phi = F.spinor_field(dims, seed=5, Ls=Ls)
+    S, dS, _ = MB.pseudofermion(U, phi, 1.8, 0.1, 1.0, 0.0)
+    S0, dS0, _ = O.pseudofermion(O.Op.dwf(Ls, 1.8, 0.1), U, phi)
+    assert abs(S - S0) < 1e-10 * abs(S0)
+    assert np.linalg.norm(dS - dS0) < 1e-9 * np.linalg.norm(dS0)
+
+
+def test_pseudofermion_dense_and_fd():
+    """b5 = 1.5, c5 = 0.5 at 2^4 x 4: S against a dense solve, and the su(3) force against a
+    central finite difference of the dense S along a random su(3) direction."""
+    from tests.lattice_testlib import su3_exp
+    dims, Ls = (2, 2, 2, 2), 4
+    kw = dict(M5=1.8, mf=0.1, b5=1.5, c5=0.5)
+    U = F.gauge_field(dims, seed=1, kind="haar")
+    phi = F.spinor_field(dims, seed=5, Ls=Ls)
+    S, dS, _ = MB.pseudofermion(U, phi, **kw)
+
+    def S_dense(UU):
+        M = _dense_mobius(UU, phi.shape, **kw)
+        return np.vdot(phi.ravel(), np.linalg.solve(M.conj().T @ M, phi.ravel())).real
+    assert abs(S - S_dense(U)) < 1e-10 * abs(S)
+    Xd = F.random_su3_algebra(dims, seed=8)
+    eps = 1e-4
+    fd = (S_dense(su3_exp(eps * Xd) @ U) - S_dense(su3_exp(-eps * Xd) @ U)) / (2 * eps)
+    an = np.sum(np.einsum("...ij,...ij->...", O.force(dS, U).conj(), Xd).real)
+    assert abs(fd - an) < 1e-6 * abs(an)
