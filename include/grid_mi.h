@@ -337,10 +337,12 @@ int grid_hmc_energy(const void *U, const void *P, const void *phi, const grid_ge
  * Two-flavour pseudofermion action (the fermion part of the HMC action, Section 4) with its
  * gradients, for callers that differentiate it (an autograd function, a force evaluation):
  *   X  = (Op^+ Op)^-1 phi by grid_cg with `params` (Op = D for GRID_WILSON, the Shamir M for
- *        GRID_DWF); X holds the initial guess on entry and the solution on exit;
+ *        GRID_DWF, the Moebius M for GRID_MOBIUS); X holds the initial guess on entry and the
+ *        solution on exit;
  *   *S = Re <phi, X> = phi^+ (Op^+ Op)^-1 phi, an FP64 sum in a fixed order (S nullable);
  *   dS_dU   (nullable) = grad_scale * dS/dU, dS/dU = -2 G(g = Op X, psi = X) with G the link
- *           gradient of grid_dhop_backward (c = -1/2), i.e. the sum there with coefficient 1;
+ *           gradient of grid_dhop_backward (c = -1/2), i.e. the sum there with coefficient 1
+ *           (Moebius: psi = B X, B = b5 + c5 S, since its link dependence is -H B / 2);
  *           force_mode 1 writes its su(3) projection TA(dS/dU U^+) instead;
  *   dS_dphi (nullable) = grad_scale * 2 X.
  * U, phi, X, dS_dphi FP64 ([V][4][3][3] / spinor layout); workspace >=

@@ -289,8 +289,10 @@ def cg(U, b, kind="dwf", mass=0.0, M5=1.8, mf=0.01, x0=None, workspace=None, rai
 
 
 def pseudofermion_action(U, phi, kind="wilson", mass=0.1, M5=1.8, mf=0.01, x0=None, grad_scale=1.0, want_S=True,
-                         want_U=False, force=False, want_phi=False, workspace=None, raise_on_fail=True, **params):
-    """Two-flavour pseudofermion action S = Re phi^dagger (Op^dagger Op)^-1 phi (Op = D or M, FP64).
+                         want_U=False, force=False, want_phi=False, workspace=None, raise_on_fail=True, b5=1.0,
+                         c5=0.0, **params):
+    """Two-flavour pseudofermion action S = Re phi^dagger (Op^dagger Op)^-1 phi (Op = D, the Shamir
+    M or the Moebius M with b5, c5; FP64).
 
     Returns (S, X, dS_dU, dS_dphi, stats): S a float (None unless want_S), X the solution, and the
     gradients scaled by grad_scale (None unless asked for); force=True gives the su(3) projection
@@ -311,7 +313,7 @@ def pseudofermion_action(U, phi, kind="wilson", mass=0.1, M5=1.8, mf=0.01, x0=No
     X = torch.zeros_like(phi) if x0 is None else x0.clone()
     gU = torch.empty(tuple(phi.shape[:4]) + (4, 3, 3), dtype=torch.complex128, device=phi.device) if want_U else None
     gphi = torch.empty_like(phi) if want_phi else None
-    op = make_op(kind, False, mass, M5, mf)
+    op = make_op(kind, False, mass, M5, mf, b5, c5)
     S = ctypes.c_double(0.0)
     st = GridCgStats()
     rc = load().grid_pseudofermion_action(_ptr(U), _ptr(phi), _ptr(X), ctypes.byref(g), ctypes.byref(op),

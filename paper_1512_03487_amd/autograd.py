@@ -31,7 +31,7 @@ class DhopFn(torch.autograd.Function):
 
 
 class PseudofermionActionFn(torch.autograd.Function):
-    """S = Re phi^dagger (Op^dagger Op)^-1 phi (Op = D or M, FP64), differentiable in U and phi.
+    """S = Re phi^dagger (Op^dagger Op)^-1 phi (Op = D, M or the Moebius M, FP64), differentiable in U and phi.
 
     The library computes S (a fixed-order FP64 reduction) and, in backward, dS/dU = -2 G(Op X, X)
     and dS/dphi = 2 X scaled by the upstream gradient (grid_pseudofermion_action); the solve X is
@@ -39,9 +39,9 @@ class PseudofermionActionFn(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, U, phi, kind="wilson", mass=0.1, M5=1.8, mf=0.01, tol=1e-12, sloppy="f64"):
+    def forward(ctx, U, phi, kind="wilson", mass=0.1, M5=1.8, mf=0.01, tol=1e-12, sloppy="f64", b5=1.0, c5=0.0):
         ctx.save_for_backward(U, phi)
-        ctx.cfg = dict(kind=kind, mass=mass, M5=M5, mf=mf, tol=tol, sloppy=sloppy)
+        ctx.cfg = dict(kind=kind, mass=mass, M5=M5, mf=mf, tol=tol, sloppy=sloppy, b5=b5, c5=c5)
         S, _, _, _, _ = api.pseudofermion_action(U, phi, **ctx.cfg)
         return torch.tensor(S, dtype=torch.float64, device=phi.device)
 
@@ -50,7 +50,7 @@ class PseudofermionActionFn(torch.autograd.Function):
         U, phi = ctx.saved_tensors
         want_U, want_phi = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         if not (want_U or want_phi):
-            return None, None, None, None, None, None, None, None
+            return None, None, None, None, None, None, None, None, None, None
         _, _, gU, gphi, _ = api.pseudofermion_action(U, phi, grad_scale=float(gS), want_S=False, want_U=want_U,
                                                      want_phi=want_phi, **ctx.cfg)
-        return gU, gphi, None, None, None, None, None, None
+        return gU, gphi, None, None, None, None, None, None, None, None

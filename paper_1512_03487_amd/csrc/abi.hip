@@ -648,8 +648,9 @@ int grid_pseudofermion_action(const void *U, const void *phi, void *X, const gri
     GeomDev g;
     TRY(check_geom(geom, &g));
     TRY(check_solver_args(g, op, params, stats));
-    if (op->kind != GRID_WILSON && op->kind != GRID_DWF)
-        return fail(GRID_EINVAL, "the pseudofermion action takes GRID_WILSON or GRID_DWF (got kind %d)", op->kind);
+    if (op->kind != GRID_WILSON && op->kind != GRID_DWF && op->kind != GRID_MOBIUS)
+        return fail(GRID_EINVAL, "the pseudofermion action takes GRID_WILSON, GRID_DWF or GRID_MOBIUS (got kind %d)",
+                    op->kind);
     if (force_mode != 0 && force_mode != 1) return fail(GRID_EINVAL, "force_mode must be 0 or 1 (got %d)", force_mode);
     if (!isfinite(grad_scale)) return fail(GRID_EINVAL, "grad_scale must be finite");
     TRY(check_ptr(U, "U", 16));

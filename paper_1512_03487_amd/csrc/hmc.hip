@@ -468,13 +468,15 @@ __global__ void __launch_bounds__(256) k_dscal(double *__restrict__ y, const dou
 }
 
 struct PfLayout {
-    size_t Y, part, cg, total;
+    size_t Y, T, part, cg, total;
 };
 
 static PfLayout pf_layout(const GeomDev &g, const grid_cg_params &p) {
     PfLayout L;
     size_t off = 0;
     L.Y = off;
+    off = al256(off + static_cast<size_t>(g.n5) * 192);
+    L.T = off;   // Moebius: the intermediate of M X, then B X
     off = al256(off + static_cast<size_t>(g.n5) * 192);
     L.part = off;
     off = al256(off + (kHmcParts + 16) * sizeof(double));
@@ -507,11 +509,20 @@ hipError_t run_pseudofermion(const void *U, const void *phi, void *X, const Geom
         a.diag = op.kind == GRID_WILSON ? 4.0 + op.mass : 5.0 - op.M5;
         a.mf = op.mf;
         a.stream = st;
-        HMCCHK(launch_dhop(a));
+        const void *psi_g = X;
+        if (op.kind == GRID_MOBIUS) {
+            // M depends on the links through -H B / 2: dS/dU = -2 G(M X, B X)
+            HMCCHK(launch_mobius(a, op.M5, op.b5, op.c5, w + L.T, nullptr));
+            HMCCHK(launch_s5axpy(GRID_F64, X, nullptr, nullptr, nullptr, w + L.T, nullptr, g.n5, g.Ls, op.b5, op.c5,
+                                 0.0, 0.0, op.mf, 0, st));
+            psi_g = w + L.T;
+        } else {
+            HMCCHK(launch_dhop(a));
+        }
         LinkGradArgs la;
         la.U = U;
         la.chi = w + L.Y;
-        la.psi = X;
+        la.psi = psi_g;
         la.G = dS_dU;
         la.g = g;
         la.prec = GRID_F64;

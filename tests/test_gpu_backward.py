@@ -174,3 +174,34 @@ def test_pseudofermion_autograd_dwf(gpu):
     assert abs(float(S) - S_ref) <= 1e-11 * abs(S_ref)
     assert rel(Ud.grad.cpu().numpy(), 3.0 * dS_ref) <= 1e-9
     assert rel(phid.grad.cpu().numpy(), 6.0 * X_ref) <= 1e-9
+
+
+def test_pseudofermion_action_mobius(gpu):
+    """The Moebius pseudofermion action (b5 = 1.5, c5 = 0.5, M5 = 1.8, mf = 0.1) at 4^4 x 8: S, X,
+    dS/dU (raw and su(3)-projected) and dS/dphi through the ABI, and S and both gradients through
+    PseudofermionActionFn, against the numpy Moebius oracle (its own CG to 1e-13)."""
+    import paper_1512_03487_amd as gm
+    from oracle import mobius as MB
+    from tests.gpu_util import dev, rel
+    dims, Ls = (4, 4, 4, 4), 8
+    kw = dict(M5=1.8, mf=0.1, b5=1.5, c5=0.5)
+    U = F.gauge_field(dims, seed=1, kind="haar")
+    phi = F.spinor_field(dims, seed=5, Ls=Ls)
+    S_ref, dS_ref, X_ref = MB.pseudofermion(U, phi, tol=1e-13, **kw)
+    Ud, phid = dev(U), dev(phi)
+    S, X, gU, gphi, st = gm.pseudofermion_action(Ud, phid, "mobius", tol=1e-13, grad_scale=0.75, want_U=True,
+                                                 want_phi=True, **kw)
+    assert st["converged"]
+    assert abs(S - S_ref) <= 1e-11 * abs(S_ref)
+    assert rel(X.cpu().numpy(), X_ref) <= 1e-9
+    assert rel(gU.cpu().numpy(), 0.75 * dS_ref) <= 1e-9
+    assert rel(gphi.cpu().numpy(), 1.5 * X_ref) <= 1e-9
+    _, _, Fk, _, _ = gm.pseudofermion_action(Ud, phid, "mobius", tol=1e-13, want_U=True, force=True, **kw)
+    assert rel(Fk.cpu().numpy(), O.force(dS_ref, U)) <= 1e-9
+    Ug = dev(U).requires_grad_(True)
+    phig = dev(phi).requires_grad_(True)
+    Sa = gm.PseudofermionActionFn.apply(Ug, phig, "mobius", 0.0, 1.8, 0.1, 1e-13, "f64", 1.5, 0.5)
+    (2.0 * Sa).backward()
+    assert abs(float(Sa) - S_ref) <= 1e-11 * abs(S_ref)
+    assert rel(Ug.grad.cpu().numpy(), 2.0 * dS_ref) <= 1e-9
+    assert rel(phig.grad.cpu().numpy(), 4.0 * X_ref) <= 1e-9
