@@ -271,7 +271,9 @@ int grid_solve_eo(const void *U, const void *b, void *x, const grid_geom *geom, 
  * Hybrid Monte Carlo molecular dynamics (HMC, Section 4), FP64, links [V][4][3][3].
  *   S_G = beta sum_{x, mu<nu} (1 - Re tr P_munu(x) / 3),
  *   P_munu(x) = U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+;
- *   S_F = phi^+ (Op^+ Op)^-1 phi (two flavours, Op = D or the Shamir M of `fermion`);
+ *   S_F = phi^+ (Op^+ Op)^-1 phi (two flavours, Op = D, the Shamir M or the Moebius M of
+ *   `fermion`; the Moebius force is -2 G(M X, B X), X = (M^+ M)^-1 phi, as in
+ *   grid_pseudofermion_action);
  *   forces F = TA(G U^+) with G = dS/dRe U + i dS/dIm U (as grid_dhop_backward);
  *   momenta P in su(3) per link ([V][4][3][3], anti-Hermitian traceless), K = sum tr(P^+ P);
  *   dU/dt = P U, dP/dt = -F/2, leapfrog: P -= (eps/2) F/2, then n_steps times
@@ -288,7 +290,8 @@ typedef struct {
     double beta;            /* Wilson gauge coupling                                            */
     double eps;             /* leapfrog step size                                               */
     int n_steps;            /* leapfrog steps                                                   */
-    grid_op fermion;        /* GRID_WILSON or GRID_DWF pseudofermion operator (phi != NULL)     */
+    grid_op fermion;        /* GRID_WILSON, GRID_DWF or GRID_MOBIUS pseudofermion operator
+                               (phi != NULL)                                                     */
     grid_cg_params cg;      /* the solves inside every fermion-force evaluation                 */
     int integrator;         /* GRID_LEAPFROG, GRID_OMELYAN or GRID_FORCE_GRADIENT               */
     int n_inner;            /* > 1: two time scales (needs GRID_LEAPFROG): per step
@@ -317,7 +320,7 @@ int grid_link_exp(void *U, const void *P, double eps, long n_links, void *stream
 
 /*
  * grid_md_leapfrog -- integrate (U, P) in place over n_steps steps of size eps with the integrator
- * params->integrator names (leapfrog or Omelyan); phi
+ * params->integrator names (leapfrog, Omelyan or force gradient); phi
  * (FP64, the 4D or 5D pseudofermion of `fermion`) adds the fermion force, NULL integrates the pure
  * gauge system. Synchronous. Returns GRID_OK or an argument / HIP error; stats->failed_solves
  * counts force solves that did not reach cg.tol.

@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import mobius as _mob
 from . import oracle as _o
 
 _AX = {0: 3, 1: 2, 2: 1, 3: 0}   # numpy axis of direction mu in (Lt, Lz, Ly, Lx, ...)
@@ -98,9 +99,13 @@ def kinetic(P) -> float:
 
 
 def fermion_force(U, fermion):
-    """(S_F, F_F) for S_F = phi^dagger (M^dagger M)^-1 phi; fermion = (Op, phi)."""
+    """(S_F, F_F) for S_F = phi^dagger (M^dagger M)^-1 phi; fermion = (Op, phi), Op an
+    ``oracle.Op`` (Wilson D or Shamir M) or an ``oracle.mobius.MobiusOp``."""
     op, phi = fermion
-    S, dS, _ = _o.pseudofermion(op, U, phi, tol=1e-12)
+    if isinstance(op, _mob.MobiusOp):
+        S, dS, _ = _mob.pseudofermion(U, phi, op.M5, op.mf, op.b5, op.c5, tol=1e-12)
+    else:
+        S, dS, _ = _o.pseudofermion(op, U, phi, tol=1e-12)
     return S, _o.force(dS, U)
 
 

@@ -14,9 +14,20 @@ Composed from the pinned ``oracle.hop`` and plain numpy shifts; used only by the
 """
 from __future__ import annotations
 
+from dataclasses import dataclass
+
 import numpy as np
 
 from . import oracle as _o
+
+
+@dataclass(frozen=True)
+class MobiusOp:
+    """The Moebius operator's parameters, as the fermion of an HMC oracle run."""
+    M5: float
+    mf: float
+    b5: float
+    c5: float
 
 
 def shift5(psi, mf: float, dag: bool = False) -> np.ndarray:

@@ -446,12 +446,12 @@ def link_exp(U, P, eps):
 
 
 def md_params(beta, eps=0.1, n_steps=10, kind="dwf", mass=0.0, M5=1.8, mf=0.01, integrator="leapfrog",
-              n_inner=1, **cg) -> GridMdParams:
+              n_inner=1, b5=1.0, c5=0.0, **cg) -> GridMdParams:
     p = GridMdParams()
     p.beta, p.eps, p.n_steps = float(beta), float(eps), int(n_steps)
     p.integrator = {"leapfrog": 0, "omelyan": 1, "force_gradient": 2}[integrator]
     p.n_inner = int(n_inner)
-    p.fermion = make_op(kind, False, mass, M5, mf)
+    p.fermion = make_op(kind, False, mass, M5, mf, b5, c5)
     p.cg = cg_params(**cg)
     return p
 

@@ -129,8 +129,9 @@ int check_md(const GeomDev &g, const grid_md_params *p, const void *phi) {
     if (p->n_inner > 1 && p->integrator != GRID_LEAPFROG)
         return fail(GRID_EINVAL, "two time scales take leapfrog outer steps (integrator %d)", p->integrator);
     if (phi) {
-        if (p->fermion.kind != GRID_WILSON && p->fermion.kind != GRID_DWF)
-            return fail(GRID_EINVAL, "the fermion force takes GRID_WILSON or GRID_DWF (got kind %d)", p->fermion.kind);
+        if (p->fermion.kind != GRID_WILSON && p->fermion.kind != GRID_DWF && p->fermion.kind != GRID_MOBIUS)
+            return fail(GRID_EINVAL, "the fermion force takes GRID_WILSON, GRID_DWF or GRID_MOBIUS (got kind %d)",
+                        p->fermion.kind);
         grid_cg_stats dummy;
         TRY(check_solver_args(g, &p->fermion, &p->cg, &dummy));
     } else {

@@ -264,7 +264,7 @@ static hipError_t daxpy(void *y, const void *x, double a, long n, hipStream_t st
 static size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct MdLayout {
-    size_t F, Ff, X, Y, Ud, part, cg, total;   // Ud: displaced links (force-gradient integrator)
+    size_t F, Ff, X, Y, T, Ud, part, cg, total;   // Ud: displaced links (force-gradient integrator)
 };
 
 static MdLayout md_layout(const GeomDev &g, const grid_md_params &p) {
@@ -282,6 +282,7 @@ static MdLayout md_layout(const GeomDev &g, const grid_md_params &p) {
     L.Ff = take(lb);
     L.X = take(sb);
     L.Y = take(sb);
+    L.T = p.fermion.kind == GRID_MOBIUS ? take(sb) : 0;   // Moebius: the intermediate of M X, then B X
     L.Ud = p.integrator == GRID_FORCE_GRADIENT ? take(lb) : 0;
     L.part = take((kHmcParts + 16) * sizeof(double));
     L.cg = off;
@@ -302,7 +303,8 @@ struct MdRun {
     grid_md_stats *stats;
 };
 
-// X = (M^dagger M)^-1 phi (warm start from the previous X), Y = M X.
+// X = (M^dagger M)^-1 phi (warm start from the previous X), Y = M X; for the Moebius operator also
+// T = B X, the field the links meet in M's hopping term -H B / 2.
 static hipError_t fermion_solve(MdRun &r) {
     int status = GRID_OK;
     grid_cg_stats cs;
@@ -325,7 +327,11 @@ static hipError_t fermion_solve(MdRun &r) {
     a.diag = r.p.fermion.kind == GRID_WILSON ? 4.0 + r.p.fermion.mass : 5.0 - r.p.fermion.M5;
     a.mf = r.p.fermion.mf;
     a.stream = r.st;
-    return launch_dhop(a);
+    if (r.p.fermion.kind != GRID_MOBIUS) return launch_dhop(a);
+    const grid_op &op = r.p.fermion;
+    HMCCHK(launch_mobius(a, op.M5, op.b5, op.c5, r.ws + r.L.T, nullptr));
+    return launch_s5axpy(GRID_F64, r.ws + r.L.X, nullptr, nullptr, nullptr, r.ws + r.L.T, nullptr, r.g.n5, r.g.Ls,
+                         op.b5, op.c5, 0.0, 0.0, op.mf, 0, r.st);
 }
 
 // The pseudofermion force into the Ff buffer (phi != NULL).
@@ -334,13 +340,13 @@ static hipError_t fermion_force(MdRun &r) {
     LinkGradArgs a;
     a.U = r.U;
     a.chi = r.ws + r.L.Y;
-    a.psi = r.ws + r.L.X;
+    a.psi = r.ws + (r.p.fermion.kind == GRID_MOBIUS ? r.L.T : r.L.X);
     a.G = r.ws + r.L.Ff;
     a.g = r.g;
     a.prec = GRID_F64;
     a.dag = 0;
     a.force_mode = 1;
-    a.coef = 1.0;   // dS_F/dU = -2 G_{c=-1/2} = G_{c=1}
+    a.coef = 1.0;   // dS_F/dU = -2 G_{c=-1/2}(M X, X or B X) = G_{c=1}
     a.stream = r.st;
     return launch_link_grad(a);
 }

@@ -189,7 +189,12 @@ def test_md_validation(lib):
         ctypes.byref(st), None)
     assert call(nb=w - 1) == _lib.GRID_ESPACE
     assert call(ws=A + 0x40000000 + 32) == _lib.GRID_EALIGN
-    assert call(pp=_lib.GridMdParams(5.5, 0.05, 4, op(kind=_lib.GRID_MOBIUS), cg)) == _lib.GRID_EINVAL
+    assert call(pp=_lib.GridMdParams(5.5, 0.05, 4, op(kind=_lib.GRID_HOP), cg)) == _lib.GRID_EINVAL
+    # the Moebius force needs one more 5D field (B X)
+    pm = _lib.GridMdParams(5.5, 0.05, 4, op(kind=_lib.GRID_MOBIUS, b5=1.5, c5=0.5), cg)
+    wm = lib.grid_md_workspace_bytes(ctypes.byref(g), ctypes.byref(pm))
+    assert wm >= w + 4 ** 4 * 4 * 192
+    assert call(pp=pm) == _lib.GRID_ESPACE
     assert call(pp=_lib.GridMdParams(5.5, 0.05, -1, op(kind=_lib.GRID_DWF), cg)) == _lib.GRID_EINVAL
     assert call(pp=_lib.GridMdParams(float("nan"), 0.05, 4, op(kind=_lib.GRID_DWF), cg)) == _lib.GRID_EINVAL
     assert call(phi=A + 0x10000000 + 64) == _lib.GRID_EINVAL                  # phi overlaps P

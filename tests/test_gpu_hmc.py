@@ -206,3 +206,26 @@ def test_nested_time_scales_match_oracle(gpu, with_fermion):
     assert st["solves"] == (4 if with_fermion else 0)
     with pytest.raises(Exception):
         gm.md_leapfrog(dev(U), dev(P), beta, 0.1, 1, None, n_inner=2, integrator="omelyan", **DWF)
+
+
+@pytest.mark.parametrize("integrator,n,solves", [("leapfrog", 4, 5), ("force_gradient", 2, 7)])
+def test_mobius_md_matches_oracle(gpu, integrator, n, solves):
+    """Moebius fermions (b5 = 1.5, c5 = 0.5) in the molecular dynamics: the steps and the energy
+    equal the oracle's (force -2 G(M X, B X) in the library, the Moebius CG in the oracle)."""
+    from oracle.mobius import MobiusOp
+    from tests.gpu_util import dev, host, rel
+    gm = _gm()
+    dims, Ls, beta = (2, 2, 2, 4), 4, 5.5
+    mob = dict(kind="mobius", M5=1.8, mf=0.2, b5=1.5, c5=0.5)
+    U = F.gauge_field(dims, seed=1, kind="weak")
+    P = F.random_su3_algebra(dims, seed=7)
+    phi = F.spinor_field(dims, seed=5, Ls=Ls)
+    Ud, Pd, phid = dev(U), dev(P), dev(phi)
+    ferm = (MobiusOp(1.8, 0.2, 1.5, 0.5), phi)
+    e = gm.hmc_energy(Ud, Pd, beta, phid, tol=1e-12, **mob)
+    assert e["S_F"] == pytest.approx(OH.fermion_force(U, ferm)[0], rel=1e-10)
+    st = gm.md_leapfrog(Ud, Pd, beta, 0.1, n, phid, tol=1e-12, integrator=integrator, **mob)
+    step = OH.leapfrog if integrator == "leapfrog" else OH.force_gradient
+    Ur, Pr = step(U, P, beta, 0.1, n, ferm)
+    assert rel(host(Ud), Ur) <= 1e-8 and rel(host(Pd), Pr) <= 1e-8
+    assert st["solves"] == solves and st["failed_solves"] == 0

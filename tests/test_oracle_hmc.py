@@ -172,3 +172,26 @@ def test_nested_leapfrog():
             dH[(ni, n)] = abs(hmc.hamiltonian(Un, Pn, beta2, ferm2) - H0)
     assert 3.0 < dH[(4, 4)] / dH[(4, 8)] < 5.0, dH
     assert dH[(4, 8)] < 0.5 * dH[(1, 8)], dH
+
+
+def test_mobius_fermion_force():
+    """The HMC oracle's Moebius fermion: at b5 = 1, c5 = 0 its action and force are the Shamir
+    ones; at b5 = 1.5, c5 = 0.5 leapfrog's energy error is second order in eps (a force missing
+    the B X factor, or off by a sign or a factor, breaks this)."""
+    from oracle.mobius import MobiusOp
+    dims, Ls, beta, tau = (2, 2, 2, 4), 4, 5.5, 0.4
+    U0, (dwf, phi) = _fermion(dims, Ls)
+    S1, F1 = hmc.fermion_force(U0, (MobiusOp(1.8, 0.2, 1.0, 0.0), phi))
+    S2, F2 = hmc.fermion_force(U0, (dwf, phi))
+    assert S1 == pytest.approx(S2, rel=1e-10) and np.max(np.abs(F1 - F2)) < 1e-9 * np.max(np.abs(F2))
+    ferm = (MobiusOp(1.8, 0.2, 1.5, 0.5), phi)
+    P0 = F.random_su3_algebra(dims, seed=7)
+    H0 = hmc.hamiltonian(U0, P0, beta, ferm)
+    dH = []
+    for n in (4, 8):
+        U1, P1 = hmc.leapfrog(U0, P0, beta, tau / n, n, ferm)
+        dH.append(abs(hmc.hamiltonian(U1, P1, beta, ferm) - H0))
+    assert 3.0 < dH[0] / dH[1] < 5.0, dH
+    # the Moebius force differs from the Shamir one at these coefficients
+    Fm = hmc.fermion_force(U0, ferm)[1]
+    assert np.max(np.abs(Fm - F2)) > 1e-2 * np.max(np.abs(F2))
