@@ -29,6 +29,16 @@ standard aggregation-based construction, written out plainly:
   orthogonalised against the previous w_j (modified Gram-Schmidt) and scaled to |w_k| = 1,
   alpha = <w_k, r>, x += alpha z_k, r -= alpha w_k; at each restart and at the end r = b - D x is
   recomputed; stop when |b - D x| <= tol |b|.
+* Multigrid pCG: flexible preconditioned CG on the Hermitian positive definite normal equations
+  N x = D^dagger b, N = D^dagger D, preconditioned with M(rho) = K(G5 K(G5 rho)), K the two-level
+  cycle above and G5 = gamma5 on the fine field: since D^dagger = G5 D G5, G5 K G5 approximates
+  D^-dagger and M approximates N^-1 = D^-1 D^-dagger (with no smoothing and exact coarse solves
+  M = P (A_c^dagger A_c)^-1 R, Hermitian positive semidefinite). M varies between iterations (the
+  MR and coarse CG coefficients depend on rho), so each search direction
+  p_k = z_k - sum_j (<N p_j, z_k> / <p_j, N p_j>) p_j is made N-conjugate to every earlier one kept
+  (up to m, then the process restarts from the true residual), alpha_k = <p_k, rho_k> /
+  <p_k, N p_k>, x += alpha_k p_k, rho -= alpha_k N p_k (flexible CG in Notay's form); stop when
+  |b - D x| <= tol |b|.
 
 Inner products are <a, b> = sum conj(a) b. Only the test-suite uses this module.
 """
@@ -270,5 +280,52 @@ def fgcr(U, vecs, A, b, mass, block, tol=1e-10, maxiter=200, restart=8, coarse_i
         if len(Z) == restart:
             Z, W = [], []
             r = b - _o.wilson(U, x, mass)
+    r = b - _o.wilson(U, x, mass)
+    return x, it, float(np.linalg.norm(r) / bn)
+
+
+def gamma5(v):
+    """gamma5 v on a fine field: +1 on spins 0, 1 and -1 on spins 2, 3."""
+    out = np.array(v, dtype=np.complex128)
+    out[..., 2:4, :] *= -1
+    return out
+
+
+def normal(U, v, mass):
+    """D^dagger D v."""
+    return _o.wilson(U, _o.wilson(U, v, mass), mass, dag=True)
+
+
+def normal_cycle(U, vecs, A, rho, mass, block, coarse_iters, coarse_tol, smooth_iters):
+    """M(rho) = K(G5 K(G5 rho)), the pCG preconditioner."""
+    y = gamma5(precondition(U, vecs, A, gamma5(rho), mass, block, coarse_iters, coarse_tol, smooth_iters))
+    return precondition(U, vecs, A, y, mass, block, coarse_iters, coarse_tol, smooth_iters)
+
+
+def fcg(U, vecs, A, b, mass, block, tol=1e-10, maxiter=200, restart=8, coarse_iters=50, coarse_tol=0.05,
+        smooth_iters=2, precondition=True):
+    """Multigrid-preconditioned flexible CG on D^dagger D x = D^dagger b (precondition=False: the
+    identity in place of the cycle). Returns (x, iterations, |b - D x| / |b|)."""
+    x = np.zeros_like(b)
+    bn = np.linalg.norm(b)
+    rho = _o.wilson(U, b, mass, dag=True)
+    it = 0
+    P, NP = [], []
+    while np.linalg.norm(b - _o.wilson(U, x, mass)) > tol * bn and it < maxiter:
+        z = normal_cycle(U, vecs, A, rho, mass, block, coarse_iters, coarse_tol, smooth_iters) \
+            if precondition else rho.copy()
+        p = z.copy()
+        for pj, npj in zip(P, NP):
+            p = p - (_dot(npj, z) / _dot(pj, npj)) * pj
+        n_p = normal(U, p, mass)
+        alpha = _dot(p, rho) / _dot(p, n_p)
+        x = x + alpha * p
+        rho = rho - alpha * n_p
+        P.append(p)
+        NP.append(n_p)
+        it += 1
+        if len(P) == restart:
+            P, NP = [], []
+            rho = _o.wilson(U, b - _o.wilson(U, x, mass), mass, dag=True)
     r = b - _o.wilson(U, x, mass)
     return x, it, float(np.linalg.norm(r) / bn)

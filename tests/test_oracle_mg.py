@@ -3,7 +3,9 @@ Galerkin coarse operator against a brute-force R D P built column by column from
 Wilson operator, a free-field closed form (coarse Wilson operator with shifted mass and hopping
 scaled by 1/b), gamma5-hermiticity, gauge invariance, the stencil adjoint, Galerkin orthogonality
 of the coarse-grid correction, the coarse CGNR, the MR smoother, and the preconditioned GCR's
-solution against CG.
+solution against CG. Multigrid pCG: textbook CG iterates with the identity preconditioner, its
+preconditioner without smoothing equal to the dense P (A_c^dagger A_c)^-1 R (Hermitian, positive),
+one step with an exact preconditioner, and its solution against CG with and without restarts.
 """
 import numpy as np
 import pytest
@@ -187,3 +189,70 @@ def test_preconditioned_gcr_solves_the_wilson_system():
     xc, st, _, _ = O.cg(op, U, O.wilson(U, b, m, dag=True), tol=1e-12)
     assert st == 0 and np.linalg.norm(x - xc) < 1e-7 * np.linalg.norm(xc)
     assert counts[2] < counts[0], counts
+
+
+def test_fcg_without_preconditioner_is_textbook_cg():
+    """With the identity in place of the cycle (and no restart within the steps compared), the
+    flexible CG's iterates are those of plain CG on D^dagger D x = D^dagger b."""
+    dims, m = (4, 4, 2, 4), 0.1
+    U = F.gauge_field(dims, seed=1, kind="haar")
+    b = F.spinor_field(dims, seed=3)
+    q = mg.orthonormalise(_vecs(dims, 2), (2, 2, 2, 2))
+    A = mg.coarse_operator(U, q, m, (2, 2, 2, 2))
+    for k in (1, 2, 5):
+        x, it, _ = mg.fcg(U, q, A, b, m, (2, 2, 2, 2), tol=1e-300, maxiter=k, restart=16, precondition=False)
+        xc, _, _, _ = O.cg(O.Op.wilson(m), U, O.wilson(U, b, m, dag=True), tol=1e-300, maxiter=k)
+        assert it == k and np.linalg.norm(x - xc) < 1e-11 * np.linalg.norm(xc), k
+
+
+def test_coarse_part_of_the_pcg_preconditioner():
+    """Without smoothing and with the coarse systems solved tightly, M = K G5 K G5 is
+    P A_c^-1 G5 A_c^-1 G5 R = P (A_c^dagger A_c)^-1 R: equal to that dense formula, Hermitian and
+    positive."""
+    dims, block, nvec, m = (4, 4, 4, 4), (2, 2, 2, 2), 3, 0.1
+    U = F.gauge_field(dims, seed=1, kind="haar")
+    q = mg.orthonormalise(_vecs(dims, nvec), block)
+    A = mg.coarse_operator(U, q, m, block)
+    Ad = _dense_coarse(A)
+    a, r = F.spinor_field(dims, seed=3), F.spinor_field(dims, seed=4)
+    Mr = mg.normal_cycle(U, q, A, r, m, block, 2000, 1e-14, 0)
+    Ma = mg.normal_cycle(U, q, A, a, m, block, 2000, 1e-14, 0)
+    rc = mg.restrict(q, r, block)
+    ref = mg.prolong(q, np.linalg.solve(Ad.conj().T @ Ad, rc.ravel()).reshape(rc.shape), block)
+    assert np.linalg.norm(Mr - ref) < 1e-10 * np.linalg.norm(ref)
+    assert abs(np.vdot(a, Mr) - np.conj(np.vdot(r, Ma))) < 1e-10 * abs(np.vdot(a, Mr))
+    assert np.vdot(r, Mr).real > 0 and abs(np.vdot(r, Mr).imag) < 1e-10 * np.vdot(r, Mr).real
+
+
+def test_fcg_with_an_exact_cycle_converges_in_one_step():
+    """One-site aggregates with nvec = 6 make P unitary and A_c = R D P the whole operator; the
+    preconditioner without smoothing then applies (D^dagger D)^-1 and the flexible CG stops after
+    one step."""
+    dims, m = (2, 2, 2, 4), 0.2
+    U = F.gauge_field(dims, seed=1, kind="weak")
+    b = F.spinor_field(dims, seed=3)
+    block = (1, 1, 1, 1)
+    q = mg.orthonormalise(_vecs(dims, 6), block)
+    A = mg.coarse_operator(U, q, m, block)
+    x, it, res = mg.fcg(U, q, A, b, m, block, tol=1e-10, coarse_iters=5000, coarse_tol=1e-14, smooth_iters=0)
+    assert it == 1 and res <= 1e-10
+
+
+def test_multigrid_pcg_solves_the_wilson_system():
+    """Multigrid pCG reaches |b - D x| <= tol |b|, agrees with the CG solution, and takes fewer
+    iterations than CG on the same normal equations."""
+    dims, block, nvec, m = (4, 4, 4, 4), (2, 2, 2, 2), 6, 0.05
+    U = F.gauge_field(dims, seed=1, kind="weak")
+    b = F.spinor_field(dims, seed=3)
+    q = mg.orthonormalise(mg.near_null(U, _vecs(dims, nvec), m, 2, 8), block)
+    A = mg.coarse_operator(U, q, m, block)
+    x, it, res = mg.fcg(U, q, A, b, m, block, tol=1e-10, restart=64, coarse_iters=40, coarse_tol=0.05,
+                        smooth_iters=2)
+    assert res <= 1e-10
+    xc, st, its_cg, _ = O.cg(O.Op.wilson(m), U, O.wilson(U, b, m, dag=True), tol=1e-12)
+    assert st == 0 and np.linalg.norm(x - xc) < 1e-7 * np.linalg.norm(xc)
+    assert 2 * it < its_cg, (it, its_cg)
+    # restarts from the true residual every four directions: still converges
+    x4, it4, res4 = mg.fcg(U, q, A, b, m, block, tol=1e-10, maxiter=400, restart=4, coarse_iters=40,
+                           coarse_tol=0.05, smooth_iters=2)
+    assert res4 <= 1e-10 and np.linalg.norm(x4 - xc) < 1e-7 * np.linalg.norm(xc)
