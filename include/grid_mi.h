@@ -441,6 +441,24 @@ int grid_mg_solve(const void *U, const void *vecs, const void *A, const void *b,
                   const grid_op *op, const grid_mg_params *params, void *workspace, size_t ws_bytes,
                   grid_cg_stats *stats, void *stream);
 
+/*
+ * grid_mg_pcg -- D x = b by multigrid-preconditioned CG (Section 4 lists multigrid pCG beside
+ * pGCR): flexible CG on the Hermitian positive definite normal equations N x = D^+ b, N = D^+ D,
+ * preconditioned with M(rho) = K(G5 K(G5 rho)), where K is grid_mg_solve's two-level cycle and
+ * G5 = gamma5 on the fine field (D^+ = G5 D G5, so M approximates N^-1 = D^-1 D^-+; with no
+ * smoothing and exact coarse solves M = P (A_c^+ A_c)^-1 R). The cycle's coefficients depend on its
+ * input, so each direction p_k = z_k - sum_j (<N p_j, z_k> / <p_j, N p_j>) p_j is made N-conjugate
+ * to the directions kept (at most params->restart, then the true residual is recomputed and the
+ * directions dropped), alpha_k = <p_k, rho_k> / <p_k, N p_k> (flexible CG in Notay's form). It is
+ * run as the loop of grid_mg_solve with z_k = M(D^+ r) in place of K(r): w = D z made orthogonal
+ * to the kept w_j is D p_k, and alpha = <w, r> / |w|^2. Per iteration two cycles and three
+ * applications of D or D^+. Parameters, workspace (grid_mg_workspace_bytes), stats, stopping rule
+ * |b - D x| <= tol |b| and return codes as grid_mg_solve. Synchronous.
+ */
+int grid_mg_pcg(const void *U, const void *vecs, const void *A, const void *b, void *x, const grid_geom *geom,
+                const grid_op *op, const grid_mg_params *params, void *workspace, size_t ws_bytes,
+                grid_cg_stats *stats, void *stream);
+
 /* grid_last_error -- message of the calling thread's last failed call ("" if none). */
 const char *grid_last_error(void);
 

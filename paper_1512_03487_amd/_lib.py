@@ -25,7 +25,7 @@ EXPORTS = ("grid_dhop", "grid_mobius", "grid_dwf_mdag_m", "grid_dwf_mdag_m_noall
            "grid_pseudofermion_workspace_bytes", "grid_pseudofermion_action",
            "grid_convert_spinor", "grid_convert_links", "grid_coarse_stencil", "grid_mg_workspace_bytes",
            "grid_mg_basis", "grid_mg_coarse_op", "grid_mg_restrict", "grid_mg_prolong", "grid_mg_solve",
-           "grid_last_error", "grid_version")
+           "grid_mg_pcg", "grid_last_error", "grid_version")
 
 
 class GridGeom(ctypes.Structure):
@@ -147,6 +147,8 @@ def load():
     lib.grid_mg_solve.argtypes = [P, P, P, P, P, G, ctypes.POINTER(GridOp), MP, P, ctypes.c_size_t,
                                   ctypes.POINTER(GridCgStats), P]
     lib.grid_mg_solve.restype = I
+    lib.grid_mg_pcg.argtypes = lib.grid_mg_solve.argtypes
+    lib.grid_mg_pcg.restype = I
     lib.grid_last_error.argtypes = []
     lib.grid_last_error.restype = ctypes.c_char_p
     lib.grid_version.argtypes = []

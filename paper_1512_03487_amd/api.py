@@ -694,14 +694,13 @@ def mg_prolong(vecs, vc, block):
     return psi
 
 
-def mg_solve(U, vecs, A, b, mass, x0=None, workspace=None, raise_on_fail=True, **params):
-    """D x = b by multigrid-preconditioned flexible GCR. Returns (x, stats)."""
+def _mg_solve_call(fn, U, vecs, A, b, mass, x0, workspace, raise_on_fail, params):
     nvec = int(vecs.shape[0])
     p = mg_params(nvec=nvec, **params)
     _check_vecs(vecs, U)
     _check_coarse_op(A, U, p.block, 2 * nvec)
     if spinor_prec(b) != GRID_F64:
-        raise TypeError("mg_solve takes a complex128 b")
+        raise TypeError("the multigrid solvers take a complex128 b")
     _check_links(U, b)
     if x0 is not None:
         _check_like(x0, b, "x0", "b")
@@ -709,14 +708,24 @@ def mg_solve(U, vecs, A, b, mass, x0=None, workspace=None, raise_on_fail=True, *
     x = torch.zeros_like(b) if x0 is None else x0.clone()
     op = make_op("wilson", False, mass)
     st = GridCgStats()
-    rc = load().grid_mg_solve(_ptr(U), _ptr(vecs), _ptr(A), _ptr(b), _ptr(x), ctypes.byref(g), ctypes.byref(op),
-                              ctypes.byref(p), _ptr(workspace), ctypes.c_size_t(workspace.numel()), ctypes.byref(st),
-                              _stream(b.device))
+    rc = getattr(load(), fn)(_ptr(U), _ptr(vecs), _ptr(A), _ptr(b), _ptr(x), ctypes.byref(g), ctypes.byref(op),
+                             ctypes.byref(p), _ptr(workspace), ctypes.c_size_t(workspace.numel()), ctypes.byref(st),
+                             _stream(b.device))
     stats = {"iterations": st.iterations, "restarts": st.reliable_updates, "converged": bool(st.converged),
              "true_residual": st.true_residual, "seconds": st.seconds, "status": rc}
     if rc != 0 and raise_on_fail:
         check(rc)
     return x, stats
+
+
+def mg_solve(U, vecs, A, b, mass, x0=None, workspace=None, raise_on_fail=True, **params):
+    """D x = b by multigrid-preconditioned flexible GCR. Returns (x, stats)."""
+    return _mg_solve_call("grid_mg_solve", U, vecs, A, b, mass, x0, workspace, raise_on_fail, params)
+
+
+def mg_pcg(U, vecs, A, b, mass, x0=None, workspace=None, raise_on_fail=True, **params):
+    """D x = b by multigrid-preconditioned flexible CG on the normal equations. Returns (x, stats)."""
+    return _mg_solve_call("grid_mg_pcg", U, vecs, A, b, mass, x0, workspace, raise_on_fail, params)
 
 
 def mg_workspace_bytes(U, **params) -> int:

@@ -819,9 +819,10 @@ int grid_mg_prolong(const void *vecs, const void *vc, void *psi, const grid_geom
     return ok();
 }
 
-int grid_mg_solve(const void *U, const void *vecs, const void *A, const void *b, void *x, const grid_geom *geom,
-                  const grid_op *op, const grid_mg_params *params, void *workspace, size_t ws_bytes,
-                  grid_cg_stats *stats, void *stream) {
+static int mg_solve_entry(const char *name, const char *method, bool pcg, const void *U, const void *vecs,
+                          const void *A, const void *b, void *x, const grid_geom *geom, const grid_op *op,
+                          const grid_mg_params *params, void *workspace, size_t ws_bytes, grid_cg_stats *stats,
+                          void *stream) {
     GeomDev g;
     TRY(check_geom(geom, &g));
     if (!op || !stats) return fail(GRID_EINVAL, "op and stats must not be NULL");
@@ -838,13 +839,28 @@ int grid_mg_solve(const void *U, const void *vecs, const void *A, const void *b,
     memset(stats, 0, sizeof(*stats));
     int status = GRID_OK;
     hipError_t e = run_mg_solve(U, vecs, A, b, x, g, op->mass, *params, workspace, static_cast<hipStream_t>(stream),
-                                stats, &status);
-    if (e != hipSuccess) return hip_fail(e, "grid_mg_solve");
+                                stats, &status, pcg);
+    if (e != hipSuccess) return hip_fail(e, name);
     if (status == GRID_ENOCONV)
-        return fail(GRID_ENOCONV, "GCR stopped at relative residual %.3e after %d iterations", stats->true_residual,
-                    stats->iterations);
-    if (status == GRID_EBREAKDOWN) return fail(GRID_EBREAKDOWN, "GCR breakdown after %d iterations", stats->iterations);
+        return fail(GRID_ENOCONV, "%s stopped at relative residual %.3e after %d iterations", method,
+                    stats->true_residual, stats->iterations);
+    if (status == GRID_EBREAKDOWN)
+        return fail(GRID_EBREAKDOWN, "%s breakdown after %d iterations", method, stats->iterations);
     return ok();
+}
+
+int grid_mg_solve(const void *U, const void *vecs, const void *A, const void *b, void *x, const grid_geom *geom,
+                  const grid_op *op, const grid_mg_params *params, void *workspace, size_t ws_bytes,
+                  grid_cg_stats *stats, void *stream) {
+    return mg_solve_entry("grid_mg_solve", "GCR", false, U, vecs, A, b, x, geom, op, params, workspace, ws_bytes, stats,
+                          stream);
+}
+
+int grid_mg_pcg(const void *U, const void *vecs, const void *A, const void *b, void *x, const grid_geom *geom,
+                const grid_op *op, const grid_mg_params *params, void *workspace, size_t ws_bytes,
+                grid_cg_stats *stats, void *stream) {
+    return mg_solve_entry("grid_mg_pcg", "pCG", true, U, vecs, A, b, x, geom, op, params, workspace, ws_bytes, stats,
+                          stream);
 }
 
 }  // extern "C"

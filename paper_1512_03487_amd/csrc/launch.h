@@ -194,6 +194,6 @@ hipError_t launch_mg_prolong(const void *vecs, const void *vc, void *psi, const 
                              hipStream_t st);
 hipError_t run_mg_solve(const void *U, const void *vecs, const void *A, const void *b, void *x, const GeomDev &g,
                         double mass, const grid_mg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats,
-                        int *status);
+                        int *status, bool pcg);
 
 }  // namespace gridmi

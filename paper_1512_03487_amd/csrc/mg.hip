@@ -524,6 +524,15 @@ k_zsub(double2 *__restrict__ out, const double2 *__restrict__ a, const double2 *
         out[i] = {a[i].x - b[i].x, a[i].y - b[i].y};
 }
 
+// out = gamma5 v on a fine field (n = 12 V complex elements; spins 2, 3 change sign); out may be v
+__global__ void __launch_bounds__(kMgThreads) k_zg5(double2 *out, const double2 *v, long n) {
+    for (long i = static_cast<long>(blockIdx.x) * kMgThreads + threadIdx.x; i < n;
+         i += static_cast<long>(gridDim.x) * kMgThreads) {
+        const double sg = (i % 12) >= 6 ? -1.0 : 1.0;
+        out[i] = {sg * v[i].x, sg * v[i].y};
+    }
+}
+
 // y *= s, y2 *= s
 __global__ void __launch_bounds__(kMgThreads)
 k_zscale2(double2 *__restrict__ y, double2 *__restrict__ y2, double s, long n) {
@@ -627,7 +636,7 @@ int vec_blocks(long n) {
 // Workspace layout of the solver and the setup (bytes, 256-aligned regions).
 struct MgLayout {
     size_t fv, cv;          // one fine / coarse vector
-    size_t r, s, t, Z, W;   // fine (Z, W: restart vectors each)
+    size_t r, s, t, u, Z, W;   // fine (Z, W: restart vectors each; u: the pCG preconditioner's)
     size_t rc, ec, cr, cp, cq, cq1;
     size_t part, scal;      // 2 x kMgParts double2, 16 double2
     size_t z32 = 0, s32 = 0, t32 = 0, r32 = 0, u32 = 0, v32 = 0, a32 = 0;   // FP32 cycle (cycle_prec GRID_F32)
@@ -646,6 +655,7 @@ MgLayout mg_layout(const MgDims &m, int restart, int setup_prec, int cycle_prec)
     L.r = o; o += L.fv;
     L.s = o; o += L.fv;
     L.t = o; o += L.fv;
+    L.u = o; o += L.fv;
     L.Z = o; o += L.fv * restart;
     L.W = o; o += L.fv * restart;
     L.rc = o; o += L.cv;
@@ -737,7 +747,7 @@ struct MgCtx {
         return hipGetLastError();
     }
 
-    hipError_t D(const void *U, const void *in, void *out) const {
+    hipError_t D(const void *U, const void *in, void *out, int dag = 0) const {
         DhopArgs a;
         a.U = U;
         a.psi = in;
@@ -748,7 +758,7 @@ struct MgCtx {
         a.prec = GRID_F64;
         a.link_fmt = GRID_L18;
         a.kind = GRID_WILSON;
-        a.dag = 0;
+        a.dag = dag;
         a.diag = 4.0 + mass;
         a.mf = 0.0;
         a.stream = st;
@@ -805,6 +815,10 @@ struct MgCtx {
     }
     hipError_t sub(double2 *out, const double2 *a, const double2 *b, long n) const {
         hipLaunchKernelGGL(k_zsub, dim3(vec_blocks(n)), dim3(kMgThreads), 0, st, out, a, b, n);
+        return hipGetLastError();
+    }
+    hipError_t g5(double2 *out, const double2 *v) const {
+        hipLaunchKernelGGL(k_zg5, dim3(vec_blocks(nf)), dim3(kMgThreads), 0, st, out, v, nf);
         return hipGetLastError();
     }
 };
@@ -1036,9 +1050,14 @@ static hipError_t mg_cycle(const MgCtx &c, const void *U, const double2 *V, cons
     return hipSuccess;
 }
 
+// Flexible GCR on D x = b with z_k = K(r) (pcg = false), or multigrid pCG: flexible CG on the normal
+// equations D^dagger D x = D^dagger b with z_k = M(rho) = K(G5 K(G5 rho)), rho = D^dagger r. In the
+// pCG, N-conjugating z_k against the kept directions p_j (N = D^dagger D) is orthogonalising D z_k
+// against the D p_j, and alpha = <p, rho> / <p, N p> = <D p, r> / |D p|^2, so both run the same loop
+// over (z_j, w_j = D z_j) with r = b - D x, and differ in the preconditioned vector only.
 hipError_t run_mg_solve(const void *U, const void *vecs, const void *A, const void *b, void *x, const GeomDev &g,
                         double mass, const grid_mg_params &p, void *ws, hipStream_t st, grid_cg_stats *stats,
-                        int *status) {
+                        int *status, bool pcg) {
     const auto t0 = std::chrono::steady_clock::now();
     MgCtx c;
     struct Release {   // the recorded coarse solve, after the caller's stream has drained
@@ -1092,7 +1111,17 @@ hipError_t run_mg_solve(const void *U, const void *vecs, const void *A, const vo
     int it = 0, k = 0;
     while (rn > p.tol * bn && it < p.maxiter) {
         double2 *zk = Z(k), *wk = W(k);
-        MGCHK(mg_cycle(c, U, V, A, r, zk));
+        if (pcg) {
+            double2 *u = c.f(c.L.u);
+            MGCHK(c.D(U, r, u, 1));   // rho = D^dagger r
+            MGCHK(c.g5(u, u));
+            MGCHK(mg_cycle(c, U, V, A, u, zk));
+            MGCHK(c.g5(zk, zk));
+            MGCHK(mg_cycle(c, U, V, A, zk, u));
+            MGCHK(hipMemcpyAsync(zk, u, static_cast<size_t>(nf) * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        } else {
+            MGCHK(mg_cycle(c, U, V, A, r, zk));
+        }
         MGCHK(c.D(U, zk, wk));
         // modified Gram-Schmidt, beta_j = <w_j, w> on the device: w -= beta_j w_j, z -= beta_j z_j
         for (int j = 0; j < k; ++j) {

@@ -272,6 +272,13 @@ def test_multigrid_validation(lib):
     assert lib.grid_mg_solve(P(A), P(A + 2**30), P(A + 2**31), P(A + 3 * 2**30), P(A + 2**32), ctypes.byref(g),
                              ctypes.byref(op), ctypes.byref(ok), P(A + 2**33), need - 1, ctypes.byref(st), None) == _lib.GRID_EINVAL
     assert "workspace" in _lib.last_error()
+    # the pCG entry shares the checks
+    for kind, nb, code in ((dwf, need, _lib.GRID_EINVAL), (op, need - 1, _lib.GRID_EINVAL)):
+        assert lib.grid_mg_pcg(P(A), P(A + 2**30), P(A + 2**31), P(A + 3 * 2**30), P(A + 2**32), ctypes.byref(g),
+                               ctypes.byref(kind), ctypes.byref(ok), P(A + 2**33), nb, ctypes.byref(st), None) == code
+    assert lib.grid_mg_pcg(P(A), P(A + 2**30), P(A + 2**31), P(A + 3 * 2**30), P(A + 3 * 2**30 + 64), ctypes.byref(g),
+                           ctypes.byref(op), ctypes.byref(ok), P(A + 2**33), need, ctypes.byref(st), None) == _lib.GRID_EINVAL
+    assert "x overlaps" in _lib.last_error()
     assert lib.grid_mg_basis(P(A), P(A + 2**30), ctypes.byref(geom(Ls=4)), ctypes.byref(op), ctypes.byref(ok),
                              P(A + 2**33), need, None) == _lib.GRID_ESHAPE
     cd = (ctypes.c_int * 4)(2, 2, 2, 2)

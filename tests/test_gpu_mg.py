@@ -1,6 +1,6 @@
 """GPU parity of the coarse stencil and the multigrid entry points (grid_coarse_stencil,
-grid_mg_basis, grid_mg_restrict, grid_mg_prolong, grid_mg_coarse_op, grid_mg_solve) against the
-FP64 oracle (oracle.mg), through the C ABI.
+grid_mg_basis, grid_mg_restrict, grid_mg_prolong, grid_mg_coarse_op, grid_mg_solve, grid_mg_pcg)
+against the FP64 oracle (oracle.mg), through the C ABI.
 
 Tolerances: the linear maps (stencil, R, P, Galerkin operator, Gram-Schmidt of a given set)
 1e-13 relative (FP64, summation order only); the setup's near-null vectors 1e-9 (sixteen CG
@@ -222,3 +222,44 @@ def test_recorded_coarse_solve_matches_direct_launches(gpu):
         x1, s1 = gm.mg_solve(Ud, qd, Ad, b, m, graph=True, **kw)
         assert s0["iterations"] == s1["iterations"] and s0["true_residual"] == s1["true_residual"]
         assert bool((x0 == x1).all())
+
+
+def test_pcg_iterates_match_the_oracle(gpu):
+    """Three multigrid pCG steps with a restart after two (no convergence): the iterate equals the
+    oracle's flexible CG, written in CG form (N-conjugate directions, rho updated by N p)."""
+    from tests.gpu_util import dev, host
+    gm = _gm()
+    dims, block, nvec, m = (4, 4, 4, 4), (2, 2, 2, 2), 6, 0.2
+    U, q, A = _setup(dims, block, nvec, m)
+    b = F.spinor_field(dims, seed=3)
+    x, st = gm.mg_pcg(dev(U), dev(q), dev(np.ascontiguousarray(np.swapaxes(A, -1, -2))), dev(b), m, maxiter=3,
+                      block=block, restart=2, coarse_iters=30, coarse_tol=0.05, smooth_iters=2, raise_on_fail=False)
+    xo, ito, _ = mg.fcg(U, q, A, b, m, block, tol=1e-10, maxiter=3, restart=2, coarse_iters=30, coarse_tol=0.05,
+                        smooth_iters=2)
+    assert st["iterations"] == ito == 3 and st["restarts"] == 1
+    assert _rel(host(x), xo) <= 1e-9
+
+
+@pytest.mark.parametrize("dims,block,nvec,cycle_prec", [((4, 4, 4, 4), (2, 2, 2, 2), 6, "f64"),
+                                                        ((8, 4, 4, 4), (2, 2, 2, 2), 4, "f64"),
+                                                        ((8, 4, 4, 4), (2, 2, 2, 2), 4, "f32")])
+def test_mg_pcg_solve(gpu, dims, block, nvec, cycle_prec):
+    """Multigrid pCG solves D x = b to 1e-10 (checked by the oracle) in as many iterations as the
+    oracle's flexible CG (within one; within three with the FP32 cycle, a slightly different
+    preconditioner), and its graph-recorded coarse solves give the same x."""
+    from tests.gpu_util import dev, host
+    gm = _gm()
+    m = 0.2
+    U, q, A = _setup(dims, block, nvec, m)
+    b = F.spinor_field(dims, seed=3)
+    Ud, qd = dev(U), dev(q)
+    Ad = gm.mg_coarse_op(Ud, qd, m, block=block)
+    kw = dict(restart=8, coarse_iters=40, coarse_tol=0.05, smooth_iters=2, tol=1e-10)
+    x, st = gm.mg_pcg(Ud, qd, Ad, dev(b), m, block=block, graph=False, cycle_prec=cycle_prec, **kw)
+    assert st["converged"]
+    res = float(np.linalg.norm(b - O.wilson(U, host(x), m)) / np.linalg.norm(b))
+    assert res <= 1.05e-10 and abs(res - st["true_residual"]) <= 1e-3 * res
+    _, ito, _ = mg.fcg(U, q, A, b, m, block, **kw)
+    assert abs(st["iterations"] - ito) <= (1 if cycle_prec == "f64" else 3), (st["iterations"], ito)
+    x1, s1 = gm.mg_pcg(Ud, qd, Ad, dev(b), m, block=block, graph=True, cycle_prec=cycle_prec, **kw)
+    assert s1["iterations"] == st["iterations"] and bool((x1 == x).all())
