@@ -80,3 +80,22 @@ def test_mobius_cg(gpu, sloppy, fmt):
     assert st["converged"]
     r = rel(MB.normal(U, host(x), 1.8, 0.1, B5, C5), b)
     assert r <= 1.05e-10 and abs(r - st["true_residual"]) <= 1e-3 * r + 1e-16
+
+
+@pytest.mark.parametrize("prec,fmt", [("f32", "L18"), ("f16s", "L12"), ("f16s", "L18"), ("f64", "L18")])
+def test_mobius_16_4_ls16_bench_size(gpu, prec, fmt):
+    """16^4 x 16, the size the benchmark times (the fused column walk over several time slices per
+    thread in FP32 / FP16 storage, the two-pass form in FP64): M and M^dagger over the whole field,
+    relative L2 and the worst per-site component error."""
+    from tests.gpu_util import as_prec, cached, host, rel
+    from tests.test_gpu_dhop import SITE_TOL, _site_err
+    gm = _gm()
+    dims, Ls = (16, 16, 16, 16), 16
+    U = cached("gauge", dims, 1, kind="haar")
+    psi = cached("spinor", dims, 2, Ls=Ls)
+    Uk, pk, Ur, pr = as_prec(U, psi, prec, fmt)
+    for dag in (False, True):
+        got = host(gm.mobius(Uk, pk, 1.8, 0.01, B5, C5, dag=dag))
+        ref = MB.mobius(Ur, pr, 1.8, 0.01, B5, C5, dag)
+        assert rel(got, ref) <= TOL[prec], (prec, fmt, dag)
+        assert _site_err(got.reshape(-1, 4, 3), ref.reshape(-1, 4, 3)) <= SITE_TOL[prec], (prec, fmt, dag)
