@@ -186,6 +186,31 @@ def nested_leapfrog(U, P, beta: float, eps: float, n: int, fermion, n_inner: int
     return U, P
 
 
+def _inner_leapfrog(U, P, beta: float, tau: float, n_inner: int):
+    """n_inner leapfrog steps of size tau / n_inner with the gauge force alone."""
+    h = tau / n_inner
+    for _ in range(n_inner):
+        P = P - 0.5 * h * gauge_md_force(U, beta)
+        U = np.einsum("...ij,...jk->...ik", su3_exp(h * P), U)
+        P = P - 0.5 * h * gauge_md_force(U, beta)
+    return U, P
+
+
+def nested_omelyan(U, P, beta: float, eps: float, n: int, fermion, n_inner: int):
+    """Two time scales with an Omelyan outer step: per outer step P -= l e f_F(U); the gauge system
+    integrated over e/2 by n_inner leapfrog steps; P -= (1 - 2 l) e f_F(U); again e/2 of gauge
+    integration; P -= l e f_F(U) (l = OMELYAN_LAMBDA)."""
+    lam = OMELYAN_LAMBDA
+    U, P = np.array(U, dtype=np.complex128), np.array(P, dtype=np.complex128)
+    for _ in range(n):
+        P = P - lam * eps * fermion_md_force(U, fermion)
+        U, P = _inner_leapfrog(U, P, beta, 0.5 * eps, n_inner)
+        P = P - (1.0 - 2.0 * lam) * eps * fermion_md_force(U, fermion)
+        U, P = _inner_leapfrog(U, P, beta, 0.5 * eps, n_inner)
+        P = P - lam * eps * fermion_md_force(U, fermion)
+    return U, P
+
+
 def leapfrog(U, P, beta: float, eps: float, n: int, fermion=None):
     U, P = np.array(U, dtype=np.complex128), np.array(P, dtype=np.complex128)
     P = P - 0.5 * eps * md_force(U, beta, fermion)

@@ -195,3 +195,27 @@ def test_mobius_fermion_force():
     # the Moebius force differs from the Shamir one at these coefficients
     Fm = hmc.fermion_force(U0, ferm)[1]
     assert np.max(np.abs(Fm - F2)) > 1e-2 * np.max(np.abs(F2))
+
+
+def test_nested_omelyan():
+    """Two time scales with Omelyan outer steps: without a fermion it is the gauge leapfrog with
+    2 n n_inner steps of e / (2 n_inner); with the gauge force switched off (beta = 0) it is the
+    Omelyan integrator of the fermion force; reversible and second order."""
+    dims, beta, tau = (2, 2, 2, 4), 5.5, 0.4
+    U0, ferm = _fermion(dims)
+    P0 = F.random_su3_algebra(dims, seed=7)
+    Ua, Pa = hmc.nested_omelyan(U0, P0, beta, 0.1, 2, None, 3)
+    Ub, Pb = hmc.leapfrog(U0, P0, beta, 0.1 / 6, 12)
+    assert np.max(np.abs(Ua - Ub)) < 1e-12 and np.max(np.abs(Pa - Pb)) < 1e-11
+    Ua, Pa = hmc.nested_omelyan(U0, P0, 0.0, 0.1, 2, ferm, 3)
+    Ub, Pb = hmc.omelyan(U0, P0, 0.0, 0.1, 2, ferm)
+    assert np.max(np.abs(Ua - Ub)) < 1e-12 and np.max(np.abs(Pa - Pb)) < 1e-11
+    U1, P1 = hmc.nested_omelyan(U0, P0, beta, 0.1, 2, ferm, 3)
+    U2, P2 = hmc.nested_omelyan(U1, -P1, beta, 0.1, 2, ferm, 3)
+    assert np.max(np.abs(U2 - U0)) < 1e-10 and np.max(np.abs(P2 + P0)) < 1e-10
+    H0 = hmc.hamiltonian(U0, P0, beta, ferm)
+    dH = []
+    for n in (4, 8):
+        Un, Pn = hmc.nested_omelyan(U0, P0, beta, tau / n, n, ferm, 2)
+        dH.append(abs(hmc.hamiltonian(Un, Pn, beta, ferm) - H0))
+    assert 3.0 < dH[0] / dH[1] < 5.0, dH
