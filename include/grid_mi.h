@@ -289,15 +289,18 @@ int grid_solve_eo(const void *U, const void *b, void *x, const grid_geom *geom, 
 typedef struct {
     double beta;            /* Wilson gauge coupling                                            */
     double eps;             /* leapfrog step size                                               */
-    int n_steps;            /* leapfrog steps                                                   */
+    int n_steps;            /* integrator steps (0: U and P unchanged)                          */
     grid_op fermion;        /* GRID_WILSON, GRID_DWF or GRID_MOBIUS pseudofermion operator
                                (phi != NULL)                                                     */
     grid_cg_params cg;      /* the solves inside every fermion-force evaluation                 */
     int integrator;         /* GRID_LEAPFROG, GRID_OMELYAN or GRID_FORCE_GRADIENT               */
-    int n_inner;            /* > 1: two time scales (needs GRID_LEAPFROG): per step
-                               P -= eps/2 F_F/2; n_inner leapfrog steps of eps / n_inner with the
-                               gauge force alone; P -= eps/2 F_F/2 (Sexton and Weingarten);
-                               0 or 1: the integrator with the total force                       */
+    int n_inner;            /* > 1: two time scales (Sexton and Weingarten) with GRID_LEAPFROG
+                               or GRID_OMELYAN outer steps: the fermion force kicks as in that
+                               integrator (leapfrog: P -= eps/2 F_F/2, gauge integration over eps,
+                               P -= eps/2 F_F/2; Omelyan: P -= l eps F_F/2, eps/2, P -= (1 - 2 l)
+                               eps F_F/2, eps/2, P -= l eps F_F/2), each gauge integration over
+                               tau being n_inner leapfrog steps of tau / n_inner with the gauge
+                               force alone; 0 or 1: the integrator with the total force           */
 } grid_md_params;
 
 enum grid_integrator { GRID_LEAPFROG = 0, GRID_OMELYAN = 1, GRID_FORCE_GRADIENT = 2 };

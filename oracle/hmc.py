@@ -213,6 +213,8 @@ def nested_omelyan(U, P, beta: float, eps: float, n: int, fermion, n_inner: int)
 
 def leapfrog(U, P, beta: float, eps: float, n: int, fermion=None):
     U, P = np.array(U, dtype=np.complex128), np.array(P, dtype=np.complex128)
+    if n == 0:   # zero steps integrate over zero time
+        return U, P
     P = P - 0.5 * eps * md_force(U, beta, fermion)
     for i in range(n):
         U = np.einsum("...ij,...jk->...ik", su3_exp(eps * P), U)

@@ -372,20 +372,20 @@ hipError_t run_md_leapfrog(void *U, void *P, const void *phi, const GeomDev &g, 
     r.st = st;
     r.stats = stats;
     memset(stats, 0, sizeof(*stats));
+    if (p.n_steps == 0) return hipSuccess;   // zero steps integrate over zero time
     const long nd = static_cast<long>(g.vol) * 4 * 18;
     if (phi) HMCCHK(hipMemsetAsync(r.ws + r.L.X, 0, static_cast<size_t>(g.n5) * 192, st));
     if (p.n_inner > 1) {
-        // two time scales (leapfrog outer steps): P -= e/2 f_F(U); n_inner leapfrog steps of
-        // h = e / n_inner with the gauge force; P -= e/2 f_F(U). Consecutive fermion kicks and,
-        // inside an outer step, consecutive gauge kicks are merged: n + 1 fermion and
-        // n (n_inner + 1) gauge force evaluations.
+        // Two time scales: the fermion kicks of a leapfrog (P -= e/2 f_F; gauge integration over e;
+        // P -= e/2 f_F) or Omelyan (P -= l e f_F; e/2; P -= (1 - 2 l) e f_F; e/2; P -= l e f_F)
+        // outer step, each gauge integration over tau being n_inner leapfrog steps of
+        // h = tau / n_inner with the gauge force alone. Consecutive fermion kicks (across outer
+        // steps) and consecutive gauge kicks (inside one integration) act at the same U and are
+        // merged.
+        constexpr double lam = 0.1931833275037836;
         const long nl = static_cast<long>(g.vol) * 4;
-        const double h = p.eps / p.n_inner;
-        if (phi) {
-            HMCCHK(fermion_force(r));
-            HMCCHK(daxpy(P, r.ws + r.L.Ff, -0.25 * p.eps, nd, st));
-        }
-        for (int i = 0; i < p.n_steps; ++i) {
+        auto gauge_integrate = [&](double tau) -> hipError_t {
+            const double h = tau / p.n_inner;
             HMCCHK(launch_gauge_force(U, r.ws + r.L.F, g, p.beta, 1.0, 0, st));
             HMCCHK(daxpy(P, r.ws + r.L.F, -0.25 * h, nd, st));
             for (int j = 0; j < p.n_inner; ++j) {
@@ -393,9 +393,25 @@ hipError_t run_md_leapfrog(void *U, void *P, const void *phi, const GeomDev &g, 
                 HMCCHK(launch_gauge_force(U, r.ws + r.L.F, g, p.beta, 1.0, 0, st));
                 HMCCHK(daxpy(P, r.ws + r.L.F, (j == p.n_inner - 1 ? -0.25 : -0.5) * h, nd, st));
             }
-            if (phi) {
-                HMCCHK(fermion_force(r));
-                HMCCHK(daxpy(P, r.ws + r.L.Ff, (i == p.n_steps - 1 ? -0.25 : -0.5) * p.eps, nd, st));
+            return hipSuccess;
+        };
+        auto fermion_kick = [&](double c) -> hipError_t {   // P -= c e F_F / 2
+            if (!phi) return hipSuccess;
+            HMCCHK(fermion_force(r));
+            return daxpy(P, r.ws + r.L.Ff, -0.5 * c * p.eps, nd, st);
+        };
+        const bool omelyan = p.integrator == GRID_OMELYAN;
+        HMCCHK(fermion_kick(omelyan ? lam : 0.5));
+        for (int i = 0; i < p.n_steps; ++i) {
+            const bool last = i == p.n_steps - 1;
+            if (omelyan) {
+                HMCCHK(gauge_integrate(0.5 * p.eps));
+                HMCCHK(fermion_kick(1.0 - 2.0 * lam));
+                HMCCHK(gauge_integrate(0.5 * p.eps));
+                HMCCHK(fermion_kick(last ? lam : 2.0 * lam));
+            } else {
+                HMCCHK(gauge_integrate(p.eps));
+                HMCCHK(fermion_kick(last ? 0.5 : 1.0));
             }
         }
         HMCCHK(hipStreamSynchronize(st));

@@ -187,10 +187,12 @@ def test_force_gradient_matches_oracle(gpu, with_fermion):
     assert rel(host(Ud), U) <= 10 * tol and rel(host(Pd), -P) <= 10 * tol
 
 
+@pytest.mark.parametrize("outer", ["leapfrog", "omelyan"])
 @pytest.mark.parametrize("with_fermion", [False, True])
-def test_nested_time_scales_match_oracle(gpu, with_fermion):
-    """Two time scales (n_inner = 3) equal the oracle's nested leapfrog, with n + 1 fermion
-    solves; n_inner > 1 with another integrator is rejected."""
+def test_nested_time_scales_match_oracle(gpu, with_fermion, outer):
+    """Two time scales (n_inner = 3) with leapfrog or Omelyan outer steps equal the oracle's nested
+    integrators, with n + 1 (leapfrog) or 2 n + 1 (Omelyan) fermion solves; force-gradient outer
+    steps are rejected; zero steps leave U and P unchanged."""
     from tests.gpu_util import dev, host, rel
     gm = _gm()
     dims, Ls, beta = (2, 2, 2, 4), 4, 5.5
@@ -198,14 +200,20 @@ def test_nested_time_scales_match_oracle(gpu, with_fermion):
     P = F.random_su3_algebra(dims, seed=7)
     phi = F.spinor_field(dims, seed=5, Ls=Ls) if with_fermion else None
     Ud, Pd = dev(U), dev(P)
-    st = gm.md_leapfrog(Ud, Pd, beta, 0.1, 3, dev(phi) if with_fermion else None, tol=1e-12, n_inner=3, **DWF)
+    st = gm.md_leapfrog(Ud, Pd, beta, 0.1, 3, dev(phi) if with_fermion else None, tol=1e-12, n_inner=3,
+                        integrator=outer, **DWF)
     ferm = (O.Op.dwf(Ls, 1.8, 0.2), phi) if with_fermion else None
-    Ur, Pr = OH.nested_leapfrog(U, P, beta, 0.1, 3, ferm, 3)
+    nested = OH.nested_leapfrog if outer == "leapfrog" else OH.nested_omelyan
+    Ur, Pr = nested(U, P, beta, 0.1, 3, ferm, 3)
     tol = 1e-12 if not with_fermion else 1e-8
     assert rel(host(Ud), Ur) <= tol and rel(host(Pd), Pr) <= tol
-    assert st["solves"] == (4 if with_fermion else 0)
+    assert st["solves"] == ((4 if outer == "leapfrog" else 7) if with_fermion else 0)
     with pytest.raises(Exception):
-        gm.md_leapfrog(dev(U), dev(P), beta, 0.1, 1, None, n_inner=2, integrator="omelyan", **DWF)
+        gm.md_leapfrog(dev(U), dev(P), beta, 0.1, 1, None, n_inner=2, integrator="force_gradient", **DWF)
+    U0, P0 = dev(U), dev(P)
+    st = gm.md_leapfrog(U0, P0, beta, 0.1, 0, dev(phi) if with_fermion else None, tol=1e-12, n_inner=3,
+                        integrator=outer, **DWF)
+    assert bool((U0 == dev(U)).all()) and bool((P0 == dev(P)).all()) and st["solves"] == 0
 
 
 @pytest.mark.parametrize("integrator,n,solves", [("leapfrog", 4, 5), ("force_gradient", 2, 7)])
