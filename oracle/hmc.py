@@ -211,6 +211,22 @@ def nested_omelyan(U, P, beta: float, eps: float, n: int, fermion, n_inner: int)
     return U, P
 
 
+def nested_force_gradient(U, P, beta: float, eps: float, n: int, fermion, n_inner: int):
+    """Two time scales with a force-gradient outer step: per outer step P -= e/6 f_F(U); the gauge
+    system integrated over e/2 by n_inner leapfrog steps; P -= 2e/3 f_F(U') with the displaced
+    links U' = exp(-(e^2/24) f_F(U)) U (the outer force's gradient term, as in force_gradient());
+    again e/2 of gauge integration; P -= e/6 f_F(U)."""
+    U, P = np.array(U, dtype=np.complex128), np.array(P, dtype=np.complex128)
+    for _ in range(n):
+        P = P - (eps / 6.0) * fermion_md_force(U, fermion)
+        U, P = _inner_leapfrog(U, P, beta, 0.5 * eps, n_inner)
+        Ud = np.einsum("...ij,...jk->...ik", su3_exp(-(eps * eps / 24.0) * fermion_md_force(U, fermion)), U)
+        P = P - (2.0 * eps / 3.0) * fermion_md_force(Ud, fermion)
+        U, P = _inner_leapfrog(U, P, beta, 0.5 * eps, n_inner)
+        P = P - (eps / 6.0) * fermion_md_force(U, fermion)
+    return U, P
+
+
 def leapfrog(U, P, beta: float, eps: float, n: int, fermion=None):
     U, P = np.array(U, dtype=np.complex128), np.array(P, dtype=np.complex128)
     if n == 0:   # zero steps integrate over zero time

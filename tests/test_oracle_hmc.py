@@ -219,3 +219,21 @@ def test_nested_omelyan():
         Un, Pn = hmc.nested_omelyan(U0, P0, beta, tau / n, n, ferm, 2)
         dH.append(abs(hmc.hamiltonian(Un, Pn, beta, ferm) - H0))
     assert 3.0 < dH[0] / dH[1] < 5.0, dH
+
+
+def test_nested_force_gradient():
+    """Two time scales with force-gradient outer steps: without a fermion it is the gauge leapfrog
+    with 2 n n_inner steps of e / (2 n_inner); with the gauge force switched off (beta = 0) it is
+    the force-gradient integrator of the fermion force; reversible."""
+    dims, beta = (2, 2, 2, 4), 5.5
+    U0, ferm = _fermion(dims)
+    P0 = F.random_su3_algebra(dims, seed=7)
+    Ua, Pa = hmc.nested_force_gradient(U0, P0, beta, 0.1, 2, None, 3)
+    Ub, Pb = hmc.leapfrog(U0, P0, beta, 0.1 / 6, 12)
+    assert np.max(np.abs(Ua - Ub)) < 1e-12 and np.max(np.abs(Pa - Pb)) < 1e-11
+    Ua, Pa = hmc.nested_force_gradient(U0, P0, 0.0, 0.1, 2, ferm, 3)
+    Ub, Pb = hmc.force_gradient(U0, P0, 0.0, 0.1, 2, ferm)
+    assert np.max(np.abs(Ua - Ub)) < 1e-12 and np.max(np.abs(Pa - Pb)) < 1e-11
+    U1, P1 = hmc.nested_force_gradient(U0, P0, beta, 0.1, 2, ferm, 3)
+    U2, P2 = hmc.nested_force_gradient(U1, -P1, beta, 0.1, 2, ferm, 3)
+    assert np.max(np.abs(U2 - U0)) < 1e-10 and np.max(np.abs(P2 + P0)) < 1e-10
