@@ -294,13 +294,15 @@ typedef struct {
                                (phi != NULL)                                                     */
     grid_cg_params cg;      /* the solves inside every fermion-force evaluation                 */
     int integrator;         /* GRID_LEAPFROG, GRID_OMELYAN or GRID_FORCE_GRADIENT               */
-    int n_inner;            /* > 1: two time scales (Sexton and Weingarten) with GRID_LEAPFROG
-                               or GRID_OMELYAN outer steps: the fermion force kicks as in that
-                               integrator (leapfrog: P -= eps/2 F_F/2, gauge integration over eps,
-                               P -= eps/2 F_F/2; Omelyan: P -= l eps F_F/2, eps/2, P -= (1 - 2 l)
-                               eps F_F/2, eps/2, P -= l eps F_F/2), each gauge integration over
-                               tau being n_inner leapfrog steps of tau / n_inner with the gauge
-                               force alone; 0 or 1: the integrator with the total force           */
+    int n_inner;            /* > 1: two time scales (Sexton and Weingarten): the fermion force
+                               kicks as in the outer integrator (leapfrog: P -= eps/2 F_F/2, gauge
+                               integration over eps, P -= eps/2 F_F/2; Omelyan: P -= l eps F_F/2,
+                               eps/2, P -= (1 - 2 l) eps F_F/2, eps/2, P -= l eps F_F/2; force
+                               gradient: P -= eps/6 F_F/2, eps/2, P -= 2 eps/3 F_F(U')/2 with
+                               U' = exp(-(eps^2/24) F_F(U)/2) U, eps/2, P -= eps/6 F_F/2), each
+                               gauge integration over tau being n_inner leapfrog steps of
+                               tau / n_inner with the gauge force alone; 0 or 1: the integrator
+                               with the total force                                              */
 } grid_md_params;
 
 enum grid_integrator { GRID_LEAPFROG = 0, GRID_OMELYAN = 1, GRID_FORCE_GRADIENT = 2 };

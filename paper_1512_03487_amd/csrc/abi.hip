@@ -126,8 +126,6 @@ int check_md(const GeomDev &g, const grid_md_params *p, const void *phi) {
     if (p->integrator != GRID_LEAPFROG && p->integrator != GRID_OMELYAN && p->integrator != GRID_FORCE_GRADIENT)
         return fail(GRID_EINVAL, "unknown integrator %d", p->integrator);
     if (p->n_inner < 0) return fail(GRID_EINVAL, "n_inner = %d is negative", p->n_inner);
-    if (p->n_inner > 1 && p->integrator == GRID_FORCE_GRADIENT)
-        return fail(GRID_EINVAL, "two time scales take leapfrog or Omelyan outer steps (integrator %d)", p->integrator);
     if (phi) {
         if (p->fermion.kind != GRID_WILSON && p->fermion.kind != GRID_DWF && p->fermion.kind != GRID_MOBIUS)
             return fail(GRID_EINVAL, "the fermion force takes GRID_WILSON, GRID_DWF or GRID_MOBIUS (got kind %d)",

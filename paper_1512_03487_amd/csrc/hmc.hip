@@ -377,11 +377,12 @@ hipError_t run_md_leapfrog(void *U, void *P, const void *phi, const GeomDev &g, 
     if (phi) HMCCHK(hipMemsetAsync(r.ws + r.L.X, 0, static_cast<size_t>(g.n5) * 192, st));
     if (p.n_inner > 1) {
         // Two time scales: the fermion kicks of a leapfrog (P -= e/2 f_F; gauge integration over e;
-        // P -= e/2 f_F) or Omelyan (P -= l e f_F; e/2; P -= (1 - 2 l) e f_F; e/2; P -= l e f_F)
-        // outer step, each gauge integration over tau being n_inner leapfrog steps of
-        // h = tau / n_inner with the gauge force alone. Consecutive fermion kicks (across outer
-        // steps) and consecutive gauge kicks (inside one integration) act at the same U and are
-        // merged.
+        // P -= e/2 f_F), Omelyan (P -= l e f_F; e/2; P -= (1 - 2 l) e f_F; e/2; P -= l e f_F) or
+        // force-gradient (P -= e/6 f_F; e/2; P -= 2e/3 f_F(U'); e/2; P -= e/6 f_F, with
+        // U' = exp(-(e^2/24) f_F(U)) U) outer step, each gauge integration over tau being n_inner
+        // leapfrog steps of h = tau / n_inner with the gauge force alone. Consecutive fermion kicks
+        // (across outer steps) and consecutive gauge kicks (inside one integration) act at the same
+        // U and are merged.
         constexpr double lam = 0.1931833275037836;
         const long nl = static_cast<long>(g.vol) * 4;
         auto gauge_integrate = [&](double tau) -> hipError_t {
@@ -400,11 +401,29 @@ hipError_t run_md_leapfrog(void *U, void *P, const void *phi, const GeomDev &g, 
             HMCCHK(fermion_force(r));
             return daxpy(P, r.ws + r.L.Ff, -0.5 * c * p.eps, nd, st);
         };
-        const bool omelyan = p.integrator == GRID_OMELYAN;
-        HMCCHK(fermion_kick(omelyan ? lam : 0.5));
+        // force-gradient outer kick: P -= 2e/3 f_F(U'), U' = exp(-(e^2/24) f_F(U)) U in the Ud copy
+        auto fermion_fg_kick = [&]() -> hipError_t {
+            if (!phi) return hipSuccess;
+            void *Ud = r.ws + r.L.Ud;
+            HMCCHK(fermion_force(r));
+            HMCCHK(hipMemcpyAsync(Ud, U, static_cast<size_t>(nl) * 144, hipMemcpyDeviceToDevice, st));
+            HMCCHK(launch_link_exp(Ud, r.ws + r.L.Ff, -0.5 * p.eps * p.eps / 24.0, nl, st));
+            r.U = Ud;
+            const hipError_t e = fermion_force(r);
+            r.U = U;
+            HMCCHK(e);
+            return daxpy(P, r.ws + r.L.Ff, -0.5 * 2.0 * p.eps / 3.0, nd, st);
+        };
+        const bool omelyan = p.integrator == GRID_OMELYAN, fg = p.integrator == GRID_FORCE_GRADIENT;
+        HMCCHK(fermion_kick(omelyan ? lam : fg ? 1.0 / 6.0 : 0.5));
         for (int i = 0; i < p.n_steps; ++i) {
             const bool last = i == p.n_steps - 1;
-            if (omelyan) {
+            if (fg) {
+                HMCCHK(gauge_integrate(0.5 * p.eps));
+                HMCCHK(fermion_fg_kick());
+                HMCCHK(gauge_integrate(0.5 * p.eps));
+                HMCCHK(fermion_kick(last ? 1.0 / 6.0 : 2.0 / 6.0));
+            } else if (omelyan) {
                 HMCCHK(gauge_integrate(0.5 * p.eps));
                 HMCCHK(fermion_kick(1.0 - 2.0 * lam));
                 HMCCHK(gauge_integrate(0.5 * p.eps));

@@ -196,8 +196,10 @@ def test_md_validation(lib):
     assert wm >= w + 4 ** 4 * 4 * 192
     assert call(pp=pm) == _lib.GRID_ESPACE
     assert call(pp=_lib.GridMdParams(5.5, 0.05, -1, op(kind=_lib.GRID_DWF), cg)) == _lib.GRID_EINVAL
-    fg2 = _lib.GridMdParams(5.5, 0.05, 4, op(kind=_lib.GRID_DWF), cg, _lib.GRID_FORCE_GRADIENT, 2)
-    assert call(pp=fg2) == _lib.GRID_EINVAL and "outer steps" in _lib.last_error()
+    bad_int = _lib.GridMdParams(5.5, 0.05, 4, op(kind=_lib.GRID_DWF), cg, 3, 2)
+    assert call(pp=bad_int) == _lib.GRID_EINVAL and "integrator" in _lib.last_error()
+    neg_inner = _lib.GridMdParams(5.5, 0.05, 4, op(kind=_lib.GRID_DWF), cg, _lib.GRID_FORCE_GRADIENT, -1)
+    assert call(pp=neg_inner) == _lib.GRID_EINVAL
     assert call(pp=_lib.GridMdParams(float("nan"), 0.05, 4, op(kind=_lib.GRID_DWF), cg)) == _lib.GRID_EINVAL
     assert call(phi=A + 0x10000000 + 64) == _lib.GRID_EINVAL                  # phi overlaps P
     assert lib.grid_link_exp(P(A), P(A + 16), ctypes.c_double(0.1), 16, None) == _lib.GRID_EINVAL

@@ -187,12 +187,12 @@ def test_force_gradient_matches_oracle(gpu, with_fermion):
     assert rel(host(Ud), U) <= 10 * tol and rel(host(Pd), -P) <= 10 * tol
 
 
-@pytest.mark.parametrize("outer", ["leapfrog", "omelyan"])
+@pytest.mark.parametrize("outer", ["leapfrog", "omelyan", "force_gradient"])
 @pytest.mark.parametrize("with_fermion", [False, True])
 def test_nested_time_scales_match_oracle(gpu, with_fermion, outer):
-    """Two time scales (n_inner = 3) with leapfrog or Omelyan outer steps equal the oracle's nested
-    integrators, with n + 1 (leapfrog) or 2 n + 1 (Omelyan) fermion solves; force-gradient outer
-    steps are rejected; zero steps leave U and P unchanged."""
+    """Two time scales (n_inner = 3) with leapfrog, Omelyan or force-gradient outer steps equal the
+    oracle's nested integrators, with n + 1, 2 n + 1 or 3 n + 1 fermion solves; zero steps leave U
+    and P unchanged."""
     from tests.gpu_util import dev, host, rel
     gm = _gm()
     dims, Ls, beta = (2, 2, 2, 4), 4, 5.5
@@ -203,13 +203,12 @@ def test_nested_time_scales_match_oracle(gpu, with_fermion, outer):
     st = gm.md_leapfrog(Ud, Pd, beta, 0.1, 3, dev(phi) if with_fermion else None, tol=1e-12, n_inner=3,
                         integrator=outer, **DWF)
     ferm = (O.Op.dwf(Ls, 1.8, 0.2), phi) if with_fermion else None
-    nested = OH.nested_leapfrog if outer == "leapfrog" else OH.nested_omelyan
+    nested = {"leapfrog": OH.nested_leapfrog, "omelyan": OH.nested_omelyan,
+              "force_gradient": OH.nested_force_gradient}[outer]
     Ur, Pr = nested(U, P, beta, 0.1, 3, ferm, 3)
     tol = 1e-12 if not with_fermion else 1e-8
     assert rel(host(Ud), Ur) <= tol and rel(host(Pd), Pr) <= tol
-    assert st["solves"] == ((4 if outer == "leapfrog" else 7) if with_fermion else 0)
-    with pytest.raises(Exception):
-        gm.md_leapfrog(dev(U), dev(P), beta, 0.1, 1, None, n_inner=2, integrator="force_gradient", **DWF)
+    assert st["solves"] == ({"leapfrog": 4, "omelyan": 7, "force_gradient": 10}[outer] if with_fermion else 0)
     U0, P0 = dev(U), dev(P)
     st = gm.md_leapfrog(U0, P0, beta, 0.1, 0, dev(phi) if with_fermion else None, tol=1e-12, n_inner=3,
                         integrator=outer, **DWF)
