@@ -25,9 +25,9 @@ def gaussian_spinor(shape, rng: np.random.Generator) -> np.ndarray:
 
 
 def trajectory(U, beta, eps, n_steps, rng, fermion=None, integrator="leapfrog", **cg):
-    """One HMC trajectory. fermion: None (pure gauge) or dict(kind, Ls, mass / M5, mf) for a
-    two-flavour pseudofermion phi = Op^dagger eta; integrator "leapfrog", "omelyan" or
-    "force_gradient". Returns
+    """One HMC trajectory. fermion: None (pure gauge) or dict(kind, Ls, mass / M5, mf, b5, c5
+    for "mobius") for a two-flavour pseudofermion phi = Op^dagger eta; integrator "leapfrog",
+    "omelyan" or "force_gradient" (n_inner in cg for two time scales). Returns
     (U_new, accepted, dH, info); U is not modified."""
     dev = U.device
     shape4 = tuple(U.shape[:4])
@@ -39,8 +39,12 @@ def trajectory(U, beta, eps, n_steps, rng, fermion=None, integrator="leapfrog", 
         kw = dict(kind=f.pop("kind"), **f)
         site = shape4 + ((Ls,) if Ls > 1 else ()) + (4, 3)
         eta = torch.from_numpy(gaussian_spinor(site, rng)).to(dev)
-        phi = api.dhop(U, eta, kw["kind"], dag=True, mass=kw.get("mass", 0.0), M5=kw.get("M5", 1.8),
-                       mf=kw.get("mf", 0.01))
+        if kw["kind"] == "mobius":
+            phi = api.mobius(U, eta, kw.get("M5", 1.8), kw.get("mf", 0.01), kw.get("b5", 1.0), kw.get("c5", 0.0),
+                             dag=True)
+        else:
+            phi = api.dhop(U, eta, kw["kind"], dag=True, mass=kw.get("mass", 0.0), M5=kw.get("M5", 1.8),
+                           mf=kw.get("mf", 0.01))
     e0 = api.hmc_energy(U, P, beta, phi, **kw, **cg)
     U1, P1 = U.clone(), P.clone()
     st = api.md_leapfrog(U1, P1, beta, eps, n_steps, phi, integrator=integrator, **kw, **cg)

@@ -236,3 +236,25 @@ def test_mobius_md_matches_oracle(gpu, integrator, n, solves):
     Ur, Pr = step(U, P, beta, 0.1, n, ferm)
     assert rel(host(Ud), Ur) <= 1e-8 and rel(host(Pd), Pr) <= 1e-8
     assert st["solves"] == solves and st["failed_solves"] == 0
+
+
+def test_mobius_trajectory_two_time_scales(gpu):
+    """A trajectory with a Moebius pseudofermion (phi = M^dagger eta) on two time scales (Omelyan
+    outer steps, two inner gauge steps): dH equals the oracle's for the same momenta and source."""
+    import paper_1512_03487_amd.hmc as H
+    from oracle.mobius import MobiusOp, mobius
+    from tests.gpu_util import dev
+    dims, Ls, beta, eps, n = (2, 2, 2, 4), 4, 5.5, 0.1, 3
+    U0 = F.gauge_field(dims, seed=1, kind="weak")
+    rng = np.random.default_rng(77)
+    P0 = H.gaussian_momenta(dims[::-1], rng)
+    eta = H.gaussian_spinor(dims[::-1] + (Ls, 4, 3), rng)
+    phi = mobius(U0, eta, 1.8, 0.2, 1.5, 0.5, dag=True)
+    ferm = (MobiusOp(1.8, 0.2, 1.5, 0.5), phi)
+    U1, P1 = OH.nested_omelyan(U0, P0, beta, eps, n, ferm, 2)
+    dH_ref = OH.hamiltonian(U1, P1, beta, ferm) - OH.hamiltonian(U0, P0, beta, ferm)
+    fermion = dict(kind="mobius", Ls=Ls, M5=1.8, mf=0.2, b5=1.5, c5=0.5)
+    _, _, dH, info = H.trajectory(dev(U0), beta, eps, n, np.random.default_rng(77), fermion=fermion,
+                                  integrator="omelyan", n_inner=2, tol=1e-12)
+    assert dH == pytest.approx(dH_ref, rel=1e-7, abs=1e-9)
+    assert info["md"]["solves"] == 2 * n + 1 and info["md"]["failed_solves"] == 0
