@@ -7,6 +7,7 @@ the bytes it must read and write divided by what the counters report).
 Usage:
   python -m paper_1512_03487_amd.profiling traffic FETCH_DIR WRITE_DIR KERNEL_SUBSTR OUT.txt [--grid N] [--cmd "..."]
   python -m paper_1512_03487_amd.profiling stats KT_DIR OUT.txt [--focus SUBSTR ...] [--cmd "..."]
+  python -m paper_1512_03487_amd.profiling counters DIR[,DIR...] KERNEL_SUBSTR OUT.txt [--grid N] [--cmd "..."]
 
 --grid N keeps only dispatches of N work-items (one launch shape of a kernel that several
 workloads share). The stats summary lists each kernel per launch shape as well.
@@ -81,6 +82,29 @@ def traffic(fetch_dir, write_dir, kernel, out, cmd="", grid=None):
     print(open(out).read())
 
 
+def counters(dirs, kernel, out, cmd="", grid=None):
+    """Median per dispatch of every counter found under the given output directories (one
+    rocprofv3 --pmc pass each, comma-separated) for the kernels matching `kernel`."""
+    vals = {}
+    for d in dirs.split(","):
+        for r in _rows(d):
+            if kernel in r["Kernel_Name"] and (grid is None or int(r["Grid_Size"]) == grid):
+                vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    if not vals:
+        raise SystemExit("no dispatches of " + kernel)
+    with open(out, "w") as fh:
+        fh.write(f"# counters per dispatch (median) of kernels matching '{kernel}'"
+                 + (f" launched with {grid} work-items" if grid else "") + " (rocprofv3 --pmc)\n")
+        if cmd:
+            fh.write(f"# command: {cmd}\n")
+        for k in sorted(vals):
+            v = sorted(vals[k])
+            fh.write(f"{k}: {v[len(v) // 2]:.6g}   (dispatches {len(v)})\n")
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        fh.write(f"source_sha256: {kernel_source_hash(root)}\n")
+    print(open(out).read())
+
+
 def stats(kt_dir, out, cmd="", focus=()):
     files = glob.glob(os.path.join(kt_dir, "**", "*kernel_stats.csv"), recursive=True)
     if not files:
@@ -136,6 +160,8 @@ if __name__ == "__main__":
         args = args[:i] + args[i + 2:]
     if args and args[0] == "traffic":
         traffic(*args[1:5], cmd=cmd, grid=grid)
+    elif args and args[0] == "counters":
+        counters(*args[1:4], cmd=cmd, grid=grid)
     elif args and args[0] == "stats":
         stats(*args[1:3], cmd=cmd, focus=tuple(focus))
     else:
