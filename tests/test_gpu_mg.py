@@ -263,3 +263,29 @@ def test_mg_pcg_solve(gpu, dims, block, nvec, cycle_prec):
     assert abs(st["iterations"] - ito) <= (1 if cycle_prec == "f64" else 3), (st["iterations"], ito)
     x1, s1 = gm.mg_pcg(Ud, qd, Ad, dev(b), m, block=block, graph=True, cycle_prec=cycle_prec, **kw)
     assert s1["iterations"] == st["iterations"] and bool((x1 == x).all())
+
+
+@pytest.mark.parametrize("solver", ["mg_solve", "mg_pcg"])
+def test_mg_status_warm_start_and_zero_source(gpu, solver):
+    """Both multigrid solvers: stopping at maxiter returns GRID_ENOCONV with the iterate so far; a
+    warm start at the converged solution takes no iterations; a zero source returns x = 0."""
+    import torch
+    from paper_1512_03487_amd import _lib
+    from tests.gpu_util import dev
+    gm = _gm()
+    dims, block, nvec, m = (4, 4, 4, 4), (2, 2, 2, 2), 6, 0.2
+    U, q, A = _setup(dims, block, nvec, m)
+    b = dev(F.spinor_field(dims, seed=3))
+    Ud, qd = dev(U), dev(q)
+    Ad = gm.mg_coarse_op(Ud, qd, m, block=block)
+    fn = getattr(gm, solver)
+    kw = dict(block=block, restart=8, coarse_iters=40, coarse_tol=0.05, smooth_iters=2, tol=1e-10)
+    x2, st2 = fn(Ud, qd, Ad, b, m, maxiter=2, raise_on_fail=False, **kw)
+    assert st2["status"] == _lib.GRID_ENOCONV and st2["iterations"] == 2 and not st2["converged"]
+    assert 1e-10 < st2["true_residual"] < 1.0
+    x, st = fn(Ud, qd, Ad, b, m, **kw)
+    assert st["converged"]
+    x1, st1 = fn(Ud, qd, Ad, b, m, x0=x, **kw)
+    assert st1["iterations"] == 0 and st1["converged"] and bool((x1 == x).all())
+    x0, st0 = fn(Ud, qd, Ad, torch.zeros_like(b), m, **kw)
+    assert st0["iterations"] == 0 and bool((x0 == 0).all())
