@@ -8,6 +8,7 @@ Usage:
   python -m paper_1512_03487_amd.profiling traffic FETCH_DIR WRITE_DIR KERNEL_SUBSTR OUT.txt [--grid N] [--cmd "..."]
   python -m paper_1512_03487_amd.profiling stats KT_DIR OUT.txt [--focus SUBSTR ...] [--cmd "..."]
   python -m paper_1512_03487_amd.profiling counters DIR[,DIR...] KERNEL_SUBSTR OUT.txt [--grid N] [--cmd "..."]
+  python -m paper_1512_03487_amd.profiling table DIR OUT.txt --focus SUBSTR [--focus ...] [--cmd "..."]
 
 --grid N keeps only dispatches of N work-items (one launch shape of a kernel that several
 workloads share). The stats summary lists each kernel per launch shape as well.
@@ -105,6 +106,35 @@ def counters(dirs, kernel, out, cmd="", grid=None):
     print(open(out).read())
 
 
+def table(d, out, cmd="", focus=()):
+    """One row per (kernel, launch shape) matching any of `focus`: the median per dispatch of every
+    counter in the pass under `d`."""
+    groups = {}
+    for r in _rows(d):
+        if any(f in r["Kernel_Name"] for f in focus):
+            key = (r["Kernel_Name"], int(r["Grid_Size"]))
+            groups.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    if not groups:
+        raise SystemExit("no dispatches of " + str(focus))
+    names = sorted({c for v in groups.values() for c in v})
+    with open(out, "w") as fh:
+        fh.write("# counters per dispatch (median) by kernel and launch shape (rocprofv3 --pmc)\n")
+        if cmd:
+            fh.write(f"# command: {cmd}\n")
+        fh.write("\n| kernel | work-items | dispatches | " + " | ".join(names) + " |\n")
+        fh.write("|---|---|---|" + "---|" * len(names) + "\n")
+        for (name, n), v in sorted(groups.items()):
+            short = name if len(name) <= 90 else name[:90] + "..."
+            cells = []
+            for c in names:
+                x = sorted(v.get(c, []))
+                cells.append(f"{x[len(x) // 2]:.4g}" if x else "")
+            fh.write(f"| `{short}` | {n} | {len(next(iter(v.values())))} | " + " | ".join(cells) + " |\n")
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        fh.write(f"\nsource_sha256: {kernel_source_hash(root)}\n")
+    print(open(out).read())
+
+
 def stats(kt_dir, out, cmd="", focus=()):
     files = glob.glob(os.path.join(kt_dir, "**", "*kernel_stats.csv"), recursive=True)
     if not files:
@@ -162,6 +192,8 @@ if __name__ == "__main__":
         traffic(*args[1:5], cmd=cmd, grid=grid)
     elif args and args[0] == "counters":
         counters(*args[1:4], cmd=cmd, grid=grid)
+    elif args and args[0] == "table":
+        table(*args[1:3], cmd=cmd, focus=tuple(focus))
     elif args and args[0] == "stats":
         stats(*args[1:3], cmd=cmd, focus=tuple(focus))
     else:
