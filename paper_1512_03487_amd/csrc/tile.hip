@@ -1,13 +1,10 @@
 // Tiled time-walk schedule of the hopping operator on 4D fields (gfx950).
 //
-// Why a third schedule. On this part every byte a lane requests through the vector-memory path
-// costs address-unit time at a fixed rate (about 40 bytes per clock per compute unit, measured),
-// whether the bytes come from HBM, L2 or L1 and whether or not other lanes ask for the same line;
-// a lane reading 16-byte pieces of a 96-byte record at a 96-byte lane stride costs twice that.
-// The column walk fetches each spinor record once per use (eight times) and each link once per
-// lane, so it requests several times the compulsory bytes per site. Here neighbour reuse happens
-// in LDS instead (Grid's observation, Section 3, that a neighbour spinor is used eight times,
-// turned into on-chip reuse).
+// Why a third schedule. The column walk fetches each spinor record once per use (eight times)
+// and each link once per lane, so it requests several times the compulsory bytes per site. Here
+// neighbour reuse happens in LDS instead (Grid's observation, Section 3, that a neighbour spinor
+// is used eight times, turned into on-chip reuse). It serves 4D fields in FP16 storage, where it
+// is the fastest schedule measured.
 //
 // A block owns a TX x TY x TZ tile of (x, y, z) columns, one thread per column (a wavefront per
 // z-plane of the tile), and walks T time slices. Per slice every thread writes its own record
@@ -370,13 +367,13 @@ static TileDev tile_dev(const GeomDev &g) {
     return td;
 }
 
-// FP32 18-real links stay on the direction-parallel schedule for 4D fields: there the eight
-// direction wavefronts of a block read a site's four links at about the same time, whereas the
-// walk reads them one direction after another and a link's cache lines are fetched again
-// (measured 157 against 166 us at 32^4); 12-real FP32 links (131 against 144 us) and FP16 storage
-// (86 against 93 us for the column walk) are faster here.
+// 4D FP16 storage only (86 against 93 us for the column walk, 74 against 132 us for the
+// direction-parallel kernel at 32^4). 4D FP32 fields, 12-real links included, run faster on the
+// direction-parallel kernel with its blocks as 4 x 2 x 2 x 2 boxes (32^4 12-real: 122.0 against
+// 132.1 us here; 18-real: the eight direction wavefronts read a site's four links at about the
+// same time, whereas this walk reads them one direction after another).
 static bool tile4_applies(const DhopArgs &a) {
-    const bool prec_ok = a.prec == GRID_F16S || (a.prec == GRID_F32 && a.link_fmt == GRID_L12);
+    const bool prec_ok = a.prec == GRID_F16S;
     return !a.custom && a.g.Ls == 1 && prec_ok && a.g.L[0] % kTX == 0 && a.g.L[1] % kTY == 0 &&
            a.g.L[2] % kTZ == 0 && (a.kind == GRID_HOP || a.kind == GRID_WILSON);
 }
