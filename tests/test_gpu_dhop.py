@@ -37,7 +37,7 @@ def test_config0_wilson_d_and_ddag_4444(gpu):
 
 
 @pytest.mark.parametrize("dims", [(2, 2, 2, 2), (2, 3, 4, 5), (4, 6, 8, 10), (6, 4, 2, 8), (8, 8, 4, 3),
-                                  (16, 8, 12, 4)])
+                                  (16, 8, 12, 4), (8, 4, 8, 2), (16, 8, 16, 6)])
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
 @pytest.mark.parametrize("fmt", ["L18", "L12"])
 def test_hop_and_wilson_parity(gpu, dims, prec, fmt):
